@@ -1,0 +1,168 @@
+/*
+ * mag.h - C ABI of the MAG multiple-pattern-matching scan on MI355X (gfx950).
+ *
+ * Problem (Section 1 of Susik, Grabowski, Fredriksson, "Multiple pattern
+ * matching revisited"): given a text T of n bytes and r patterns P_0..P_{r-1},
+ * all of the same length m, report every occurrence
+ *
+ *     (i, id)  with  0 <= i <= n-m  and  T[i..i+m) == P_id.
+ *
+ * Method (Sections 2-3, "MAG"): bytes are reduced to sigma' codes (Section 3.3),
+ * the patterns are cut into non-overlapping q-grams for all q shifts and
+ * superimposed into character classes (Section 2), the classes are split into
+ * k interleaved sub-patterns searched with one bit-parallel Shift-Or automaton
+ * that reads every k-th q-gram of the text (Sections 3.1-3.2), and each window
+ * that survives is verified exactly (Section 3.2). The filter only prunes, so
+ * the output is exactly the occurrence set above.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named d_* are device pointers (HIP, current device); all others
+ *    are host pointers. The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued in stream order; device outputs are valid once the stream
+ *    has reached that point.
+ *  - Every call returns mag_status; on failure mag_last_error() holds a
+ *    thread-local description. Calls are thread-compatible: one plan may be
+ *    scanned by one stream at a time (its scratch buffers are shared).
+ *  - A match record is 16 bytes {u64 pos, u32 pattern_id, u32 reserved=0}.
+ *    Records are sorted ascending by (pos, pattern_id); positions are
+ *    0-based starts; overlapping matches are all reported and every id of a
+ *    repeated pattern is reported.
+ */
+#ifndef MAG_H
+#define MAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MAG_OK = 0,
+    MAG_E_INVALID = -1,     /* bad argument or parameter combination           */
+    MAG_E_UNSUPPORTED = -2, /* valid but outside this build's limits           */
+    MAG_E_NOMEM = -3,       /* host or device allocation failed                */
+    MAG_E_DEVICE = -4,      /* a HIP call failed (detail in mag_last_error)    */
+    MAG_E_OVERFLOW = -5     /* output capacity too small; count still returned */
+} mag_status;
+
+/* How the filter parameters (q, k, sigma') are chosen. */
+typedef enum {
+    MAG_SELECT_HEURISTIC = 0, /* q = log_sigma(rm), k from Section 3.2, sigma'
+                                 lowered until the mask table fits the budget */
+    MAG_SELECT_EXPLICIT = 1,  /* q, k, sigma_prime taken from mag_params       */
+    MAG_SELECT_LEARNED = 2,   /* argmin of the selector network's predicted
+                                 cost over feasible triples; heuristic fallback */
+    MAG_SELECT_AUTOTUNE = 3   /* measured on the device over a small grid      */
+} mag_select;
+
+/* Alphabet reduction mu: byte -> [0, sigma') (Section 3.3). */
+typedef enum {
+    MAG_MAP_GREEDY = 0, /* equal-weight bins by longest-processing-time greedy */
+    MAG_MAP_RANK = 1    /* frequency rank; ranks >= sigma'-1 share the last code */
+} mag_map_kind;
+
+typedef struct {
+    int32_t select;       /* mag_select                                         */
+    int32_t map_kind;     /* mag_map_kind                                       */
+    int32_t q;            /* q-gram length (explicit selection)                 */
+    int32_t k;            /* sampling parameter (explicit selection)            */
+    int32_t sigma_prime;  /* reduced alphabet size (explicit selection)         */
+    int32_t table_budget; /* bytes the heuristic allows for the mask table;
+                             0 = 96 KiB                                         */
+    int32_t reserved[6];  /* must be zero                                       */
+} mag_params;
+
+typedef struct {
+    uint64_t pos;
+    uint32_t pattern_id;
+    uint32_t reserved;
+} mag_match;
+
+/* Resolved shape of a plan (filled by mag_plan_info). */
+typedef struct {
+    int32_t q, k, sigma_prime;
+    int32_t L;            /* gram positions shared by all shifts: (m-q+1)/q     */
+    int32_t m_prime;      /* sub-pattern length: min(L/k, 64/k)                 */
+    int32_t W;            /* automaton bits: k * m_prime                        */
+    int32_t entry_bytes;  /* bytes per mask-table entry (1, 2, 4 or 8)          */
+    int32_t map_kind;
+    int32_t select;       /* how the parameters were chosen                     */
+    uint32_t r, m;
+    uint32_t n_unique;    /* distinct patterns                                  */
+    uint64_t n_codes;     /* sigma'^q mask-table entries                        */
+    uint64_t table_bytes; /* n_codes * entry_bytes                              */
+} mag_plan_desc;
+
+/* Work counters of one scan (integers; equal to the oracle's counts). */
+typedef struct {
+    uint64_t samples;        /* text q-grams read by the filter                 */
+    uint64_t cand_windows;   /* (x, j) windows that passed the filter           */
+    uint64_t verifications;  /* start positions verified exactly                */
+    uint64_t matches;        /* occurrences found                               */
+} mag_stats;
+
+typedef struct mag_plan mag_plan;
+
+/* Builds a plan for r patterns of length m (host array, row-major r*m bytes;
+ * copied, so the caller may free it on return). params may be NULL (heuristic,
+ * greedy map). Host-only work: device tables are uploaded on first use.
+ * Errors: m == 0 or m > 64, explicit q with 2q-1 > m, k outside [1, L],
+ * sigma' outside [1, 256] or a mask table above 1 GiB -> MAG_E_INVALID /
+ * MAG_E_UNSUPPORTED. r == 0 is valid (every scan returns no match). */
+mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
+                           const mag_params *params, mag_plan **out);
+
+/* Releases the plan and its device tables. NULL is ignored. The caller must
+ * not destroy a plan while a stream still runs work that uses it. */
+void mag_plan_destroy(mag_plan *plan);
+
+/* Resolved parameters and table sizes of a plan. */
+mag_status mag_plan_info(const mag_plan *plan, mag_plan_desc *desc);
+
+/* Host copies of the plan's alphabet map (256 bytes) and mask table
+ * (desc.table_bytes bytes, little-endian entries of desc.entry_bytes). Either
+ * output may be NULL. table_cap is the capacity of table_out in bytes. */
+mag_status mag_plan_export(const mag_plan *plan, uint8_t *mu_out, void *table_out,
+                           uint64_t table_cap);
+
+/* Scans d_text[0..n) and enqueues everything on `stream` without waiting:
+ * filter, verification and the final sort. Writes min(z, out_cap) sorted
+ * records to d_out and z, the exact number of occurrences, to *d_count (a
+ * device uint64). If z > out_cap the records are unspecified (never written
+ * past out_cap) and the caller should retry with a larger buffer. d_stats may
+ * be NULL or a device mag_stats that receives the work counters. Any d_text
+ * alignment is accepted. The plan's device scratch holds 16 bytes per unit of
+ * out_cap. */
+mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
+                          mag_match *d_out, uint64_t out_cap, uint64_t *d_count,
+                          mag_stats *d_stats, void *stream);
+
+/* As mag_scan_async, then waits for the stream and returns the count in
+ * *n_matches (host) and the counters in *stats (host, may be NULL). Returns
+ * MAG_E_OVERFLOW when z > out_cap (with *n_matches = z). */
+mag_status mag_scan(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                    uint64_t out_cap, uint64_t *n_matches, mag_stats *stats, void *stream);
+
+/* Kernel timing for benchmarks. While enabled (process-wide), every scan
+ * records HIP events on its own stream around its filter/verify kernel and its
+ * finishing (count + sort) kernel. mag_profile_read waits for the recorded
+ * events, adds their elapsed times (milliseconds) to *scan_ms and *finish_ms,
+ * sets *launches to the number of scans measured, and clears the record.
+ * Enabling adds two event records per scan; disabled by default. */
+mag_status mag_profile_enable(int enable);
+mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launches);
+
+const char *mag_status_string(mag_status s);
+const char *mag_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t mag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAG_H */

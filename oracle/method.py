@@ -37,6 +37,7 @@ import math
 import numpy as np
 
 MAX_W = 64          # state bits of the bit-parallel automaton (w = 64 in Section 3.2)
+MAX_Q = 8           # q is a small constant in practice (Section 2 names 2..6)
 DEFAULT_TABLE_BUDGET = 96 * 1024   # bytes of mask table the fixed heuristic allows
 
 
@@ -123,10 +124,11 @@ def entry_bytes(W: int) -> int:
 def heuristic_q(sigma: int, r: int, m: int) -> int:
     """q = log_sigma(r m) (Section 3.2). Reading: sigma is the number of
     distinct pattern bytes (at least 2), rounded half up, clamped to
-    [1, (m+1)//2] so that at least one gram position exists."""
+    [1, min((m+1)//2, 8)]: at least one gram position must exist, and q stays
+    the small constant Section 2 describes."""
     s = max(sigma, 2)
     q = round_half_up(math.log(r * m) / math.log(s))
-    return max(1, min(q, (m + 1) // 2))
+    return max(1, min(q, (m + 1) // 2, MAX_Q))
 
 
 def heuristic_k(sigma: int, r: int, m: int, L: int) -> int:

@@ -1,0 +1,162 @@
+"""MAG multiple pattern matching on MI355X.
+
+Thin Python front end of ``libmag.so`` (C ABI in ``include/mag.h``): it only
+marshals arguments. Every step of the scan runs in the library's HIP kernels;
+PyTorch supplies device memory and streams.
+
+    import torch, paper_1405_5483_amd as mag
+    plan = mag.Plan(patterns)                 # [r, m] uint8 (numpy / bytes list)
+    occ = mag.scan(text_cuda_u8, plan)        # int64 [z, 2]: (pos, pattern id)
+
+The occurrence set is the one of Section 1 of the paper: every (i, id) with
+``T[i..i+m) == P_id``, sorted by (i, id).
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import (MAG_E_OVERFLOW, MAP_KIND, SELECT, MagError, MagParams, MagPlanDesc,
+                   MagStats, check, lib)
+
+__all__ = ["Plan", "scan", "scan_async", "profile_enable", "profile_read", "MagError", "lib"]
+
+_ENTRY_DTYPE = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+
+
+def _as_patterns(patterns) -> np.ndarray:
+    if isinstance(patterns, (list, tuple)):
+        rows = [np.frombuffer(bytes(p), dtype=np.uint8) for p in patterns]
+        if not rows:
+            raise ValueError("empty pattern list needs an explicit length; pass a [0, m] array")
+        return np.ascontiguousarray(np.stack(rows))
+    if hasattr(patterns, "detach"):          # torch tensor
+        patterns = patterns.detach().cpu().numpy()
+    p = np.ascontiguousarray(patterns, dtype=np.uint8)
+    if p.ndim != 2:
+        raise ValueError("patterns must be [r, m]")
+    return p
+
+
+class Plan:
+    """A pattern set prepared for scanning (``mag_plan_create``)."""
+
+    def __init__(self, patterns, *, select: str = "heuristic", q: int | None = None,
+                 k: int | None = None, sigma_prime: int | None = None,
+                 map_kind: str = "greedy", table_budget: int = 0):
+        p = _as_patterns(patterns)
+        self.r, self.m = int(p.shape[0]), int(p.shape[1])
+        prm = MagParams()
+        if q is not None or k is not None or sigma_prime is not None:
+            if select == "heuristic":
+                select = "explicit"
+        prm.select = SELECT[select]
+        prm.map_kind = MAP_KIND[map_kind]
+        prm.q = int(q or 0)
+        prm.k = int(k or 0)
+        prm.sigma_prime = int(sigma_prime or 0)
+        prm.table_budget = int(table_budget)
+        handle = ctypes.c_void_p()
+        self._h = None
+        check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,
+                                    ctypes.byref(prm), ctypes.byref(handle)), "mag_plan_create")
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan is closed")
+        return self._h
+
+    def info(self) -> dict:
+        d = MagPlanDesc()
+        check(lib().mag_plan_info(self.handle, ctypes.byref(d)), "mag_plan_info")
+        return {name: getattr(d, name) for name, _ in MagPlanDesc._fields_}
+
+    def export(self):
+        """(mu [256] uint8, mask table [sigma'^q] of the entry dtype)."""
+        info = self.info()
+        mu = np.empty(256, dtype=np.uint8)
+        table = np.empty(info["n_codes"], dtype=_ENTRY_DTYPE[info["entry_bytes"]])
+        check(lib().mag_plan_export(self.handle, mu.ctypes.data, table.ctypes.data,
+                                    table.nbytes), "mag_plan_export")
+        return mu, table
+
+    def close(self):
+        if self._h is not None:
+            lib().mag_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_text(text):
+    import torch
+    if not isinstance(text, torch.Tensor) or text.dtype != torch.uint8 or not text.is_cuda:
+        raise TypeError("text must be a torch.uint8 CUDA (HIP) tensor")
+    if not text.is_contiguous():
+        raise ValueError("text must be contiguous")
+
+
+def scan(text, plan: Plan, out_cap: int | None = None, stats: bool = False, stream=None):
+    """All occurrences as an int64 tensor [z, 2] of (pos, pattern id), sorted.
+    With ``stats=True`` also returns the work counters as a dict."""
+    import torch
+    _check_text(text)
+    n = text.numel()
+    cap = int(out_cap) if out_cap is not None else max(1024, min(n // 8, 1 << 22))
+    st = MagStats()
+    count = ctypes.c_uint64(0)
+    for _ in range(2):
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=text.device)
+        status = lib().mag_scan(plan.handle, ctypes.c_void_p(text.data_ptr()), n,
+                                ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(count),
+                                ctypes.byref(st), _stream_ptr(stream))
+        if status == MAG_E_OVERFLOW and out_cap is None:
+            cap = int(count.value)
+            continue
+        check(status, "mag_scan")
+        break
+    z = int(count.value)
+    res = out[:z]
+    if stats:
+        return res, {name: int(getattr(st, name)) for name, _ in MagStats._fields_}
+    return res
+
+
+def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> None:
+    """Enqueues a scan without waiting (``mag_scan_async``). ``out`` is an
+    int64 [cap, 2] CUDA tensor, ``d_count`` an int64 [1] CUDA tensor that
+    receives the exact occurrence count, ``d_stats`` an optional int64 [4]
+    CUDA tensor for the counters."""
+    _check_text(text)
+    check(lib().mag_scan_async(plan.handle, ctypes.c_void_p(text.data_ptr()), text.numel(),
+                               ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                               ctypes.c_void_p(d_count.data_ptr()),
+                               ctypes.c_void_p(d_stats.data_ptr()) if d_stats is not None else None,
+                               _stream_ptr(stream)), "mag_scan_async")
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around each scan's kernels (``mag_profile_enable``)."""
+    check(lib().mag_profile_enable(1 if on else 0), "mag_profile_enable")
+
+
+def profile_read() -> dict:
+    """Summed kernel times since the last read (``mag_profile_read``)."""
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
+    check(lib().mag_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+          "mag_profile_read")
+    return {"scan_ms": a.value, "finish_ms": b.value, "launches": int(n.value)}

@@ -1,0 +1,111 @@
+"""ctypes declarations mirroring ``include/mag.h``.
+
+Loading fails loudly when ``libmag.so`` has not been built: there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmag.so")
+
+MAG_OK = 0
+MAG_E_INVALID = -1
+MAG_E_UNSUPPORTED = -2
+MAG_E_NOMEM = -3
+MAG_E_DEVICE = -4
+MAG_E_OVERFLOW = -5
+
+SELECT = {"heuristic": 0, "explicit": 1, "learned": 2, "autotune": 3}
+MAP_KIND = {"greedy": 0, "rank": 1}
+
+
+class MagParams(ctypes.Structure):
+    _fields_ = [
+        ("select", ctypes.c_int32),
+        ("map_kind", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("sigma_prime", ctypes.c_int32),
+        ("table_budget", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class MagMatch(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_uint64), ("pattern_id", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class MagPlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_int32), ("k", ctypes.c_int32), ("sigma_prime", ctypes.c_int32),
+        ("L", ctypes.c_int32), ("m_prime", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("entry_bytes", ctypes.c_int32), ("map_kind", ctypes.c_int32), ("select", ctypes.c_int32),
+        ("r", ctypes.c_uint32), ("m", ctypes.c_uint32), ("n_unique", ctypes.c_uint32),
+        ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+    ]
+
+
+class MagStats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_uint64), ("cand_windows", ctypes.c_uint64),
+                ("verifications", ctypes.c_uint64), ("matches", ctypes.c_uint64)]
+
+
+# name -> (restype, argtypes); every function declared in include/mag.h
+SIGNATURES = {
+    "mag_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_void_p)]),
+    "mag_plan_destroy": (None, [ctypes.c_void_p]),
+    "mag_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MagPlanDesc)]),
+    "mag_plan_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_uint64]),
+    "mag_scan_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_scan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(MagStats), ctypes.c_void_p]),
+    "mag_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "mag_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "mag_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mag_last_error": (ctypes.c_char_p, []),
+    "mag_version": (ctypes.c_int32, []),
+}
+
+
+class MagError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1405_5483_amd.build` "
+                "(there is no fallback path)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status: int, what: str = "") -> int:
+    if status != MAG_OK:
+        detail = lib().mag_last_error().decode(errors="replace")
+        raise MagError(status, f"{what}: {detail}" if what else detail)
+    return status

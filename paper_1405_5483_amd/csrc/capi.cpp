@@ -1,0 +1,339 @@
+// C ABI of the MAG library (declared in include/mag.h): plan life cycle,
+// device upload, scratch management and the scan entry points.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mag_internal.hpp"
+
+namespace mag {
+
+namespace {
+thread_local std::string g_last_error;
+
+// benchmark timing: events recorded around each scan's two kernels
+struct ProfileRecord {
+    hipEvent_t start, mid, end;
+};
+std::mutex g_prof_mtx;
+bool g_prof_on = false;
+std::vector<ProfileRecord> g_prof;
+
+hipEvent_t make_event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+uint64_t round16(uint64_t v) { return (v + 15) & ~15ull; }
+
+int ceil_log2(uint64_t v) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < v) ++b;
+    return b;
+}
+
+// Uploads the plan's tables to the current device on first use.
+mag_status ensure_device(mag_plan *p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (p->device >= 0) {
+        if (p->device != dev)
+            return fail(MAG_E_INVALID, "plan was uploaded to another device");
+        return MAG_OK;
+    }
+    const uint64_t o_mu = 0;
+    const uint64_t o_tab = 256;
+    const uint64_t o_slots = round16(o_tab + round16(p->table.size()) + 16);
+    const uint64_t o_pw = round16(o_slots + p->slots.size() * 8);
+    const uint64_t o_ids0 = round16(o_pw + p->pwords.size() * 4 + 16);
+    const uint64_t o_ids = round16(o_ids0 + p->idstart.size() * 4);
+    const uint64_t total = round16(o_ids + p->ids.size() * 4 + 16);
+    uint8_t *base = nullptr;
+    e = hipMalloc(&base, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of plan tables failed");
+    }
+    std::string host(total, '\0');
+    std::memcpy(&host[o_mu], p->mu, 256);
+    if (!p->table.empty()) std::memcpy(&host[o_tab], p->table.data(), p->table.size());
+    if (!p->slots.empty()) std::memcpy(&host[o_slots], p->slots.data(), p->slots.size() * 8);
+    if (!p->pwords.empty()) std::memcpy(&host[o_pw], p->pwords.data(), p->pwords.size() * 4);
+    if (!p->idstart.empty()) std::memcpy(&host[o_ids0], p->idstart.data(), p->idstart.size() * 4);
+    if (!p->ids.empty()) std::memcpy(&host[o_ids], p->ids.data(), p->ids.size() * 4);
+    e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        return hip_fail(e, "upload of plan tables");
+    }
+    p->dev.base = base;
+    p->dev.mu = base + o_mu;
+    p->dev.table = base + o_tab;
+    p->dev.slots = reinterpret_cast<const uint64_t *>(base + o_slots);
+    p->dev.pwords = reinterpret_cast<const uint32_t *>(base + o_pw);
+    p->dev.idstart = reinterpret_cast<const uint32_t *>(base + o_ids0);
+    p->dev.ids = reinterpret_cast<const uint32_t *>(base + o_ids);
+
+    // fixed scratch: counters[4], count, stats
+    Scratch &sc = p->scratch;
+    sc.device = dev;
+    sc.sort_groups = finish_groups();
+    if (sc.sort_groups < 1) return fail(MAG_E_DEVICE, "cannot size the finishing kernel");
+    e = hipMalloc(&sc.counters, 16 * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&sc.hist, (size_t)256 * sc.sort_groups * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of scan scratch failed");
+    }
+    p->device = dev;
+    return MAG_OK;
+}
+
+// Grows the key buffers to hold 2 * cap keys. Waits for `stream` first so no
+// earlier scan still uses the old buffer.
+mag_status ensure_keys(mag_plan *p, uint64_t cap, hipStream_t stream) {
+    Scratch &sc = p->scratch;
+    if (sc.keys_cap >= cap && sc.keys) return MAG_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (sc.keys) {
+        (void)hipFree(sc.keys);
+        sc.keys = nullptr;
+        sc.keys_cap = 0;
+    }
+    uint64_t want = cap < 1024 ? 1024 : cap;
+    e = hipMalloc(&sc.keys, want * 2 * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of sort keys failed");
+    }
+    sc.keys_cap = want;
+    return MAG_OK;
+}
+
+}  // namespace
+
+mag_status fail(mag_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+mag_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return MAG_E_DEVICE;
+}
+
+}  // namespace mag
+
+using namespace mag;
+
+extern "C" {
+
+int32_t mag_version(void) { return 100; }
+
+const char *mag_status_string(mag_status s) {
+    switch (s) {
+        case MAG_OK: return "ok";
+        case MAG_E_INVALID: return "invalid argument";
+        case MAG_E_UNSUPPORTED: return "unsupported";
+        case MAG_E_NOMEM: return "out of memory";
+        case MAG_E_DEVICE: return "device error";
+        case MAG_E_OVERFLOW: return "output overflow";
+    }
+    return "unknown status";
+}
+
+const char *mag_last_error(void) { return g_last_error.c_str(); }
+
+mag_status mag_profile_enable(int enable) {
+    std::lock_guard<std::mutex> pl(g_prof_mtx);
+    g_prof_on = enable != 0;
+    return MAG_OK;
+}
+
+mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launches) {
+    if (!scan_ms || !finish_ms || !launches) return fail(MAG_E_INVALID, "NULL argument");
+    std::vector<ProfileRecord> recs;
+    {
+        std::lock_guard<std::mutex> pl(g_prof_mtx);
+        recs.swap(g_prof);
+    }
+    double a = 0, b = 0;
+    mag_status st = MAG_OK;
+    for (auto &r : recs) {
+        float t1 = 0, t2 = 0;
+        hipError_t e = hipEventSynchronize(r.end);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t1, r.start, r.mid);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t2, r.mid, r.end);
+        if (e != hipSuccess && st == MAG_OK) st = hip_fail(e, "reading profile events");
+        a += t1;
+        b += t2;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.mid);
+        (void)hipEventDestroy(r.end);
+    }
+    *scan_ms = a;
+    *finish_ms = b;
+    *launches = recs.size();
+    return st;
+}
+
+mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
+                           const mag_params *params, mag_plan **out) {
+    if (!out) return fail(MAG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (params) {
+        for (int v : params->reserved)
+            if (v) return fail(MAG_E_INVALID, "mag_params.reserved must be zero");
+    }
+    mag_plan *p = new (std::nothrow) mag_plan();
+    if (!p) return fail(MAG_E_NOMEM, "host allocation failed");
+    mag_status s;
+    try {
+        s = build_plan(p, patterns, r, m, params);
+    } catch (const std::bad_alloc &) {
+        s = fail(MAG_E_NOMEM, "host allocation failed while building the plan");
+    }
+    if (s != MAG_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return MAG_OK;
+}
+
+void mag_plan_destroy(mag_plan *p) {
+    if (!p) return;
+    if (p->device >= 0) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->dev.base);
+        (void)hipFree(p->scratch.counters);
+        (void)hipFree(p->scratch.hist);
+        (void)hipFree(p->scratch.keys);
+        (void)hipSetDevice(cur);
+    }
+    delete p;
+}
+
+mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
+    if (!p || !d) return fail(MAG_E_INVALID, "NULL argument");
+    std::memset(d, 0, sizeof(*d));
+    d->q = p->q;
+    d->k = p->k;
+    d->sigma_prime = p->sigma_prime;
+    d->L = p->L;
+    d->m_prime = p->mprime;
+    d->W = p->W;
+    d->entry_bytes = p->esz;
+    d->map_kind = p->map_kind;
+    d->select = p->select;
+    d->r = p->r;
+    d->m = p->m;
+    d->n_unique = p->n_unique;
+    d->n_codes = p->n_codes;
+    d->table_bytes = p->table.size();
+    return MAG_OK;
+}
+
+mag_status mag_plan_export(const mag_plan *p, uint8_t *mu_out, void *table_out, uint64_t table_cap) {
+    if (!p) return fail(MAG_E_INVALID, "plan is NULL");
+    if (mu_out) std::memcpy(mu_out, p->mu, 256);
+    if (table_out) {
+        if (table_cap < p->table.size()) return fail(MAG_E_INVALID, "table_out too small");
+        std::memcpy(table_out, p->table.data(), p->table.size());
+    }
+    return MAG_OK;
+}
+
+mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                          uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream_) {
+    if (!p) return fail(MAG_E_INVALID, "plan is NULL");
+    if (!d_count) return fail(MAG_E_INVALID, "d_count is NULL");
+    if (n && !d_text) return fail(MAG_E_INVALID, "d_text is NULL");
+    if (out_cap && !d_out) return fail(MAG_E_INVALID, "d_out is NULL");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    std::lock_guard<std::mutex> lock(p->mtx);
+    mag_status s = ensure_device(p);
+    if (s != MAG_OK) return s;
+    s = ensure_keys(p, out_cap, stream);
+    if (s != MAG_OK) return s;
+
+    const int idbits = ceil_log2(p->r > 1 ? p->r : 2);
+    const int posbits = ceil_log2(n + 1 > 2 ? n + 1 : 2);
+    if (idbits + posbits > 64) return fail(MAG_E_UNSUPPORTED, "positions and ids need more than 64 key bits");
+    const uint64_t kq = (uint64_t)p->k * p->q;
+    const uint64_t samples = n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0;
+
+    s = launch_fill_u64(p->scratch.counters, 4, 0, stream);
+    if (s != MAG_OK) return s;
+    ScanLaunch sl;
+    sl.text = d_text;
+    sl.n = n;
+    sl.keys = p->scratch.keys;
+    sl.cap = out_cap;
+    sl.counters = p->scratch.counters;
+    sl.idbits = idbits;
+    ProfileRecord rec{nullptr, nullptr, nullptr};
+    bool prof;
+    {
+        std::lock_guard<std::mutex> pl(g_prof_mtx);
+        prof = g_prof_on;
+    }
+    if (prof) {
+        rec.start = make_event();
+        rec.mid = make_event();
+        rec.end = make_event();
+        if (!rec.start || !rec.mid || !rec.end) return fail(MAG_E_DEVICE, "hipEventCreate");
+        (void)hipEventRecord(rec.start, stream);
+    }
+    s = launch_scan(p, sl, stream);
+    if (s != MAG_OK) return s;
+    if (prof) (void)hipEventRecord(rec.mid, stream);
+    s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits,
+                      idbits + posbits, stream);
+    if (s != MAG_OK) return s;
+    if (prof) {
+        (void)hipEventRecord(rec.end, stream);
+        std::lock_guard<std::mutex> pl(g_prof_mtx);
+        g_prof.push_back(rec);
+    }
+    return MAG_OK;
+}
+
+mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                    uint64_t out_cap, uint64_t *n_matches, mag_stats *stats, void *stream_) {
+    if (!p) return fail(MAG_E_INVALID, "plan is NULL");
+    if (!n_matches) return fail(MAG_E_INVALID, "n_matches is NULL");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    {
+        std::lock_guard<std::mutex> lock(p->mtx);
+        mag_status s = ensure_device(p);
+        if (s != MAG_OK) return s;
+    }
+    // the count and the counters land in the plan's own scratch words
+    uint64_t *d_cnt = p->scratch.counters + 4;
+    mag_stats *d_st = reinterpret_cast<mag_stats *>(p->scratch.counters + 8);
+    mag_status s = mag_scan_async(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_);
+    if (s != MAG_OK) return s;
+    uint64_t host[12];
+    hipError_t e = hipMemcpyAsync(host, p->scratch.counters + 4, 8 * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the match count");
+    *n_matches = host[0];
+    if (stats) std::memcpy(stats, &host[4], sizeof(mag_stats));
+    return host[0] > out_cap ? fail(MAG_E_OVERFLOW, "output capacity smaller than the match count")
+                             : MAG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations of the MAG library: the plan, the verification hash
+// (shared by the host builder and the device kernels) and the kernel launch
+// entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mag.h"
+
+namespace mag {
+
+constexpr int kMaxM = 64;           // longest pattern this build verifies
+constexpr int kMaxQ = 8;            // longest q-gram
+constexpr int kMaxW = 64;           // automaton bits
+constexpr int kMaxK = 32;           // candidate mask of one window fits 32 bits
+constexpr uint64_t kMaxTableBytes = 1ull << 30;
+constexpr int kDefaultTableBudget = 96 * 1024;
+constexpr int kHashWords = 4;       // the verification hash reads the first 16 bytes
+
+// Fingerprint of the first min(m, 16) bytes of a pattern or text window, given
+// as little-endian 32-bit words with bytes past m zeroed. It only has to spread
+// keys over the probe table; equality is decided by a full compare.
+__host__ __device__ inline uint32_t window_hash(const uint32_t *w, int nwords) {
+    uint32_t h = 0x9E3779B9u;
+    for (int t = 0; t < nwords; ++t) {
+        h ^= w[t];
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 15;
+    }
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Everything a scan needs on the device. Plain pointers into one allocation.
+struct DeviceTables {
+    uint8_t *base = nullptr;        // the single allocation
+    const uint8_t *mu = nullptr;    // 256 B
+    const void *table = nullptr;    // n_codes * entry_bytes
+    const uint64_t *slots = nullptr;   // 2^slot_bits probe slots: (hash << 32) | (u + 1)
+    const uint32_t *pwords = nullptr;  // n_unique * mw words
+    const uint32_t *idstart = nullptr; // n_unique + 1
+    const uint32_t *ids = nullptr;     // r
+};
+
+struct Scratch {
+    int device = -1;
+    uint64_t *counters = nullptr;   // [0] matches [1] cand windows [2] verifications [3] samples
+    uint64_t *keys = nullptr;       // two key buffers of keys_cap entries each
+    uint64_t keys_cap = 0;
+    uint32_t *hist = nullptr;       // radix counts: 256 * max groups
+    int sort_groups = 0;
+};
+
+}  // namespace mag
+
+struct mag_plan {
+    // pattern set
+    uint32_t r = 0, m = 0, mw = 0;
+    std::vector<uint8_t> patterns;
+
+    // filter parameters
+    int q = 1, k = 1, sigma_prime = 1, L = 0, mprime = 0, W = 0, esz = 1;
+    int map_kind = MAG_MAP_GREEDY, select = MAG_SELECT_HEURISTIC;
+    uint8_t mu[256] = {0};
+    uint64_t n_codes = 0;
+    std::vector<uint8_t> table;      // n_codes * esz bytes
+
+    // verification set: distinct patterns, their ids, and a probe table
+    uint32_t n_unique = 0, slot_bits = 1;
+    std::vector<uint32_t> pwords, idstart, ids;
+    std::vector<uint64_t> slots;
+
+    // device side
+    std::mutex mtx;
+    int device = -1;
+    mag::DeviceTables dev;
+    mag::Scratch scratch;
+};
+
+namespace mag {
+
+// Thread-local error text (capi.cpp).
+mag_status fail(mag_status s, const std::string &msg);
+mag_status hip_fail(hipError_t e, const char *what);
+
+// Host plan builder (plan.cpp).
+mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
+                      const mag_params *params);
+
+// Kernel launches (scan.hip, sort.hip).
+struct ScanLaunch {
+    const uint8_t *text;
+    uint64_t n;
+    uint64_t *keys;       // key output, capacity cap
+    uint64_t cap;
+    uint64_t *counters;
+    int idbits;
+};
+mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream);
+mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStream_t stream);
+// Groups of the cooperative finishing kernel on the current device (0 on error).
+int finish_groups();
+mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
+                         mag_stats *d_stats, mag_match *out, int idbits, int nbits,
+                         hipStream_t stream);
+
+}  // namespace mag

@@ -1,0 +1,222 @@
+// Host side of a MAG plan: parameter choice, alphabet map, superimposed mask
+// table and the verification set.
+//
+//  - fixed heuristic for (q, k, sigma')            Section 3.2 and 3.3
+//  - alphabet map mu (frequency rank / greedy bins) Section 3.3
+//  - q-gram classes over all q shifts, superimposed Section 2
+//  - k interleaved sub-patterns, Shift-Or masks     Sections 3.1-3.2
+//  - exact verification set                         Section 3.2
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "mag_internal.hpp"
+
+namespace mag {
+namespace {
+
+int round_half_up(double v) { return (int)std::floor(v + 0.5); }
+
+int entry_bytes_for(int W) {
+    if (W <= 8) return 1;
+    if (W <= 16) return 2;
+    if (W <= 32) return 4;
+    return 8;
+}
+
+// Byte histogram of the pattern set and the present bytes ordered by
+// descending count, equal counts by ascending byte value.
+void frequency_order(const mag_plan *p, uint64_t hist[256], std::vector<int> &order) {
+    std::fill(hist, hist + 256, 0);
+    for (uint8_t c : p->patterns) hist[c]++;
+    order.clear();
+    for (int c = 0; c < 256; ++c)
+        if (hist[c]) order.push_back(c);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return hist[a] > hist[b]; });
+}
+
+// mu by frequency rank: rank i -> code i, ranks >= sigma'-1 and absent bytes
+// -> sigma'-1.
+void map_rank(mag_plan *p) {
+    uint64_t hist[256];
+    std::vector<int> order;
+    frequency_order(p, hist, order);
+    std::fill(p->mu, p->mu + 256, (uint8_t)(p->sigma_prime - 1));
+    for (size_t i = 0; i < order.size(); ++i)
+        p->mu[order[i]] = (uint8_t)std::min<size_t>(i, p->sigma_prime - 1);
+}
+
+// mu by equal-weight bins: each byte, heaviest first, joins the lightest bin
+// (lowest index on ties); absent bytes -> sigma'-1.
+void map_greedy(mag_plan *p) {
+    uint64_t hist[256];
+    std::vector<int> order;
+    frequency_order(p, hist, order);
+    std::fill(p->mu, p->mu + 256, (uint8_t)(p->sigma_prime - 1));
+    std::vector<uint64_t> load(p->sigma_prime, 0);
+    for (int c : order) {
+        int best = 0;
+        for (int b = 1; b < p->sigma_prime; ++b)
+            if (load[b] < load[best]) best = b;
+        p->mu[c] = (uint8_t)best;
+        load[best] += hist[c];
+    }
+}
+
+void heuristic(const mag_plan *p, int budget, int &q, int &k, int &sp) {
+    uint64_t hist[256];
+    std::vector<int> order;
+    frequency_order(p, hist, order);
+    const int sigma = (int)order.size();
+    if (p->r == 0) {        // nothing to find: the cheapest valid plan
+        q = k = sp = 1;
+        return;
+    }
+    const double s = std::max(sigma, 2);
+    const double lg = std::log((double)p->r * p->m) / std::log(s);   // log_sigma(rm)
+    q = std::max(1, std::min({round_half_up(lg), (int)(p->m + 1) / 2, kMaxQ}));
+    const int L = ((int)p->m - q + 1) / q;
+    const double rho = lg / p->m;
+    if (rho >= 1.0 || lg <= 0) {
+        k = 1;
+    } else {
+        const double inv = std::log(1.0 / rho) / std::log(s);
+        k = round_half_up((double)p->m / lg * inv / (lg + inv));
+        k = std::max(1, std::min(k, std::max(L, 1)));
+    }
+    k = std::min(k, kMaxK);
+    const int mprime = std::min(L / k, kMaxW / k);
+    const int eb = entry_bytes_for(k * mprime);
+    sp = std::max(sigma, 1);
+    auto fits = [&](int sg) {
+        double codes = std::pow((double)sg, q);
+        return codes * eb <= (double)budget;
+    };
+    while (sp > 1 && !fits(sp)) --sp;
+}
+
+void build_table(mag_plan *p) {
+    const int q = p->q, sp = p->sigma_prime, W = p->W, esz = p->esz;
+    p->table.assign(p->n_codes * esz, 0xFF);
+    uint8_t *tb = p->table.data();
+    const uint8_t *mu = p->mu;
+    for (uint32_t i = 0; i < p->r; ++i) {
+        const uint8_t *pat = p->patterns.data() + (size_t)i * p->m;
+        for (int s = 0; s < q; ++s) {
+            for (int b = 0; b < W; ++b) {
+                const uint8_t *g = pat + s + b * q;
+                uint64_t code = 0;
+                for (int t = q - 1; t >= 0; --t) code = code * sp + mu[g[t]];
+                // clear bit b of entry `code` (little-endian storage)
+                tb[code * esz + (b >> 3)] &= (uint8_t)~(1u << (b & 7));
+            }
+        }
+    }
+}
+
+void build_verifier(mag_plan *p) {
+    const uint32_t r = p->r, m = p->m, mw = p->mw;
+    // ids ordered by (pattern bytes, id): equal patterns become one run
+    std::vector<uint32_t> order(r);
+    std::iota(order.begin(), order.end(), 0u);
+    const uint8_t *P = p->patterns.data();
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return std::memcmp(P + (size_t)a * m, P + (size_t)b * m, m) < 0;
+    });
+    p->ids = order;
+    p->idstart.clear();
+    p->pwords.clear();
+    for (uint32_t i = 0; i < r; ++i) {
+        if (i == 0 || std::memcmp(P + (size_t)order[i] * m, P + (size_t)order[i - 1] * m, m) != 0) {
+            p->idstart.push_back(i);
+            const uint8_t *src = P + (size_t)order[i] * m;
+            for (uint32_t t = 0; t < mw; ++t) {
+                uint32_t w = 0;
+                for (uint32_t b = 0; b < 4; ++b)
+                    if (4 * t + b < m) w |= (uint32_t)src[4 * t + b] << (8 * b);
+                p->pwords.push_back(w);
+            }
+        }
+    }
+    p->n_unique = (uint32_t)p->idstart.size();
+    p->idstart.push_back(r);
+
+    uint32_t bits = 1;
+    while ((1ull << bits) < 2ull * std::max<uint32_t>(p->n_unique, 1)) ++bits;
+    p->slot_bits = bits;
+    p->slots.assign(1ull << bits, 0);
+    const uint64_t mask = (1ull << bits) - 1;
+    const int hw = std::min<int>(mw, kHashWords);
+    for (uint32_t u = 0; u < p->n_unique; ++u) {
+        const uint32_t h = window_hash(&p->pwords[(size_t)u * mw], hw);
+        uint64_t s = (uint64_t)(h >> (32 - bits));
+        while (p->slots[s]) s = (s + 1) & mask;
+        p->slots[s] = ((uint64_t)h << 32) | (uint64_t)(u + 1);
+    }
+}
+
+}  // namespace
+
+mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
+                      const mag_params *params) {
+    mag_params prm;
+    std::memset(&prm, 0, sizeof(prm));
+    if (params) prm = *params;
+    if (m == 0) return fail(MAG_E_INVALID, "pattern length m must be >= 1");
+    if (m > (uint32_t)kMaxM) return fail(MAG_E_UNSUPPORTED, "pattern length above 64");
+    if (r > 0 && !patterns) return fail(MAG_E_INVALID, "patterns is NULL");
+    if (prm.map_kind != MAG_MAP_GREEDY && prm.map_kind != MAG_MAP_RANK)
+        return fail(MAG_E_INVALID, "unknown map_kind");
+    if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
+
+    p->r = r;
+    p->m = m;
+    p->mw = (m + 3) / 4;
+    p->patterns.assign(patterns, patterns + (size_t)r * m);
+    p->map_kind = prm.map_kind;
+    p->select = prm.select;
+
+    int q, k, sp;
+    switch (prm.select) {
+        case MAG_SELECT_HEURISTIC:
+        case MAG_SELECT_LEARNED:
+        case MAG_SELECT_AUTOTUNE:   // the C library resolves these two as the heuristic;
+                                    // the Python layer passes its picks as explicit
+            heuristic(p, prm.table_budget > 0 ? prm.table_budget : kDefaultTableBudget, q, k, sp);
+            break;
+        case MAG_SELECT_EXPLICIT:
+            q = prm.q;
+            k = prm.k;
+            sp = prm.sigma_prime;
+            break;
+        default:
+            return fail(MAG_E_INVALID, "unknown select");
+    }
+    if (q < 1 || 2 * q - 1 > (int)m) return fail(MAG_E_INVALID, "need 1 <= q and 2q-1 <= m");
+    if (q > kMaxQ) return fail(MAG_E_UNSUPPORTED, "q above 8");
+    const int L = ((int)m - q + 1) / q;
+    if (k < 1 || k > L) return fail(MAG_E_INVALID, "need 1 <= k <= L = (m-q+1)/q");
+    if (k > kMaxK) return fail(MAG_E_UNSUPPORTED, "k above 32");
+    if (sp < 1 || sp > 256) return fail(MAG_E_INVALID, "sigma' must be in [1, 256]");
+    double codes = std::pow((double)sp, q);
+    p->q = q;
+    p->k = k;
+    p->sigma_prime = sp;
+    p->L = L;
+    p->mprime = std::min(L / k, kMaxW / k);
+    p->W = k * p->mprime;
+    p->esz = entry_bytes_for(p->W);
+    if (codes * p->esz > (double)kMaxTableBytes)
+        return fail(MAG_E_UNSUPPORTED, "mask table above 1 GiB");
+    p->n_codes = 1;
+    for (int t = 0; t < q; ++t) p->n_codes *= (uint64_t)sp;
+
+    if (p->map_kind == MAG_MAP_RANK) map_rank(p); else map_greedy(p);
+    build_table(p);
+    build_verifier(p);
+    return MAG_OK;
+}
+
+}  // namespace mag

@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library is loaded, every function that ``include/mag.h`` declares must be
+exported, and the host plan builder (alphabet map, fixed heuristic,
+superimposed mask table) must equal the oracle's objects exactly. Plan creation
+does no device work: tables are uploaded on first scan.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import method as mm
+from synth import gen_patterns, gen_text
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    path = os.path.join(ROOT, "paper_1405_5483_amd", "libmag.so")
+    if not os.path.exists(path):
+        pytest.fail("libmag.so is not built (python -m paper_1405_5483_amd.build)")
+    import paper_1405_5483_amd as mag
+    return mag
+
+
+def test_every_declared_symbol_is_exported():
+    _lib_or_skip()
+    header = open(os.path.join(ROOT, "include", "mag.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    names = sorted(set(re.findall(r"\b(mag_[a-z_]+)\s*\(", header)))
+    assert "mag_scan" in names and "mag_plan_create" in names
+    so = ctypes.CDLL(os.path.join(ROOT, "paper_1405_5483_amd", "libmag.so"))
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+    from paper_1405_5483_amd._lib import SIGNATURES
+    assert sorted(SIGNATURES) == names
+
+
+CASES = [
+    # sigma, r, m, q, k, sigma', kind
+    (4, 20, 8, 2, 1, 4, "greedy"),
+    (4, 20, 8, 2, 2, 3, "rank"),
+    (4, 100, 16, 5, 1, 4, "greedy"),
+    (20, 50, 16, 3, 4, 7, "greedy"),
+    (20, 50, 16, 1, 5, 20, "rank"),
+    (20, 300, 16, 4, 1, 12, "greedy"),
+    (64, 40, 32, 2, 3, 16, "greedy"),
+    (64, 40, 32, 2, 3, 64, "rank"),
+    (64, 40, 32, 4, 2, 16, "greedy"),
+    (64, 10, 64, 1, 1, 64, "greedy"),      # W = 64: 8-byte entries
+    (64, 10, 64, 2, 7, 9, "rank"),         # W = 28 -> 4-byte entries
+    (2, 5, 9, 5, 1, 2, "greedy"),
+    (4, 8, 12, 4, 1, 1, "greedy"),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_plan_tables_equal_oracle(case):
+    mag = _lib_or_skip()
+    sigma, r, m, q, k, sp, kind = case
+    T = gen_text(4096, sigma, rng=r + m)
+    P = gen_patterns(T, r, m, r // 2, sigma, rng=q * 100 + k)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind)
+    info = plan.info()
+    f = mm.Filter(P, q, k, sp, kind)
+    assert (info["q"], info["k"], info["sigma_prime"]) == (q, k, sp)
+    assert (info["L"], info["m_prime"], info["W"]) == (f.L, f.mprime, f.W)
+    assert info["entry_bytes"] == mm.entry_bytes(f.W)
+    assert info["n_codes"] == f.n_codes
+    mu, table = plan.export()
+    assert np.array_equal(mu, f.mu)
+    want = f.table()
+    bits = 8 * info["entry_bytes"]
+    mask = np.uint64((1 << bits) - 1) if bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.array_equal(table.astype(np.uint64), want & mask)
+    assert info["n_unique"] == len({bytes(row) for row in P})
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_heuristic_equals_oracle(seed):
+    mag = _lib_or_skip()
+    rng = np.random.default_rng(seed)
+    sigma = int(rng.choice([2, 4, 20, 64]))
+    r = int(round(10 ** rng.uniform(0.5, 4.5)))
+    m = int(rng.choice([4, 8, 16, 32, 64]))
+    T = gen_text(8192, sigma, rng=seed)
+    P = gen_patterns(T, r, m, r // 2, sigma, rng=seed + 1)
+    for budget in (0, 8 * 1024, 1 << 20):
+        plan = mag.Plan(P, table_budget=budget)
+        info = plan.info()
+        want = mm.heuristic_params(P, budget or mm.DEFAULT_TABLE_BUDGET)
+        assert (info["q"], info["k"], info["sigma_prime"]) == want
+
+
+def test_workload_heuristics():
+    mag = _lib_or_skip()
+    from synth import workload
+    for name in ("dna1m", "zipf256m", "prot1g"):
+        P = workload(name, n=1 << 20).patterns
+        info = mag.Plan(P).info()
+        assert (info["q"], info["k"], info["sigma_prime"]) == mm.heuristic_params(P)
+
+
+def test_invalid_parameters():
+    mag = _lib_or_skip()
+    P = np.frombuffer(b"ABCDEFGHIJKLMNOP", dtype=np.uint8).reshape(1, 16)
+    bad = [dict(q=9, k=1, sigma_prime=4),       # 2q-1 > m
+           dict(q=4, k=4, sigma_prime=4),       # k > L = 3
+           dict(q=2, k=1, sigma_prime=0),
+           dict(q=2, k=1, sigma_prime=257),
+           dict(q=0, k=1, sigma_prime=4)]
+    for kw in bad:
+        with pytest.raises(mag.MagError) as ei:
+            mag.Plan(P, **kw)
+        assert ei.value.status in (-1, -2)
+    with pytest.raises(mag.MagError):
+        mag.Plan(np.zeros((1, 0), dtype=np.uint8))
+    with pytest.raises(mag.MagError) as ei:
+        mag.Plan(np.zeros((1, 65), dtype=np.uint8))
+    assert ei.value.status == -2
+
+
+def test_empty_pattern_set_is_valid():
+    mag = _lib_or_skip()
+    plan = mag.Plan(np.zeros((0, 8), dtype=np.uint8))
+    assert plan.info()["r"] == 0

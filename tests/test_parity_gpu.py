@@ -1,0 +1,238 @@
+"""Parity of the HIP scan against the oracle (GPU).
+
+Every case compares the library's occurrence list element by element with the
+oracle's (bit-exact: positions and ids are integers), and where the sizes let
+the numpy oracle finish in seconds also the filter's work counters (candidate
+windows and verified start positions) with the counts the oracle derives from
+the definitions of Sections 2-3.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import match as om
+from oracle import method as mm
+from synth import gen_patterns, gen_text, make_job, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mag():
+    import paper_1405_5483_amd as m
+    return m
+
+
+def _gpu_occ(torch, mag, text_np, plan, offset=0, out_cap=None, stats=False):
+    buf = torch.empty(text_np.size + offset + 16, dtype=torch.uint8, device="cuda")
+    view = buf[offset:offset + text_np.size]
+    view.copy_(torch.from_numpy(text_np))
+    res = mag.scan(view, plan, out_cap=out_cap, stats=stats)
+    if stats:
+        occ, st = res
+    else:
+        occ, st = res, None
+    occ = occ.cpu().numpy()
+    return occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), st
+
+
+def _assert_same(pos, ids, ref):
+    rpos, rids = ref
+    assert pos.size == rpos.size, (pos.size, rpos.size)
+    assert np.array_equal(pos, rpos)
+    assert np.array_equal(ids, rids)
+
+
+CASES = [
+    # sigma, n, r, m, q, k, sigma', kind
+    (4, 200_001, 30, 8, 2, 1, 4, "greedy"),
+    (4, 150_003, 30, 8, 2, 2, 3, "rank"),
+    (4, 300_007, 100, 16, 5, 1, 4, "greedy"),
+    (4, 120_000, 50, 16, 3, 4, 4, "greedy"),
+    (20, 250_013, 60, 16, 3, 4, 7, "greedy"),
+    (20, 250_000, 60, 16, 1, 5, 20, "rank"),
+    (20, 180_001, 500, 16, 4, 1, 12, "greedy"),
+    (64, 200_000, 40, 32, 2, 3, 16, "greedy"),
+    (64, 200_003, 40, 32, 2, 3, 64, "rank"),
+    (64, 220_000, 40, 32, 4, 2, 16, "greedy"),
+    (64, 100_000, 10, 64, 1, 1, 64, "greedy"),    # W = 64, u64 state
+    (64, 100_000, 10, 64, 2, 7, 9, "rank"),       # W = 28
+    (64, 100_000, 12, 64, 1, 32, 64, "greedy"),   # k = 32, m' = 2
+    (2, 90_000, 5, 9, 5, 1, 2, "greedy"),         # m = 2q - 1
+    (4, 80_000, 8, 12, 4, 1, 1, "greedy"),        # sigma' = 1: every window verified
+    (20, 150_000, 30, 15, 7, 1, 6, "greedy"),     # q = 7: grams straddle two words
+    (20, 150_000, 30, 17, 8, 1, 5, "rank"),       # q = 8
+    (4, 100_000, 20, 16, 1, 16, 4, "greedy"),     # k = L
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-r{c[2]}-m{c[3]}-q{c[4]}-k{c[5]}-sp{c[6]}-{c[7]}" for c in CASES])
+def test_parity_and_counts(torch_cuda, mag, case):
+    sigma, n, r, m, q, k, sp, kind = case
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+    ref = om.occ_hashed(T, P)
+    assert ref[0].size > 0
+    _assert_same(pos, ids, ref)
+    want = mm.Filter(P, q, k, sp, kind).counts(T)
+    assert st["samples"] == want["samples"]
+    assert st["cand_windows"] == want["cand_windows"]
+    assert st["verifications"] == want["verifications"]
+    assert st["matches"] == ref[0].size
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3, 7, 13])
+def test_unaligned_text(torch_cuda, mag, offset):
+    T = gen_text(100_003, 4, rng=offset)
+    P = gen_patterns(T, 40, 16, 30, 4, rng=5)
+    plan = mag.Plan(P)
+    pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=offset)
+    _assert_same(pos, ids, om.occ_hashed(T, P))
+
+
+def test_edge_lengths(torch_cuda, mag):
+    P = np.frombuffer(b"ACGTACGTAC", dtype=np.uint8).reshape(1, 10)
+    plan = mag.Plan(P, q=2, k=2, sigma_prime=4)
+    for n in (0, 1, 5, 9, 10, 11, 19, 20, 21, 64, 65):
+        T = np.frombuffer((b"ACGT" * 20)[:n], dtype=np.uint8).copy()
+        pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+        _assert_same(pos, ids, om.occ_hashed(T, P))
+        want = mm.Filter(P, 2, 2, 4).counts(T)
+        assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
+
+
+def test_matches_at_both_ends_and_duplicates(torch_cuda, mag):
+    rng = np.random.default_rng(2)
+    n, m = 70_001, 16
+    T = gen_text(n, 20, rng=3)
+    P = gen_patterns(T, 20, m, 0, 20, rng=4)
+    T[:m] = P[3]
+    T[n - m:] = P[7]
+    P = np.concatenate([P, P[[3, 7, 3]]])        # ids 20, 22 repeat pattern 3; 21 repeats 7
+    for kw in (dict(), dict(q=3, k=2, sigma_prime=20), dict(q=1, k=1, sigma_prime=20)):
+        plan = mag.Plan(P, **kw)
+        pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan)
+        ref = om.occ_hashed(T, P)
+        _assert_same(pos, ids, ref)
+        assert pos[0] == 0 and list(ids[pos == 0]) == [3, 20, 22]
+        assert pos[-1] == n - m and list(ids[pos == n - m]) == [7, 21]
+
+
+def test_extreme_bytes(torch_cuda, mag):
+    rng = np.random.default_rng(9)
+    T = rng.choice(np.array([0, 255, 1, 254], dtype=np.uint8), size=50_000)
+    P = np.stack([T[u:u + 12] for u in rng.integers(0, 50_000 - 12, size=25)])
+    P[0] = 0
+    P[1] = 255
+    T[100:112] = 0
+    T[40_000:40_012] = 255
+    for kw in (dict(), dict(q=3, k=1, sigma_prime=4, map_kind="rank")):
+        plan = mag.Plan(P, **kw)
+        pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan)
+        _assert_same(pos, ids, om.occ_hashed(T, P))
+
+
+def test_many_matches_radix_path(torch_cuda, mag):
+    # a^n against {a^m} x 3 ids: 3(n-m+1) occurrences, far beyond the LDS sort
+    n, m = 200_000, 8
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    P = np.full((3, m), ord("a"), dtype=np.uint8)
+    plan = mag.Plan(P, q=2, k=2, sigma_prime=2)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+    assert pos.size == 3 * (n - m + 1)
+    assert np.array_equal(pos, np.repeat(np.arange(n - m + 1, dtype=np.uint64), 3))
+    assert np.array_equal(ids, np.tile(np.arange(3, dtype=np.uint32), n - m + 1))
+    assert st["verifications"] == n - m + 1
+
+
+def test_overflow_reports_exact_count(torch_cuda, mag):
+    T = gen_text(100_000, 4, rng=1)
+    P = gen_patterns(T, 50, 8, 50, 4, rng=2)
+    plan = mag.Plan(P)
+    ref = om.occ_hashed(T, P)
+    z = ref[0].size
+    assert z > 10
+    buf = torch_cuda.from_numpy(T).cuda()
+    with pytest.raises(mag.MagError) as ei:
+        mag.scan(buf, plan, out_cap=z - 1)
+    assert ei.value.status == -5
+    occ = mag.scan(buf, plan, out_cap=z).cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+
+
+def test_empty_pattern_set_and_absent_byte(torch_cuda, mag):
+    T = gen_text(10_000, 4, rng=1)
+    buf = torch_cuda.from_numpy(T).cuda()
+    assert mag.scan(buf, mag.Plan(np.zeros((0, 8), dtype=np.uint8))).shape[0] == 0
+    P = np.frombuffer(b"ACGTACGN", dtype=np.uint8).reshape(1, 8)
+    assert mag.scan(buf, mag.Plan(P)).shape[0] == 0
+
+
+def test_async_entry_point(torch_cuda, mag):
+    torch = torch_cuda
+    T = gen_text(300_000, 20, rng=4)
+    P = gen_patterns(T, 200, 16, 150, 20, rng=5)
+    plan = mag.Plan(P)
+    ref = om.occ_hashed(T, P)
+    buf = torch.from_numpy(T).cuda()
+    out = torch.empty((4096, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for _ in range(3):                 # repeated calls reuse the plan's scratch
+        mag.scan_async(buf, plan, out, cnt, st)
+    torch.cuda.synchronize()
+    z = int(cnt.item())
+    assert z == ref[0].size
+    occ = out[:z].cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+    assert int(st[3].item()) == z
+
+
+@pytest.mark.parametrize("sel", ["heuristic", "explicit-best"])
+def test_dna1m_workload(torch_cuda, mag, sel):
+    job = workload("dna1m")
+    kw = {} if sel == "heuristic" else dict(q=8, k=1, sigma_prime=4)
+    plan = mag.Plan(job.patterns, **kw)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, job.text, plan, stats=True)
+    ref = om.occ_hashed(job.text, job.patterns)
+    _assert_same(pos, ids, ref)
+    info = plan.info()
+    want = mm.Filter(job.patterns, info["q"], info["k"], info["sigma_prime"]).counts(job.text)
+    assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
+
+
+def test_zipf256m_full_size(torch_cuda, mag):
+    job = workload("zipf256m")
+    ref = om.occ_hashed(job.text, job.patterns)
+    buf = torch_cuda.from_numpy(job.text).cuda()
+    for kw in (dict(), dict(q=4, k=1, sigma_prime=16), dict(q=4, k=2, sigma_prime=16)):
+        plan = mag.Plan(job.patterns, **kw)
+        occ = mag.scan(buf, plan).cpu().numpy()
+        _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+    # counters on a prefix the numpy oracle finishes quickly
+    pre = job.text[: 1 << 21]
+    plan = mag.Plan(job.patterns)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, pre, plan, stats=True)
+    _assert_same(pos, ids, om.occ_hashed(pre, job.patterns))
+    info = plan.info()
+    want = mm.Filter(job.patterns, info["q"], info["k"], info["sigma_prime"]).counts(pre)
+    assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
+
+
+def test_prot1g_full_size(torch_cuda, mag):
+    job = workload("prot1g")
+    ref = om.occ_hashed(job.text, job.patterns)
+    buf = torch_cuda.from_numpy(job.text).cuda()
+    for kw in (dict(), dict(q=5, k=1, sigma_prime=20)):
+        plan = mag.Plan(job.patterns, **kw)
+        occ = mag.scan(buf, plan).cpu().numpy()
+        _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
