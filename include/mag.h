@@ -147,11 +147,12 @@ mag_status mag_scan(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match
                     uint64_t out_cap, uint64_t *n_matches, mag_stats *stats, void *stream);
 
 /* Kernel timing for benchmarks. While enabled (process-wide), every scan
- * records HIP events on its own stream around its filter/verify kernel and its
- * finishing (count + sort) kernel. mag_profile_read waits for the recorded
- * events, adds their elapsed times (milliseconds) to *scan_ms and *finish_ms,
- * sets *launches to the number of scans measured, and clears the record.
- * Enabling adds two event records per scan; disabled by default. */
+ * records HIP events on its own stream around each of its two kernels: the
+ * scan kernel (filter with fused exact verification) and the finishing kernel
+ * (count, counters and sorted output). mag_profile_read waits for the recorded
+ * events, stores their summed elapsed times in milliseconds, sets *launches to
+ * the number of scans measured, and clears the record. Enabling adds three
+ * event records per scan; disabled by default. */
 mag_status mag_profile_enable(int enable);
 mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launches);
 

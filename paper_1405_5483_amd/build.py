@@ -37,9 +37,11 @@ def common_flags() -> list[str]:
     ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + common_flags()
+def _compile(job) -> str:
+    src, defines = job
+    tag = "".join(f".{d.replace('=', '')}" for d in defines)
+    obj = os.path.join(BUILD_DIR, os.path.basename(src) + tag + ".o")
+    cmd = [hipcc(), "-x", "hip", "-c", src, "-o", obj] + common_flags() + [f"-D{d}" for d in defines]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
@@ -49,8 +51,15 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     sources = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(sources))) as ex:
-        objs = list(ex.map(_compile, sources))
+    jobs = []
+    for src in sources:
+        if os.path.basename(src) == "scan.hip":       # one object per q-gram length
+            jobs += [(src, [f"MAG_SCAN_Q={q}"]) for q in range(1, 9)]
+        else:
+            jobs.append((src, []))
+    workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc(), "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-fPIC"]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -16,7 +16,7 @@ thread_local std::string g_last_error;
 
 // benchmark timing: events recorded around each scan's two kernels
 struct ProfileRecord {
-    hipEvent_t start, mid, end;
+    hipEvent_t ev[3];   // before the scan, after the scan, after the finishing kernel
 };
 std::mutex g_prof_mtx;
 bool g_prof_on = false;
@@ -166,22 +166,20 @@ mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launch
         std::lock_guard<std::mutex> pl(g_prof_mtx);
         recs.swap(g_prof);
     }
-    double a = 0, b = 0;
+    double acc[2] = {0, 0};
     mag_status st = MAG_OK;
     for (auto &r : recs) {
-        float t1 = 0, t2 = 0;
-        hipError_t e = hipEventSynchronize(r.end);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t1, r.start, r.mid);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t2, r.mid, r.end);
+        hipError_t e = hipEventSynchronize(r.ev[2]);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            float t = 0;
+            e = hipEventElapsedTime(&t, r.ev[i], r.ev[i + 1]);
+            acc[i] += t;
+        }
         if (e != hipSuccess && st == MAG_OK) st = hip_fail(e, "reading profile events");
-        a += t1;
-        b += t2;
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.mid);
-        (void)hipEventDestroy(r.end);
+        for (auto ev : r.ev) (void)hipEventDestroy(ev);
     }
-    *scan_ms = a;
-    *finish_ms = b;
+    *scan_ms = acc[0];
+    *finish_ms = acc[1];
     *launches = recs.size();
     return st;
 }
@@ -283,27 +281,27 @@ mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_ma
     sl.cap = out_cap;
     sl.counters = p->scratch.counters;
     sl.idbits = idbits;
-    ProfileRecord rec{nullptr, nullptr, nullptr};
+    ProfileRecord rec{{nullptr, nullptr, nullptr}};
     bool prof;
     {
         std::lock_guard<std::mutex> pl(g_prof_mtx);
         prof = g_prof_on;
     }
     if (prof) {
-        rec.start = make_event();
-        rec.mid = make_event();
-        rec.end = make_event();
-        if (!rec.start || !rec.mid || !rec.end) return fail(MAG_E_DEVICE, "hipEventCreate");
-        (void)hipEventRecord(rec.start, stream);
+        for (auto &ev : rec.ev) {
+            ev = make_event();
+            if (!ev) return fail(MAG_E_DEVICE, "hipEventCreate");
+        }
+        (void)hipEventRecord(rec.ev[0], stream);
     }
     s = launch_scan(p, sl, stream);
     if (s != MAG_OK) return s;
-    if (prof) (void)hipEventRecord(rec.mid, stream);
+    if (prof) (void)hipEventRecord(rec.ev[1], stream);
     s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits,
                       idbits + posbits, stream);
     if (s != MAG_OK) return s;
     if (prof) {
-        (void)hipEventRecord(rec.end, stream);
+        (void)hipEventRecord(rec.ev[2], stream);
         std::lock_guard<std::mutex> pl(g_prof_mtx);
         g_prof.push_back(rec);
     }

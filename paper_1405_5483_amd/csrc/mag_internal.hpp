@@ -100,7 +100,7 @@ struct ScanLaunch {
     uint64_t n;
     uint64_t *keys;       // key output, capacity cap
     uint64_t cap;
-    uint64_t *counters;
+    uint64_t *counters;   // [0] occurrences [1] candidate windows [2] verifications
     int idbits;
 };
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream);

@@ -1,234 +1,337 @@
 // MAG scan kernel for gfx950: the sampled Shift-Or filter over superimposed
 // q-gram classes (Sections 3.1-3.2) with fused exact verification.
 //
-// Work decomposition. Sample x is the text q-gram at byte x*k*q. A workgroup
-// owns a tile of consecutive samples; each lane owns S consecutive samples of
-// the tile and warms its state up on the m'-1 samples before them, so every
-// window (x, j) is evaluated by exactly one lane. Window (x, j) stands for the
-// q start positions i0 = (x-m'+1)kq - jq - s (s < q); every start position
-// maps to exactly one (x, j, s), so each position is verified at most once and
-// no de-duplication is needed.
+// Sample x is the text q-gram at byte x*k*q; its code is the Horner value of
+// the mapped bytes (Section 3.2, "Implementation") and B[code] is its Shift-Or
+// mask. Window (x, j) is a candidate when bit (m'-1)k + j of
+// D_x = (D_{x-1} << k) | B[g_x] is 0; it stands for the q start positions
+// i0 = (x-m'+1)kq - jq - s (s < q). Each start position maps to exactly one
+// (x, j, s), so every position is verified at most once.
 //
-// Per tile: the text bytes the tile reads (samples, warm-up and every
-// verification window) are staged into LDS with 128-bit buffer loads
-// (range-checked, so any text alignment is fine); the alphabet map and, when it
-// fits, the mask table live in LDS for the whole kernel. Candidate windows are
-// compacted per wavefront with a ballot + mbcnt prefix into an LDS queue and
-// verified 64 at a time, one per lane: a hash of the window's first 16 bytes
-// probes an open-addressing table of the distinct patterns, a fingerprint hit
-// is confirmed by a full word compare, and every id of the matching pattern is
+// A workgroup owns tiles of TS consecutive samples and works on a tile in two
+// phases:
+//  A. consecutive threads take consecutive samples (coalesced 32-bit buffer
+//     loads of the q bytes, range-checked so any text alignment works), map the
+//     bytes through mu, look the code up in the mask table (LDS when it fits,
+//     else global/L2) and store the mask entry in an LDS array E. There are no
+//     dependences between samples, so all lookups of a thread can be in flight.
+//  B. lane t runs the Shift-Or recurrence over E[tS - (m'-1) .. tS + S): the
+//     m'-1 entries before its own S samples warm its state up, so each window
+//     is evaluated by exactly one lane. E is read 16 bytes at a time; a wave
+//     only leaves the register-only fast path when one of its lanes has a
+//     candidate (ballot), and then compacts the candidate windows with a
+//     ballot + mbcnt prefix into an LDS queue.
+// Queued windows are verified 64 at a time, one per lane: the window's bytes
+// are read from the text (L2), the hash of its first 16 bytes probes an
+// open-addressing table of the distinct patterns, a fingerprint hit is
+// confirmed by a full word compare, and every id of the matching pattern is
 // emitted as a 64-bit key (pos << idbits | id).
+//
+// The gram length Q is a compile-time parameter: this file is compiled once per
+// Q (MAG_SCAN_Q) and scan_dispatch.cpp picks the object.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 
 #include "mag_internal.hpp"
+#include "scan_args.hpp"
+
+#ifndef MAG_SCAN_Q
+#error "compile with -DMAG_SCAN_Q=<1..8>"
+#endif
 
 namespace mag {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-constexpr int kQueue = 128;          // per-wave candidate queue entries
+constexpr int Q = MAG_SCAN_Q;
+constexpr int kNT = kScanThreads;
+constexpr int kWaves = kNT / 64;
+constexpr int kQueue = 128;          // per-wave queue of start positions (64-bit)
 constexpr uint32_t kBufferWord3 = 0x00020000u;   // raw 32-bit buffer resource (gfx9)
 
-struct ScanArgs {
-    const uint8_t *tbase;      // text pointer rounded down to 16 bytes
-    uint64_t delta;            // text - tbase
-    uint64_t n, X, ntiles;
-    uint32_t q, k, kq, mprime, W, sp, m, mw, hw;
-    uint32_t S, tile_samples, tile_lds, table_vec;
-    uint32_t slot_shift, slot_mask, idbits, lastmask;
-    const uint8_t *mu;
-    const void *table;
-    const uint64_t *slots;
-    const uint32_t *pwords, *idstart, *ids;
-    uint64_t *keys;
-    uint64_t cap;
-    uint64_t *counters;
+__device__ __forceinline__ uint32_t ld32(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+}
+
+// The 32-bit words holding the q bytes of the gram that starts at resource
+// offset p (the third word only for q > 4).
+struct GramWords {
+    uint32_t w0, w1, w2, sh;
 };
 
-__device__ __forceinline__ uint32_t lds_word(const uint32_t *s32, uint32_t o) {
-    const uint32_t lo = s32[o >> 2];
-    const uint32_t hi = s32[(o >> 2) + 1];
-    return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+__device__ __forceinline__ GramWords gram_words(__amdgpu_buffer_rsrc_t rs, uint32_t p) {
+    GramWords g;
+    const uint32_t a = p & ~3u;
+    g.sh = p & 3;
+    g.w0 = ld32(rs, a);
+    g.w1 = ld32(rs, a + 4);
+    g.w2 = Q > 4 ? ld32(rs, a + 8) : 0u;
+    return g;
 }
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Verifies start position i0 (0 <= i0 <= n-m) whose bytes are staged in LDS at
-// offset o, and emits every (i0, id) occurrence.
-__device__ void verify_start(const ScanArgs &a, const uint32_t *s32, uint32_t o, uint64_t i0) {
-    uint32_t hv[kHashWords];
+// Code of a q-gram: Horner over the mapped bytes, last byte first. With MUL24
+// every partial value is below 2^24 (the host checks sigma'^(q-1) < 2^24), so
+// the full-rate 24-bit multiply-add is exact.
+template <bool MUL24>
+__device__ __forceinline__ uint32_t gram_code(const GramWords &gw, const uint8_t *s_mu, uint32_t sp) {
+    const uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    const uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    uint32_t g = 0;
 #pragma unroll
-    for (int t = 0; t < kHashWords; ++t) {
-        uint32_t w = 0;
-        if (t < (int)a.hw) {
-            w = lds_word(s32, o + 4 * t);
-            if (t == (int)a.mw - 1) w &= a.lastmask;
-        }
-        hv[t] = w;
+    for (int t = Q - 1; t >= 0; --t) {
+        const uint32_t byte = t < 4 ? __builtin_amdgcn_ubfe(lo, 8 * t, 8)
+                                    : __builtin_amdgcn_ubfe(hi, 8 * (t - 4), 8);
+        const uint32_t c = s_mu[byte];
+        if (t == Q - 1) g = c;
+        else if (MUL24) g = __umul24(g, sp) + c;
+        else g = g * sp + c;
     }
-    const uint32_t h = window_hash(hv, (int)a.hw);
-    uint32_t slot = h >> a.slot_shift;
-    for (;;) {
-        const uint64_t e = a.slots[slot];
-        if (e == 0) return;
-        if ((uint32_t)(e >> 32) == h) {
-            const uint32_t u = (uint32_t)e - 1u;
-            const uint32_t *pw = a.pwords + (size_t)u * a.mw;
-            bool eq = true;
-            for (uint32_t t = 0; t < a.mw; ++t) {
-                uint32_t w = lds_word(s32, o + 4 * t);
-                if (t == a.mw - 1) w &= a.lastmask;
-                if (w != pw[t]) { eq = false; break; }
-            }
-            if (eq) {
-                const uint32_t b = a.idstart[u], c = a.idstart[u + 1] - b;
-                const uint64_t base = atomicAdd((unsigned long long *)&a.counters[0],
-                                                (unsigned long long)c);
-                for (uint32_t t = 0; t < c; ++t)
-                    if (base + t < a.cap)
-                        a.keys[base + t] = (i0 << a.idbits) | (uint64_t)a.ids[b + t];
-                return;     // distinct patterns: at most one can be equal
-            }
-        }
-        slot = (slot + 1) & a.slot_mask;
+    return g;
+}
+
+// Raw buffer resource over [base, base + bytes). The operands are wave-uniform;
+// readfirstlane says so to the compiler, which otherwise may keep them in
+// vector registers and wrap every load in a loop over distinct values.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const uint8_t *base, uint32_t bytes) {
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint32_t n = __builtin_amdgcn_readfirstlane(bytes);
+    void *p = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)n, (int)kBufferWord3);
+}
+
+// Out-of-line verification of one start position. `v` points at the
+// verification arguments inside the kernel-argument segment (constant
+// address space; the kernel computes it, since only a kernel receives the
+// segment pointer), so they are read on this cold path with scalar loads and
+// occupy no registers in the scan loops.
+typedef const __attribute__((address_space(4))) VerifyArgs KVerifyArgs;
+
+__device__ __attribute__((noinline)) void verify_one(KVerifyArgs *v, uint64_t i0) {
+#if __HIP_DEVICE_COMPILE__
+    VerifyArgs args;
+    __builtin_memcpy(&args, (const VerifyArgs *)v, sizeof(args));
+    verify_start(args, i0);
+#else
+    (void)v;
+    (void)i0;
+#endif
+}
+
+// Verifies the 64 start positions queue[from .. from+64) of this wave, one per
+// lane. The queue is written by other lanes of the same wave.
+__device__ __forceinline__ void drain64(KVerifyArgs *v, const uint64_t *queue, uint32_t from,
+                                        int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint64_t e = queue[from + lane];
+    __builtin_amdgcn_wave_barrier();
+    verify_one(v, e);
+}
+
+template <typename ET>
+__device__ __forceinline__ void store4(ET *dst, const ET e[4]) {
+    if constexpr (sizeof(ET) == 1) {
+        *reinterpret_cast<uint32_t *>(dst) = (uint32_t)e[0] | ((uint32_t)e[1] << 8) |
+                                             ((uint32_t)e[2] << 16) | ((uint32_t)e[3] << 24);
+    } else if constexpr (sizeof(ET) == 2) {
+        *reinterpret_cast<uint2 *>(dst) = make_uint2((uint32_t)e[0] | ((uint32_t)e[1] << 16),
+                                                     (uint32_t)e[2] | ((uint32_t)e[3] << 16));
+    } else if constexpr (sizeof(ET) == 4) {
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(e[0], e[1], e[2], e[3]);
+    } else {
+        uint4 *d = reinterpret_cast<uint4 *>(dst);
+        d[0] = make_uint4((uint32_t)e[0], (uint32_t)(e[0] >> 32), (uint32_t)e[1], (uint32_t)(e[1] >> 32));
+        d[1] = make_uint4((uint32_t)e[2], (uint32_t)(e[2] >> 32), (uint32_t)e[3], (uint32_t)(e[3] >> 32));
     }
 }
 
-// All q start positions of window (x, j).
-__device__ __forceinline__ uint32_t verify_window(const ScanArgs &a, const uint32_t *s32,
-                                                  int64_t obase, int64_t x, uint32_t j) {
-    uint32_t nv = 0;
-    const int64_t top = (x - (int64_t)a.mprime + 1) * a.kq - (int64_t)j * a.q;
-    const int64_t last = (int64_t)a.n - (int64_t)a.m;
-    for (uint32_t s = 0; s < a.q; ++s) {
-        const int64_t i0 = top - s;
-        if (i0 < 0 || i0 > last) continue;
-        ++nv;
-        verify_start(a, s32, (uint32_t)(obase + i0), (uint64_t)i0);
+// Phase A for one tile: mask entries of samples X0-W0 .. X0+TS-1 into
+// E[s + W0]. Each thread takes G consecutive samples per round; the words of
+// the next round are loaded before the current round's lookups, so global
+// latency overlaps LDS work, and each round's entries leave in G/4 LDS
+// stores. Outside interior tiles, samples before the text or past the last
+// sample get the all-ones (no match) entry. Loads past the tile are
+// range-checked by the buffer resource and their entries are never read.
+constexpr int kGroup = 8;
+
+template <bool INTERIOR, bool MUL24, bool TLDS, typename ET>
+__device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq,
+                                        uint32_t sp, const uint8_t *s_mu, const ET *s_tab,
+                                        const ET *g_tab, int W0, uint32_t TS, int64_t X0, uint64_t X,
+                                        int tid) {
+    const ET none = (ET)~(ET)0;
+    int s0 = kGroup * tid - W0;
+    GramWords cur[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u)
+        cur[u] = gram_words(rs, (uint32_t)(p0 + (s0 + u) * (int32_t)kq));
+    for (; s0 < (int)TS; s0 += kGroup * kNT) {
+        GramWords nxt[kGroup];
+        const int s1 = s0 + kGroup * kNT;
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+            nxt[u] = gram_words(rs, (uint32_t)(p0 + (s1 + u) * (int32_t)kq));
+        uint32_t g[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) g[u] = gram_code<MUL24>(cur[u], s_mu, sp);
+        ET e[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            e[u] = TLDS ? s_tab[g[u]] : g_tab[g[u]];
+            if (!INTERIOR) {
+                const int64_t x = X0 + s0 + u;
+                if (x < 0 || x >= (int64_t)X) e[u] = none;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; u += 4) store4(s_E + (s0 + W0 + u), e + u);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) cur[u] = nxt[u];
     }
-    return nv;
 }
 
-template <typename DT, typename ET, bool TLDS>
-__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+template <typename ET, typename DT, bool TLDS, bool MUL24>
+__global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *s_mu = smem;
-    uint32_t *s_queue = reinterpret_cast<uint32_t *>(smem + 256);
-    uint8_t *s_text = smem + 256 + kWaves * kQueue * 4;
-    ET *s_tab = reinterpret_cast<ET *>(s_text + a.tile_lds);
-    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(s_text);
+    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256);
+    ET *s_E = reinterpret_cast<ET *>(smem + 256 + kWaves * kQueue * 8);
+    ET *s_tab = reinterpret_cast<ET *>(smem + 256 + kWaves * kQueue * 8 + a.e_lds);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    s_mu[tid] = a.mu[tid];
+    // the kernel's only argument is `a`, at the start of the argument segment
+    KVerifyArgs *vargs = (KVerifyArgs *)((const __attribute__((address_space(4))) char *)
+                                             __builtin_amdgcn_kernarg_segment_ptr() +
+                                         offsetof(ScanArgs, v));
+    for (int i = tid; i < 256; i += kNT) s_mu[i] = a.mu[i];
     if (TLDS) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.table);
         uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
-        for (uint32_t v = tid; v < a.table_vec; v += kThreads) dst[v] = src[v];
+        for (uint32_t v = tid; v < a.table_vec; v += kNT) dst[v] = src[v];
     }
     const ET *g_tab = reinterpret_cast<const ET *>(a.table);
 
-    uint32_t *queue = s_queue + wave * kQueue;
+    uint64_t *queue = s_queue + wave * kQueue;     // start positions awaiting verification
     uint32_t qn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t kmask = a.k >= 32 ? 0xFFFFFFFFu : ((1u << a.k) - 1u);
     const uint32_t topshift = a.W - a.k;
-    const uint32_t sp = a.sp, q = a.q;
+    const uint32_t sp = a.sp, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
+    constexpr int EPV = 16 / (int)sizeof(ET);            // entries per 16-byte LDS read
+    const int warm = (int)a.mprime - 1;
+    const int W0 = (int)a.w0;                             // warm-up entries kept before a tile
+    (void)warm;
+    const int64_t last = (int64_t)a.n - (int64_t)a.m;   // last valid start position
 
     for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int64_t X0 = (int64_t)tile * a.tile_samples;
-        int64_t b0 = (X0 - (int64_t)a.mprime) * a.kq + 1;
+        const int64_t X0 = (int64_t)tile * TS;
+        // text bytes the tile touches: warm-up samples through the last
+        // verification window
+        int64_t b0 = (X0 - (int64_t)a.mprime) * kq + 1;
         if (b0 < 0) b0 = 0;
-        int64_t b1 = (X0 + (int64_t)a.tile_samples - (int64_t)a.mprime) * a.kq + a.m;
+        int64_t b1 = (X0 + (int64_t)TS - (int64_t)a.mprime) * kq + a.m;
         if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
         if (b1 < b0) b1 = b0;
         const uint64_t pa0 = (a.delta + (uint64_t)b0) & ~15ull;
         const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
-        const uint32_t nvec = (uint32_t)((pa1 - pa0) >> 4);
-        __syncthreads();    // the previous tile is fully consumed
-        {
-            __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void *)(a.tbase + pa0), (short)0, (int)(pa1 - pa0), (int)kBufferWord3);
-            uint4 *dst = reinterpret_cast<uint4 *>(s_text);
-            for (uint32_t v = tid; v < nvec; v += kThreads) {
-                auto val = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(v * 16), 0, 0);
-                dst[v] = make_uint4(val[0], val[1], val[2], val[3]);
-            }
-        }
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
+        const int64_t pbase = (int64_t)a.delta - (int64_t)pa0;   // resource offset of text byte 0
+        __syncthreads();    // the previous tile's E is fully consumed
+
+        // ---- phase A: mask entries of samples X0-W0 .. X0+TS-1, stored at
+        // E[s + W0] (W0 >= m'-1 warm-up samples, rounded up so that every
+        // lane's own samples start on a 16-byte boundary); each thread takes 4
+        // consecutive samples per round so their lookups overlap and the
+        // entries leave in one LDS store
+        const bool interior = X0 - W0 >= 0 && X0 + (int64_t)TS <= (int64_t)a.X;
+        const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
+        if (interior)
+            phase_a<true, MUL24, TLDS>(s_E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+        else
+            phase_a<false, MUL24, TLDS>(s_E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
         __syncthreads();
 
-        const int64_t obase = (int64_t)a.delta - (int64_t)pa0;   // LDS offset of text byte 0
-        const int64_t xs = X0 + (int64_t)tid * a.S;
+        // ---- phase B: Shift-Or over the lane's S samples. The W0 entries
+        // before them warm the state up (only the last m' entries reach the
+        // candidate bits, so the extra older ones are harmless).
+        const uint4 *vE = reinterpret_cast<const uint4 *>(s_E) + (uint32_t)tid * (S / EPV);
         DT D = ~(DT)0;
-        for (int i = -(int)(a.mprime - 1); i < (int)a.S; ++i) {
-            const int64_t x = xs + i;
-            const bool valid = x >= 0 && x < (int64_t)a.X;
-            uint32_t c = 0;
-            if (valid) {
-                const uint32_t o = (uint32_t)(obase + x * (int64_t)a.kq);
-                const uint32_t lo = lds_word(s32, o);
-                const uint32_t hi = q > 4 ? lds_word(s32, o + 4) : 0u;
-                uint32_t g = 0;
+        for (int v = 0; v < W0 / EPV; ++v) {
+            const uint4 raw = vE[v];
+            ET ent[EPV];
+            __builtin_memcpy(ent, &raw, 16);
 #pragma unroll
-                for (int t = kMaxQ - 1; t >= 0; --t) {
-                    if (t < (int)q) {
-                        const uint32_t byte = (t < 4 ? (lo >> (8 * t)) : (hi >> (8 * (t - 4)))) & 0xFFu;
-                        g = g * sp + s_mu[byte];
+            for (int u = 0; u < EPV; ++u) D = (D << k) | (DT)ent[u];
+        }
+        vE += W0 / EPV;
+        for (uint32_t v = 0; v < S / EPV; ++v) {
+            const uint4 raw = vE[v];
+            ET ent[EPV];
+            __builtin_memcpy(ent, &raw, 16);
+            const DT Dstart = D;
+            DT all = ~(DT)0;     // a 0 in a candidate bit of the AND: some entry fired
+#pragma unroll
+            for (int u = 0; u < EPV; ++u) {
+                D = (D << k) | (DT)ent[u];
+                all &= D;
+            }
+            const uint32_t anyc = (uint32_t)((~all) >> topshift) & kmask;
+            if (!__ballot(anyc != 0)) continue;
+            // slow path: replay the vector and queue the start positions of
+            // its candidate windows
+            DT R = Dstart;
+            const int64_t xv = X0 + (int64_t)((uint32_t)tid * S + v * EPV);
+#pragma unroll
+            for (int u = 0; u < EPV; ++u) {
+                R = (R << k) | (DT)ent[u];
+                uint32_t c = (uint32_t)((~R) >> topshift) & kmask;
+                if (!__ballot(c != 0)) continue;
+                const int64_t topx = (xv + u - (int64_t)a.mprime + 1) * (int64_t)kq;
+                for (;;) {
+                    const bool has = c != 0;
+                    const uint64_t hb = __ballot(has);
+                    if (!hb) break;
+                    ncand += (uint64_t)__popcll(hb);
+                    const uint32_t bit = has ? __builtin_ctz(c) : 0u;
+                    if (has) c &= c - 1u;
+                    const int64_t top = topx - (int64_t)bit * Q;
+#pragma unroll
+                    for (int sft = 0; sft < Q; ++sft) {
+                        const int64_t i0 = top - sft;
+                        const bool ok = has && i0 >= 0 && i0 <= last;
+                        const uint64_t bal = __ballot(ok);
+                        if (ok) {
+                            queue[qn + lanes_below(bal)] = (uint64_t)i0;
+                            ++nver;
+                        }
+                        qn += (uint32_t)__popcll(bal);
+                        if (qn >= 64) {
+                            qn -= 64;
+                            drain64(vargs, queue, qn, lane);
+                        }
                     }
                 }
-                const ET e = TLDS ? s_tab[g] : g_tab[g];
-                D = (D << a.k) | (DT)e;
-                if (i >= 0) c = (uint32_t)((~D) >> topshift) & kmask;
             }
-            uint64_t any = __ballot(c != 0);
-            while (any) {
-                const bool has = c != 0;
-                if (has) {
-                    const uint32_t j = __builtin_ctz(c);
-                    c &= c - 1u;
-                    queue[qn + lanes_below(any)] = ((uint32_t)(x - X0) << 5) | j;
-                }
-                const uint32_t cnt = (uint32_t)__popcll(any);
-                qn += cnt;
-                ncand += cnt;
-                if (qn >= 64) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    const uint32_t e = queue[qn - 64 + lane];
-                    __builtin_amdgcn_wave_barrier();
-                    qn -= 64;
-                    nver += verify_window(a, s32, obase, X0 + (int64_t)(e >> 5), e & 31u);
-                }
-                any = __ballot(c != 0);
-            }
-        }
-        if (qn) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if ((uint32_t)lane < qn) {
-                const uint32_t e = queue[lane];
-                nver += verify_window(a, s32, obase, X0 + (int64_t)(e >> 5), e & 31u);
-            }
-            __builtin_amdgcn_wave_barrier();
-            qn = 0;
         }
     }
+    // starts still queued
+    if (qn) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if ((uint32_t)lane < qn) verify_one(vargs, queue[lane]);
+    }
     if (lane == 0 && ncand) atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)ncand);
-    // wave sum of verifications
     unsigned long long nv = nver;
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
-    nver = nv;
-    if (lane == 0 && nver) atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)nver);
+    if (lane == 0 && nv) atomicAdd((unsigned long long *)&a.counters[2], nv);
 }
 
-template <typename DT, typename ET, bool TLDS>
-mag_status launch_one(const ScanArgs &a, size_t shmem, hipStream_t stream) {
-    auto fn = k_scan<DT, ET, TLDS>;
+template <typename ET, typename DT, bool TLDS, bool MUL24>
+mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stream) {
+    auto fn = k_scan<ET, DT, TLDS, MUL24>;
     static int configured_bytes = 0;    // per instantiation
     if ((int)shmem > configured_bytes) {
         // not every runtime needs the opt-in; a real LDS overflow fails the launch below
@@ -237,97 +340,41 @@ mag_status launch_one(const ScanArgs &a, size_t shmem, hipStream_t stream) {
         (void)hipGetLastError();
         configured_bytes = (int)shmem;
     }
-    int dev = 0, ncu = 0, occ = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, shmem);
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kNT, shmem);
     if (e != hipSuccess) return hip_fail(e, "occupancy query (scan)");
     if (occ < 1) return fail(MAG_E_UNSUPPORTED, "scan kernel does not fit on a compute unit");
     uint64_t grid = (uint64_t)ncu * (uint64_t)occ;
     if (grid > a.ntiles) grid = a.ntiles;
     if (grid == 0) return MAG_OK;
-    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), shmem, stream, a);
+    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kNT), shmem, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scan launch");
     return MAG_OK;
 }
 
-uint32_t pick_samples_per_lane(uint32_t kq, uint32_t mprime) {
-    // enough samples per lane to amortise the m'-1 warm-up steps, a tile of
-    // roughly 8-32 KiB, and a lane stride (S*kq bytes) that is an odd number of
-    // 32-bit words when possible so lanes hit distinct LDS banks
-    uint32_t S = 64 / kq;
-    S = S < 8 ? 8 : S;
-    const uint32_t warm = 4 * (mprime > 0 ? mprime - 1 : 0);
-    if (S < warm) S = warm;
-    while ((uint64_t)kThreads * S * kq > 32768 && S > 4) --S;
-    for (uint32_t c = S; c < S + 8; ++c)
-        if (((uint64_t)c * kq) % 8 == 4 && (uint64_t)kThreads * c * kq <= 32768) return c;
-    return S;
+template <typename ET, typename DT>
+mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int ncu,
+                     hipStream_t stream) {
+    if (tlds) return launch_one<ET, DT, true, true>(a, shmem, ncu, stream);   // LDS tables are small
+    return mul24 ? launch_one<ET, DT, false, true>(a, shmem, ncu, stream)
+                 : launch_one<ET, DT, false, false>(a, shmem, ncu, stream);
 }
 
 }  // namespace
 
-mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream) {
-    if (s.n < p->q || p->r == 0) return MAG_OK;
-    ScanArgs a{};
-    const uintptr_t t = reinterpret_cast<uintptr_t>(s.text);
-    a.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
-    a.delta = t & 15;
-    a.n = s.n;
-    a.q = p->q;
-    a.k = p->k;
-    a.kq = p->k * p->q;
-    a.mprime = p->mprime;
-    a.W = p->W;
-    a.sp = p->sigma_prime;
-    a.m = p->m;
-    a.mw = p->mw;
-    a.hw = p->mw < (uint32_t)kHashWords ? p->mw : (uint32_t)kHashWords;
-    a.X = (s.n - p->q) / a.kq + 1;
-    a.S = pick_samples_per_lane(a.kq, a.mprime);
-    a.tile_samples = kThreads * a.S;
-    a.ntiles = (a.X + a.tile_samples - 1) / a.tile_samples;
-    // staged bytes: at most tile_samples*kq + m - 1 plus 30 bytes of 16-byte
-    // alignment; word reads run up to 7 bytes past the last staged byte
-    a.tile_lds = (uint32_t)(((uint64_t)a.tile_samples * a.kq + a.m + 64) & ~15ull);
-    a.slot_shift = 32 - p->slot_bits;
-    a.slot_mask = (uint32_t)((1ull << p->slot_bits) - 1);
-    a.idbits = (uint32_t)s.idbits;
-    a.lastmask = (p->m & 3) ? ((1u << (8 * (p->m & 3))) - 1u) : 0xFFFFFFFFu;
-    a.mu = p->dev.mu;
-    a.table = p->dev.table;
-    a.slots = p->dev.slots;
-    a.pwords = p->dev.pwords;
-    a.idstart = p->dev.idstart;
-    a.ids = p->dev.ids;
-    a.keys = s.keys;
-    a.cap = s.cap;
-    a.counters = s.counters;
+#define MAG_CAT2(a, b) a##b
+#define MAG_CAT(a, b) MAG_CAT2(a, b)
 
-    const uint64_t tbytes = p->table.size();
-    const bool tlds = tbytes <= 64 * 1024;
-    a.table_vec = (uint32_t)((tbytes + 15) / 16);
-    const size_t shmem = 256 + (size_t)kWaves * kQueue * 4 + a.tile_lds +
-                         (tlds ? (size_t)a.table_vec * 16 : 0);
-    const bool wide = p->W > 32 || p->k >= 32;
-    switch (p->esz) {
-        case 1:
-            if (wide) return tlds ? launch_one<uint64_t, uint8_t, true>(a, shmem, stream)
-                                  : launch_one<uint64_t, uint8_t, false>(a, shmem, stream);
-            return tlds ? launch_one<uint32_t, uint8_t, true>(a, shmem, stream)
-                        : launch_one<uint32_t, uint8_t, false>(a, shmem, stream);
-        case 2:
-            return tlds ? launch_one<uint32_t, uint16_t, true>(a, shmem, stream)
-                        : launch_one<uint32_t, uint16_t, false>(a, shmem, stream);
+mag_status MAG_CAT(launch_scan_q, MAG_SCAN_Q)(const ScanArgs &a, int esz, bool wide, bool tlds,
+                                             bool mul24, size_t shmem, int ncu, hipStream_t stream) {
+    switch (esz) {
+        case 1: return launch_et<uint8_t, uint32_t>(a, tlds, mul24, shmem, ncu, stream);
+        case 2: return launch_et<uint16_t, uint32_t>(a, tlds, mul24, shmem, ncu, stream);
         case 4:
-            if (wide) return tlds ? launch_one<uint64_t, uint32_t, true>(a, shmem, stream)
-                                  : launch_one<uint64_t, uint32_t, false>(a, shmem, stream);
-            return tlds ? launch_one<uint32_t, uint32_t, true>(a, shmem, stream)
-                        : launch_one<uint32_t, uint32_t, false>(a, shmem, stream);
-        default:
-            return tlds ? launch_one<uint64_t, uint64_t, true>(a, shmem, stream)
-                        : launch_one<uint64_t, uint64_t, false>(a, shmem, stream);
+            if (wide) return launch_et<uint32_t, uint64_t>(a, tlds, mul24, shmem, ncu, stream);
+            return launch_et<uint32_t, uint32_t>(a, tlds, mul24, shmem, ncu, stream);
+        default: return launch_et<uint64_t, uint64_t>(a, tlds, mul24, shmem, ncu, stream);
     }
 }
 

@@ -1,0 +1,45 @@
+// Arguments of the scan kernel, shared by its per-q objects and the dispatcher.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mag.h"
+#include "verify.hpp"
+
+namespace mag {
+
+constexpr int kScanThreads = 1024;   // threads per scan workgroup (16 wavefronts)
+
+struct ScanArgs {
+    const uint8_t *tbase;      // text pointer rounded down to 16 bytes
+    uint64_t delta;            // text - tbase
+    uint64_t n, X, ntiles;     // text bytes, samples, tiles
+    uint32_t k, kq, mprime, W, sp, m;
+    uint32_t S;                // samples per lane in the Shift-Or phase
+    uint32_t tile_samples;     // kScanThreads * S
+    uint32_t e_lds;            // bytes of LDS for the tile's mask entries
+    uint32_t table_vec;        // 16-byte vectors of the mask table (LDS copy)
+    uint32_t w0;               // entries kept before a tile's first sample (>= m'-1)
+    const uint8_t *mu;
+    const void *table;
+    uint64_t *counters;        // [1] candidate windows [2] verifications
+    VerifyArgs v;              // verification of the queued start positions
+};
+
+VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s);
+
+#define MAG_DECLARE_SCAN_Q(q)                                                            \
+    mag_status launch_scan_q##q(const ScanArgs &a, int esz, bool wide, bool tlds,        \
+                                bool mul24, size_t shmem, int ncu, hipStream_t stream);
+MAG_DECLARE_SCAN_Q(1)
+MAG_DECLARE_SCAN_Q(2)
+MAG_DECLARE_SCAN_Q(3)
+MAG_DECLARE_SCAN_Q(4)
+MAG_DECLARE_SCAN_Q(5)
+MAG_DECLARE_SCAN_Q(6)
+MAG_DECLARE_SCAN_Q(7)
+MAG_DECLARE_SCAN_Q(8)
+#undef MAG_DECLARE_SCAN_Q
+
+}  // namespace mag

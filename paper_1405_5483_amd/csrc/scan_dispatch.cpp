@@ -1,0 +1,112 @@
+// Host side of the scan launch: tile sizing and the choice among the per-q
+// kernel objects (scan.hip compiled once per q).
+#include "mag_internal.hpp"
+#include "scan_args.hpp"
+
+namespace mag {
+
+namespace {
+
+constexpr uint64_t kTableLdsMax = 64 * 1024;   // mask tables up to this size are staged in LDS
+constexpr uint32_t kEntryBytesPerTile = 32 * 1024;
+
+int compute_units() {
+    static int ncu = 0;
+    if (ncu) return ncu;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    ncu = v;
+    return ncu;
+}
+
+}  // namespace
+
+VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
+    VerifyArgs v{};
+    const uintptr_t t = reinterpret_cast<uintptr_t>(s.text);
+    v.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
+    v.delta = t & 15;
+    v.last_word = s.n ? ((v.delta + s.n - 1) & ~3ull) : 0;
+    v.m = p->m;
+    v.mw = p->mw;
+    v.hw = p->mw < (uint32_t)kHashWords ? p->mw : (uint32_t)kHashWords;
+    v.lastmask = (p->m & 3) ? ((1u << (8 * (p->m & 3))) - 1u) : 0xFFFFFFFFu;
+    v.slot_shift = 32 - p->slot_bits;
+    v.slot_mask = (uint32_t)((1ull << p->slot_bits) - 1);
+    v.idbits = (uint32_t)s.idbits;
+    v.slots = p->dev.slots;
+    v.pwords = p->dev.pwords;
+    v.idstart = p->dev.idstart;
+    v.ids = p->dev.ids;
+    v.keys = s.keys;
+    v.cap = s.cap;
+    v.counters = s.counters;
+    return v;
+}
+
+mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream) {
+    if (s.n < (uint64_t)p->q || p->r == 0) return MAG_OK;
+    const int ncu = compute_units();
+    if (ncu < 1) return fail(MAG_E_DEVICE, "cannot query the compute unit count");
+    ScanArgs a{};
+    const uintptr_t t = reinterpret_cast<uintptr_t>(s.text);
+    a.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
+    a.delta = t & 15;
+    a.n = s.n;
+    a.k = p->k;
+    a.kq = p->k * p->q;
+    a.mprime = p->mprime;
+    a.W = p->W;
+    a.sp = p->sigma_prime;
+    a.m = p->m;
+    a.X = (s.n - p->q) / a.kq + 1;
+
+    const uint32_t esz = (uint32_t)p->esz;
+    const uint32_t epv = 16 / esz;                      // entries per 16-byte LDS read
+    uint32_t S = kEntryBytesPerTile / (kScanThreads * esz);
+    // small texts: shorter lane runs so that every compute unit gets tiles
+    while (S > epv && (a.X + (uint64_t)kScanThreads * S - 1) / ((uint64_t)kScanThreads * S) <
+                          2ull * (uint64_t)ncu)
+        S -= epv;
+    a.S = S;
+    a.tile_samples = kScanThreads * S;
+    a.ntiles = (a.X + a.tile_samples - 1) / a.tile_samples;
+    const uint32_t warm = p->mprime - 1;
+    const uint32_t align = epv > 8 ? epv : 8;          // phase A writes groups of 8 entries
+    a.w0 = (warm + align - 1) / align * align;
+    // entries 0 .. TS+w0-1 are read; phase A's last group ends at most 7
+    // entries past them
+    a.e_lds = (uint32_t)((((uint64_t)a.tile_samples + a.w0 + 16) * esz + 15) & ~15ull);
+    a.mu = p->dev.mu;
+    a.table = p->dev.table;
+    a.counters = s.counters;
+    a.v = make_verify_args(p, s);
+
+    const uint64_t tbytes = p->table.size();
+    const bool tlds = tbytes <= kTableLdsMax;
+    a.table_vec = (uint32_t)((tbytes + 15) / 16);
+    const size_t shmem = 256 + (size_t)(kScanThreads / 64) * 128 * 8 + a.e_lds +
+                         (tlds ? (size_t)a.table_vec * 16 : 0);
+    const bool wide = p->W > 32 || p->k >= 32;
+    // 24-bit Horner steps are exact when every partial code stays below 2^24
+    uint64_t partial = 1;
+    for (int t = 0; t + 1 < p->q; ++t) partial *= (uint64_t)p->sigma_prime;
+    const bool mul24 = partial < (1ull << 24);
+    switch (p->q) {
+        case 1: return launch_scan_q1(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 2: return launch_scan_q2(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 3: return launch_scan_q3(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 4: return launch_scan_q4(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 5: return launch_scan_q5(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 6: return launch_scan_q6(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 7: return launch_scan_q7(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        case 8: return launch_scan_q8(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
+        default: return fail(MAG_E_UNSUPPORTED, "q outside [1, 8]");
+    }
+}
+
+}  // namespace mag

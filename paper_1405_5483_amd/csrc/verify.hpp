@@ -1,0 +1,93 @@
+// Exact verification of one start position (Section 3.2: the filter only
+// prunes; every surviving position is checked against the patterns). Shared by
+// the scan kernel (fallback when the candidate buffer is full) and the
+// verification kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mag_internal.hpp"
+
+namespace mag {
+
+struct VerifyArgs {
+    const uint8_t *tbase;      // text pointer rounded down to 16 bytes
+    uint64_t delta;            // text - tbase
+    uint64_t last_word;        // offset from tbase of the last 32-bit word holding text bytes
+    uint32_t m, mw, hw, lastmask;
+    uint32_t slot_shift, slot_mask, idbits, pad_;
+    const uint64_t *slots;     // (hash << 32) | (u + 1), 0 = empty
+    const uint32_t *pwords, *idstart, *ids;
+    uint64_t *keys;            // output keys (pos << idbits | id)
+    uint64_t cap;
+    uint64_t *counters;        // [0] = occurrences found
+};
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// 32-bit text word at physical byte offset `a` (a multiple of 4) from the
+// 16-byte-aligned text base; offsets past the last word that holds text bytes
+// are clamped to it, so no load leaves the caller's buffer (the clamped
+// bytes are never used).
+__device__ __forceinline__ uint32_t gword(const VerifyArgs &a, uint64_t off) {
+    off = off < a.last_word ? off : a.last_word;
+    return *reinterpret_cast<const uint32_t *>(a.tbase + off);
+}
+
+// Verifies start position i0 and emits every (i0, id) occurrence.
+__device__ inline void verify_start(const VerifyArgs &a, uint64_t i0) {
+    const uint64_t p = a.delta + i0;
+    const uint64_t base = p & ~3ull;
+    const uint32_t sh = (uint32_t)(p & 3);
+    uint32_t w[kMaxM / 4 + 1];
+    w[0] = gword(a, base);
+#pragma unroll
+    for (int t = 0; t < kHashWords; ++t)
+        if (t < (int)a.hw) w[t + 1] = gword(a, base + 4 * t + 4);
+    uint32_t hv[kHashWords];
+#pragma unroll
+    for (int t = 0; t < kHashWords; ++t) {
+        uint32_t x = 0;
+        if (t < (int)a.hw) {
+            x = __builtin_amdgcn_alignbyte(w[t + 1], w[t], sh);
+            if (t == (int)a.mw - 1) x &= a.lastmask;
+        }
+        hv[t] = x;
+    }
+    const uint32_t h = window_hash(hv, (int)a.hw);
+    uint32_t slot = h >> a.slot_shift;
+    for (;;) {
+        const uint64_t e = a.slots[slot];
+        if (e == 0) return;
+        if ((uint32_t)(e >> 32) == h) {
+            const uint32_t u = (uint32_t)e - 1u;
+            const uint32_t *pw = a.pwords + (size_t)u * a.mw;
+            bool eq = true;
+            uint32_t lo = w[0];
+            for (uint32_t t = 0; t < a.mw; ++t) {
+                const uint32_t hi = gword(a, base + 4 * t + 4);
+                uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, sh);
+                lo = hi;
+                if (t == a.mw - 1) x &= a.lastmask;
+                if (x != pw[t]) { eq = false; break; }
+            }
+            if (eq) {
+                const uint32_t b = a.idstart[u], c = a.idstart[u + 1] - b;
+                const uint64_t at = atomicAdd((unsigned long long *)&a.counters[0],
+                                              (unsigned long long)c);
+                for (uint32_t t = 0; t < c; ++t)
+                    if (at + t < a.cap)
+                        a.keys[at + t] = (i0 << a.idbits) | (uint64_t)a.ids[b + t];
+                return;     // distinct patterns: at most one can be equal
+            }
+        }
+        slot = (slot + 1) & a.slot_mask;
+    }
+}
+
+
+}  // namespace mag
