@@ -25,15 +25,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 CPU_SHARE = 16          # host threads one GPU's share of the box may use
+SAMPLE_BYTES = 16 << 20 # text prefix the autotuner times candidates on
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def plan_for(mag, job, select: str):
+def plan_for(mag, job, select: str, text=None):
     if select == "heuristic":
         return mag.Plan(job.patterns)
+    if select == "autotune":
+        sample = text[: min(text.numel(), SAMPLE_BYTES)]
+        best = mag.autotune(job.patterns, sample)
+        log(f"autotune picked {best}")
+        return mag.Plan(job.patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
+                        map_kind=best["map_kind"])
     if select.startswith("explicit:"):
         q, k, sp = (int(v) for v in select.split(":")[1].split(","))
         return mag.Plan(job.patterns, q=q, k=k, sigma_prime=sp)
@@ -79,7 +86,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf256m")
-    ap.add_argument("--select", default="heuristic")
+    ap.add_argument("--select", default="autotune",
+                    help="autotune | heuristic | explicit:q,k,sigma'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     args = ap.parse_args()
@@ -100,14 +108,15 @@ def main() -> int:
     log(f"generating workload {args.workload}")
     job = workload(args.workload)
     n = job.n
+    text = torch.from_numpy(job.text).cuda()
+    torch.cuda.synchronize()
     t = time.perf_counter()
-    plan = plan_for(mag, job, args.select)
+    plan = plan_for(mag, job, args.select, text)
     plan_ms = (time.perf_counter() - t) * 1e3
     info = plan.info()
     log(f"plan q={info['q']} k={info['k']} sigma'={info['sigma_prime']} W={info['W']} "
         f"table={info['table_bytes']} B ({plan_ms:.1f} ms)")
 
-    text = torch.from_numpy(job.text).cuda()
     # exact occurrence list once, with counters, and verified against the oracle
     occ, st = mag.scan(text, plan, stats=True)
     z = occ.shape[0]

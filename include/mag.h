@@ -146,6 +146,31 @@ mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
 mag_status mag_scan(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                     uint64_t out_cap, uint64_t *n_matches, mag_stats *stats, void *stream);
 
+/* Options of mag_autotune (NULL = defaults). */
+typedef struct {
+    int32_t map_kinds;    /* bit 0: greedy, bit 1: rank; 0 = both                   */
+    int32_t max_q;        /* largest q tried; 0 = 8                                  */
+    int32_t max_k;        /* largest k tried; 0 = 8                                  */
+    int64_t table_budget; /* largest mask table in bytes; 0 = 64 KiB (LDS-resident)  */
+    int32_t repeats;      /* timed scans per candidate (median); 0 = 3               */
+    int32_t max_candidates; /* cap on candidates timed, best predicted first; 0 = 64 */
+    int32_t reserved[4];  /* must be zero                                            */
+} mag_tune_opts;
+
+/* Autotuner: picks (q, k, sigma', map) for a pattern set by timing the scan on
+ * a device-resident text sample d_sample[0..n_sample). Candidates are every q
+ * with 2q-1 <= m, k <= L, reduced alphabet sizes from 2 to sigma_P and both
+ * maps whose mask table fits the budget; they are ranked by a density
+ * estimate (superimposed classes of Section 2: expected verifications per
+ * sample) plus the sampling cost, and the best-ranked ones are timed. Any
+ * choice returns exactly the same occurrences (the filter only prunes); the
+ * pick only changes the time. *best receives explicit parameters
+ * (select = MAG_SELECT_EXPLICIT) and *best_ms the median scan time of the
+ * sample (either may be NULL). Uses the device and stream like mag_scan. */
+mag_status mag_autotune(const uint8_t *patterns, uint32_t r, uint32_t m,
+                        const mag_tune_opts *opts, const uint8_t *d_sample, uint64_t n_sample,
+                        mag_params *best, float *best_ms, void *stream);
+
 /* Kernel timing for benchmarks. While enabled (process-wide), every scan
  * records HIP events on its own stream around each of its two kernels: the
  * scan kernel (filter with fused exact verification) and the finishing kernel

@@ -19,9 +19,10 @@ import ctypes
 import numpy as np
 
 from ._lib import (MAG_E_OVERFLOW, MAP_KIND, SELECT, MagError, MagParams, MagPlanDesc,
-                   MagStats, check, lib)
+                   MagStats, MagTuneOpts, check, lib)
 
-__all__ = ["Plan", "scan", "scan_async", "profile_enable", "profile_read", "MagError", "lib"]
+__all__ = ["Plan", "scan", "scan_async", "autotune", "profile_enable", "profile_read",
+           "MagError", "lib"]
 
 _ENTRY_DTYPE = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
 
@@ -160,3 +161,26 @@ def profile_read() -> dict:
     check(lib().mag_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
           "mag_profile_read")
     return {"scan_ms": a.value, "finish_ms": b.value, "launches": int(n.value)}
+
+
+_MAP_NAME = {v: k for k, v in MAP_KIND.items()}
+
+
+def autotune(patterns, sample, *, map_kinds: int = 0, max_q: int = 0, max_k: int = 0,
+             table_budget: int = 0, repeats: int = 0, max_candidates: int = 0, stream=None) -> dict:
+    """Parameters picked by ``mag_autotune`` from scans of ``sample`` (a uint8
+    CUDA tensor): dict with q, k, sigma_prime, map_kind and the sample's median
+    scan time in ms. Pass the dict's parameters to :class:`Plan`."""
+    p = _as_patterns(patterns)
+    _check_text(sample)
+    o = MagTuneOpts()
+    o.map_kinds, o.max_q, o.max_k = map_kinds, max_q, max_k
+    o.table_budget, o.repeats, o.max_candidates = table_budget, repeats, max_candidates
+    best = MagParams()
+    ms = ctypes.c_float(0.0)
+    check(lib().mag_autotune(p.ctypes.data if p.size else None, p.shape[0], p.shape[1],
+                             ctypes.byref(o), ctypes.c_void_p(sample.data_ptr()), sample.numel(),
+                             ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)),
+          "mag_autotune")
+    return {"q": best.q, "k": best.k, "sigma_prime": best.sigma_prime,
+            "map_kind": _MAP_NAME[best.map_kind], "sample_ms": ms.value}

@@ -50,6 +50,14 @@ class MagPlanDesc(ctypes.Structure):
     ]
 
 
+class MagTuneOpts(ctypes.Structure):
+    _fields_ = [
+        ("map_kinds", ctypes.c_int32), ("max_q", ctypes.c_int32), ("max_k", ctypes.c_int32),
+        ("table_budget", ctypes.c_int64), ("repeats", ctypes.c_int32),
+        ("max_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
 class MagStats(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_uint64), ("cand_windows", ctypes.c_uint64),
                 ("verifications", ctypes.c_uint64), ("matches", ctypes.c_uint64)]
@@ -69,6 +77,10 @@ SIGNATURES = {
     "mag_scan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                 ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(MagStats), ctypes.c_void_p]),
+    "mag_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.POINTER(MagTuneOpts), ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.c_void_p]),
     "mag_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "mag_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64)]),

@@ -82,17 +82,18 @@ mag_status ensure_device(mag_plan *p) {
     p->dev.idstart = reinterpret_cast<const uint32_t *>(base + o_ids0);
     p->dev.ids = reinterpret_cast<const uint32_t *>(base + o_ids);
 
-    // fixed scratch: counters[4], count, stats
+    // fixed scratch: counters[4], the count and the stats of mag_scan
     Scratch &sc = p->scratch;
     sc.device = dev;
-    sc.sort_groups = finish_groups();
-    if (sc.sort_groups < 1) return fail(MAG_E_DEVICE, "cannot size the finishing kernel");
     e = hipMalloc(&sc.counters, 16 * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc(&sc.hist, (size_t)256 * sc.sort_groups * sizeof(uint32_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(MAG_E_NOMEM, "device allocation of scan scratch failed");
     }
+    // the finishing kernel of every scan returns the counters to zero
+    e = hipMemset(sc.counters, 0, 16 * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "clearing scan counters");
     p->device = dev;
     return MAG_OK;
 }
@@ -217,6 +218,7 @@ void mag_plan_destroy(mag_plan *p) {
         (void)hipFree(p->dev.base);
         (void)hipFree(p->scratch.counters);
         (void)hipFree(p->scratch.hist);
+        (void)hipFree(p->scratch.radix_off);
         (void)hipFree(p->scratch.keys);
         (void)hipSetDevice(cur);
     }
@@ -253,8 +255,14 @@ mag_status mag_plan_export(const mag_plan *p, uint8_t *mu_out, void *table_out, 
     return MAG_OK;
 }
 
-mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
-                          uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream_) {
+}  // extern "C"
+
+namespace mag {
+namespace {
+// Enqueues counter reset, scan and finishing kernel; returns the key layout.
+mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                        uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream_,
+                        bool host_sorts, int *idbits_out, int *nbits_out) {
     if (!p) return fail(MAG_E_INVALID, "plan is NULL");
     if (!d_count) return fail(MAG_E_INVALID, "d_count is NULL");
     if (n && !d_text) return fail(MAG_E_INVALID, "d_text is NULL");
@@ -272,8 +280,6 @@ mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_ma
     const uint64_t kq = (uint64_t)p->k * p->q;
     const uint64_t samples = n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0;
 
-    s = launch_fill_u64(p->scratch.counters, 4, 0, stream);
-    if (s != MAG_OK) return s;
     ScanLaunch sl;
     sl.text = d_text;
     sl.n = n;
@@ -297,8 +303,10 @@ mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_ma
     s = launch_scan(p, sl, stream);
     if (s != MAG_OK) return s;
     if (prof) (void)hipEventRecord(rec.ev[1], stream);
+    if (idbits_out) *idbits_out = idbits;
+    if (nbits_out) *nbits_out = idbits + posbits;
     s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits,
-                      idbits + posbits, stream);
+                      idbits + posbits, host_sorts, stream);
     if (s != MAG_OK) return s;
     if (prof) {
         (void)hipEventRecord(rec.ev[2], stream);
@@ -306,6 +314,17 @@ mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_ma
         g_prof.push_back(rec);
     }
     return MAG_OK;
+}
+
+}  // namespace
+}  // namespace mag
+
+extern "C" {
+
+mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                          uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream) {
+    return scan_enqueue(p, d_text, n, d_out, out_cap, d_count, d_stats, stream, false, nullptr,
+                        nullptr);
 }
 
 mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
@@ -321,7 +340,9 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
     // the count and the counters land in the plan's own scratch words
     uint64_t *d_cnt = p->scratch.counters + 4;
     mag_stats *d_st = reinterpret_cast<mag_stats *>(p->scratch.counters + 8);
-    mag_status s = mag_scan_async(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_);
+    int idbits = 0, nbits = 0;
+    mag_status s = scan_enqueue(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_, true, &idbits,
+                                &nbits);
     if (s != MAG_OK) return s;
     uint64_t host[12];
     hipError_t e = hipMemcpyAsync(host, p->scratch.counters + 4, 8 * sizeof(uint64_t),
@@ -330,8 +351,13 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
     if (e != hipSuccess) return hip_fail(e, "reading the match count");
     *n_matches = host[0];
     if (stats) std::memcpy(stats, &host[4], sizeof(mag_stats));
-    return host[0] > out_cap ? fail(MAG_E_OVERFLOW, "output capacity smaller than the match count")
-                             : MAG_OK;
+    if (host[0] > out_cap)
+        return fail(MAG_E_OVERFLOW, "output capacity smaller than the match count");
+    if (host[0] > small_sort_max()) {
+        std::lock_guard<std::mutex> lock(p->mtx);
+        s = launch_radix_sort(p->scratch, host[0], out_cap, d_out, idbits, nbits, stream);
+    }
+    return s;
 }
 
 }  // extern "C"

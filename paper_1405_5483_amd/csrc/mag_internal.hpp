@@ -54,8 +54,9 @@ struct Scratch {
     uint64_t *counters = nullptr;   // [0] matches [1] cand windows [2] verifications [3] samples
     uint64_t *keys = nullptr;       // two key buffers of keys_cap entries each
     uint64_t keys_cap = 0;
-    uint32_t *hist = nullptr;       // radix counts: 256 * max groups
-    int sort_groups = 0;
+    uint32_t *hist = nullptr;       // device-wide radix sort: digit counts [256][blocks]
+    uint64_t *radix_off = nullptr;  // and their start offsets
+    uint64_t radix_blocks = 0;
 };
 
 }  // namespace mag
@@ -105,10 +106,14 @@ struct ScanLaunch {
 };
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream);
 mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStream_t stream);
-// Groups of the cooperative finishing kernel on the current device (0 on error).
-int finish_groups();
+// Occurrence counts up to this many are sorted inside the finishing kernel.
+uint32_t small_sort_max();
+// Publishes the count and counters and sorts small outputs; larger ones too
+// (one workgroup) unless host_sorts, in which case launch_radix_sort follows.
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
-                         mag_stats *d_stats, mag_match *out, int idbits, int nbits,
+                         mag_stats *d_stats, mag_match *out, int idbits, int nbits, bool host_sorts,
                          hipStream_t stream);
+mag_status launch_radix_sort(Scratch &sc, uint64_t z, uint64_t cap, mag_match *out, int idbits,
+                             int nbits, hipStream_t stream);
 
 }  // namespace mag

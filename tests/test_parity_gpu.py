@@ -236,3 +236,36 @@ def test_prot1g_full_size(torch_cuda, mag):
         plan = mag.Plan(job.patterns, **kw)
         occ = mag.scan(buf, plan).cpu().numpy()
         _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+
+
+def test_async_many_matches_one_workgroup_sort(torch_cuda, mag):
+    # the asynchronous entry point sorts large outputs without the host
+    torch = torch_cuda
+    n, m = 60_000, 8
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    T[::97] = ord("b")
+    P = np.stack([np.full(m, ord("a"), dtype=np.uint8)] * 2 +
+                 [np.frombuffer(b"aaabaaaa", dtype=np.uint8)])
+    plan = mag.Plan(P, q=2, k=1, sigma_prime=2)
+    ref = om.occ_hashed(T, P)
+    assert ref[0].size > 20_000
+    buf = torch.from_numpy(T).cuda()
+    out = torch.empty((ref[0].size + 10, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    mag.scan_async(buf, plan, out, cnt)
+    torch.cuda.synchronize()
+    z = int(cnt.item())
+    occ = out[:z].cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+
+
+def test_autotune_pick_is_exact(torch_cuda, mag):
+    job = make_job(3 << 20, 64, "zipf", 300, 32, 0.5, seed=21)
+    buf = torch_cuda.from_numpy(job.text).cuda()
+    best = mag.autotune(job.patterns, buf[: 1 << 20], max_candidates=12)
+    assert 2 * best["q"] - 1 <= 32 and best["sample_ms"] > 0
+    plan = mag.Plan(job.patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
+                    map_kind=best["map_kind"])
+    occ = mag.scan(buf, plan).cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32),
+                 om.occ_hashed(job.text, job.patterns))
