@@ -8,20 +8,22 @@
 // i0 = (x-m'+1)kq - jq - s (s < q). Each start position maps to exactly one
 // (x, j, s), so every position is verified at most once.
 //
-// A workgroup owns tiles of TS consecutive samples and works on a tile in two
-// phases:
-//  A. consecutive threads take consecutive samples (coalesced 32-bit buffer
-//     loads of the q bytes, range-checked so any text alignment works), map the
-//     bytes through mu, look the code up in the mask table (LDS when it fits,
-//     else global/L2) and store the mask entry in an LDS array E. There are no
-//     dependences between samples, so all lookups of a thread can be in flight.
-//  B. lane t runs the Shift-Or recurrence over E[tS - (m'-1) .. tS + S): the
-//     m'-1 entries before its own S samples warm its state up, so each window
-//     is evaluated by exactly one lane. E is read 16 bytes at a time; a wave
-//     only leaves the register-only fast path when one of its lanes has a
-//     candidate (ballot), and then compacts the candidate windows with a
-//     ballot + mbcnt prefix into an LDS queue.
-// Queued windows are verified 64 at a time, one per lane: the window's bytes
+// A workgroup owns tiles of TS consecutive samples. Its waves have two roles,
+// working one tile apart on two LDS buffers of mask entries E:
+//  - producer waves take consecutive samples (coalesced 32-bit buffer loads of
+//    the q bytes, range-checked so any text alignment works; the next rounds'
+//    words are prefetched), map the bytes through mu, look the code up in the
+//    mask table (LDS when it fits, else global/L2) and store the entry in E;
+//    no sample depends on another, so every lookup can be in flight;
+//  - consumer lanes run the Shift-Or recurrence over a contiguous run of S
+//    entries of the previous tile's E, after the W0 entries before it (warm-up:
+//    only the last m' entries reach the candidate bits, so each window is
+//    evaluated by exactly one lane). E is read 16 bytes at a time and a wave
+//    leaves the register-only fast path only when one of its lanes has a
+//    candidate (ballot); it then queues the start positions of the candidate
+//    windows in LDS with a ballot + mbcnt prefix.
+// One barrier per tile separates the rounds. Full queues (64 starts) are
+// verified one start per lane by an out-of-line function: the window's bytes
 // are read from the text (L2), the hash of its first 16 bytes probes an
 // open-addressing table of the distinct patterns, a fingerprint hit is
 // confirmed by a full word compare, and every id of the matching pattern is
@@ -44,7 +46,9 @@ namespace {
 
 constexpr int Q = MAG_SCAN_Q;
 constexpr int kNT = kScanThreads;
-constexpr int kWaves = kNT / 64;
+constexpr int kProducerWaves = kScanProducerWaves;
+constexpr int kConsumerWaves = kNT / 64 - kScanProducerWaves;
+constexpr int kProducerThreads = kProducerWaves * 64;
 constexpr int kQueue = 128;          // per-wave queue of start positions (64-bit)
 constexpr uint32_t kBufferWord3 = 0x00020000u;   // raw 32-bit buffer resource (gfx9)
 
@@ -130,6 +134,20 @@ __device__ __forceinline__ void drain64(KVerifyArgs *v, const uint64_t *queue, u
     verify_one(v, e);
 }
 
+// Entry t (runtime index) of a 16-byte vector of mask entries.
+template <typename ET>
+__device__ __forceinline__ ET entry_at(const uint4 &raw, int t) {
+    constexpr int per_word = 4 / (int)(sizeof(ET) < 4 ? sizeof(ET) : 4);
+    if constexpr (sizeof(ET) == 8) {
+        const uint32_t lo = t == 0 ? raw.x : raw.z, hi = t == 0 ? raw.y : raw.w;
+        return (ET)(((uint64_t)hi << 32) | lo);
+    } else {
+        const int w = t / per_word;
+        const uint32_t word = w == 0 ? raw.x : w == 1 ? raw.y : w == 2 ? raw.z : raw.w;
+        return (ET)(word >> (8 * sizeof(ET) * (t % per_word)));
+    }
+}
+
 template <typename ET>
 __device__ __forceinline__ void store4(ET *dst, const ET e[4]) {
     if constexpr (sizeof(ET) == 1) {
@@ -154,53 +172,91 @@ __device__ __forceinline__ void store4(ET *dst, const ET e[4]) {
 // stores. Outside interior tiles, samples before the text or past the last
 // sample get the all-ones (no match) entry. Loads past the tile are
 // range-checked by the buffer resource and their entries are never read.
-constexpr int kGroup = 8;
+#ifndef MAG_SCAN_GROUP
+#define MAG_SCAN_GROUP 4
+#endif
+constexpr int kGroup = MAG_SCAN_GROUP;
+#ifndef MAG_SCAN_PREFETCH
+#define MAG_SCAN_PREFETCH 2
+#endif
+constexpr int kPrefetch = MAG_SCAN_PREFETCH;   // rounds of loads in flight in phase A
+
+template <int G>
+__device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, int32_t p0,
+                                           int s, uint32_t kq) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) w[u] = gram_words(rs, (uint32_t)(p0 + (s + u) * (int32_t)kq));
+}
+
+template <bool INTERIOR, bool MUL24, bool TLDS, int G, typename ET>
+__device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, int s, int W0,
+                                              uint32_t sp, const uint8_t *s_mu, const ET *s_tab,
+                                              const ET *g_tab, int64_t X0, uint64_t X) {
+    const ET none = (ET)~(ET)0;
+    uint32_t g[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) g[u] = gram_code<MUL24>(w[u], s_mu, sp);
+    ET e[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        e[u] = TLDS ? s_tab[g[u]] : g_tab[g[u]];
+        if (!INTERIOR) {
+            const int64_t x = X0 + s + u;
+            if (x < 0 || x >= (int64_t)X) e[u] = none;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < G; u += 4) store4(s_E + (s + W0 + u), e + u);
+}
 
 template <bool INTERIOR, bool MUL24, bool TLDS, typename ET>
 __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq,
                                         uint32_t sp, const uint8_t *s_mu, const ET *s_tab,
                                         const ET *g_tab, int W0, uint32_t TS, int64_t X0, uint64_t X,
                                         int tid) {
-    const ET none = (ET)~(ET)0;
-    int s0 = kGroup * tid - W0;
-    GramWords cur[kGroup];
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u)
-        cur[u] = gram_words(rs, (uint32_t)(p0 + (s0 + u) * (int32_t)kq));
-    for (; s0 < (int)TS; s0 += kGroup * kNT) {
-        GramWords nxt[kGroup];
-        const int s1 = s0 + kGroup * kNT;
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-            nxt[u] = gram_words(rs, (uint32_t)(p0 + (s1 + u) * (int32_t)kq));
-        uint32_t g[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) g[u] = gram_code<MUL24>(cur[u], s_mu, sp);
-        ET e[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            e[u] = TLDS ? s_tab[g[u]] : g_tab[g[u]];
-            if (!INTERIOR) {
-                const int64_t x = X0 + s0 + u;
-                if (x < 0 || x >= (int64_t)X) e[u] = none;
-            }
+    constexpr int G = kGroup;
+    const int step = G * kProducerThreads;
+    int s = G * tid - W0;
+    if (kPrefetch >= 2) {
+        // two rounds in flight while a third is processed
+        GramWords b0[G], b1[G];
+        load_group<G>(b0, rs, p0, s, kq);
+        load_group<G>(b1, rs, p0, s + step, kq);
+        for (;;) {
+            if (s >= (int)TS) break;
+            process_group<INTERIOR, MUL24, TLDS, G>(b0, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
+            load_group<G>(b0, rs, p0, s + 2 * step, kq);
+            s += step;
+            if (s >= (int)TS) break;
+            process_group<INTERIOR, MUL24, TLDS, G>(b1, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
+            load_group<G>(b1, rs, p0, s + 2 * step, kq);
+            s += step;
         }
+    } else {
+        GramWords cur[G];
+        load_group<G>(cur, rs, p0, s, kq);
+        for (; s < (int)TS; s += step) {
+            GramWords nxt[G];
+            load_group<G>(nxt, rs, p0, s + step, kq);
+            process_group<INTERIOR, MUL24, TLDS, G>(cur, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
 #pragma unroll
-        for (int u = 0; u < kGroup; u += 4) store4(s_E + (s0 + W0 + u), e + u);
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < G; ++u) cur[u] = nxt[u];
+        }
     }
 }
 
 template <typename ET, typename DT, bool TLDS, bool MUL24>
 __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
+    constexpr int EPV = 16 / (int)sizeof(ET);            // entries per 16-byte LDS read
     uint8_t *s_mu = smem;
     uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256);
-    ET *s_E = reinterpret_cast<ET *>(smem + 256 + kWaves * kQueue * 8);
-    ET *s_tab = reinterpret_cast<ET *>(smem + 256 + kWaves * kQueue * 8 + a.e_lds);
+    ET *s_E0 = reinterpret_cast<ET *>(smem + 256 + kConsumerWaves * kQueue * 8);
+    ET *s_E1 = reinterpret_cast<ET *>(smem + 256 + kConsumerWaves * kQueue * 8 + a.e_lds);
+    ET *s_tab = reinterpret_cast<ET *>(smem + 256 + kConsumerWaves * kQueue * 8 + 2 * a.e_lds);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool producer = wave < kProducerWaves;
     // the kernel's only argument is `a`, at the start of the argument segment
     KVerifyArgs *vargs = (KVerifyArgs *)((const __attribute__((address_space(4))) char *)
                                              __builtin_amdgcn_kernarg_segment_ptr() +
@@ -213,120 +269,138 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     }
     const ET *g_tab = reinterpret_cast<const ET *>(a.table);
 
-    uint64_t *queue = s_queue + wave * kQueue;     // start positions awaiting verification
+    // consumer state
+    const int ct = tid - kProducerThreads;                // consumer lane index
+    uint64_t *queue = s_queue + (producer ? 0 : (wave - kProducerWaves)) * kQueue;
     uint32_t qn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t kmask = a.k >= 32 ? 0xFFFFFFFFu : ((1u << a.k) - 1u);
     const uint32_t topshift = a.W - a.k;
-    const uint32_t sp = a.sp, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
-    constexpr int EPV = 16 / (int)sizeof(ET);            // entries per 16-byte LDS read
-    const int warm = (int)a.mprime - 1;
+    // sigma' <= 256: the mask tells the compiler so, and Horner keeps 24-bit multiply-adds
+    const uint32_t sp = a.sp & 0x1FFu, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
     const int W0 = (int)a.w0;                             // warm-up entries kept before a tile
-    (void)warm;
     const int64_t last = (int64_t)a.n - (int64_t)a.m;   // last valid start position
 
-    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int64_t X0 = (int64_t)tile * TS;
-        // text bytes the tile touches: warm-up samples through the last
-        // verification window
-        int64_t b0 = (X0 - (int64_t)a.mprime) * kq + 1;
-        if (b0 < 0) b0 = 0;
-        int64_t b1 = (X0 + (int64_t)TS - (int64_t)a.mprime) * kq + a.m;
-        if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
-        if (b1 < b0) b1 = b0;
-        const uint64_t pa0 = (a.delta + (uint64_t)b0) & ~15ull;
-        const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
-        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
-        const int64_t pbase = (int64_t)a.delta - (int64_t)pa0;   // resource offset of text byte 0
-        __syncthreads();    // the previous tile's E is fully consumed
-
-        // ---- phase A: mask entries of samples X0-W0 .. X0+TS-1, stored at
-        // E[s + W0] (W0 >= m'-1 warm-up samples, rounded up so that every
-        // lane's own samples start on a 16-byte boundary); each thread takes 4
-        // consecutive samples per round so their lookups overlap and the
-        // entries leave in one LDS store
-        const bool interior = X0 - W0 >= 0 && X0 + (int64_t)TS <= (int64_t)a.X;
-        const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
-        if (interior)
-            phase_a<true, MUL24, TLDS>(s_E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
-        else
-            phase_a<false, MUL24, TLDS>(s_E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
-        __syncthreads();
-
-        // ---- phase B: Shift-Or over the lane's S samples. The W0 entries
-        // before them warm the state up (only the last m' entries reach the
-        // candidate bits, so the extra older ones are harmless).
-        const uint4 *vE = reinterpret_cast<const uint4 *>(s_E) + (uint32_t)tid * (S / EPV);
-        DT D = ~(DT)0;
-        for (int v = 0; v < W0 / EPV; ++v) {
-            const uint4 raw = vE[v];
-            ET ent[EPV];
-            __builtin_memcpy(ent, &raw, 16);
-#pragma unroll
-            for (int u = 0; u < EPV; ++u) D = (D << k) | (DT)ent[u];
-        }
-        vE += W0 / EPV;
-        for (uint32_t v = 0; v < S / EPV; ++v) {
-            const uint4 raw = vE[v];
-            ET ent[EPV];
-            __builtin_memcpy(ent, &raw, 16);
-            const DT Dstart = D;
-            DT all = ~(DT)0;     // a 0 in a candidate bit of the AND: some entry fired
-#pragma unroll
-            for (int u = 0; u < EPV; ++u) {
-                D = (D << k) | (DT)ent[u];
-                all &= D;
+    // Producer waves fill E for this workgroup's it-th tile while consumer
+    // waves run the Shift-Or over the (it-1)-th, in alternating buffers; one
+    // barrier per round.
+    const uint64_t nlocal = a.ntiles > blockIdx.x ? (a.ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+    for (uint64_t it = 0; it <= nlocal; ++it) {
+        if (producer) {
+            if (it < nlocal) {
+                const int64_t X0 = (int64_t)(blockIdx.x + it * gridDim.x) * TS;
+                // text bytes the tile's samples touch, warm-up included
+                int64_t b0 = (X0 - (int64_t)W0) * kq;
+                if (b0 < 0) b0 = 0;
+                int64_t b1 = (X0 + (int64_t)TS) * kq + kMaxQ;
+                if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
+                if (b1 < b0) b1 = b0;
+                const uint64_t pa0 = (a.delta + (uint64_t)b0) & ~15ull;
+                const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
+                const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
+                const int64_t pbase = (int64_t)a.delta - (int64_t)pa0;
+                const bool interior = X0 - W0 >= 0 && X0 + (int64_t)TS <= (int64_t)a.X;
+                const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
+                ET *E = (it & 1) ? s_E1 : s_E0;
+                if (interior)
+                    phase_a<true, MUL24, TLDS>(E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                else
+                    phase_a<false, MUL24, TLDS>(E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
             }
-            const uint32_t anyc = (uint32_t)((~all) >> topshift) & kmask;
-            if (!__ballot(anyc != 0)) continue;
-            // slow path: replay the vector and queue the start positions of
-            // its candidate windows
-            DT R = Dstart;
-            const int64_t xv = X0 + (int64_t)((uint32_t)tid * S + v * EPV);
+        } else if (it >= 1) {
+            // Shift-Or over the lane's S samples. The W0 entries before them
+            // warm the state up (only the last m' entries reach the candidate
+            // bits, so the extra older ones are harmless).
+            const int64_t X0 = (int64_t)(blockIdx.x + (it - 1) * gridDim.x) * TS;
+            const ET *E = ((it - 1) & 1) ? s_E1 : s_E0;
+            const uint4 *vE = reinterpret_cast<const uint4 *>(E) + (uint32_t)ct * (S / EPV);
+            DT D = ~(DT)0;
+            for (int v = 0; v < W0 / EPV; ++v) {
+                const uint4 raw = vE[v];
+                ET ent[EPV];
+                __builtin_memcpy(ent, &raw, 16);
 #pragma unroll
-            for (int u = 0; u < EPV; ++u) {
-                R = (R << k) | (DT)ent[u];
-                uint32_t c = (uint32_t)((~R) >> topshift) & kmask;
-                if (!__ballot(c != 0)) continue;
-                const int64_t topx = (xv + u - (int64_t)a.mprime + 1) * (int64_t)kq;
+                for (int u = 0; u < EPV; ++u) D = (D << k) | (DT)ent[u];
+            }
+            vE += W0 / EPV;
+            for (uint32_t v = 0; v < S / EPV; ++v) {
+                const uint4 raw = vE[v];
+                ET ent[EPV];
+                __builtin_memcpy(ent, &raw, 16);
+                const DT Dstart = D;
+                DT all = ~(DT)0;     // a 0 in a candidate bit of the AND: some entry fired
+#pragma unroll
+                for (int u = 0; u < EPV; ++u) {
+                    D = (D << k) | (DT)ent[u];
+                    all &= D;
+                }
+                const uint32_t anyc = (uint32_t)((~all) >> topshift) & kmask;
+                if (!__ballot(anyc != 0)) continue;
+                // slow path: replay the vector once to mark which entries
+                // fired, then visit only those: recompute the state there and
+                // queue the start positions of each candidate window
+                uint32_t fired = 0;
+                {
+                    DT R = Dstart;
+#pragma unroll
+                    for (int u = 0; u < EPV; ++u) {
+                        R = (R << k) | (DT)ent[u];
+                        fired |= ((((uint32_t)((~R) >> topshift)) & kmask) != 0u ? 1u : 0u) << u;
+                    }
+                }
+                const int64_t xv = X0 + (int64_t)((uint32_t)ct * S + v * EPV);
                 for (;;) {
-                    const bool has = c != 0;
-                    const uint64_t hb = __ballot(has);
-                    if (!hb) break;
-                    ncand += (uint64_t)__popcll(hb);
-                    const uint32_t bit = has ? __builtin_ctz(c) : 0u;
-                    if (has) c &= c - 1u;
-                    const int64_t top = topx - (int64_t)bit * Q;
+                    const bool hasu = fired != 0;
+                    if (!__ballot(hasu)) break;
+                    const int u = hasu ? __builtin_ctz(fired) : 0;
+                    if (hasu) fired &= fired - 1u;
+                    DT R = Dstart;
+                    for (int t = 0; t <= u; ++t) R = (R << k) | (DT)entry_at<ET>(raw, t);
+                    uint32_t c = hasu ? ((uint32_t)((~R) >> topshift) & kmask) : 0u;
+                    const int64_t topx = (xv + u - (int64_t)a.mprime + 1) * (int64_t)kq;
+                    for (;;) {
+                        const bool has = c != 0;
+                        const uint64_t hb = __ballot(has);
+                        if (!hb) break;
+                        ncand += (uint64_t)__popcll(hb);
+                        const uint32_t bit = has ? __builtin_ctz(c) : 0u;
+                        if (has) c &= c - 1u;
+                        const int64_t top = topx - (int64_t)bit * Q;
 #pragma unroll
-                    for (int sft = 0; sft < Q; ++sft) {
-                        const int64_t i0 = top - sft;
-                        const bool ok = has && i0 >= 0 && i0 <= last;
-                        const uint64_t bal = __ballot(ok);
-                        if (ok) {
-                            queue[qn + lanes_below(bal)] = (uint64_t)i0;
-                            ++nver;
-                        }
-                        qn += (uint32_t)__popcll(bal);
-                        if (qn >= 64) {
-                            qn -= 64;
-                            drain64(vargs, queue, qn, lane);
+                        for (int sft = 0; sft < Q; ++sft) {
+                            const int64_t i0 = top - sft;
+                            const bool ok = has && i0 >= 0 && i0 <= last;
+                            const uint64_t bal = __ballot(ok);
+                            if (ok) {
+                                queue[qn + lanes_below(bal)] = (uint64_t)i0;
+                                ++nver;
+                            }
+                            qn += (uint32_t)__popcll(bal);
+                            if (qn >= 64) {
+                                qn -= 64;
+                                drain64(vargs, queue, qn, lane);
+                            }
                         }
                     }
                 }
             }
         }
+        __syncthreads();
     }
-    // starts still queued
-    if (qn) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if ((uint32_t)lane < qn) verify_one(vargs, queue[lane]);
+    if (!producer) {
+        // starts still queued
+        if (qn) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if ((uint32_t)lane < qn) verify_one(vargs, queue[lane]);
+        }
+        if (lane == 0 && ncand)
+            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)ncand);
+        unsigned long long nv = nver;
+        for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
+        if (lane == 0 && nv) atomicAdd((unsigned long long *)&a.counters[2], nv);
     }
-    if (lane == 0 && ncand) atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)ncand);
-    unsigned long long nv = nver;
-    for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
-    if (lane == 0 && nv) atomicAdd((unsigned long long *)&a.counters[2], nv);
 }
 
 template <typename ET, typename DT, bool TLDS, bool MUL24>

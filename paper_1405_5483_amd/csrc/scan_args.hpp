@@ -9,16 +9,24 @@
 
 namespace mag {
 
-constexpr int kScanThreads = 1024;   // threads per scan workgroup (16 wavefronts)
+#ifndef MAG_SCAN_THREADS
+#define MAG_SCAN_THREADS 512
+#endif
+#ifndef MAG_SCAN_PRODUCERS
+#define MAG_SCAN_PRODUCERS 6
+#endif
+constexpr int kScanThreads = MAG_SCAN_THREADS;        // threads per scan workgroup
+constexpr int kScanProducerWaves = MAG_SCAN_PRODUCERS; // waves that compute mask entries
+constexpr int kScanConsumerLanes = kScanThreads - 64 * kScanProducerWaves;  // Shift-Or lanes
 
 struct ScanArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes
     uint64_t delta;            // text - tbase
     uint64_t n, X, ntiles;     // text bytes, samples, tiles
     uint32_t k, kq, mprime, W, sp, m;
-    uint32_t S;                // samples per lane in the Shift-Or phase
-    uint32_t tile_samples;     // kScanThreads * S
-    uint32_t e_lds;            // bytes of LDS for the tile's mask entries
+    uint32_t S;                // samples per consumer lane
+    uint32_t tile_samples;     // kScanConsumerLanes * S
+    uint32_t e_lds;            // bytes of LDS for one buffer of a tile's mask entries
     uint32_t table_vec;        // 16-byte vectors of the mask table (LDS copy)
     uint32_t w0;               // entries kept before a tile's first sample (>= m'-1)
     const uint8_t *mu;

@@ -8,7 +8,7 @@ namespace mag {
 namespace {
 
 constexpr uint64_t kTableLdsMax = 64 * 1024;   // mask tables up to this size are staged in LDS
-constexpr uint32_t kEntryBytesPerTile = 32 * 1024;
+constexpr uint32_t kEntryBytesPerTile = 16 * 1024;   // one of the two mask-entry buffers
 
 int compute_units() {
     static int ncu = 0;
@@ -67,20 +67,23 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
 
     const uint32_t esz = (uint32_t)p->esz;
     const uint32_t epv = 16 / esz;                      // entries per 16-byte LDS read
-    uint32_t S = kEntryBytesPerTile / (kScanThreads * esz);
+    // lane runs start on 16-byte vector boundaries: S is a multiple of epv
+    uint32_t S = kEntryBytesPerTile / (kScanConsumerLanes * esz) / epv * epv;
+    if (S < epv) S = epv;
     // small texts: shorter lane runs so that every compute unit gets tiles
-    while (S > epv && (a.X + (uint64_t)kScanThreads * S - 1) / ((uint64_t)kScanThreads * S) <
-                          2ull * (uint64_t)ncu)
+    while (S > epv && (a.X + (uint64_t)kScanConsumerLanes * S - 1) /
+                              ((uint64_t)kScanConsumerLanes * S) < 2ull * (uint64_t)ncu)
         S -= epv;
     a.S = S;
-    a.tile_samples = kScanThreads * S;
+    a.tile_samples = kScanConsumerLanes * S;
     a.ntiles = (a.X + a.tile_samples - 1) / a.tile_samples;
     const uint32_t warm = p->mprime - 1;
-    const uint32_t align = epv > 8 ? epv : 8;          // phase A writes groups of 8 entries
+    const uint32_t align = epv > 8 ? epv : 8;          // phase A writes groups of up to 8 entries
     a.w0 = (warm + align - 1) / align * align;
     // entries 0 .. TS+w0-1 are read; phase A's last group ends at most 7
     // entries past them
     a.e_lds = (uint32_t)((((uint64_t)a.tile_samples + a.w0 + 16) * esz + 15) & ~15ull);
+
     a.mu = p->dev.mu;
     a.table = p->dev.table;
     a.counters = s.counters;
@@ -89,7 +92,7 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
     const uint64_t tbytes = p->table.size();
     const bool tlds = tbytes <= kTableLdsMax;
     a.table_vec = (uint32_t)((tbytes + 15) / 16);
-    const size_t shmem = 256 + (size_t)(kScanThreads / 64) * 128 * 8 + a.e_lds +
+    const size_t shmem = 256 + (size_t)(kScanConsumerLanes / 64) * 128 * 8 + 2 * (size_t)a.e_lds +
                          (tlds ? (size_t)a.table_vec * 16 : 0);
     const bool wide = p->W > 32 || p->k >= 32;
     // 24-bit Horner steps are exact when every partial code stays below 2^24
