@@ -134,8 +134,10 @@ mag_status mag_plan_export(const mag_plan *plan, uint8_t *mu_out, void *table_ou
  * device uint64). If z > out_cap the records are unspecified (never written
  * past out_cap) and the caller should retry with a larger buffer. d_stats may
  * be NULL or a device mag_stats that receives the work counters. Any d_text
- * alignment is accepted. The plan's device scratch holds 16 bytes per unit of
- * out_cap. */
+ * alignment is accepted. The plan's device scratch holds about 17 bytes per
+ * unit of out_cap; a call that needs more scratch than earlier ones allocates
+ * it and waits for the stream first, while a call within the capacity of an
+ * earlier one only enqueues kernels (and can be captured in a hipGraph). */
 mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
                           mag_match *d_out, uint64_t out_cap, uint64_t *d_count,
                           mag_stats *d_stats, void *stream);
@@ -145,6 +147,34 @@ mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
  * MAG_E_OVERFLOW when z > out_cap (with *n_matches = z). */
 mag_status mag_scan(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                     uint64_t out_cap, uint64_t *n_matches, mag_stats *stats, void *stream);
+
+/* ---- batched scans: many independent (text, pattern set) jobs at once ---- */
+
+typedef struct mag_batch mag_batch;
+
+/* A batch over njobs plans (plans[j] is job j's pattern set and parameters;
+ * each needs W = k*m' <= 32). The batch keeps the plan pointers: the plans
+ * must outlive it and not be scanned concurrently with it. */
+mag_status mag_batch_create(mag_plan *const *plans, uint32_t njobs, mag_batch **out);
+void mag_batch_destroy(mag_batch *batch);
+
+/* Binds the jobs' texts: d_texts[j] (device pointer) of n[j] bytes (both host
+ * arrays). Uploads the job table and sizes the device scratch for outputs of
+ * up to out_cap occurrences in total; waits for the upload. Rebinding
+ * replaces the previous texts. */
+mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const uint64_t *n,
+                          uint64_t out_cap, void *stream);
+
+/* Scans every bound job in one persistent launch and sorts the output, all
+ * enqueued on `stream` without host synchronization or allocation (so the
+ * sequence can be captured in a hipGraph and replayed). Occurrences land in
+ * d_out job by job, each job's records sorted by (pos, id) with positions
+ * relative to that job's text; d_offsets (device, njobs + 1 uint64) receives
+ * the first record of each job and the total, and *d_count (device) the total
+ * count. If the total exceeds the bound out_cap, d_offsets[njobs] and
+ * *d_count still hold the exact total and the records are unspecified. */
+mag_status mag_batch_run_async(mag_batch *batch, mag_match *d_out, uint64_t *d_offsets,
+                               uint64_t *d_count, void *stream);
 
 /* Options of mag_autotune (NULL = defaults). */
 typedef struct {

@@ -21,8 +21,8 @@ import numpy as np
 from ._lib import (MAG_E_OVERFLOW, MAP_KIND, SELECT, MagError, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
-__all__ = ["Plan", "scan", "scan_async", "autotune", "profile_enable", "profile_read",
-           "MagError", "lib"]
+__all__ = ["Plan", "Batch", "scan", "scan_async", "scan_batch", "autotune", "profile_enable",
+           "profile_read", "MagError", "lib"]
 
 _ENTRY_DTYPE = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
 
@@ -148,6 +148,108 @@ def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> Non
                                ctypes.c_void_p(d_count.data_ptr()),
                                ctypes.c_void_p(d_stats.data_ptr()) if d_stats is not None else None,
                                _stream_ptr(stream)), "mag_scan_async")
+
+
+class Batch:
+    """Many (text, plan) jobs scanned in one persistent launch (``mag_batch_*``).
+
+    ``Batch(plans)`` fixes the jobs' pattern sets (a plan may serve several
+    jobs); :meth:`bind` attaches their texts and the output capacity;
+    :meth:`run_async` enqueues scan, sort and per-job offsets on a stream with
+    no host synchronization or allocation, so it can be captured in a graph.
+    """
+
+    def __init__(self, plans):
+        self.plans = list(plans)          # the library keeps raw pointers to them
+        arr = (ctypes.c_void_p * max(len(self.plans), 1))(
+            *[p.handle.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        self._h = None
+        check(lib().mag_batch_create(arr, len(self.plans), ctypes.byref(handle)),
+              "mag_batch_create")
+        self._h = handle
+        self.texts = []
+        self.out_cap = 0
+
+    @property
+    def njobs(self) -> int:
+        return len(self.plans)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch is closed")
+        return self._h
+
+    def bind(self, texts, out_cap: int, stream=None) -> None:
+        """Attach one uint8 CUDA tensor per job (kept referenced until the next
+        bind) and size the scratch for ``out_cap`` occurrences in total."""
+        texts = list(texts)
+        if len(texts) != self.njobs:
+            raise ValueError(f"{len(texts)} texts for {self.njobs} jobs")
+        for t in texts:
+            _check_text(t)
+        nj = max(self.njobs, 1)
+        ptrs = (ctypes.c_void_p * nj)(*[t.data_ptr() or None for t in texts])
+        ns = (ctypes.c_uint64 * nj)(*[t.numel() for t in texts])
+        check(lib().mag_batch_bind(self.handle, ptrs, ns, int(out_cap), _stream_ptr(stream)),
+              "mag_batch_bind")
+        self.texts = texts
+        self.out_cap = int(out_cap)
+
+    def run_async(self, out, offsets, count, stream=None) -> None:
+        """``out``: int64 [out_cap, 2] CUDA tensor of (pos, pattern id) records,
+        job after job; ``offsets``: int64 [njobs + 1] CUDA tensor, job j's
+        records are ``out[offsets[j]:offsets[j+1]]``; ``count``: int64 [1]."""
+        if out.shape[0] < self.out_cap:
+            raise ValueError("out is smaller than the bound capacity")
+        if offsets.numel() < self.njobs + 1:
+            raise ValueError("offsets needs njobs + 1 entries")
+        check(lib().mag_batch_run_async(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(offsets.data_ptr()),
+                                        ctypes.c_void_p(count.data_ptr()), _stream_ptr(stream)),
+              "mag_batch_run_async")
+
+    def run(self, stream=None):
+        """Runs the bound jobs and returns one int64 [z_j, 2] tensor per job.
+        Rebinds with the exact capacity and runs again if the output overflowed."""
+        import torch
+        dev = self.texts[0].device if self.texts else torch.device("cuda")
+        for _ in range(2):
+            out = torch.empty((max(self.out_cap, 1), 2), dtype=torch.int64, device=dev)
+            offsets = torch.empty(self.njobs + 1, dtype=torch.int64, device=dev)
+            count = torch.empty(1, dtype=torch.int64, device=dev)
+            self.run_async(out, offsets, count, stream)
+            (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+            z = int(count.item())
+            if z <= self.out_cap:
+                off = offsets.cpu().tolist()
+                return [out[off[j]:off[j + 1]] for j in range(self.njobs)]
+            self.bind(self.texts, z, stream)
+        raise MagError(MAG_E_OVERFLOW, "batch output still overflows after rebinding")
+
+    def close(self):
+        if self._h is not None:
+            lib().mag_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def scan_batch(texts, plans, out_cap: int | None = None, stream=None):
+    """One-shot batched scan: job j scans ``texts[j]`` with ``plans[j]``.
+    Returns one int64 [z_j, 2] tensor of sorted (pos, pattern id) per job."""
+    b = Batch(plans)
+    try:
+        cap = out_cap if out_cap is not None else max(1 << 16, sum(t.numel() for t in texts) // 64)
+        b.bind(texts, cap, stream)
+        return b.run(stream)
+    finally:
+        b.close()
 
 
 def profile_enable(on: bool = True) -> None:

@@ -77,6 +77,13 @@ SIGNATURES = {
     "mag_scan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                 ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(MagStats), ctypes.c_void_p]),
+    "mag_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "mag_batch_destroy": (None, [ctypes.c_void_p]),
+    "mag_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_uint64, ctypes.c_void_p]),
+    "mag_batch_run_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "mag_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.POINTER(MagTuneOpts), ctypes.c_void_p, ctypes.c_uint64,
                                     ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_float),

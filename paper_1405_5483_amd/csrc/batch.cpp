@@ -1,0 +1,310 @@
+// C ABI of batched scans (include/mag.h): a batch binds many (text, plan)
+// jobs, lays their tiles out for one persistent launch and enqueues scan,
+// sort and per-job offsets without host synchronization.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "batch.hpp"
+#include "scan_args.hpp"
+
+namespace mag {
+namespace {
+
+int ceil_log2(uint64_t v) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < v) ++b;
+    return b;
+}
+
+// Fixed cost of a tile (barriers, setup) in text-byte equivalents, for the
+// split of the tile sequence among workgroups.
+constexpr uint64_t kTileOverheadBytes = 2048;
+
+int device_compute_units() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return v;
+}
+
+template <typename T>
+mag_status grow(T **p, size_t *have, size_t want_bytes, const char *what) {
+    if (*p && *have >= want_bytes) return MAG_OK;
+    (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, want_bytes ? want_bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(MAG_E_NOMEM, std::string("device allocation failed: ") + what);
+    }
+    *have = want_bytes;
+    return MAG_OK;
+}
+
+}  // namespace
+}  // namespace mag
+
+struct mag_batch {
+    std::vector<mag_plan *> plans;
+    std::mutex mtx;
+    int device = -1;
+    bool bound = false;
+    uint64_t cap = 0;
+    int idbits = 1, posbits = 1, nbits = 3;
+    uint64_t total_tiles = 0;
+    uint32_t grid = 0;
+    mag::JobDesc *d_jobs = nullptr;
+    size_t jobs_bytes = 0;
+    uint64_t *d_ranges = nullptr;
+    size_t ranges_bytes = 0;
+    mag::Scratch sc;
+};
+
+using namespace mag;
+
+extern "C" {
+
+mag_status mag_batch_create(mag_plan *const *plans, uint32_t njobs, mag_batch **out) {
+    if (!out) return fail(MAG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (njobs && !plans) return fail(MAG_E_INVALID, "plans is NULL");
+    if (njobs > (1u << 24)) return fail(MAG_E_UNSUPPORTED, "more than 2^24 jobs in one batch");
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const mag_plan *p = plans[j];
+        if (!p) return fail(MAG_E_INVALID, "plans[" + std::to_string(j) + "] is NULL");
+        if (p->r == 0) continue;               // no tiles are ever scanned for it
+        if (p->W > 32 || p->k >= 32)
+            return fail(MAG_E_UNSUPPORTED, "batched jobs need W = k*m' <= 32 and k < 32 (job " +
+                                               std::to_string(j) + ")");
+        uint64_t partial = 1;
+        for (int t = 0; t + 1 < p->q; ++t) partial *= (uint64_t)p->sigma_prime;
+        if (partial >= (1ull << 24))
+            return fail(MAG_E_UNSUPPORTED, "batched jobs need sigma'^(q-1) < 2^24 (job " +
+                                               std::to_string(j) + ")");
+    }
+    mag_batch *b = new (std::nothrow) mag_batch();
+    if (!b) return fail(MAG_E_NOMEM, "host allocation failed");
+    b->plans.assign(plans, plans + njobs);
+    *out = b;
+    return MAG_OK;
+}
+
+void mag_batch_destroy(mag_batch *b) {
+    if (!b) return;
+    if (b->device >= 0) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(b->device);
+        (void)hipFree(b->d_jobs);
+        (void)hipFree(b->d_ranges);
+        (void)hipFree(b->sc.counters);
+        (void)hipFree(b->sc.keys);
+        (void)hipFree(b->sc.hist);
+        (void)hipFree(b->sc.radix_off);
+        (void)hipSetDevice(cur);
+    }
+    delete b;
+}
+
+mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uint64_t *n,
+                          uint64_t out_cap, void *stream_) {
+    if (!b) return fail(MAG_E_INVALID, "batch is NULL");
+    const uint32_t njobs = (uint32_t)b->plans.size();
+    if (njobs && (!d_texts || !n)) return fail(MAG_E_INVALID, "d_texts or n is NULL");
+    for (uint32_t j = 0; j < njobs; ++j)
+        if (n[j] && !d_texts[j]) return fail(MAG_E_INVALID, "d_texts[" + std::to_string(j) + "] is NULL");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    std::lock_guard<std::mutex> lock(b->mtx);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (b->device >= 0 && b->device != dev) return fail(MAG_E_INVALID, "batch was bound on another device");
+    b->bound = false;
+    for (mag_plan *p : b->plans) {
+        std::lock_guard<std::mutex> pl(p->mtx);
+        mag_status s = ensure_device(p);
+        if (s != MAG_OK) return s;
+    }
+    // earlier runs may still read the job table or the scratch
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    b->device = dev;
+
+    // key layout: job | position | pattern id
+    int idbits = 1, posbits = 1;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        idbits = std::max(idbits, ceil_log2(std::max<uint64_t>(b->plans[j]->r, 2)));
+        posbits = std::max(posbits, ceil_log2(std::max<uint64_t>(n[j] + 1, 2)));
+    }
+    const int jobbits = ceil_log2(std::max<uint32_t>(njobs, 2));
+    if (idbits + posbits + jobbits > 64)
+        return fail(MAG_E_UNSUPPORTED, "job numbers, positions and ids need more than 64 key bits");
+
+    // scratch
+    Scratch &sc = b->sc;
+    if (!sc.counters) {
+        size_t have = 0;
+        mag_status s = grow(&sc.counters, &have, 16 * sizeof(uint64_t), "batch counters");
+        if (s != MAG_OK) return s;
+        // the finishing kernel of every run returns the counters to zero
+        e = hipMemset(sc.counters, 0, 16 * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "clearing batch counters");
+    }
+    const uint64_t kcap = std::max<uint64_t>(out_cap, 1024);
+    if (!sc.keys || sc.keys_cap < kcap) {
+        size_t have = 0;
+        (void)hipFree(sc.keys);
+        sc.keys = nullptr;
+        sc.keys_cap = 0;
+        mag_status s = grow(&sc.keys, &have, (size_t)kcap * 2 * sizeof(uint64_t), "batch sort keys");
+        if (s != MAG_OK) return s;
+        sc.keys_cap = kcap;
+    }
+    if (out_cap > small_sort_max()) {
+        mag_status s = ensure_radix_scratch(sc, out_cap, stream);
+        if (s != MAG_OK) return s;
+    }
+
+    // jobs and their tiles
+    std::vector<JobDesc> jobs(njobs);
+    std::vector<uint64_t> tiles_of(njobs), tile_bytes_full(njobs), tail_samples(njobs);
+    uint64_t total_tiles = 0;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const mag_plan *p = b->plans[j];
+        JobDesc &J = jobs[j];
+        std::memset(&J, 0, sizeof(J));
+        const uint64_t kq = (uint64_t)p->k * p->q;
+        const bool scans = p->r > 0 && n[j] >= p->m && n[j] >= (uint64_t)p->q;
+        const uint64_t X = scans ? (n[j] - p->q) / kq + 1 : 0;
+        const uintptr_t t = reinterpret_cast<uintptr_t>(d_texts[j]);
+        J.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
+        J.delta = t & 15;
+        J.n = n[j];
+        J.X = X;
+        J.tile_first = total_tiles;
+        J.ntiles = (X + kBatchTileSamples - 1) / kBatchTileSamples;
+        J.mu = p->dev.mu;
+        J.table = p->dev.table;
+        J.q = p->q;
+        J.k = p->k;
+        J.kq = (uint32_t)kq;
+        J.mprime = p->mprime;
+        J.W = p->W;
+        J.sp = p->sigma_prime;
+        J.esz = p->esz;
+        J.w0 = ((uint32_t)p->mprime - 1 + 3) / 4 * 4;
+        J.tlds = p->table.size() <= kBatchTableLds ? 1 : 0;
+        J.table_vec = (uint32_t)((p->table.size() + 15) / 16);
+        ScanLaunch sl;
+        sl.text = d_texts[j];
+        sl.n = n[j];
+        sl.keys = sc.keys;
+        sl.cap = out_cap;
+        sl.counters = sc.counters;
+        sl.idbits = idbits;
+        J.v = make_verify_args(p, sl);
+        J.v.key_or = (uint64_t)j << (posbits + idbits);
+        tiles_of[j] = J.ntiles;
+        tile_bytes_full[j] = (uint64_t)kBatchTileSamples * kq;
+        tail_samples[j] = X - (J.ntiles ? (J.ntiles - 1) * kBatchTileSamples : 0);
+        total_tiles += J.ntiles;
+    }
+
+    // contiguous tile ranges of about equal weight, one per workgroup
+    const int ncu = device_compute_units();
+    const int occ = batch_occupancy();
+    if (ncu < 1 || occ < 1) return fail(MAG_E_DEVICE, "cannot size the batch launch");
+    uint64_t grid = (uint64_t)ncu * occ;
+    if (grid > total_tiles) grid = total_tiles;
+    std::vector<uint64_t> ranges(3 * std::max<uint64_t>(grid, 1), 0);
+    if (grid) {
+        auto tile_weight = [&](uint32_t j, uint64_t t) {
+            const uint64_t samples = t + 1 < tiles_of[j] ? (uint64_t)kBatchTileSamples : tail_samples[j];
+            return samples * jobs[j].kq + kTileOverheadBytes;
+        };
+        long double total = 0;
+        for (uint32_t j = 0; j < njobs; ++j)
+            for (uint64_t t = 0; t < tiles_of[j]; ++t) total += (long double)tile_weight(j, t);
+        std::vector<uint64_t> begin(grid + 1, total_tiles);
+        std::vector<uint32_t> job_of(grid, 0);
+        uint64_t next_wg = 0, g = 0;
+        long double run = 0;
+        for (uint32_t j = 0; j < njobs; ++j) {
+            for (uint64_t t = 0; t < tiles_of[j]; ++t, ++g) {
+                uint64_t w = (uint64_t)(run * (long double)grid / total);
+                if (w >= grid) w = grid - 1;
+                while (next_wg <= w) {
+                    begin[next_wg] = g;
+                    job_of[next_wg] = j;
+                    ++next_wg;
+                }
+                run += (long double)tile_weight(j, t);
+            }
+        }
+        for (uint64_t wg = 0; wg < grid; ++wg) {
+            ranges[3 * wg] = begin[wg];
+            ranges[3 * wg + 1] = begin[wg + 1] > begin[wg] ? begin[wg + 1] : begin[wg];
+            ranges[3 * wg + 2] = begin[wg] < total_tiles ? job_of[wg] : 0;
+        }
+    }
+    mag_status s = grow(&b->d_jobs, &b->jobs_bytes, std::max<size_t>(njobs, 1) * sizeof(JobDesc), "job table");
+    if (s != MAG_OK) return s;
+    s = grow(&b->d_ranges, &b->ranges_bytes, ranges.size() * sizeof(uint64_t), "tile ranges");
+    if (s != MAG_OK) return s;
+    if (njobs) e = hipMemcpy(b->d_jobs, jobs.data(), njobs * sizeof(JobDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload of the job table");
+    b->cap = out_cap;
+    b->idbits = idbits;
+    b->posbits = posbits;
+    b->nbits = idbits + posbits + jobbits;
+    b->total_tiles = total_tiles;
+    b->grid = (uint32_t)grid;
+    b->bound = true;
+    return MAG_OK;
+}
+
+mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offsets,
+                               uint64_t *d_count, void *stream_) {
+    if (!b) return fail(MAG_E_INVALID, "batch is NULL");
+    if (!d_offsets || !d_count) return fail(MAG_E_INVALID, "d_offsets or d_count is NULL");
+    std::lock_guard<std::mutex> lock(b->mtx);
+    if (!b->bound) return fail(MAG_E_INVALID, "batch has no bound texts");
+    if (b->cap && !d_out) return fail(MAG_E_INVALID, "d_out is NULL");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    const uint32_t njobs = (uint32_t)b->plans.size();
+    Scratch &sc = b->sc;
+    const uint64_t posmask = (1ull << b->posbits) - 1ull;
+    uint64_t *sorted = sorted_keys(sc, b->cap, b->nbits);
+
+    BatchLaunch bl;
+    bl.jobs = b->d_jobs;
+    bl.ranges = b->d_ranges;
+    bl.grid = b->grid;
+    bl.total_tiles = b->total_tiles;
+    bl.counters = sc.counters;
+    mag_status s = launch_batch(bl, stream);
+    if (s == MAG_OK)
+        s = launch_finish(sc, b->cap, 0, d_count, nullptr, d_out, b->idbits, posmask, sorted, stream);
+    if (s == MAG_OK && b->cap > small_sort_max()) {
+        s = launch_radix_sort(sc, b->cap, b->cap, b->nbits, stream);
+        if (s == MAG_OK)
+            s = launch_expand(sc, b->cap, b->cap, b->nbits, d_out, b->idbits, posmask, stream);
+    }
+    if (s == MAG_OK)
+        s = launch_batch_offsets(sorted, sc.counters + kSortCountSlot, b->cap, d_offsets, njobs,
+                                 b->posbits + b->idbits, stream);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// Batched MAG scans: many independent (text, pattern set) jobs in one
+// persistent launch.
+//
+// Every job is cut into tiles of kBatchTileSamples samples; the tiles of all
+// jobs form one global sequence (job after job) that the host splits into
+// contiguous ranges of about equal text bytes, one per workgroup, so a
+// workgroup restages a job's alphabet map and mask table in LDS only when its
+// range crosses into the next job. Per tile the kernel runs the two phases of
+// the single-job scan with all of its threads: the mask entries of the
+// tile's samples (with the job's q, k, sigma' and table; q selects one of
+// eight compile-time variants per tile), then the Shift-Or recurrence over
+// each lane's run of entries, with ballot-compacted candidate windows and
+// exact verification of their start positions. Keys carry the job number
+// above the position, so one device-wide sort orders the whole output job by
+// job, and a last kernel finds each job's first record. Nothing waits on the
+// host, so the launch sequence can be captured in a hipGraph.
+//
+// Batched jobs keep their state in 32 bits: W = k*m' <= 32 and k < 32.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "scan_common.hpp"
+
+namespace mag {
+namespace {
+
+using namespace dev;
+
+constexpr int kBT = kBatchThreads;
+constexpr int kWaves = kBT / 64;
+constexpr int kTS = kBatchTileSamples;
+constexpr int kS = kTS / kBT;                 // samples per lane in the Shift-Or phase
+constexpr int kLaneVecs = kS / 4;             // 16-byte vectors of u32 entries per lane
+static_assert(kS % 4 == 0 && kBatchMaxWarm % 4 == 0, "lane runs are whole vectors");
+
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// readfirstlane returns int: each half goes through uint32_t so that the low
+// word is not sign-extended into the high one
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ T *uniptr(T *p) {
+    return reinterpret_cast<T *>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
+// Entries are read and written as 16-byte vectors of four u32 entries;
+// vector V lives at V ^ ((V >> 3) & 7). A Shift-Or read step has the lanes
+// kLaneVecs vectors apart; with the swizzle any eight consecutive lanes read
+// eight different 16-byte bank groups. Phase A's stores of consecutive
+// vectors stay conflict-free.
+__device__ __forceinline__ uint32_t swz(uint32_t V) { return V ^ ((V >> 3) & 7u); }
+
+template <int ESZ>
+__device__ __forceinline__ uint32_t lds_entry(const uint8_t *s_tab, uint32_t g) {
+    if constexpr (ESZ == 1) return s_tab[g];
+    else if constexpr (ESZ == 2) return reinterpret_cast<const uint16_t *>(s_tab)[g];
+    else return reinterpret_cast<const uint32_t *>(s_tab)[g];
+}
+
+template <int ESZ>
+__device__ __forceinline__ uint32_t l2_entry(__amdgpu_buffer_rsrc_t trs, uint32_t g) {
+    if constexpr (ESZ == 1) return __builtin_amdgcn_raw_buffer_load_b8(trs, (int)g, 0, 0);
+    else if constexpr (ESZ == 2) return __builtin_amdgcn_raw_buffer_load_b16(trs, (int)(2 * g), 0, 0);
+    else return __builtin_amdgcn_raw_buffer_load_b32(trs, (int)(4 * g), 0, 0);
+}
+
+// Mask entries (as u32) of samples X0-w0 .. X0+kTS-1 of one job: entry of
+// sample X0+s goes to E index s + w0. Thread tid computes vectors tid,
+// tid + kBT, ... two at a time (both loads issued before the lookups).
+template <int Q, int ESZ>
+__device__ void phase_a(uint4 *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq, uint32_t sp,
+                        const uint8_t *s_mu, const uint8_t *s_tab, __amdgpu_buffer_rsrc_t trs,
+                        bool tlds, int w0, int64_t X0, int64_t X, int tid) {
+    const uint32_t none = ESZ == 1 ? 0xFFu : ESZ == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+    const int nvec = (kTS + w0) / 4;
+    for (int V = tid; V < nvec; V += 2 * kBT) {
+        GramWords w[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int s = 4 * (V + h * kBT) - w0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                w[h][u] = gram_words<Q>(rs, (uint32_t)(p0 + (s + u) * (int32_t)kq));
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int Vh = V + h * kBT;
+            if (Vh >= nvec) break;
+            const int s = 4 * Vh - w0;
+            uint32_t e[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t g = gram_code<Q, true>(w[h][u], s_mu, sp);
+                e[u] = tlds ? lds_entry<ESZ>(s_tab, g) : l2_entry<ESZ>(trs, g);
+                const int64_t x = X0 + s + u;
+                if (x < 0 || x >= X) e[u] = none;
+            }
+            s_E[swz((uint32_t)Vh)] = make_uint4(e[0], e[1], e[2], e[3]);
+        }
+    }
+}
+
+template <int Q>
+__device__ __forceinline__ void phase_a_q(uint32_t esz, uint4 *s_E, __amdgpu_buffer_rsrc_t rs,
+                                          int32_t p0, uint32_t kq, uint32_t sp, const uint8_t *s_mu,
+                                          const uint8_t *s_tab, __amdgpu_buffer_rsrc_t trs, bool tlds,
+                                          int w0, int64_t X0, int64_t X, int tid) {
+    if (esz == 1) phase_a<Q, 1>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+    else if (esz == 2) phase_a<Q, 2>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+    else phase_a<Q, 4>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+}
+
+// Verifies the first qn queued starts of this wave, one per lane.
+__device__ __forceinline__ void drain_partial(const VerifyArgs *v, const uint64_t *queue, uint32_t qn,
+                                              int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if ((uint32_t)lane < qn) verify_one(v, queue[lane]);
+}
+
+__global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
+                                               const uint64_t *__restrict__ ranges,
+                                               uint64_t *counters) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t *s_mu = smem;
+    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256);
+    uint4 *s_E = reinterpret_cast<uint4 *>(smem + 256 + kWaves * kBatchQueue * 8);
+    uint8_t *s_tab = smem + 256 + kWaves * kBatchQueue * 8 + kBatchEntryBytes;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *queue = s_queue + wave * kBatchQueue;
+    uint32_t qn = 0;
+    uint64_t ncand = 0, nver = 0;
+
+    const uint64_t g0 = uni64(ranges[3 * blockIdx.x]);
+    const uint64_t g1 = uni64(ranges[3 * blockIdx.x + 1]);
+    const uint32_t first_job = uni32((uint32_t)ranges[3 * blockIdx.x + 2]);
+
+    // the current job, in scalar registers
+    int cur = -1;
+    const VerifyArgs *vp = nullptr;
+    const uint8_t *tbase = nullptr;
+    __amdgpu_buffer_rsrc_t trs = tile_rsrc(nullptr, 0);
+    uint64_t delta = 0, n = 0, X = 0, tfirst = 0, tend = 0;
+    uint32_t q = 1, k = 1, kq = 1, mprime = 1, W = 1, sp = 1, esz = 1, w0 = 0, tlds = 0, m = 1;
+
+    for (uint64_t g = g0; g < g1; ++g) {
+        if (cur < 0 || g >= tend) {
+            if (cur >= 0 && qn) {
+                drain_partial(vp, queue, qn, lane);   // starts of the previous job
+                qn = 0;
+            }
+            uint32_t j = cur < 0 ? first_job : (uint32_t)cur + 1;
+            while (jobs[j].tile_first + jobs[j].ntiles <= g) ++j;   // skips jobs without tiles
+            j = uni32(j);
+            const JobDesc &J = jobs[j];
+            cur = (int)j;
+            vp = &J.v;
+            tbase = uniptr(J.tbase);
+            delta = uni64(J.delta);
+            n = uni64(J.n);
+            X = uni64(J.X);
+            tfirst = uni64(J.tile_first);
+            tend = tfirst + uni64(J.ntiles);
+            q = uni32(J.q);
+            k = uni32(J.k);
+            kq = uni32(J.kq);
+            mprime = uni32(J.mprime);
+            W = uni32(J.W);
+            sp = uni32(J.sp) & 0x1FFu;      // sigma' <= 256: keeps 24-bit Horner steps
+            esz = uni32(J.esz);
+            w0 = uni32(J.w0);
+            tlds = uni32(J.tlds);
+            m = uni32(J.v.m);
+            const uint32_t tvec = uni32(J.table_vec);
+            const uint8_t *mu = uniptr(J.mu);
+            const uint8_t *table = uniptr(reinterpret_cast<const uint8_t *>(J.table));
+            trs = tile_rsrc(table, tvec * 16u);
+            __syncthreads();                // the previous tile is done with the LDS tables
+            for (int i = tid; i < 256; i += kBT) s_mu[i] = mu[i];
+            if (tlds) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(table);
+                uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
+                for (uint32_t v = tid; v < tvec; v += kBT) dst[v] = src[v];
+            }
+        }
+        const int64_t X0 = (int64_t)(g - tfirst) * kTS;
+        // text bytes the tile's samples touch, warm-up included
+        int64_t b0 = (X0 - (int64_t)w0) * kq;
+        if (b0 < 0) b0 = 0;
+        int64_t b1 = (X0 + kTS) * (int64_t)kq + kMaxQ;
+        if (b1 > (int64_t)n) b1 = (int64_t)n;
+        if (b1 < b0) b1 = b0;
+        const uint64_t pa0 = (delta + (uint64_t)b0) & ~15ull;
+        const uint64_t pa1 = (delta + (uint64_t)b1 + 15) & ~15ull;
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(tbase + pa0, (uint32_t)(pa1 - pa0));
+        const int32_t p0 = (int32_t)((int64_t)delta - (int64_t)pa0 + X0 * (int64_t)kq);
+        __syncthreads();                    // tables staged; the previous tile's entries consumed
+        switch (q) {
+            case 1: phase_a_q<1>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 2: phase_a_q<2>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 3: phase_a_q<3>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 4: phase_a_q<4>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 5: phase_a_q<5>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 6: phase_a_q<6>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 7: phase_a_q<7>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            default: phase_a_q<8>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+        }
+        __syncthreads();
+
+        // Shift-Or over the lane's kS samples, after w0 warm-up entries (only
+        // the last m' entries reach the candidate bits, so older ones are harmless)
+        const uint32_t kmask = (1u << k) - 1u;           // k < 32
+        const uint32_t topshift = W - k;
+        const int64_t last = (int64_t)n - (int64_t)m;    // last valid start position
+        const uint32_t vb = (uint32_t)tid * kLaneVecs;
+        uint32_t D = 0xFFFFFFFFu;
+        for (uint32_t v = 0; v < w0 / 4; ++v) {
+            const uint4 raw = s_E[swz(vb + v)];
+            D = (D << k) | raw.x;
+            D = (D << k) | raw.y;
+            D = (D << k) | raw.z;
+            D = (D << k) | raw.w;
+        }
+#pragma unroll
+        for (int v = 0; v < kLaneVecs; ++v) {
+            const uint4 raw = s_E[swz(vb + w0 / 4 + v)];
+            const uint32_t ent[4] = {raw.x, raw.y, raw.z, raw.w};
+            const uint32_t Dstart = D;
+            uint32_t all = 0xFFFFFFFFu;      // a 0 in a candidate bit: some entry fired
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                D = (D << k) | ent[u];
+                all &= D;
+            }
+            if (!__ballot((((~all) >> topshift) & kmask) != 0u)) continue;
+            // slow path: step through the vector again, queueing the start
+            // positions of every candidate window
+            const int64_t xv = X0 + (int64_t)tid * kS + 4 * v;
+            uint32_t R = Dstart;
+            for (int u = 0; u < 4; ++u) {
+                R = (R << k) | ent[u];
+                uint32_t c = ((~R) >> topshift) & kmask;
+                if (!__ballot(c != 0u)) continue;
+                const int64_t topx = (xv + u - (int64_t)mprime + 1) * (int64_t)kq;
+                for (;;) {
+                    const bool has = c != 0u;
+                    const uint64_t hb = __ballot(has);
+                    if (!hb) break;
+                    ncand += (uint64_t)__popcll(hb);
+                    const uint32_t bit = has ? (uint32_t)__builtin_ctz(c) : 0u;
+                    if (has) c &= c - 1u;
+                    const int64_t top = topx - (int64_t)bit * q;
+                    for (uint32_t sft = 0; sft < q; ++sft) {
+                        const int64_t i0 = top - sft;
+                        const bool ok = has && i0 >= 0 && i0 <= last;
+                        const uint64_t bal = __ballot(ok);
+                        if (ok) {
+                            queue[qn + lanes_below(bal)] = (uint64_t)i0;
+                            ++nver;
+                        }
+                        qn += (uint32_t)__popcll(bal);
+                        if (qn >= 64) {
+                            qn -= 64;
+                            drain64(vp, queue, qn, lane);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (cur >= 0 && qn) drain_partial(vp, queue, qn, lane);
+    if (lane == 0 && ncand) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)ncand);
+    unsigned long long nv = nver;
+    for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
+    if (lane == 0 && nv) atomicAdd((unsigned long long *)&counters[2], nv);
+}
+
+// offsets[j] = first record of job j (binary search of the sorted keys on the
+// job field), offsets[njobs] = the count. One thread per entry.
+__global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
+                                uint64_t *offsets, uint32_t njobs, int job_shift) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > njobs) return;
+    const uint64_t z = *zp;
+    uint64_t at = 0;
+    if (j == njobs) {
+        at = z;
+    } else if (z <= cap) {
+        uint64_t lo = 0, hi = z;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if ((sorted[mid] >> job_shift) < j) lo = mid + 1;
+            else hi = mid;
+        }
+        at = lo;
+    }
+    offsets[j] = at;
+}
+
+}  // namespace
+
+mag_status batch_configure() {
+    static bool done = false;
+    if (done) return MAG_OK;
+    // not every runtime needs the opt-in; a real LDS overflow fails the launch
+    (void)hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kBatchLdsBytes);
+    (void)hipGetLastError();
+    done = true;
+    return MAG_OK;
+}
+
+int batch_occupancy() {
+    batch_configure();
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBT, kBatchLdsBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return occ;
+}
+
+mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
+    if (!b.total_tiles || !b.grid) return MAG_OK;
+    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), kBatchLdsBytes, stream, b.jobs, b.ranges,
+                       b.counters);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch scan launch");
+}
+
+mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
+                                uint64_t *d_offsets, uint32_t njobs, int job_shift,
+                                hipStream_t stream) {
+    const uint32_t threads = 256;
+    const uint32_t blocks = (njobs + 1 + threads - 1) / threads;
+    hipLaunchKernelGGL(k_batch_offsets, dim3(blocks), dim3(threads), 0, stream, sorted, zp, cap,
+                       d_offsets, njobs, job_shift);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch offsets launch");
+}
+
+}  // namespace mag

@@ -1,0 +1,56 @@
+// Batched scans: the per-job descriptors that the persistent kernel reads and
+// its launch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mag_internal.hpp"
+#include "verify.hpp"
+
+namespace mag {
+
+constexpr int kBatchThreads = 512;               // threads per workgroup
+constexpr int kBatchTileSamples = 8192;          // samples per tile: 16 per thread
+constexpr int kBatchMaxWarm = 32;                // warm-up entries before a tile (>= m' - 1)
+constexpr int kBatchQueue = 128;                 // per-wave queue of start positions
+// mask entries of one tile as u32, in whole groups of eight 16-byte vectors
+constexpr uint32_t kBatchEntryBytes =
+    ((kBatchTileSamples + kBatchMaxWarm) * 4 + 127) / 128 * 128;
+constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
+constexpr uint32_t kBatchLdsBytes =
+    256 + (kBatchThreads / 64) * kBatchQueue * 8 + kBatchEntryBytes + kBatchTableLds;
+
+// One job as the kernel sees it. Written by the host at bind time.
+struct JobDesc {
+    const uint8_t *tbase;      // text pointer rounded down to 16 bytes
+    uint64_t delta;            // text - tbase
+    uint64_t n, X;             // text bytes, samples
+    uint64_t tile_first;       // global index of the job's first tile
+    uint64_t ntiles;
+    const uint8_t *mu;         // the plan's alphabet map (256 B)
+    const void *table;         // its mask table
+    uint32_t q, k, kq, mprime, W, sp, esz, w0;
+    uint32_t tlds;             // table staged in LDS
+    uint32_t table_vec;        // 16-byte vectors of the table
+    VerifyArgs v;              // verification, with the job number in key_or
+};
+
+struct BatchLaunch {
+    const JobDesc *jobs;
+    const uint64_t *ranges;    // per workgroup: first tile, end tile, job of the first tile
+    uint32_t grid;
+    uint64_t total_tiles;
+    uint64_t *counters;
+};
+
+// Workgroups of the batch kernel that fit on one compute unit (0 on error).
+int batch_occupancy();
+mag_status batch_configure();
+mag_status launch_batch(const BatchLaunch &b, hipStream_t stream);
+// offsets[j] = first record of job j in the sorted keys, offsets[njobs] = count.
+mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
+                                uint64_t *d_offsets, uint32_t njobs, int job_shift,
+                                hipStream_t stream);
+
+}  // namespace mag

@@ -39,6 +39,40 @@ int ceil_log2(uint64_t v) {
     return b;
 }
 
+// Grows the key buffers to hold 2 * cap keys. Waits for `stream` first so no
+// earlier scan still uses the old buffer.
+mag_status ensure_keys(mag_plan *p, uint64_t cap, hipStream_t stream) {
+    Scratch &sc = p->scratch;
+    if (sc.keys_cap >= cap && sc.keys) return MAG_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (sc.keys) {
+        (void)hipFree(sc.keys);
+        sc.keys = nullptr;
+        sc.keys_cap = 0;
+    }
+    uint64_t want = cap < 1024 ? 1024 : cap;
+    e = hipMalloc(&sc.keys, want * 2 * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of sort keys failed");
+    }
+    sc.keys_cap = want;
+    return MAG_OK;
+}
+
+}  // namespace
+
+mag_status fail(mag_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+mag_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return MAG_E_DEVICE;
+}
+
 // Uploads the plan's tables to the current device on first use.
 mag_status ensure_device(mag_plan *p) {
     int dev = 0;
@@ -96,40 +130,6 @@ mag_status ensure_device(mag_plan *p) {
     if (e != hipSuccess) return hip_fail(e, "clearing scan counters");
     p->device = dev;
     return MAG_OK;
-}
-
-// Grows the key buffers to hold 2 * cap keys. Waits for `stream` first so no
-// earlier scan still uses the old buffer.
-mag_status ensure_keys(mag_plan *p, uint64_t cap, hipStream_t stream) {
-    Scratch &sc = p->scratch;
-    if (sc.keys_cap >= cap && sc.keys) return MAG_OK;
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (sc.keys) {
-        (void)hipFree(sc.keys);
-        sc.keys = nullptr;
-        sc.keys_cap = 0;
-    }
-    uint64_t want = cap < 1024 ? 1024 : cap;
-    e = hipMalloc(&sc.keys, want * 2 * sizeof(uint64_t));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(MAG_E_NOMEM, "device allocation of sort keys failed");
-    }
-    sc.keys_cap = want;
-    return MAG_OK;
-}
-
-}  // namespace
-
-mag_status fail(mag_status s, const std::string &msg) {
-    g_last_error = msg;
-    return s;
-}
-
-mag_status hip_fail(hipError_t e, const char *what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-    return MAG_E_DEVICE;
 }
 
 }  // namespace mag
@@ -262,7 +262,7 @@ namespace {
 // Enqueues counter reset, scan and finishing kernel; returns the key layout.
 mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                         uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream_,
-                        bool host_sorts, int *idbits_out, int *nbits_out) {
+                        bool device_sort, int *idbits_out, int *nbits_out) {
     if (!p) return fail(MAG_E_INVALID, "plan is NULL");
     if (!d_count) return fail(MAG_E_INVALID, "d_count is NULL");
     if (n && !d_text) return fail(MAG_E_INVALID, "d_text is NULL");
@@ -273,6 +273,13 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     if (s != MAG_OK) return s;
     s = ensure_keys(p, out_cap, stream);
     if (s != MAG_OK) return s;
+    // without the host reading the count, large outputs are sorted by
+    // kernels sized for the capacity
+    const bool sort_on_device = device_sort && out_cap > small_sort_max();
+    if (sort_on_device) {
+        s = ensure_radix_scratch(p->scratch, out_cap, stream);
+        if (s != MAG_OK) return s;
+    }
 
     const int idbits = ceil_log2(p->r > 1 ? p->r : 2);
     const int posbits = ceil_log2(n + 1 > 2 ? n + 1 : 2);
@@ -305,9 +312,15 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     if (prof) (void)hipEventRecord(rec.ev[1], stream);
     if (idbits_out) *idbits_out = idbits;
     if (nbits_out) *nbits_out = idbits + posbits;
-    s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits,
-                      idbits + posbits, host_sorts, stream);
+    s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits, ~0ull, nullptr,
+                      stream);
     if (s != MAG_OK) return s;
+    if (sort_on_device) {
+        s = launch_radix_sort(p->scratch, out_cap, out_cap, idbits + posbits, stream);
+        if (s == MAG_OK)
+            s = launch_expand(p->scratch, out_cap, out_cap, idbits + posbits, d_out, idbits, ~0ull, stream);
+        if (s != MAG_OK) return s;
+    }
     if (prof) {
         (void)hipEventRecord(rec.ev[2], stream);
         std::lock_guard<std::mutex> pl(g_prof_mtx);
@@ -323,7 +336,7 @@ extern "C" {
 
 mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                           uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream) {
-    return scan_enqueue(p, d_text, n, d_out, out_cap, d_count, d_stats, stream, false, nullptr,
+    return scan_enqueue(p, d_text, n, d_out, out_cap, d_count, d_stats, stream, true, nullptr,
                         nullptr);
 }
 
@@ -341,7 +354,7 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
     uint64_t *d_cnt = p->scratch.counters + 4;
     mag_stats *d_st = reinterpret_cast<mag_stats *>(p->scratch.counters + 8);
     int idbits = 0, nbits = 0;
-    mag_status s = scan_enqueue(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_, true, &idbits,
+    mag_status s = scan_enqueue(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_, false, &idbits,
                                 &nbits);
     if (s != MAG_OK) return s;
     uint64_t host[12];
@@ -355,7 +368,9 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
         return fail(MAG_E_OVERFLOW, "output capacity smaller than the match count");
     if (host[0] > small_sort_max()) {
         std::lock_guard<std::mutex> lock(p->mtx);
-        s = launch_radix_sort(p->scratch, host[0], out_cap, d_out, idbits, nbits, stream);
+        s = ensure_radix_scratch(p->scratch, host[0], stream);
+        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[0], out_cap, nbits, stream);
+        if (s == MAG_OK) s = launch_expand(p->scratch, host[0], out_cap, nbits, d_out, idbits, ~0ull, stream);
     }
     return s;
 }

@@ -21,6 +21,10 @@ constexpr int kMaxK = 32;           // candidate mask of one window fits 32 bits
 constexpr uint64_t kMaxTableBytes = 1ull << 30;
 constexpr int kDefaultTableBudget = 96 * 1024;
 constexpr int kHashWords = 4;       // the verification hash reads the first 16 bytes
+// Scratch counters: [0] occurrences [1] candidate windows [2] verifications,
+// [4] and [8..11] the count and stats that mag_scan reads back, and
+// [kSortCountSlot] the count that the device-wide sort reads.
+constexpr int kSortCountSlot = 12;
 
 // Fingerprint of the first min(m, 16) bytes of a pattern or text window, given
 // as little-endian 32-bit words with bytes past m zeroed. It only has to spread
@@ -51,12 +55,12 @@ struct DeviceTables {
 
 struct Scratch {
     int device = -1;
-    uint64_t *counters = nullptr;   // [0] matches [1] cand windows [2] verifications [3] samples
+    uint64_t *counters = nullptr;   // 16 words, see kSortCountSlot
     uint64_t *keys = nullptr;       // two key buffers of keys_cap entries each
     uint64_t keys_cap = 0;
-    uint32_t *hist = nullptr;       // device-wide radix sort: digit counts [256][blocks]
-    uint64_t *radix_off = nullptr;  // and their start offsets
-    uint64_t radix_blocks = 0;
+    uint32_t *hist = nullptr;       // device-wide radix sort: digit counts [256][chunks]
+    uint64_t *radix_off = nullptr;  // their start offsets [256][chunks], then 256 digit totals
+    uint64_t radix_chunks = 0;
 };
 
 }  // namespace mag
@@ -91,6 +95,10 @@ namespace mag {
 mag_status fail(mag_status s, const std::string &msg);
 mag_status hip_fail(hipError_t e, const char *what);
 
+// Uploads the plan's tables and scratch counters to the current device on
+// first use; fails if the plan lives on another device (capi.cpp).
+mag_status ensure_device(mag_plan *p);
+
 // Host plan builder (plan.cpp).
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
                       const mag_params *params);
@@ -108,12 +116,22 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
 mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStream_t stream);
 // Occurrence counts up to this many are sorted inside the finishing kernel.
 uint32_t small_sort_max();
-// Publishes the count and counters and sorts small outputs; larger ones too
-// (one workgroup) unless host_sorts, in which case launch_radix_sort follows.
+// Publishes the count (and the stats if d_stats), leaves the count in
+// counters[kSortCountSlot], returns the other counters to zero, and sorts
+// outputs of up to small_sort_max() occurrences into `out` (and their keys
+// into `sorted` if not null). Records hold ((key >> idbits) & posmask, key's
+// low idbits).
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
-                         mag_stats *d_stats, mag_match *out, int idbits, int nbits, bool host_sorts,
-                         hipStream_t stream);
-mag_status launch_radix_sort(Scratch &sc, uint64_t z, uint64_t cap, mag_match *out, int idbits,
-                             int nbits, hipStream_t stream);
+                         mag_stats *d_stats, mag_match *out, int idbits, uint64_t posmask,
+                         uint64_t *sorted, hipStream_t stream);
+// Device-wide radix sort of the keys for counts in (small_sort_max(), cap],
+// with grids sized for counts up to `bound`: the scratch for `bound`, the
+// passes over the nbits low key bits, and the records.
+mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream);
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, hipStream_t stream);
+mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, mag_match *out,
+                         int idbits, uint64_t posmask, hipStream_t stream);
+// The key buffer that holds the sorted keys after the radix passes.
+uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits);
 
 }  // namespace mag

@@ -36,6 +36,7 @@
 
 #include "mag_internal.hpp"
 #include "scan_args.hpp"
+#include "scan_common.hpp"
 
 #ifndef MAG_SCAN_Q
 #error "compile with -DMAG_SCAN_Q=<1..8>"
@@ -50,128 +51,8 @@ constexpr int kProducerWaves = kScanProducerWaves;
 constexpr int kConsumerWaves = kNT / 64 - kScanProducerWaves;
 constexpr int kProducerThreads = kProducerWaves * 64;
 constexpr int kQueue = 128;          // per-wave queue of start positions (64-bit)
-constexpr uint32_t kBufferWord3 = 0x00020000u;   // raw 32-bit buffer resource (gfx9)
+using namespace dev;
 
-__device__ __forceinline__ uint32_t ld32(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
-}
-
-// The 32-bit words holding the q bytes of the gram that starts at resource
-// offset p (the third word only for q > 4).
-struct GramWords {
-    uint32_t w0, w1, w2, sh;
-};
-
-__device__ __forceinline__ GramWords gram_words(__amdgpu_buffer_rsrc_t rs, uint32_t p) {
-    GramWords g;
-    const uint32_t a = p & ~3u;
-    g.sh = p & 3;
-    g.w0 = ld32(rs, a);
-    g.w1 = ld32(rs, a + 4);
-    g.w2 = Q > 4 ? ld32(rs, a + 8) : 0u;
-    return g;
-}
-
-// Code of a q-gram: Horner over the mapped bytes, last byte first. With MUL24
-// every partial value is below 2^24 (the host checks sigma'^(q-1) < 2^24), so
-// the full-rate 24-bit multiply-add is exact.
-template <bool MUL24>
-__device__ __forceinline__ uint32_t gram_code(const GramWords &gw, const uint8_t *s_mu, uint32_t sp) {
-    const uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
-    const uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
-    uint32_t g = 0;
-#pragma unroll
-    for (int t = Q - 1; t >= 0; --t) {
-        const uint32_t byte = t < 4 ? __builtin_amdgcn_ubfe(lo, 8 * t, 8)
-                                    : __builtin_amdgcn_ubfe(hi, 8 * (t - 4), 8);
-        const uint32_t c = s_mu[byte];
-        if (t == Q - 1) g = c;
-        else if (MUL24) g = __umul24(g, sp) + c;
-        else g = g * sp + c;
-    }
-    return g;
-}
-
-// Raw buffer resource over [base, base + bytes). The operands are wave-uniform;
-// readfirstlane says so to the compiler, which otherwise may keep them in
-// vector registers and wrap every load in a loop over distinct values.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const uint8_t *base, uint32_t bytes) {
-    const uint64_t b = reinterpret_cast<uint64_t>(base);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
-    const uint32_t n = __builtin_amdgcn_readfirstlane(bytes);
-    void *p = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
-    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)n, (int)kBufferWord3);
-}
-
-// Out-of-line verification of one start position. `v` points at the
-// verification arguments inside the kernel-argument segment (constant
-// address space; the kernel computes it, since only a kernel receives the
-// segment pointer), so they are read on this cold path with scalar loads and
-// occupy no registers in the scan loops.
-typedef const __attribute__((address_space(4))) VerifyArgs KVerifyArgs;
-
-__device__ __attribute__((noinline)) void verify_one(KVerifyArgs *v, uint64_t i0) {
-#if __HIP_DEVICE_COMPILE__
-    VerifyArgs args;
-    __builtin_memcpy(&args, (const VerifyArgs *)v, sizeof(args));
-    verify_start(args, i0);
-#else
-    (void)v;
-    (void)i0;
-#endif
-}
-
-// Verifies the 64 start positions queue[from .. from+64) of this wave, one per
-// lane. The queue is written by other lanes of the same wave.
-__device__ __forceinline__ void drain64(KVerifyArgs *v, const uint64_t *queue, uint32_t from,
-                                        int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint64_t e = queue[from + lane];
-    __builtin_amdgcn_wave_barrier();
-    verify_one(v, e);
-}
-
-// Entry t (runtime index) of a 16-byte vector of mask entries.
-template <typename ET>
-__device__ __forceinline__ ET entry_at(const uint4 &raw, int t) {
-    constexpr int per_word = 4 / (int)(sizeof(ET) < 4 ? sizeof(ET) : 4);
-    if constexpr (sizeof(ET) == 8) {
-        const uint32_t lo = t == 0 ? raw.x : raw.z, hi = t == 0 ? raw.y : raw.w;
-        return (ET)(((uint64_t)hi << 32) | lo);
-    } else {
-        const int w = t / per_word;
-        const uint32_t word = w == 0 ? raw.x : w == 1 ? raw.y : w == 2 ? raw.z : raw.w;
-        return (ET)(word >> (8 * sizeof(ET) * (t % per_word)));
-    }
-}
-
-template <typename ET>
-__device__ __forceinline__ void store4(ET *dst, const ET e[4]) {
-    if constexpr (sizeof(ET) == 1) {
-        *reinterpret_cast<uint32_t *>(dst) = (uint32_t)e[0] | ((uint32_t)e[1] << 8) |
-                                             ((uint32_t)e[2] << 16) | ((uint32_t)e[3] << 24);
-    } else if constexpr (sizeof(ET) == 2) {
-        *reinterpret_cast<uint2 *>(dst) = make_uint2((uint32_t)e[0] | ((uint32_t)e[1] << 16),
-                                                     (uint32_t)e[2] | ((uint32_t)e[3] << 16));
-    } else if constexpr (sizeof(ET) == 4) {
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(e[0], e[1], e[2], e[3]);
-    } else {
-        uint4 *d = reinterpret_cast<uint4 *>(dst);
-        d[0] = make_uint4((uint32_t)e[0], (uint32_t)(e[0] >> 32), (uint32_t)e[1], (uint32_t)(e[1] >> 32));
-        d[1] = make_uint4((uint32_t)e[2], (uint32_t)(e[2] >> 32), (uint32_t)e[3], (uint32_t)(e[3] >> 32));
-    }
-}
-
-// Phase A for one tile: mask entries of samples X0-W0 .. X0+TS-1 into
-// E[s + W0]. Each thread takes G consecutive samples per round; the words of
-// the next round are loaded before the current round's lookups, so global
-// latency overlaps LDS work, and each round's entries leave in G/4 LDS
-// stores. Outside interior tiles, samples before the text or past the last
-// sample get the all-ones (no match) entry. Loads past the tile are
-// range-checked by the buffer resource and their entries are never read.
 #ifndef MAG_SCAN_GROUP
 #define MAG_SCAN_GROUP 4
 #endif
@@ -185,7 +66,7 @@ template <int G>
 __device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, int32_t p0,
                                            int s, uint32_t kq) {
 #pragma unroll
-    for (int u = 0; u < G; ++u) w[u] = gram_words(rs, (uint32_t)(p0 + (s + u) * (int32_t)kq));
+    for (int u = 0; u < G; ++u) w[u] = gram_words<Q>(rs, (uint32_t)(p0 + (s + u) * (int32_t)kq));
 }
 
 template <bool INTERIOR, bool MUL24, bool TLDS, int G, typename ET>
@@ -195,7 +76,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     const ET none = (ET)~(ET)0;
     uint32_t g[G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) g[u] = gram_code<MUL24>(w[u], s_mu, sp);
+    for (int u = 0; u < G; ++u) g[u] = gram_code<Q, MUL24>(w[u], s_mu, sp);
     ET e[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -258,9 +139,9 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool producer = wave < kProducerWaves;
     // the kernel's only argument is `a`, at the start of the argument segment
-    KVerifyArgs *vargs = (KVerifyArgs *)((const __attribute__((address_space(4))) char *)
-                                             __builtin_amdgcn_kernarg_segment_ptr() +
-                                         offsetof(ScanArgs, v));
+    const VerifyArgs *vargs = (const VerifyArgs *)((const __attribute__((address_space(4))) char *)
+                                                       __builtin_amdgcn_kernarg_segment_ptr() +
+                                                   offsetof(ScanArgs, v));
     for (int i = tid; i < 256; i += kNT) s_mu[i] = a.mu[i];
     if (TLDS) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.table);
@@ -268,6 +149,8 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
         for (uint32_t v = tid; v < a.table_vec; v += kNT) dst[v] = src[v];
     }
     const ET *g_tab = reinterpret_cast<const ET *>(a.table);
+    // every wave stages part of the map and the table; producers read all of it
+    __syncthreads();
 
     // consumer state
     const int ct = tid - kProducerThreads;                // consumer lane index

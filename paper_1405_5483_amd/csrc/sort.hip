@@ -1,14 +1,16 @@
 // Canonical output order: occurrences sorted ascending by (pos, id).
 //
-// The scan emits 64-bit keys (pos << idbits | id) in arbitrary order; keys are
-// unique, since every (pos, id) is reported once. The finishing kernel (one
-// workgroup, launched right after the scan) publishes the occurrence count and
-// the work counters, and sorts up to kSmallMax keys in LDS with a bitonic
-// network. Larger outputs are sorted by a stable LSD radix sort with 8-bit
-// digits: either inside the finishing kernel by its one workgroup (when the
-// host does not know the count), or by per-digit histogram / offset / scatter
-// kernels across the whole device that the host enqueues once it has read the
-// count. No kernel waits on another workgroup.
+// The scan emits 64-bit keys (pos << idbits | id, batched scans add the job
+// number above the position) in arbitrary order; keys are unique, since every
+// (pos, id) is reported once. The finishing kernel (one workgroup, launched
+// right after the scan) publishes the occurrence count and the work counters
+// and sorts up to kSmallMax keys in LDS. Larger outputs are sorted by a stable
+// LSD radix sort with 8-bit digits across the whole device: per pass a
+// histogram, a scan of the counts and a scatter kernel. Those kernels read the
+// count from device memory (the finishing kernel leaves it in counters[5]), so
+// they can be enqueued before the host knows it: the grid is sized for an
+// upper bound and workgroups past the real count return at once. No kernel
+// waits on another workgroup.
 #include <hip/hip_runtime.h>
 
 #include "mag_internal.hpp"
@@ -20,8 +22,8 @@ constexpr int kFinishThreads = 1024;
 constexpr uint32_t kSmallMax = 8192;
 constexpr uint32_t kRankMax = 2048;           // rank counting below this, bitonic above
 constexpr int kRadixThreads = 256;
-constexpr uint32_t kRadixChunk = 4096;      // keys per block and pass in the device-wide sort
-constexpr uint32_t kMaxRadixBlocks = 2048;
+constexpr uint32_t kRadixChunk = 4096;        // keys per chunk of the device-wide sort
+constexpr uint32_t kRadixGrid = 1024;         // workgroups per radix kernel (they loop over chunks)
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -34,9 +36,9 @@ __device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ mag_match to_record(uint64_t key, int idbits) {
+__device__ __forceinline__ mag_match to_record(uint64_t key, int idbits, uint64_t posmask) {
     mag_match r;
-    r.pos = key >> idbits;
+    r.pos = (key >> idbits) & posmask;
     r.pattern_id = (uint32_t)(key & ((1ull << idbits) - 1ull));
     r.reserved = 0;
     return r;
@@ -88,23 +90,46 @@ __device__ void stable_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg,
     }
 }
 
+// Exclusive prefix sum over a 256-thread block (one value per thread); the
+// block total goes to *total. s_tmp holds 4 words.
+__device__ uint64_t block_exclusive_scan256(uint64_t v, uint64_t *s_tmp, uint64_t *total) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t o = __shfl_up(inc, off);
+        if (lane >= (uint32_t)off) inc += o;
+    }
+    if (lane == 63) s_tmp[wave] = inc;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint64_t t = s_tmp[w];
+        if (w < (int)wave) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
 struct FinishArgs {
-    uint64_t *keys;        // two buffers of cap keys: [0, cap) holds the scan output
+    const uint64_t *keys;  // the scan's keys, [0, cap)
     uint64_t cap;
     uint64_t *counters;    // read, published, then returned to zero
     uint64_t *d_count;
     mag_stats *d_stats;
     uint64_t samples;
     mag_match *out;
-    int idbits, nbits;
-    int host_sorts;        // large outputs are left to the device-wide sort
+    uint64_t *sorted;      // optional: the sorted keys of small outputs too
+    uint64_t posmask;
+    int idbits;
 };
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
     __shared__ uint64_t s_keys[kSmallMax];
-    __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_wcnt[kFinishThreads / 64][256];
-    __shared__ uint64_t s_off[256];
+    __shared__ uint32_t s_rank[kRankMax];
     const uint32_t tid = threadIdx.x;
     const uint64_t z = a.counters[0];
     const uint64_t cw = a.counters[1], nv = a.counters[2];
@@ -117,19 +142,20 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
             a.d_stats->verifications = nv;
             a.d_stats->matches = z;
         }
-        // leave the counters at zero for the next scan of this plan
+        // the count stays for the device-wide sort; the others return to zero
+        // for the next scan
+        a.counters[kSortCountSlot] = z;
         a.counters[0] = 0;
         a.counters[1] = 0;
         a.counters[2] = 0;
         a.counters[3] = 0;
     }
-    if (z > a.cap || z == 0) return;      // overflow leaves the records unspecified
+    if (z > a.cap || z == 0 || z > kSmallMax) return;
 
     if (z <= kRankMax) {
         // keys are unique: a key's output slot is the number of smaller keys.
         // Each key's count is split over `parts` threads (8 independent sums
         // each, so LDS reads overlap) and combined with LDS atomics.
-        uint32_t *s_rank = reinterpret_cast<uint32_t *>(&s_wcnt[0][0]);   // kRankMax entries
         for (uint32_t i = tid; i < z; i += kFinishThreads) {
             s_keys[i] = a.keys[i];
             s_rank[i] = 0;
@@ -151,120 +177,122 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
             atomicAdd(&s_rank[i], acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5] + acc[6] + acc[7]);
         }
         __syncthreads();
-        for (uint32_t i = tid; i < z; i += kFinishThreads)
-            a.out[s_rank[i]] = to_record(s_keys[i], a.idbits);
-        return;
-    }
-    if (z <= kSmallMax) {
-        uint32_t N = 1;
-        while (N < z) N <<= 1;
-        for (uint32_t i = tid; i < N; i += kFinishThreads) s_keys[i] = i < z ? a.keys[i] : ~0ull;
-        __syncthreads();
-        for (uint32_t k = 2; k <= N; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < N; i += kFinishThreads) {
-                    const uint32_t p = i ^ j;
-                    if (p > i) {
-                        const uint64_t x = s_keys[i], y = s_keys[p];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) { s_keys[i] = y; s_keys[p] = x; }
-                    }
-                }
-                __syncthreads();
-            }
+        for (uint32_t i = tid; i < z; i += kFinishThreads) {
+            a.out[s_rank[i]] = to_record(s_keys[i], a.idbits, a.posmask);
+            if (a.sorted) a.sorted[s_rank[i]] = s_keys[i];
         }
-        for (uint32_t i = tid; i < z; i += kFinishThreads) a.out[i] = to_record(s_keys[i], a.idbits);
         return;
     }
-    if (a.host_sorts) return;
+    uint32_t N = 1;
+    while (N < z) N <<= 1;
+    for (uint32_t i = tid; i < N; i += kFinishThreads) s_keys[i] = i < z ? a.keys[i] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < N; i += kFinishThreads) {
+                const uint32_t p = i ^ j;
+                if (p > i) {
+                    const uint64_t x = s_keys[i], y = s_keys[p];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) { s_keys[i] = y; s_keys[p] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = tid; i < z; i += kFinishThreads) {
+        a.out[i] = to_record(s_keys[i], a.idbits, a.posmask);
+        if (a.sorted) a.sorted[i] = s_keys[i];
+    }
+}
 
-    // one-workgroup LSD radix sort over global memory
-    for (uint32_t v = tid; v < (kFinishThreads / 64) * 256; v += kFinishThreads)
-        (&s_wcnt[0][0])[v] = 0;
-    uint64_t *src = a.keys, *dst = a.keys + a.cap;
-    const int passes = (a.nbits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        if (tid < 256) s_hist[tid] = 0;
+// ---- device-wide LSD radix sort. The count z is read from *zp; every kernel
+// returns at once unless kSmallMax < z <= cap. Keys are cut into chunks of
+// kRadixChunk; cnt and off are digit-major [256][C], C = ceil(z / chunk).
+
+__device__ __forceinline__ bool radix_active(const uint64_t *zp, uint64_t cap, uint64_t *z) {
+    *z = *zp;
+    return *z > kSmallMax && *z <= cap;
+}
+
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *src, const uint64_t *zp,
+                                                              uint64_t cap, int shift, uint32_t *cnt) {
+    __shared__ uint32_t s_hist[256];
+    uint64_t z;
+    if (!radix_active(zp, cap, &z)) return;
+    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        s_hist[tid] = 0;
         __syncthreads();
-        for (uint64_t i = tid; i < z; i += kFinishThreads)
+        const uint64_t beg = c * kRadixChunk;
+        const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
+        for (uint64_t i = beg + tid; i < end; i += kRadixThreads)
             atomicAdd(&s_hist[(src[i] >> shift) & 255u], 1u);
         __syncthreads();
-        if (tid == 0) {
-            uint64_t run = 0;
-            for (int d = 0; d < 256; ++d) {
-                s_off[d] = run;
-                run += s_hist[d];
-            }
-        }
-        __syncthreads();
-        stable_scatter(src, dst, 0, z, shift, s_off, s_wcnt);
-        uint64_t *t = src;
-        src = dst;
-        dst = t;
+        cnt[(size_t)tid * C + c] = s_hist[tid];
         __syncthreads();
     }
-    for (uint64_t i = tid; i < z; i += kFinishThreads) a.out[i] = to_record(src[i], a.idbits);
 }
 
-// ---- device-wide LSD radix sort, one launch per phase and digit
-
-__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *src, uint64_t z,
-                                                              int shift, uint32_t *cnt) {
-    __shared__ uint32_t s_hist[256];
-    const uint32_t g = blockIdx.x, G = gridDim.x, tid = threadIdx.x;
-    s_hist[tid] = 0;
-    __syncthreads();
-    const uint64_t beg = (uint64_t)g * kRadixChunk;
-    const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
-    for (uint64_t i = beg + tid; i < end; i += kRadixThreads)
-        atomicAdd(&s_hist[(src[i] >> shift) & 255u], 1u);
-    __syncthreads();
-    cnt[(size_t)tid * G + g] = s_hist[tid];
-}
-
-// cnt (digit-major, [256][G]) -> exclusive start offsets, in place (64-bit out)
-__global__ __launch_bounds__(256) void k_radix_offsets(const uint32_t *cnt, uint64_t *off, uint32_t G) {
-    __shared__ uint64_t s_tot[256];
-    const uint32_t d = threadIdx.x;
-    uint64_t run = 0;
-    for (uint32_t g = 0; g < G; ++g) run += cnt[(size_t)d * G + g];
-    s_tot[d] = run;
-    __syncthreads();
-    if (d == 0) {
-        uint64_t acc = 0;
-        for (int i = 0; i < 256; ++i) {
-            const uint64_t t = s_tot[i];
-            s_tot[i] = acc;
-            acc += t;
-        }
+// One workgroup per digit d: off[d][c] = sum of cnt[d][c' < c], tot[d] = row sum.
+__global__ __launch_bounds__(256) void k_radix_scan(const uint32_t *cnt, uint64_t *off, uint64_t *tot,
+                                                    const uint64_t *zp, uint64_t cap) {
+    __shared__ uint64_t s_tmp[4];
+    uint64_t z;
+    if (!radix_active(zp, cap, &z)) return;
+    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint32_t d = blockIdx.x, tid = threadIdx.x;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < C; base += 256) {
+        const uint64_t c = base + tid;
+        const uint64_t v = c < C ? cnt[(size_t)d * C + c] : 0;
+        uint64_t part;
+        const uint64_t ex = block_exclusive_scan256(v, s_tmp, &part);
+        if (c < C) off[(size_t)d * C + c] = carry + ex;
+        carry += part;
     }
-    __syncthreads();
-    uint64_t acc = s_tot[d];
-    for (uint32_t g = 0; g < G; ++g) {
-        off[(size_t)d * G + g] = acc;
-        acc += cnt[(size_t)d * G + g];
-    }
+    if (tid == 0) tot[d] = carry;
 }
 
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t *src, uint64_t *dst,
-                                                                 uint64_t z, int shift,
-                                                                 const uint64_t *off) {
+                                                                 const uint64_t *zp, uint64_t cap,
+                                                                 int shift, const uint64_t *off,
+                                                                 const uint64_t *tot) {
+    __shared__ uint64_t s_base[256];
     __shared__ uint64_t s_off[256];
+    __shared__ uint64_t s_tmp[4];
     __shared__ uint32_t s_wcnt[kRadixThreads / 64][256];
-    const uint32_t g = blockIdx.x, G = gridDim.x, tid = threadIdx.x;
-    s_off[tid] = off[(size_t)tid * G + g];
+    uint64_t z;
+    if (!radix_active(zp, cap, &z)) return;
+    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint32_t tid = threadIdx.x;
+    uint64_t all;
+    s_base[tid] = block_exclusive_scan256(tot[tid], s_tmp, &all);
     for (int v = 0; v < kRadixThreads / 64; ++v) s_wcnt[v][tid] = 0;
-    __syncthreads();
-    const uint64_t beg = (uint64_t)g * kRadixChunk;
-    const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
-    stable_scatter(src, dst, beg, end, shift, s_off, s_wcnt);
+    for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        s_off[tid] = s_base[tid] + off[(size_t)tid * C + c];
+        __syncthreads();
+        const uint64_t beg = c * kRadixChunk;
+        const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
+        stable_scatter(src, dst, beg, end, shift, s_off, s_wcnt);
+    }
 }
 
-__global__ void k_expand(const uint64_t *keys, uint64_t z, mag_match *out, int idbits) {
+__global__ void k_expand(const uint64_t *keys, const uint64_t *zp, uint64_t cap, mag_match *out,
+                         int idbits, uint64_t posmask) {
+    uint64_t z;
+    if (!radix_active(zp, cap, &z)) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z; i += stride)
-        out[i] = to_record(keys[i], idbits);
+        out[i] = to_record(keys[i], idbits, posmask);
+}
+
+uint64_t radix_chunks(uint64_t bound) { return (bound + kRadixChunk - 1) / kRadixChunk; }
+
+uint32_t radix_grid(uint64_t bound) {
+    const uint64_t C = radix_chunks(bound);
+    return (uint32_t)(C < kRadixGrid ? (C ? C : 1) : kRadixGrid);
 }
 
 }  // namespace
@@ -280,9 +308,11 @@ mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStr
 
 uint32_t small_sort_max() { return kSmallMax; }
 
+int radix_passes(int nbits) { return (nbits + 7) / 8; }
+
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
-                         mag_stats *d_stats, mag_match *out, int idbits, int nbits, bool host_sorts,
-                         hipStream_t stream) {
+                         mag_stats *d_stats, mag_match *out, int idbits, uint64_t posmask,
+                         uint64_t *sorted, hipStream_t stream) {
     FinishArgs a;
     a.keys = sc.keys;
     a.cap = cap;
@@ -291,59 +321,76 @@ mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *
     a.d_stats = d_stats;
     a.samples = samples;
     a.out = out;
+    a.sorted = sorted;
+    a.posmask = posmask;
     a.idbits = idbits;
-    a.nbits = nbits;
-    a.host_sorts = host_sorts ? 1 : 0;
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "finish launch");
 }
 
-mag_status ensure_radix_scratch(Scratch &sc, uint64_t z) {
-    const uint64_t G = (z + kRadixChunk - 1) / kRadixChunk;
-    if (G > kMaxRadixBlocks * 64ull) return fail(MAG_E_UNSUPPORTED, "too many occurrences to sort");
-    if (sc.radix_blocks >= G && sc.hist) return MAG_OK;
+mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream) {
+    const uint64_t C = radix_chunks(bound);
+    if (sc.radix_chunks >= C && sc.hist) return MAG_OK;
+    hipError_t e = hipStreamSynchronize(stream);     // earlier sorts may still use the old buffers
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     (void)hipFree(sc.hist);
     (void)hipFree(sc.radix_off);
     sc.hist = nullptr;
     sc.radix_off = nullptr;
-    sc.radix_blocks = 0;
-    hipError_t e = hipMalloc(&sc.hist, (size_t)256 * G * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&sc.radix_off, (size_t)256 * G * sizeof(uint64_t));
+    sc.radix_chunks = 0;
+    e = hipMalloc(&sc.hist, (size_t)256 * C * sizeof(uint32_t));
+    // offsets [256][C], then the 256 digit totals
+    if (e == hipSuccess) e = hipMalloc(&sc.radix_off, ((size_t)256 * C + 256) * sizeof(uint64_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(MAG_E_NOMEM, "device allocation of radix counts failed");
     }
-    sc.radix_blocks = G;
+    sc.radix_chunks = C;
     return MAG_OK;
 }
 
-mag_status launch_radix_sort(Scratch &sc, uint64_t z, uint64_t cap, mag_match *out, int idbits,
-                             int nbits, hipStream_t stream) {
-    if (z <= kSmallMax || z > cap) return MAG_OK;    // done by the finishing kernel / overflow
-    mag_status s = ensure_radix_scratch(sc, z);
-    if (s != MAG_OK) return s;
-    const uint32_t G = (uint32_t)((z + kRadixChunk - 1) / kRadixChunk);
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, hipStream_t stream) {
+    if (bound <= kSmallMax) return MAG_OK;
+    if (sc.radix_chunks < radix_chunks(bound) || !sc.hist)
+        return fail(MAG_E_INVALID, "radix scratch smaller than the bound");
+    if (bound > cap) bound = cap;
+    const uint32_t G = radix_grid(bound);
+    const uint64_t *zp = sc.counters + kSortCountSlot;
     uint64_t *src = sc.keys, *dst = sc.keys + cap;
-    const int passes = (nbits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
+    uint64_t *tot = sc.radix_off + (size_t)256 * sc.radix_chunks;
+    for (int p = 0; p < radix_passes(nbits); ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kRadixThreads), 0, stream,
-                           (const uint64_t *)src, z, shift, sc.hist);
-        hipLaunchKernelGGL(k_radix_offsets, dim3(1), dim3(256), 0, stream,
-                           (const uint32_t *)sc.hist, sc.radix_off, G);
+                           (const uint64_t *)src, zp, cap, shift, sc.hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, stream, (const uint32_t *)sc.hist,
+                           sc.radix_off, tot, zp, cap);
         hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kRadixThreads), 0, stream,
-                           (const uint64_t *)src, dst, z, shift, (const uint64_t *)sc.radix_off);
+                           (const uint64_t *)src, dst, zp, cap, shift, (const uint64_t *)sc.radix_off,
+                           (const uint64_t *)tot);
         uint64_t *t = src;
         src = dst;
         dst = t;
     }
-    uint64_t blocks = (z + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_expand, dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint64_t *)src, z, out, idbits);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "radix sort launch");
+}
+
+uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits) {
+    return (radix_passes(nbits) & 1) ? sc.keys + cap : sc.keys;
+}
+
+mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, mag_match *out,
+                         int idbits, uint64_t posmask, hipStream_t stream) {
+    if (bound <= kSmallMax) return MAG_OK;
+    if (bound > cap) bound = cap;
+    uint64_t blocks = (bound + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_expand, dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       (const uint64_t *)sorted_keys(sc, cap, nbits),
+                       (const uint64_t *)(sc.counters + kSortCountSlot), cap, out, idbits, posmask);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "expand launch");
 }
 
 }  // namespace mag

@@ -19,8 +19,9 @@ struct VerifyArgs {
     uint32_t slot_shift, slot_mask, idbits, pad_;
     const uint64_t *slots;     // (hash << 32) | (u + 1), 0 = empty
     const uint32_t *pwords, *idstart, *ids;
-    uint64_t *keys;            // output keys (pos << idbits | id)
+    uint64_t *keys;            // output keys (pos << idbits | id) | key_or
     uint64_t cap;
+    uint64_t key_or;           // batched scans: the job number in the key's top bits
     uint64_t *counters;        // [0] = occurrences found
 };
 
@@ -81,7 +82,7 @@ __device__ inline void verify_start(const VerifyArgs &a, uint64_t i0) {
                                               (unsigned long long)c);
                 for (uint32_t t = 0; t < c; ++t)
                     if (at + t < a.cap)
-                        a.keys[at + t] = (i0 << a.idbits) | (uint64_t)a.ids[b + t];
+                        a.keys[at + t] = a.key_or | (i0 << a.idbits) | (uint64_t)a.ids[b + t];
                 return;     // distinct patterns: at most one can be equal
             }
         }

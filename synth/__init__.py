@@ -168,10 +168,19 @@ def batch_recipes(njobs: int = 512, seed: int = 4, n_log2_range=(12.0, 24.0),
     return out
 
 
+def _job_from_recipe(item) -> Job:
+    rec, ss = item
+    return make_job(rec["n"], rec["sigma"], rec["dist"], rec["r"], rec["m"], rec["frac"], ss)
+
+
 def batch_jobs(njobs: int = 512, seed: int = 4, n_log2_range=(12.0, 24.0),
-               r_log10_range=(1.0, 4.0)) -> list[Job]:
-    jobs = []
-    for rec, ss in batch_recipes(njobs, seed, n_log2_range, r_log10_range):
-        jobs.append(make_job(rec["n"], rec["sigma"], rec["dist"], rec["r"], rec["m"],
-                             rec["frac"], ss))
-    return jobs
+               r_log10_range=(1.0, 4.0), workers: int = 1) -> list[Job]:
+    """The jobs of :func:`batch_recipes`; ``workers > 1`` draws them in that
+    many processes (each job's bytes depend only on its own seed)."""
+    items = batch_recipes(njobs, seed, n_log2_range, r_log10_range)
+    if workers <= 1:
+        return [_job_from_recipe(it) for it in items]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_job_from_recipe, items, chunksize=4))

@@ -1,0 +1,210 @@
+"""Parity of batched scans (many jobs in one persistent launch) against the
+oracle (GPU).
+
+Each job's records, cut out of the shared output by the per-job offsets, must
+equal the oracle's occurrence list of that job's text and pattern set,
+element by element. The cases cover jobs of every kind in one batch (empty
+texts, texts shorter than m, empty pattern sets, a plan shared by two jobs,
+texts at unaligned addresses, mask tables too large for LDS), output
+overflow, the device-wide sort, replays of a captured graph, rebinding, and
+the full 512-job workload.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import match as om
+from synth import batch_jobs, batch_recipes, gen_patterns, gen_text, make_job
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mag():
+    import paper_1405_5483_amd as m
+    return m
+
+
+def _upload(torch, texts, offsets=None):
+    """Device copies of the texts, job j at byte offset offsets[j] of its own
+    buffer (so its address has that alignment)."""
+    out = []
+    for j, t in enumerate(texts):
+        off = offsets[j] if offsets else 0
+        buf = torch.empty(t.size + off + 16, dtype=torch.uint8, device="cuda")
+        view = buf[off:off + t.size]
+        if t.size:
+            view.copy_(torch.from_numpy(t))
+        out.append(view)
+    return out
+
+
+def _check_jobs(results, jobs):
+    for j, (res, job) in enumerate(zip(results, jobs)):
+        occ = res.cpu().numpy()
+        rpos, rids = om.occ_hashed(job.text, job.patterns)
+        assert occ.shape[0] == rpos.size, (j, occ.shape[0], rpos.size, job.recipe)
+        assert np.array_equal(occ[:, 0].astype(np.uint64), rpos), (j, job.recipe)
+        assert np.array_equal(occ[:, 1].astype(np.uint32), rids), (j, job.recipe)
+
+
+def _small_jobs(count, seed, n_log2=(10.0, 17.0), r_log10=(1.0, 3.0)):
+    return [make_job(rec["n"], rec["sigma"], rec["dist"], rec["r"], rec["m"], rec["frac"], ss)
+            for rec, ss in batch_recipes(count, seed, n_log2, r_log10)]
+
+
+def test_batch_mixed_jobs(torch_cuda, mag):
+    torch = torch_cuda
+    jobs = _small_jobs(24, seed=101)
+    # special jobs
+    jobs.append(make_job(0, 4, "uniform", 10, 8, 0.5, 7))                  # empty text
+    jobs.append(make_job(5, 4, "uniform", 10, 8, 0.5, 8))                  # n < m
+    t = gen_text(20_000, 20, rng=9)
+    jobs.append(type(jobs[0])(t, np.zeros((0, 16), np.uint8), {"r": 0}))   # no patterns
+    t = gen_text(300_000, 20, rng=10)
+    p = gen_patterns(t, 400, 16, 300, 20, rng=11)
+    jobs.append(type(jobs[0])(t, p, {"big_table": True}))                  # table read from L2
+    plans = [mag.Plan(j.patterns) for j in jobs[:-1]]
+    plans.append(mag.Plan(jobs[-1].patterns, q=4, k=1, sigma_prime=20))
+    assert plans[-1].info()["table_bytes"] > 32 * 1024
+    # a plan shared by two jobs (same patterns, another text)
+    t2 = gen_text(70_001, jobs[3].recipe["sigma"], rng=12)
+    jobs.append(type(jobs[0])(t2, jobs[3].patterns, {"shared": True}))
+    plans.append(plans[3])
+    offsets = [(7 * j) % 16 for j in range(len(jobs))]
+    texts = _upload(torch, [j.text for j in jobs], offsets)
+    b = mag.Batch(plans)
+    b.bind(texts, 1 << 16)
+    _check_jobs(b.run(), jobs)
+    # a second run of the same binding gives the same lists
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
+def test_batch_overflow_reports_exact_count(torch_cuda, mag):
+    torch = torch_cuda
+    jobs = _small_jobs(6, seed=202)
+    plans = [mag.Plan(j.patterns) for j in jobs]
+    texts = _upload(torch, [j.text for j in jobs])
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    assert total > 16
+    b = mag.Batch(plans)
+    b.bind(texts, 16)
+    out = torch.full((16, 2), -7, dtype=torch.int64, device="cuda")
+    offsets = torch.empty(len(jobs) + 1, dtype=torch.int64, device="cuda")
+    count = torch.empty(1, dtype=torch.int64, device="cuda")
+    b.run_async(out, offsets, count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == total
+    assert int(offsets[-1].item()) == total
+    # run() rebinds with the exact capacity
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
+def test_batch_device_wide_sort(torch_cuda, mag):
+    """Outputs above the finishing kernel's in-LDS limit go through the
+    device-wide radix sort."""
+    torch = torch_cuda
+    jobs = []
+    for s in range(4):
+        jobs.append(make_job(1 << 18, 4, "uniform", 2000, 8, 0.5, 300 + s))
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    assert total > 8192
+    plans = [mag.Plan(j.patterns) for j in jobs]
+    texts = _upload(torch, [j.text for j in jobs], [1, 2, 3, 0])
+    b = mag.Batch(plans)
+    b.bind(texts, total + 100)
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
+def test_batch_graph_replay(torch_cuda, mag):
+    torch = torch_cuda
+    jobs = _small_jobs(12, seed=404)
+    jobs.append(make_job(1 << 17, 4, "uniform", 1500, 8, 0.5, 405))    # > 8192 occurrences in all
+    plans = [mag.Plan(j.patterns) for j in jobs]
+    texts = _upload(torch, [j.text for j in jobs])
+    refs = [om.occ_hashed(j.text, j.patterns) for j in jobs]
+    total = sum(r[0].size for r in refs)
+    cap = total + 64
+    b = mag.Batch(plans)
+    stream = torch.cuda.Stream()
+    b.bind(texts, cap, stream)
+    out = torch.empty((cap, 2), dtype=torch.int64, device="cuda")
+    offsets = torch.empty(len(jobs) + 1, dtype=torch.int64, device="cuda")
+    count = torch.empty(1, dtype=torch.int64, device="cuda")
+    with torch.cuda.stream(stream):
+        b.run_async(out, offsets, count, stream)       # eager warm-up
+    stream.synchronize()
+    eager = (out[:total].clone(), offsets.clone(), count.clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.run_async(out, offsets, count, torch.cuda.current_stream())
+    for rep in range(3):
+        out.fill_(-1)
+        offsets.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(count.item()) == total, rep
+        assert torch.equal(offsets, eager[1]), rep
+        assert torch.equal(out[:total], eager[0]), rep
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        del junk
+    off = offsets.cpu().tolist()
+    _check_jobs([out[off[j]:off[j + 1]] for j in range(len(jobs))], jobs)
+    b.close()
+
+
+def test_batch_rebind_smaller(torch_cuda, mag):
+    torch = torch_cuda
+    jobs_a = _small_jobs(8, seed=505, n_log2=(15.0, 18.0))
+    plans = [mag.Plan(j.patterns) for j in jobs_a]
+    b = mag.Batch(plans)
+    b.bind(_upload(torch, [j.text for j in jobs_a]), 1 << 15)
+    _check_jobs(b.run(), jobs_a)
+    # same pattern sets, shorter texts
+    jobs_b = []
+    for j, job in enumerate(jobs_a):
+        t = gen_text(max(job.n // 5, 1), job.recipe["sigma"], job.recipe["dist"], rng=600 + j)
+        jobs_b.append(type(job)(t, job.patterns, {}))
+    b.bind(_upload(torch, [j.text for j in jobs_b]), 1 << 10)
+    _check_jobs(b.run(), jobs_b)
+    b.close()
+
+
+def test_batch_rejects_wide_plans(torch_cuda, mag):
+    t = gen_text(10_000, 64, rng=1)
+    p = gen_patterns(t, 10, 64, 5, 64, rng=2)
+    plan = mag.Plan(p, q=1, k=1, sigma_prime=64)       # W = 64
+    with pytest.raises(mag.MagError):
+        mag.Batch([plan])
+
+
+def test_batch_full_workload(torch_cuda, mag):
+    """The 512-job workload at full size (about 1.1 GB of text), heuristic
+    parameters: every job's list equals the oracle's."""
+    torch = torch_cuda
+    jobs = batch_jobs(512, workers=16)
+    plans = [mag.Plan(j.patterns) for j in jobs]
+    texts = _upload(torch, [j.text for j in jobs])
+    refs = [om.occ_hashed(j.text, j.patterns) for j in jobs]
+    total = sum(r[0].size for r in refs)
+    b = mag.Batch(plans)
+    b.bind(texts, total + 1024)
+    res = b.run()
+    for j, (occ, (rpos, rids)) in enumerate(zip(res, refs)):
+        occ = occ.cpu().numpy()
+        assert occ.shape[0] == rpos.size, (j, occ.shape[0], rpos.size, jobs[j].recipe)
+        assert np.array_equal(occ[:, 0].astype(np.uint64), rpos), j
+        assert np.array_equal(occ[:, 1].astype(np.uint32), rids), j
+    b.close()

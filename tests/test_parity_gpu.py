@@ -238,8 +238,10 @@ def test_prot1g_full_size(torch_cuda, mag):
         _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
 
 
-def test_async_many_matches_one_workgroup_sort(torch_cuda, mag):
-    # the asynchronous entry point sorts large outputs without the host
+def test_async_many_matches_device_sort(torch_cuda, mag):
+    # the asynchronous entry point sorts large outputs without the host: its
+    # radix kernels are sized for the capacity and read the count on the device.
+    # Two scans in a row, the second with fewer occurrences than the first.
     torch = torch_cuda
     n, m = 60_000, 8
     T = np.full(n, ord("a"), dtype=np.uint8)
@@ -257,6 +259,13 @@ def test_async_many_matches_one_workgroup_sort(torch_cuda, mag):
     z = int(cnt.item())
     occ = out[:z].cpu().numpy()
     _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+    T2 = T[: 40_003]
+    ref2 = om.occ_hashed(T2, P)
+    mag.scan_async(buf[: T2.size], plan, out, cnt)
+    torch.cuda.synchronize()
+    z = int(cnt.item())
+    occ = out[:z].cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref2)
 
 
 def test_autotune_pick_is_exact(torch_cuda, mag):
