@@ -65,6 +65,8 @@ struct mag_batch {
     size_t jobs_bytes = 0;
     uint64_t *d_ranges = nullptr;
     size_t ranges_bytes = 0;
+    uint64_t *d_next = nullptr;      // tile claim counters, one per workgroup
+    size_t next_bytes = 0;
     mag::Scratch sc;
 };
 
@@ -105,6 +107,7 @@ void mag_batch_destroy(mag_batch *b) {
         (void)hipSetDevice(b->device);
         (void)hipFree(b->d_jobs);
         (void)hipFree(b->d_ranges);
+        (void)hipFree(b->d_next);
         (void)hipFree(b->sc.counters);
         (void)hipFree(b->sc.keys);
         (void)hipFree(b->sc.hist);
@@ -260,6 +263,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     if (s != MAG_OK) return s;
     s = grow(&b->d_ranges, &b->ranges_bytes, ranges.size() * sizeof(uint64_t), "tile ranges");
     if (s != MAG_OK) return s;
+    s = grow(&b->d_next, &b->next_bytes, std::max<size_t>(grid, 1) * sizeof(uint64_t), "tile claims");
+    if (s != MAG_OK) return s;
     if (njobs) e = hipMemcpy(b->d_jobs, jobs.data(), njobs * sizeof(JobDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
@@ -289,7 +294,9 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
 
     BatchLaunch bl;
     bl.jobs = b->d_jobs;
+    bl.njobs = njobs;
     bl.ranges = b->d_ranges;
+    bl.next = b->d_next;
     bl.grid = b->grid;
     bl.total_tiles = b->total_tiles;
     bl.counters = sc.counters;

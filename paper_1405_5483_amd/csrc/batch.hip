@@ -113,32 +113,72 @@ __device__ __forceinline__ void phase_a_q(uint32_t esz, uint4 *s_E, __amdgpu_buf
     else phase_a<Q, 4>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
 }
 
-// Verifies the first qn queued starts of this wave, one per lane.
-__device__ __forceinline__ void drain_partial(const VerifyArgs *v, const uint64_t *queue, uint32_t qn,
-                                              int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if ((uint32_t)lane < qn) verify_one(v, queue[lane]);
+constexpr uint64_t kNoTile = ~0ull;
+
+// Wave 0 of a workgroup picks the workgroup with the most unclaimed tiles
+// (other than `me`) and claims one of them; kNoTile when none is left. The
+// claim counters only grow, so a tile is never handed out twice, and once
+// every range is exhausted it stays so.
+__device__ uint64_t steal_tile(uint64_t *next, const uint64_t *ranges, uint32_t G, uint32_t me,
+                               int lane) {
+    for (;;) {
+        uint64_t best = 0;                       // (remaining << 16) | workgroup
+        for (uint32_t base = 0; base < G; base += 64) {
+            const uint32_t v = base + (uint32_t)lane;
+            if (v < G && v != me) {
+                const uint64_t nx = __hip_atomic_load(&next[v], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t end = ranges[3 * v + 1];
+                const uint64_t rem = nx < end ? end - nx : 0;
+                const uint64_t key = (rem << 16) | v;
+                if (rem && key > best) best = key;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = __shfl_xor(best, off);
+            best = o > best ? o : best;
+        }
+        if (best == 0) return kNoTile;
+        const uint32_t v = (uint32_t)(best & 0xFFFF);
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd((unsigned long long *)&next[v], 1ull);
+        c = __shfl(c, 0);
+        if (c < ranges[3 * v + 1]) return c;
+    }
 }
 
-__global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs, uint32_t njobs,
                                                const uint64_t *__restrict__ ranges,
-                                               uint64_t *counters) {
+                                               uint64_t *next, uint64_t *counters) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *s_mu = smem;
-    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256);
-    uint4 *s_E = reinterpret_cast<uint4 *>(smem + 256 + kWaves * kBatchQueue * 8);
-    uint8_t *s_tab = smem + 256 + kWaves * kBatchQueue * 8 + kBatchEntryBytes;
+    uint64_t *s_ctl = reinterpret_cast<uint64_t *>(smem + 256);          // claimed tiles, 2 slots
+    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256 + 16);
+    uint4 *s_E = reinterpret_cast<uint4 *>(smem + 256 + 16 + kWaves * kBatchQueue * 8);
+    uint8_t *s_tab = smem + 256 + 16 + kWaves * kBatchQueue * 8 + kBatchEntryBytes;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *queue = s_queue + wave * kBatchQueue;
     uint32_t qn = 0;
     uint64_t ncand = 0, nver = 0;
+    const uint32_t me = blockIdx.x, G = gridDim.x;
+    const uint64_t own_end = uni64(ranges[3 * me + 1]);
+    bool own_done = false;
 
-    const uint64_t g0 = uni64(ranges[3 * blockIdx.x]);
-    const uint64_t g1 = uni64(ranges[3 * blockIdx.x + 1]);
-    const uint32_t first_job = uni32((uint32_t)ranges[3 * blockIdx.x + 2]);
+    // first tile
+    if (wave == 0) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd((unsigned long long *)&next[me], 1ull);
+        c = __shfl(c, 0);
+        uint64_t t = c;
+        if (c >= own_end) {
+            own_done = true;
+            t = steal_tile(next, ranges, G, me, lane);
+        }
+        if (lane == 0) s_ctl[0] = t;
+    }
+    __syncthreads();
 
     // the current job, in scalar registers
     int cur = -1;
@@ -148,15 +188,27 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
     uint64_t delta = 0, n = 0, X = 0, tfirst = 0, tend = 0;
     uint32_t q = 1, k = 1, kq = 1, mprime = 1, W = 1, sp = 1, esz = 1, w0 = 0, tlds = 0, m = 1;
 
-    for (uint64_t g = g0; g < g1; ++g) {
-        if (cur < 0 || g >= tend) {
+    for (uint32_t slot = 0;; slot ^= 1) {
+        const uint64_t g = uni64(s_ctl[slot]);
+        if (g == kNoTile) break;
+        // wave 0 asks for the next tile now and settles the claim after phase A
+        unsigned long long pending = 0;
+        if (wave == 0 && !own_done && lane == 0)
+            pending = atomicAdd((unsigned long long *)&next[me], 1ull);
+        if (cur < 0 || g < tfirst || g >= tend) {
             if (cur >= 0 && qn) {
                 drain_partial(vp, queue, qn, lane);   // starts of the previous job
                 qn = 0;
             }
-            uint32_t j = cur < 0 ? first_job : (uint32_t)cur + 1;
-            while (jobs[j].tile_first + jobs[j].ntiles <= g) ++j;   // skips jobs without tiles
-            j = uni32(j);
+            // the job holding tile g: the last one whose first tile is <= g
+            // (jobs without tiles share their first tile with the next job)
+            uint32_t lo = 0, hi = njobs - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (jobs[mid].tile_first <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t j = uni32(lo);
             const JobDesc &J = jobs[j];
             cur = (int)j;
             vp = &J.v;
@@ -209,6 +261,16 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
             case 6: phase_a_q<6>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
             case 7: phase_a_q<7>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
             default: phase_a_q<8>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+        }
+        if (wave == 0) {
+            uint64_t t = kNoTile;
+            if (!own_done) {
+                const uint64_t c = __shfl(pending, 0);
+                if (c < own_end) t = c;
+                else own_done = true;
+            }
+            if (t == kNoTile) t = steal_tile(next, ranges, G, me, lane);
+            if (lane == 0) s_ctl[slot ^ 1] = t;
         }
         __syncthreads();
 
@@ -280,6 +342,12 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
     if (lane == 0 && nv) atomicAdd((unsigned long long *)&counters[2], nv);
 }
 
+// Claim counters back to the first tile of each workgroup's range.
+__global__ void k_batch_init(const uint64_t *ranges, uint64_t *next, uint32_t G) {
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < G) next[w] = ranges[3 * w];
+}
+
 // offsets[j] = first record of job j (binary search of the sorted keys on the
 // job field), offsets[njobs] = the count. One thread per entry.
 __global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
@@ -327,8 +395,10 @@ int batch_occupancy() {
 
 mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
     if (!b.total_tiles || !b.grid) return MAG_OK;
-    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), kBatchLdsBytes, stream, b.jobs, b.ranges,
-                       b.counters);
+    hipLaunchKernelGGL(k_batch_init, dim3((b.grid + 255) / 256), dim3(256), 0, stream, b.ranges,
+                       b.next, b.grid);
+    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), kBatchLdsBytes, stream, b.jobs, b.njobs,
+                       b.ranges, b.next, b.counters);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "batch scan launch");
 }

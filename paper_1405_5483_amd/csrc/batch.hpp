@@ -18,8 +18,9 @@ constexpr int kBatchQueue = 128;                 // per-wave queue of start posi
 constexpr uint32_t kBatchEntryBytes =
     ((kBatchTileSamples + kBatchMaxWarm) * 4 + 127) / 128 * 128;
 constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
+// alphabet map, two claimed-tile slots, queues, entries, table
 constexpr uint32_t kBatchLdsBytes =
-    256 + (kBatchThreads / 64) * kBatchQueue * 8 + kBatchEntryBytes + kBatchTableLds;
+    256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + kBatchEntryBytes + kBatchTableLds;
 
 // One job as the kernel sees it. Written by the host at bind time.
 struct JobDesc {
@@ -38,7 +39,9 @@ struct JobDesc {
 
 struct BatchLaunch {
     const JobDesc *jobs;
+    uint32_t njobs;
     const uint64_t *ranges;    // per workgroup: first tile, end tile, job of the first tile
+    uint64_t *next;            // per workgroup: next unclaimed tile of its range
     uint32_t grid;
     uint64_t total_tiles;
     uint64_t *counters;

@@ -272,12 +272,7 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     }
     if (!producer) {
         // starts still queued
-        if (qn) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if ((uint32_t)lane < qn) verify_one(vargs, queue[lane]);
-        }
+        if (qn) drain_partial(vargs, queue, qn, lane);
         if (lane == 0 && ncand)
             atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)ncand);
         unsigned long long nv = nver;

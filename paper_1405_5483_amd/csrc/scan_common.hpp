@@ -67,14 +67,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const uint8_t *base,
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)n, (int)kBufferWord3);
 }
 
-// Out-of-line verification of one start position. `v` points at the
-// verification arguments in memory (the scan kernel passes their place in its
-// kernel-argument segment; only a kernel receives that segment's pointer), so
-// they are read on this cold path and occupy no registers in the scan loops.
-__device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v, uint64_t i0) {
+// Out-of-line verification of the start positions of a wave, one per lane
+// (lanes with active false only take part in the wave's output reservation;
+// every lane must call it). `v` points at the verification arguments in
+// memory (the scan kernel passes their place in its kernel-argument segment,
+// the batched kernel its job table), so they are read on this cold path and
+// occupy no registers in the scan loops.
+__device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v, uint64_t i0,
+                                                            bool active) {
     VerifyArgs args;
     __builtin_memcpy(&args, v, sizeof(args));
-    verify_start(args, i0);
+    verify_wave(args, i0, active);
 }
 
 // Verifies the 64 start positions queue[from .. from+64) of this wave, one per
@@ -86,7 +89,19 @@ __device__ __forceinline__ void drain64(const VerifyArgs *v, const uint64_t *que
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const uint64_t e = queue[from + lane];
     __builtin_amdgcn_wave_barrier();
-    verify_one(v, e);
+    verify_one(v, e, true);
+}
+
+// Verifies the first qn queued starts of this wave (qn < 64).
+__device__ __forceinline__ void drain_partial(const VerifyArgs *v, const uint64_t *queue, uint32_t qn,
+                                              int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const bool active = (uint32_t)lane < qn;
+    const uint64_t e = active ? queue[lane] : 0ull;
+    __builtin_amdgcn_wave_barrier();
+    verify_one(v, e, active);
 }
 
 // Entry t (runtime index) of a 16-byte vector of mask entries.

@@ -39,8 +39,9 @@ __device__ __forceinline__ uint32_t gword(const VerifyArgs &a, uint64_t off) {
     return *reinterpret_cast<const uint32_t *>(a.tbase + off);
 }
 
-// Verifies start position i0 and emits every (i0, id) occurrence.
-__device__ inline void verify_start(const VerifyArgs &a, uint64_t i0) {
+// Index + 1 of the distinct pattern that equals the window at start position
+// i0, or 0 if none does.
+__device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
     const uint64_t p = a.delta + i0;
     const uint64_t base = p & ~3ull;
     const uint32_t sh = (uint32_t)(p & 3);
@@ -63,7 +64,7 @@ __device__ inline void verify_start(const VerifyArgs &a, uint64_t i0) {
     uint32_t slot = h >> a.slot_shift;
     for (;;) {
         const uint64_t e = a.slots[slot];
-        if (e == 0) return;
+        if (e == 0) return 0;
         if ((uint32_t)(e >> 32) == h) {
             const uint32_t u = (uint32_t)e - 1u;
             const uint32_t *pw = a.pwords + (size_t)u * a.mw;
@@ -76,19 +77,60 @@ __device__ inline void verify_start(const VerifyArgs &a, uint64_t i0) {
                 if (t == a.mw - 1) x &= a.lastmask;
                 if (x != pw[t]) { eq = false; break; }
             }
-            if (eq) {
-                const uint32_t b = a.idstart[u], c = a.idstart[u + 1] - b;
-                const uint64_t at = atomicAdd((unsigned long long *)&a.counters[0],
-                                              (unsigned long long)c);
-                for (uint32_t t = 0; t < c; ++t)
-                    if (at + t < a.cap)
-                        a.keys[at + t] = a.key_or | (i0 << a.idbits) | (uint64_t)a.ids[b + t];
-                return;     // distinct patterns: at most one can be equal
-            }
+            if (eq) return u + 1;     // distinct patterns: at most one can be equal
         }
         slot = (slot + 1) & a.slot_mask;
     }
 }
 
+// Verifies the start positions of the wave's lanes that have `active` set
+// and emits every (i0, id) occurrence, reserving output room with one atomic
+// add per wave so that outputs with many occurrences do not serialize on the
+// counter. With all 64 lanes executing (the scan kernels call it so) a wave
+// prefix sum gives each lane its slots at once; otherwise round t writes the
+// t-th id of each lane's run of equal patterns, from ballots only.
+__device__ inline void verify_wave(const VerifyArgs &a, uint64_t i0, bool active) {
+    const uint32_t u1 = active ? find_pattern(a, i0) : 0u;
+    uint32_t b = 0, c = 0;
+    if (u1) {
+        b = a.idstart[u1 - 1];
+        c = a.idstart[u1] - b;
+    }
+    const uint64_t exec = __ballot(true);
+    const uint32_t lane = __lane_id();
+    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    if (exec == ~0ull) {
+        uint32_t inc = c;                     // inclusive prefix of c over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane >= (uint32_t)off) inc += o;
+        }
+        const uint32_t total = __shfl(inc, 63);
+        if (total == 0) return;
+        unsigned long long base = 0;
+        if (lane == 63) base = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)total);
+        base = __shfl(base, 63);
+        const uint64_t at = base + inc - c;
+        for (uint32_t t = 0; t < c; ++t)
+            if (at + t < a.cap) a.keys[at + t] = emit | (uint64_t)a.ids[b + t];
+        return;
+    }
+    const uint32_t first = (uint32_t)__builtin_ctzll(exec);
+    for (uint32_t t = 0;; ++t) {
+        const bool has = t < c;
+        const uint64_t mask = __ballot(has);
+        if (!mask) break;
+        unsigned long long base = 0;
+        if (lane == first)
+            base = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)__popcll(mask));
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        if (has) {
+            const uint64_t at = (((uint64_t)hi << 32) | lo) + lanes_below(mask);
+            if (at < a.cap) a.keys[at] = emit | (uint64_t)a.ids[b + t];
+        }
+    }
+}
 
 }  // namespace mag
