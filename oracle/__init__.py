@@ -14,4 +14,6 @@ it.
   candidate windows, plus the class-density estimate of Section 2.
 * ``oracle.mlp``    - float64 forward/backward/Adam of the parameter-selector
   MLP (no counterpart in the paper; pinned by finite differences).
+* ``oracle.selector`` - the selector's pattern-set features and its grid of
+  candidate (q, k, sigma') triples (pinned by hand-computed small cases).
 """
