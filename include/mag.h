@@ -53,8 +53,8 @@ typedef enum {
     MAG_SELECT_HEURISTIC = 0, /* q = log_sigma(rm), k from Section 3.2, sigma'
                                  lowered until the mask table fits the budget */
     MAG_SELECT_EXPLICIT = 1,  /* q, k, sigma_prime taken from mag_params       */
-    MAG_SELECT_LEARNED = 2,   /* argmin of the selector network's predicted
-                                 cost over feasible triples; heuristic fallback */
+    MAG_SELECT_LEARNED = 2,   /* a pick of mag_select_learned: q, k, sigma_prime
+                                 as it filled them; all zero = the heuristic   */
     MAG_SELECT_AUTOTUNE = 3   /* measured on the device over a small grid      */
 } mag_select;
 
@@ -175,6 +175,82 @@ mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const
  * *d_count still hold the exact total and the records are unspecified. */
 mag_status mag_batch_run_async(mag_batch *batch, mag_match *d_out, uint64_t *d_offsets,
                                uint64_t *d_count, void *stream);
+
+/* ---- learned parameter selection ----
+ *
+ * The paper fixes q and k by formulas (Section 3.2) and lowers sigma' until
+ * the sigma'^q table fits (Section 3.3). The selector predicts instead, from
+ * 16 statistics of the pattern set, the scan cost per text byte of each
+ * triple of a fixed grid of 64 (q, k, sigma') candidates, with a small
+ * network (16 -> 64 ReLU -> 64 ReLU -> 64, FP32) whose forward, gradient,
+ * Adam and selection kernels run on the device; it takes the cheapest
+ * feasible candidate and falls back to the heuristic.
+ *
+ * Features (host floats): f0 log2(sigma_P)/8, f1 m/32, f2 log10(r)/4, f3 byte
+ * entropy/8, f4 largest byte frequency, f5 distinct patterns / r, f5+q for
+ * q = 1..8 min(1, -log2(D_q / sigma_P^q)/32) with D_q the distinct q-byte
+ * substrings of the patterns (1 if q > m, 0 if sigma_P = 1), f14 heuristic
+ * q/8, f15 log2(r*m)/20.
+ *
+ * Candidate c < 64: q = c/8 + 1, k = (c/2)%4 + 1; feasible iff 2q-1 <= m,
+ * k <= L and W = k*m' <= 32; sigma' = fit (even c) or max(2, fit/2) (odd c,
+ * infeasible when equal to fit), fit = the largest s <= sigma_P with
+ * s^q * entry_bytes(W) <= 64 KiB; greedy map. Feasible picks also run in
+ * batches (W <= 32). */
+
+/* out: 16 floats. Errors: r == 0 or m == 0 -> MAG_E_INVALID. */
+mag_status mag_select_features(const uint8_t *patterns, uint32_t r, uint32_t m, float *out);
+
+/* out[64] parameters (select = explicit) and feasible[64] (1 or 0). */
+mag_status mag_select_candidates(const uint8_t *patterns, uint32_t r, uint32_t m,
+                                 mag_params *out, uint8_t *feasible);
+
+typedef struct mag_mlp mag_mlp;
+
+/* Number of FP32 parameters: W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], rows are output units. */
+uint32_t mag_mlp_param_count(void);
+
+/* A network on the current device, parameters zero. */
+mag_status mag_mlp_create(mag_mlp **out);
+void mag_mlp_destroy(mag_mlp *mlp);
+
+/* Host copies of the parameters; setting them also clears the Adam state. */
+mag_status mag_mlp_set_params(mag_mlp *mlp, const float *params);
+mag_status mag_mlp_get_params(mag_mlp *mlp, float *params);
+
+/* d_y[B][64] = network(d_x[B][16]). */
+mag_status mag_mlp_forward(mag_mlp *mlp, const float *d_x, uint32_t B, float *d_y, void *stream);
+
+/* Gradient of the masked mean squared error sum M (y - t)^2 / sum M over
+ * the batch (d_t [B][64] targets, d_mask [B][64] of 0/1) into d_grad
+ * (param_count floats) and the loss into *d_loss (device float); zero when
+ * nothing is labelled. */
+mag_status mag_mlp_grad(mag_mlp *mlp, const float *d_x, const float *d_t, const uint8_t *d_mask,
+                        uint32_t B, float *d_grad, float *d_loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
+ * network's own step counter) with gradient d_grad. */
+mag_status mag_mlp_adam(mag_mlp *mlp, const float *d_grad, float lr, void *stream);
+
+/* mag_mlp_grad into the network's own buffer, then mag_mlp_adam. d_loss may
+ * be NULL. */
+mag_status mag_mlp_train_step(mag_mlp *mlp, const float *d_x, const float *d_t,
+                              const uint8_t *d_mask, uint32_t B, float lr, float *d_loss,
+                              void *stream);
+
+/* d_pick[b] = the feasible candidate (d_feasible [B][64] of 0/1) with the
+ * smallest predicted cost, lowest index on ties; -1 if none is feasible. */
+mag_status mag_mlp_select(mag_mlp *mlp, const float *d_x, const uint8_t *d_feasible, uint32_t B,
+                          int32_t *d_pick, void *stream);
+
+/* Features, candidates and one selection for a pattern set (waits for the
+ * stream). *out receives the pick with select = MAG_SELECT_LEARNED, or the
+ * heuristic (select = MAG_SELECT_HEURISTIC) when mlp is NULL or has no
+ * parameters, r == 0 or no candidate is feasible. Pass *out to
+ * mag_plan_create. */
+mag_status mag_select_learned(mag_mlp *mlp, const uint8_t *patterns, uint32_t r, uint32_t m,
+                              mag_params *out, void *stream);
 
 /* Options of mag_autotune (NULL = defaults). */
 typedef struct {

@@ -21,8 +21,9 @@ import numpy as np
 from ._lib import (MAG_E_OVERFLOW, MAP_KIND, SELECT, MagError, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
-__all__ = ["Plan", "Batch", "scan", "scan_async", "scan_batch", "autotune", "profile_enable",
-           "profile_read", "MagError", "lib"]
+__all__ = ["Plan", "Batch", "Selector", "scan", "scan_async", "scan_batch", "autotune",
+           "select_features", "select_candidates", "profile_enable", "profile_read", "MagError",
+           "lib"]
 
 _ENTRY_DTYPE = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
 
@@ -46,9 +47,10 @@ class Plan:
 
     def __init__(self, patterns, *, select: str = "heuristic", q: int | None = None,
                  k: int | None = None, sigma_prime: int | None = None,
-                 map_kind: str = "greedy", table_budget: int = 0):
+                 map_kind: str = "greedy", table_budget: int = 0, candidate: int | None = None):
         p = _as_patterns(patterns)
         self.r, self.m = int(p.shape[0]), int(p.shape[1])
+        self.candidate = candidate        # selector grid index of a learned pick (informational)
         prm = MagParams()
         if q is not None or k is not None or sigma_prime is not None:
             if select == "heuristic":
@@ -286,3 +288,162 @@ def autotune(patterns, sample, *, map_kinds: int = 0, max_q: int = 0, max_k: int
           "mag_autotune")
     return {"q": best.q, "k": best.k, "sigma_prime": best.sigma_prime,
             "map_kind": _MAP_NAME[best.map_kind], "sample_ms": ms.value}
+
+
+# ------------------------------------------------------------------ learned selection
+
+SEL_FEATURES = 16
+SEL_CANDIDATES = 64
+
+
+def select_features(patterns) -> np.ndarray:
+    """The selector's 16 features of a pattern set (``mag_select_features``)."""
+    p = _as_patterns(patterns)
+    out = np.empty(SEL_FEATURES, dtype=np.float32)
+    check(lib().mag_select_features(p.ctypes.data if p.size else None, p.shape[0], p.shape[1],
+                                    out.ctypes.data), "mag_select_features")
+    return out
+
+
+def select_candidates(patterns):
+    """The 64 candidate triples of a set: list of (q, k, sigma') or None."""
+    p = _as_patterns(patterns)
+    prm = (MagParams * SEL_CANDIDATES)()
+    feas = np.zeros(SEL_CANDIDATES, dtype=np.uint8)
+    check(lib().mag_select_candidates(p.ctypes.data if p.size else None, p.shape[0], p.shape[1],
+                                      ctypes.cast(prm, ctypes.c_void_p), feas.ctypes.data),
+          "mag_select_candidates")
+    return [(prm[c].q, prm[c].k, prm[c].sigma_prime) if feas[c] else None
+            for c in range(SEL_CANDIDATES)]
+
+
+class Selector:
+    """The learned parameter selector (``mag_mlp_*``): 16 features -> 64 ReLU ->
+    64 ReLU -> predicted cost of each of the 64 candidate triples."""
+
+    def __init__(self, params=None):
+        h = ctypes.c_void_p()
+        self._h = None
+        check(lib().mag_mlp_create(ctypes.byref(h)), "mag_mlp_create")
+        self._h = h
+        self.n_params = int(lib().mag_mlp_param_count())
+        if params is not None:
+            self.set_params(params)
+
+    @classmethod
+    def load(cls, path: str | None = None) -> "Selector":
+        """The trained network shipped with the package (or the .npz at path)."""
+        import os
+        path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.npz")
+        with np.load(path, allow_pickle=False) as z:
+            return cls(z["params"])
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("selector is closed")
+        return self._h
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        check(lib().mag_mlp_set_params(self.handle, p.ctypes.data), "mag_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, dtype=np.float32)
+        check(lib().mag_mlp_get_params(self.handle, p.ctypes.data), "mag_mlp_get_params")
+        return p
+
+    def forward(self, x, stream=None):
+        """x: float32 CUDA tensor [B, 16] -> [B, 64] predicted costs."""
+        import torch
+        y = torch.empty((x.shape[0], SEL_CANDIDATES), dtype=torch.float32, device=x.device)
+        check(lib().mag_mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                    ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)),
+              "mag_mlp_forward")
+        return y
+
+    def grad(self, x, t, mask, stream=None):
+        """Gradient and loss of the masked mean squared error (CUDA tensors)."""
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        check(lib().mag_mlp_grad(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+                                 x.shape[0], ctypes.c_void_p(g.data_ptr()),
+                                 ctypes.c_void_p(loss.data_ptr()), _stream_ptr(stream)),
+              "mag_mlp_grad")
+        return g, loss
+
+    def adam(self, grad, lr: float, stream=None) -> None:
+        check(lib().mag_mlp_adam(self.handle, ctypes.c_void_p(grad.data_ptr()), float(lr),
+                                 _stream_ptr(stream)), "mag_mlp_adam")
+
+    def train_step(self, x, t, mask, lr: float, loss=None, stream=None) -> None:
+        check(lib().mag_mlp_train_step(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(t.data_ptr()),
+                                       ctypes.c_void_p(mask.data_ptr()), x.shape[0], float(lr),
+                                       ctypes.c_void_p(loss.data_ptr()) if loss is not None else None,
+                                       _stream_ptr(stream)), "mag_mlp_train_step")
+
+    def select(self, x, feasible, stream=None):
+        """Per row the cheapest feasible candidate (int32 CUDA tensor, -1 if none)."""
+        import torch
+        pick = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
+        check(lib().mag_mlp_select(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(feasible.data_ptr()), x.shape[0],
+                                   ctypes.c_void_p(pick.data_ptr()), _stream_ptr(stream)),
+              "mag_mlp_select")
+        return pick
+
+    def pick(self, patterns, stream=None) -> dict:
+        """Parameters for one set (``mag_select_learned``), ready for :class:`Plan`."""
+        p = _as_patterns(patterns)
+        out = MagParams()
+        check(lib().mag_select_learned(self.handle, p.ctypes.data if p.size else None, p.shape[0],
+                                       p.shape[1], ctypes.byref(out), _stream_ptr(stream)),
+              "mag_select_learned")
+        if out.select == SELECT["learned"]:
+            return {"q": out.q, "k": out.k, "sigma_prime": out.sigma_prime, "map_kind": "greedy",
+                    "select": "learned"}
+        return {"select": "heuristic"}
+
+    def picks(self, pattern_sets, threads: int = 16, stream=None) -> list[dict]:
+        """Parameters for many sets: features on host threads, one selection
+        launch for all of them."""
+        import concurrent.futures as cf
+        import torch
+        sets = [_as_patterns(p) for p in pattern_sets]
+
+        def prep(p):
+            if p.shape[0] == 0:
+                return np.zeros(SEL_FEATURES, np.float32), [None] * SEL_CANDIDATES
+            return select_features(p), select_candidates(p)
+        with cf.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+            prepped = list(ex.map(prep, sets))
+        X = np.stack([f for f, _ in prepped]).astype(np.float32)
+        F = np.array([[c is not None for c in cand] for _, cand in prepped], dtype=np.uint8)
+        xd = torch.from_numpy(X).cuda()
+        fd = torch.from_numpy(F).cuda()
+        pk = self.select(xd, fd, stream).cpu().numpy()
+        out = []
+        for (_, cand), c in zip(prepped, pk):
+            if c < 0:
+                out.append({"select": "heuristic"})
+            else:
+                q, k, sp = cand[c]
+                out.append({"q": q, "k": k, "sigma_prime": sp, "map_kind": "greedy",
+                            "select": "learned", "candidate": int(c)})
+        return out
+
+    def close(self):
+        if self._h is not None:
+            lib().mag_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -84,6 +84,30 @@ SIGNATURES = {
                                       ctypes.c_uint64, ctypes.c_void_p]),
     "mag_batch_run_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_select_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_void_p]),
+    "mag_select_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_param_count": (ctypes.c_uint32, []),
+    "mag_mlp_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
+    "mag_mlp_destroy": (None, [ctypes.c_void_p]),
+    "mag_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                                    ctypes.c_void_p]),
+    "mag_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.c_float,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_mlp_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_select_learned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.POINTER(MagParams),
+                                          ctypes.c_void_p]),
     "mag_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.POINTER(MagTuneOpts), ctypes.c_void_p, ctypes.c_uint64,
                                     ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_float),

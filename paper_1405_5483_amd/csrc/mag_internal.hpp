@@ -99,6 +99,10 @@ mag_status hip_fail(hipError_t e, const char *what);
 // first use; fails if the plan lives on another device (capi.cpp).
 mag_status ensure_device(mag_plan *p);
 
+// q of the fixed heuristic: log base max(sigma, 2) of r*m, rounded half up,
+// clamped to [1, min((m+1)/2, kMaxQ)] (plan.cpp).
+int heuristic_q(int sigma, uint32_t r, uint32_t m);
+
 // Host plan builder (plan.cpp).
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
                       const mag_params *params);

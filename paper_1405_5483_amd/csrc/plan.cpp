@@ -76,7 +76,7 @@ void heuristic(const mag_plan *p, int budget, int &q, int &k, int &sp) {
     }
     const double s = std::max(sigma, 2);
     const double lg = std::log((double)p->r * p->m) / std::log(s);   // log_sigma(rm)
-    q = std::max(1, std::min({round_half_up(lg), (int)(p->m + 1) / 2, kMaxQ}));
+    q = heuristic_q(sigma, p->r, p->m);
     const int L = ((int)p->m - q + 1) / q;
     const double rho = lg / p->m;
     if (rho >= 1.0 || lg <= 0) {
@@ -159,6 +159,12 @@ void build_verifier(mag_plan *p) {
 
 }  // namespace
 
+int heuristic_q(int sigma, uint32_t r, uint32_t m) {
+    const double s = std::max(sigma, 2);
+    const double lg = std::log((double)r * m) / std::log(s);   // log_sigma(rm)
+    return std::max(1, std::min({round_half_up(lg), (int)(m + 1) / 2, kMaxQ}));
+}
+
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
                       const mag_params *params) {
     mag_params prm;
@@ -180,10 +186,17 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
 
     int q, k, sp;
     switch (prm.select) {
+        case MAG_SELECT_LEARNED:    // a pick resolved by mag_select_learned
+            if (prm.q > 0 && prm.k > 0 && prm.sigma_prime > 0) {
+                q = prm.q;
+                k = prm.k;
+                sp = prm.sigma_prime;
+                break;
+            }
+            heuristic(p, prm.table_budget > 0 ? prm.table_budget : kDefaultTableBudget, q, k, sp);
+            break;
         case MAG_SELECT_HEURISTIC:
-        case MAG_SELECT_LEARNED:
-        case MAG_SELECT_AUTOTUNE:   // the C library resolves these two as the heuristic;
-                                    // the Python layer passes its picks as explicit
+        case MAG_SELECT_AUTOTUNE:   // mag_autotune returns its pick as explicit parameters
             heuristic(p, prm.table_budget > 0 ? prm.table_budget : kDefaultTableBudget, q, k, sp);
             break;
         case MAG_SELECT_EXPLICIT:

@@ -1,0 +1,243 @@
+"""Training data, training and evaluation of the learned parameter selector.
+
+    python -m paper_1405_5483_amd.train_selector collect --sets 20000 --out data.npz
+    python -m paper_1405_5483_amd.train_selector train data.npz [more.npz ...] --model selector_model.npz
+    python -m paper_1405_5483_amd.train_selector evaluate --model selector_model.npz --sets 2000
+
+collect: pattern sets drawn like the batched workload's (sigma in {4, 20, 64},
+uniform or Zipf(1.0) text, r log-uniform over 10..10^4, m in {8, 16, 32},
+half of the set sampled from its text), against six 16 MiB training texts
+(one per sigma and distribution). For each set, ``--per-set`` random
+feasible candidates of the grid are timed: the scan kernel's device time
+(HIP events around it), the smaller of two runs, as log2 nanoseconds per
+text byte. Set seeds come from SeedSequence(5) and text seeds from
+SeedSequence(5) too (a separate spawn).
+
+train: the network (16 -> 64 -> 64 -> 64) is trained on the device by the
+library's own gradient and Adam kernels, on targets standardized over the
+training labels, with the masked squared error over the timed candidates.
+
+evaluate: held-out sets (SeedSequence(6)) over six 64 MiB texts: each set is
+scanned with the fixed heuristic's parameters and with the network's pick;
+reports the geometric-mean speedup, the win rate and the total times, and
+checks that both scans find the same number of occurrences.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_MODEL = os.path.join(HERE, "selector_model.npz")
+TEXT_KINDS = [(4, "uniform"), (4, "zipf"), (20, "uniform"), (20, "zipf"), (64, "uniform"), (64, "zipf")]
+
+
+def _import():
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import synth
+    import paper_1405_5483_amd as mag
+    return torch, synth, mag
+
+
+def make_texts(synth, n: int, seed: int):
+    kids = np.random.SeedSequence(seed).spawn(len(TEXT_KINDS))
+    return [synth.gen_text(n, s, d, rng=np.random.Generator(np.random.PCG64(k)))
+            for (s, d), k in zip(TEXT_KINDS, kids)]
+
+
+def set_recipes(count: int, seed: int):
+    """(text index, r, m, generator seed) per pattern set."""
+    ss = np.random.SeedSequence([seed, 1])
+    out = []
+    for child in ss.spawn(count):
+        rng = np.random.Generator(np.random.PCG64(child))
+        t = int(rng.integers(0, len(TEXT_KINDS)))
+        r = int(round(10.0 ** rng.uniform(1.0, 4.0)))
+        m = int(rng.choice([8, 16, 32]))
+        out.append((t, r, m, child.spawn(1)[0]))
+    return out
+
+
+def make_set(synth, texts, recipe):
+    t, r, m, sseed = recipe
+    sigma = TEXT_KINDS[t][0]
+    rng = np.random.Generator(np.random.PCG64(sseed))
+    return synth.gen_patterns(texts[t], r, m, r // 2, sigma, rng)
+
+
+def _scan_ms(torch, mag, text, plan, out, cnt, repeats=2):
+    """Device time of the scan kernel alone (the library's profiling
+    events), the smaller of `repeats` runs."""
+    best = math.inf
+    for _ in range(repeats):
+        mag.profile_read()
+        mag.scan_async(text, plan, out, cnt)
+        t = mag.profile_read()["scan_ms"]
+        best = min(best, t)
+    return best
+
+
+def collect(args):
+    torch, synth, mag = _import()
+    texts = make_texts(synth, args.text_bytes, 5)
+    dtexts = [torch.from_numpy(t).cuda() for t in texts]
+    recipes = set_recipes(args.start + args.sets, 5)[args.start:]
+    rng = np.random.default_rng(args.start + 12345)
+    out = torch.empty((8192, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    mag.profile_enable(True)
+    X = np.zeros((len(recipes), mag.SEL_FEATURES), np.float32)
+    T = np.zeros((len(recipes), mag.SEL_CANDIDATES), np.float32)
+    M = np.zeros((len(recipes), mag.SEL_CANDIDATES), np.uint8)
+    H = np.zeros(len(recipes), np.float32)     # the heuristic's own cost, for reference
+    ex = cf.ThreadPoolExecutor(max_workers=args.threads)
+    t0 = time.time()
+    for i, rec in enumerate(recipes):
+        P = make_set(synth, texts, rec)
+        X[i] = mag.select_features(P)
+        cand = mag.select_candidates(P)
+        feas = [c for c in range(mag.SEL_CANDIDATES) if cand[c] is not None]
+        pick = rng.choice(feas, size=min(args.per_set, len(feas)), replace=False)
+        specs = [dict(q=cand[c][0], k=cand[c][1], sigma_prime=cand[c][2]) for c in pick] + [{}]
+        plans = list(ex.map(lambda kw: mag.Plan(P, **kw), specs))
+        n = texts[rec[0]].size
+        for c, plan in zip(list(pick) + [-1], plans):
+            ms = _scan_ms(torch, mag, dtexts[rec[0]], plan, out, cnt)
+            lab = math.log2(ms * 1e6 / n)
+            if c >= 0:
+                T[i, c] = lab
+                M[i, c] = 1
+            else:
+                H[i] = lab
+            plan.close()
+        if (i + 1) % 200 == 0:
+            print(f"collect: {i + 1}/{len(recipes)} sets, {time.time() - t0:.0f} s", flush=True)
+    np.savez(args.out, X=X, T=T, M=M, H=H, start=args.start, text_bytes=args.text_bytes)
+    print(f"collect: wrote {args.out}", flush=True)
+
+
+def train(args):
+    torch, synth, mag = _import()
+    parts = [np.load(f, allow_pickle=False) for f in args.data]
+    X = np.concatenate([p["X"] for p in parts]).astype(np.float32)
+    T = np.concatenate([p["T"] for p in parts]).astype(np.float64)
+    M = np.concatenate([p["M"] for p in parts]).astype(np.uint8)
+    lab = T[M == 1]
+    mu, sd = float(lab.mean()), float(lab.std() + 1e-9)
+    Tn = np.where(M == 1, (T - mu) / sd, 0.0).astype(np.float32)
+    n = X.shape[0]
+    rng = np.random.default_rng(args.seed)
+    perm = rng.permutation(n)
+    nval = max(1, n // 10)
+    val, tr = perm[:nval], perm[nval:]
+    # He-normal start
+    p0 = np.concatenate([
+        rng.normal(0, math.sqrt(2 / 16), 64 * 16), np.zeros(64),
+        rng.normal(0, math.sqrt(2 / 64), 64 * 64), np.zeros(64),
+        rng.normal(0, math.sqrt(1 / 64), 64 * 64), np.zeros(64)]).astype(np.float32)
+    sel = mag.Selector(p0)
+    xd = torch.from_numpy(X).cuda()
+    td = torch.from_numpy(Tn).cuda()
+    md = torch.from_numpy(M).cuda()
+    vx, vt, vm = xd[val], td[val], md[val]
+    best, best_p = math.inf, sel.get_params()
+    loss = torch.empty(1, device="cuda")
+    bs = args.batch
+    steps_per_epoch = max(1, len(tr) // bs)
+    for ep in range(args.epochs):
+        lr = args.lr * (0.5 * (1 + math.cos(math.pi * ep / args.epochs)))
+        order = torch.from_numpy(rng.permutation(tr)).cuda()
+        for s in range(steps_per_epoch):
+            idx = order[s * bs:(s + 1) * bs]
+            sel.train_step(xd[idx], td[idx], md[idx], lr, loss)
+        _, vl = sel.grad(vx, vt, vm)
+        v = float(vl.item())
+        if v < best:
+            best, best_p = v, sel.get_params()
+        if ep % 20 == 0 or ep == args.epochs - 1:
+            _, tl = sel.grad(xd[torch.from_numpy(tr).cuda()], td[torch.from_numpy(tr).cuda()],
+                             md[torch.from_numpy(tr).cuda()])
+            print(f"train: epoch {ep} lr {lr:.2e} train {float(tl.item()):.4f} val {v:.4f}", flush=True)
+    np.savez(args.model, params=best_p, target_mean=mu, target_std=sd, val_loss=best,
+             n_sets=n, n_labels=int(M.sum()))
+    print(f"train: best val {best:.4f}, wrote {args.model}", flush=True)
+
+
+def evaluate(args):
+    torch, synth, mag = _import()
+    texts = make_texts(synth, args.text_bytes, 6)
+    dtexts = [torch.from_numpy(t).cuda() for t in texts]
+    recipes = set_recipes(args.sets, 6)
+    sel = mag.Selector.load(args.model)
+    out = torch.empty((8192, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    mag.profile_enable(True)
+    sets = [make_set(synth, texts, rec) for rec in recipes]
+    picks = sel.picks(sets, threads=args.threads)
+    ratios, th, tl, same = [], 0.0, 0.0, 0
+    rows = []
+    for i, (rec, P, pk) in enumerate(zip(recipes, sets, picks)):
+        text = dtexts[rec[0]]
+        hp = mag.Plan(P)
+        lp = mag.Plan(P, **pk)
+        h = _scan_ms(torch, mag, text, hp, out, cnt)
+        zh = int(cnt.item())
+        lt = _scan_ms(torch, mag, text, lp, out, cnt)
+        zl = int(cnt.item())
+        same += int(zh == zl)
+        ratios.append(h / lt)
+        th += h
+        tl += lt
+        rows.append((i, rec[0], rec[1], rec[2], h, lt, zh, zl))
+        hp.close()
+        lp.close()
+        if (i + 1) % 200 == 0:
+            print(f"evaluate: {i + 1}/{len(sets)}", flush=True)
+    r = np.array(ratios)
+    res = dict(sets=len(sets), text_bytes=args.text_bytes,
+               geomean_speedup=float(np.exp(np.log(r).mean())), win_rate=float((r > 1).mean()),
+               heuristic_total_ms=th, learned_total_ms=tl, total_speedup=th / tl,
+               same_count=same)
+    print("evaluate:", res, flush=True)
+    if args.out:
+        np.savez(args.out, rows=np.array(rows, dtype=np.float64), **{k: v for k, v in res.items()})
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--sets", type=int, default=20000)
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--per-set", type=int, default=6)
+    c.add_argument("--text-bytes", type=int, default=16 << 20)
+    c.add_argument("--threads", type=int, default=16)
+    c.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("data", nargs="+")
+    t.add_argument("--model", default=DEFAULT_MODEL)
+    t.add_argument("--epochs", type=int, default=200)
+    t.add_argument("--batch", type=int, default=256)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--seed", type=int, default=0)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--model", default=DEFAULT_MODEL)
+    e.add_argument("--sets", type=int, default=2000)
+    e.add_argument("--text-bytes", type=int, default=64 << 20)
+    e.add_argument("--threads", type=int, default=16)
+    e.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    {"collect": collect, "train": train, "evaluate": evaluate}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()
