@@ -3,17 +3,29 @@
 A step is one full scan of the workload's text, resident in HBM, through the
 library's asynchronous entry point: filter, candidate compaction, exact
 verification and the sorted output, all on the GPU. The plan (pattern-set
-preprocessing) is built once before the timed region and timed separately.
+preprocessing, including the learned selector's pick) is built once before
+the timed region and timed separately.
 
-Prints ONE JSON line: throughput in GB/s (1e9 bytes of text per second), the
-roofline of the dominant kernel (the scan kernel, timed with HIP events on its
-own stream), and the CPU oracle timed on the host's cores.
+Prints ONE JSON line: throughput in GB/s (1e9 bytes of text per second) of
+the 256 MiB Zipf workload with the learned selector's parameters (and with
+the fixed heuristic's, beside it), the roofline of the dominant kernel (the
+scan kernel, timed with HIP events recorded by the library on the scan's own
+stream), the CPU oracle timed on the host's cores, and three further
+measurements:
+
+* learned_vs_fixed: held-out pattern sets over 64 MiB texts, scan-kernel time
+  with the heuristic's parameters and with the selector's pick;
+* batch: the 512-job workload (about 1.1 GB of text) as per-job scans with
+  fixed parameters, and batched (one persistent launch, graph replay) with
+  fixed and with learned parameters, every job checked against the oracle;
+* workloads: the 1 MiB DNA and the 1 GiB protein-like scans.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -32,22 +44,25 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def plan_for(mag, job, select: str, text=None):
+def plan_for(mag, patterns, select: str, text=None, selector=None):
     if select == "heuristic":
-        return mag.Plan(job.patterns)
+        return mag.Plan(patterns)
+    if select == "learned":
+        return mag.Plan(patterns, **selector.pick(patterns))
     if select == "autotune":
         sample = text[: min(text.numel(), SAMPLE_BYTES)]
-        best = mag.autotune(job.patterns, sample)
+        best = mag.autotune(patterns, sample)
         log(f"autotune picked {best}")
-        return mag.Plan(job.patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
+        return mag.Plan(patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
                         map_kind=best["map_kind"])
     if select.startswith("explicit:"):
         q, k, sp = (int(v) for v in select.split(":")[1].split(","))
-        return mag.Plan(job.patterns, q=q, k=k, sigma_prime=sp)
+        return mag.Plan(patterns, q=q, k=k, sigma_prime=sp)
     raise ValueError(f"unknown selection {select!r}")
 
 
 def time_scans(torch, mag, text, plan, out, cnt, steps: int, warmup: int):
+    """(ms per step, summed library profile) over `steps` scans."""
     for _ in range(warmup):
         mag.scan_async(text, plan, out, cnt)
     torch.cuda.synchronize()
@@ -65,6 +80,17 @@ def time_scans(torch, mag, text, plan, out, cnt, steps: int, warmup: int):
     return t0.elapsed_time(t1) / steps, prof
 
 
+def scan_kernel_ms(mag, text, plan, out, cnt, repeats=2):
+    best = math.inf
+    mag.profile_enable(True)
+    for _ in range(repeats):
+        mag.profile_read()
+        mag.scan_async(text, plan, out, cnt)
+        best = min(best, mag.profile_read()["scan_ms"])
+    mag.profile_enable(False)
+    return best
+
+
 def cpu_baseline(job, threads: int, max_bytes: int):
     from oracle import match as om
     sample = job.text[:max_bytes]
@@ -80,16 +106,152 @@ def cpu_baseline(job, threads: int, max_bytes: int):
                       f"median of 3 runs of the C hashed matcher ({sec:.2f} s each)"}
 
 
+def oracle_equal(occ_np, ref):
+    import numpy as np
+    pos, ids = ref
+    return bool(pos.size == occ_np.shape[0] and np.array_equal(occ_np[:, 0].astype(np.uint64), pos)
+                and np.array_equal(occ_np[:, 1].astype(np.uint32), ids))
+
+
+def learned_vs_fixed(torch, mag, selector, sets: int, text_bytes: int):
+    import synth
+    from paper_1405_5483_amd import train_selector as ts
+    texts = ts.make_texts(synth, text_bytes, 6)
+    dtexts = [torch.from_numpy(t).cuda() for t in texts]
+    recipes = ts.set_recipes(sets, 6)
+    psets = [ts.make_set(synth, texts, rec) for rec in recipes]
+    picks = selector.picks(psets, threads=CPU_SHARE)
+    out = torch.empty((8192, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    ratios, th, tl, same = [], 0.0, 0.0, 0
+    for rec, P, pk in zip(recipes, psets, picks):
+        hp, lp = mag.Plan(P), mag.Plan(P, **pk)
+        h = scan_kernel_ms(mag, dtexts[rec[0]], hp, out, cnt)
+        zh = int(cnt.item())
+        lt = scan_kernel_ms(mag, dtexts[rec[0]], lp, out, cnt)
+        same += int(zh == int(cnt.item()))
+        ratios.append(h / lt)
+        th += h
+        tl += lt
+        hp.close()
+        lp.close()
+    geo = math.exp(sum(math.log(r) for r in ratios) / len(ratios))
+    return {"sets": sets, "text_bytes": text_bytes, "held_out_seed": 6,
+            "geomean_speedup": round(geo, 3), "win_rate": round(sum(r > 1 for r in ratios) / len(ratios), 3),
+            "heuristic_total_ms": round(th, 3), "learned_total_ms": round(tl, 3),
+            "total_speedup": round(th / tl, 3), "same_count": same,
+            "timing": "scan-kernel device time, smaller of 2 runs"}
+
+
+def batch_section(torch, mag, selector, steps: int):
+    import numpy as np
+    from oracle import match as om
+    from synth import batch_jobs
+    jobs = batch_jobs(512, workers=CPU_SHARE)
+    total = sum(j.n for j in jobs)
+    texts = [torch.from_numpy(j.text).cuda() for j in jobs]
+    refs = [om.occ_hashed(j.text, j.patterns, threads=CPU_SHARE) for j in jobs]
+    z = sum(r[0].size for r in refs)
+    fixed = [mag.Plan(j.patterns) for j in jobs]
+    t = time.perf_counter()
+    picks = selector.picks([j.patterns for j in jobs], threads=CPU_SHARE)
+    learned = [mag.Plan(j.patterns, **pk) for j, pk in zip(jobs, picks)]
+    select_ms = (time.perf_counter() - t) * 1e3
+
+    # per-job scans with fixed parameters, one after another
+    torch.cuda.synchronize()
+    per_job = []
+    for rep in range(2):
+        t = time.perf_counter()
+        for tx, p in zip(texts, fixed):
+            mag.scan(tx, p)
+        torch.cuda.synchronize()
+        per_job.append((time.perf_counter() - t) * 1e3)
+    per_job_ms = min(per_job)
+
+    def batched(plans):
+        b = mag.Batch(plans)
+        stream = torch.cuda.Stream()
+        b.bind(texts, z + 4096, stream)
+        out = torch.empty((z + 4096, 2), dtype=torch.int64, device="cuda")
+        offs = torch.empty(513, dtype=torch.int64, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(stream):
+            b.run_async(out, offs, cnt, stream)
+        stream.synchronize()
+        off = offs.cpu().tolist()
+        o = out.cpu().numpy()
+        exact = all(oracle_equal(o[off[j]:off[j + 1]], refs[j]) for j in range(512))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            b.run_async(out, offs, cnt, torch.cuda.current_stream())
+        for _ in range(2):
+            g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        exact = exact and int(cnt.item()) == z
+        del g
+        b.close()
+        return ms, exact
+
+    bf_ms, bf_exact = batched(fixed)
+    bl_ms, bl_exact = batched(learned)
+    return {"jobs": 512, "text_bytes": total, "occurrences": z,
+            "per_job_fixed_ms": round(per_job_ms, 3),
+            "batched_fixed_ms": round(bf_ms, 3), "batched_learned_ms": round(bl_ms, 3),
+            "batched_learned_GBps": round(total / (bl_ms * 1e-3) / 1e9, 2),
+            "per_job_fixed_GBps": round(total / (per_job_ms * 1e-3) / 1e9, 2),
+            "speedup_vs_per_job_fixed": round(per_job_ms / bl_ms, 2),
+            "speedup_learned_vs_fixed_batched": round(bf_ms / bl_ms, 3),
+            "selector_ms": round(select_ms, 1),
+            "bit_exact": bool(bf_exact and bl_exact),
+            "timing": "graph replays of bind-time launches; per-job scans wall clock"}
+
+
+def single_workload(torch, mag, selector, name: str, steps: int):
+    import numpy as np
+    from oracle import match as om
+    from synth import workload
+    job = workload(name)
+    text = torch.from_numpy(job.text).cuda()
+    ref = om.occ_hashed(job.text, job.patterns, threads=CPU_SHARE)
+    res = {"text_bytes": job.n, "r": job.r, "m": job.m}
+    for sel in ("heuristic", "learned"):
+        plan = plan_for(mag, job.patterns, sel, text, selector)
+        info = plan.info()
+        occ = mag.scan(text, plan, out_cap=ref[0].size + 1024)
+        exact = oracle_equal(occ.cpu().numpy(), ref)
+        out = torch.empty((ref[0].size + 1024, 2), dtype=torch.int64, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        ms, prof = time_scans(torch, mag, text, plan, out, cnt, steps, 2)
+        res[sel] = {"GBps": round(job.n / (ms * 1e-3) / 1e9, 2), "ms_per_step": round(ms, 4),
+                    "scan_kernel_ms": round(prof["scan_ms"] / max(prof["launches"], 1), 4),
+                    "q": info["q"], "k": info["k"], "sigma_prime": info["sigma_prime"],
+                    "bit_exact": exact}
+        plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf256m")
-    ap.add_argument("--select", default="autotune",
-                    help="autotune | heuristic | explicit:q,k,sigma'")
+    ap.add_argument("--select", default="learned",
+                    help="learned | heuristic | autotune | explicit:q,k,sigma'")
+    ap.add_argument("--eval-sets", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned-vs-fixed, batch and other-workload sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -105,13 +267,14 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    selector = mag.Selector.load()
     log(f"generating workload {args.workload}")
     job = workload(args.workload)
     n = job.n
     text = torch.from_numpy(job.text).cuda()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    plan = plan_for(mag, job, args.select, text)
+    plan = plan_for(mag, job.patterns, args.select, text, selector)
     plan_ms = (time.perf_counter() - t) * 1e3
     info = plan.info()
     log(f"plan q={info['q']} k={info['k']} sigma'={info['sigma_prime']} W={info['W']} "
@@ -121,12 +284,11 @@ def main() -> int:
     occ, st = mag.scan(text, plan, stats=True)
     z = occ.shape[0]
     verified = None
+    ref = None
     if not args.no_verify:
         from oracle import match as om
-        pos, ids = om.occ_hashed(job.text, job.patterns, threads=min(os.cpu_count() or 1, CPU_SHARE))
-        o = occ.cpu().numpy()
-        verified = bool(pos.size == z and np.array_equal(o[:, 0].astype(np.uint64), pos)
-                        and np.array_equal(o[:, 1].astype(np.uint32), ids))
+        ref = om.occ_hashed(job.text, job.patterns, threads=min(os.cpu_count() or 1, CPU_SHARE))
+        verified = oracle_equal(occ.cpu().numpy(), ref)
         log(f"bit-exact vs oracle: {verified} ({z} occurrences)")
         if not verified:
             return 1
@@ -142,6 +304,31 @@ def main() -> int:
     finish_ms = prof["finish_ms"] / max(prof["launches"], 1)
     alg_bytes = n                         # the filter kernel reads the text once
     achieved = alg_bytes / (scan_ms * 1e-3) / 1e9
+
+    # the same workload with the fixed heuristic's parameters
+    fixed_plan = mag.Plan(job.patterns)
+    finfo = fixed_plan.info()
+    fixed_ms, fprof = time_scans(torch, mag, text, fixed_plan, out, cnt, args.steps, args.warmup)
+    fixed_exact = int(cnt.item()) == z
+    fixed = {"GBps": round(n / (fixed_ms * 1e-3) / 1e9, 3), "ms_per_step": round(fixed_ms, 5),
+             "q": finfo["q"], "k": finfo["k"], "sigma_prime": finfo["sigma_prime"],
+             "same_count": fixed_exact}
+    fixed_plan.close()
+
+    extras = {}
+    if not args.no_extras:
+        log(f"learned vs fixed on {args.eval_sets} held-out sets")
+        extras["learned_vs_fixed"] = learned_vs_fixed(torch, mag, selector, args.eval_sets, 64 << 20)
+        log(f"learned vs fixed: {extras['learned_vs_fixed']}")
+        log("batched workload (512 jobs)")
+        extras["batch"] = batch_section(torch, mag, selector, 10)
+        log(f"batch: {extras['batch']}")
+        extras["workloads"] = {}
+        for name in ("dna1m", "prot1g"):
+            log(f"workload {name}")
+            extras["workloads"][name] = single_workload(torch, mag, selector, name,
+                                                        args.steps if name == "dna1m" else 5)
+            log(f"{name}: {extras['workloads'][name]}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -172,11 +359,13 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_scan", "kernel_ms": round(scan_ms, 5),
                      "alg_bytes_per_launch": alg_bytes},
+        "fixed_params": fixed,
         "finish_kernel_ms": round(finish_ms, 5),
         "plan_ms": round(plan_ms, 3),
         "occurrences": z,
         "bit_exact": verified,
         "counters": st,
+        **extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
