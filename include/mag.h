@@ -58,6 +58,16 @@ typedef enum {
     MAG_SELECT_AUTOTUNE = 3   /* measured on the device over a small grid      */
 } mag_select;
 
+/* How start positions reach exact verification. */
+typedef enum {
+    MAG_MODE_AUTO = 0,   /* dense when the filter is expected to pass more than
+                            0.1 start positions per text byte                  */
+    MAG_MODE_FILTER = 1, /* the q-gram Shift-Or filter of Sections 2-3         */
+    MAG_MODE_DENSE = 2   /* every start position, through a Bloom bitmap of the
+                            patterns' first min(m, 16) bytes (the degenerate
+                            filter that passes every window, Section 3.2)      */
+} mag_mode;
+
 /* Alphabet reduction mu: byte -> [0, sigma') (Section 3.3). */
 typedef enum {
     MAG_MAP_GREEDY = 0, /* equal-weight bins by longest-processing-time greedy */
@@ -72,7 +82,8 @@ typedef struct {
     int32_t sigma_prime;  /* reduced alphabet size (explicit selection)         */
     int32_t table_budget; /* bytes the heuristic allows for the mask table;
                              0 = 96 KiB                                         */
-    int32_t reserved[6];  /* must be zero                                       */
+    int32_t mode;         /* mag_mode                                           */
+    int32_t reserved[5];  /* must be zero                                       */
 } mag_params;
 
 typedef struct {
@@ -92,8 +103,12 @@ typedef struct {
     int32_t select;       /* how the parameters were chosen                     */
     uint32_t r, m;
     uint32_t n_unique;    /* distinct patterns                                  */
+    int32_t dense;        /* 1: scans test every start position (mag_mode)      */
+    int32_t bloom_log2;   /* bits of the dense mode's Bloom bitmap (log2)       */
     uint64_t n_codes;     /* sigma'^q mask-table entries                        */
     uint64_t table_bytes; /* n_codes * entry_bytes                              */
+    double est_verif;     /* estimated verifications per text byte of the
+                             filter (-1: not evaluated)                        */
 } mag_plan_desc;
 
 /* Work counters of one scan (integers; equal to the oracle's counts). */

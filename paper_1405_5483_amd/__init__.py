@@ -18,7 +18,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (MAG_E_OVERFLOW, MAP_KIND, SELECT, MagError, MagParams, MagPlanDesc,
+from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, MagError, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
 __all__ = ["Plan", "Batch", "Selector", "scan", "scan_async", "scan_batch", "autotune",
@@ -47,7 +47,8 @@ class Plan:
 
     def __init__(self, patterns, *, select: str = "heuristic", q: int | None = None,
                  k: int | None = None, sigma_prime: int | None = None,
-                 map_kind: str = "greedy", table_budget: int = 0, candidate: int | None = None):
+                 map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
+                 candidate: int | None = None):
         p = _as_patterns(patterns)
         self.r, self.m = int(p.shape[0]), int(p.shape[1])
         self.candidate = candidate        # selector grid index of a learned pick (informational)
@@ -61,6 +62,7 @@ class Plan:
         prm.k = int(k or 0)
         prm.sigma_prime = int(sigma_prime or 0)
         prm.table_budget = int(table_budget)
+        prm.mode = MODE[mode]
         handle = ctypes.c_void_p()
         self._h = None
         check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,

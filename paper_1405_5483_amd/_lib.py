@@ -21,6 +21,7 @@ MAG_E_OVERFLOW = -5
 
 SELECT = {"heuristic": 0, "explicit": 1, "learned": 2, "autotune": 3}
 MAP_KIND = {"greedy": 0, "rank": 1}
+MODE = {"auto": 0, "filter": 1, "dense": 2}
 
 
 class MagParams(ctypes.Structure):
@@ -31,7 +32,8 @@ class MagParams(ctypes.Structure):
         ("k", ctypes.c_int32),
         ("sigma_prime", ctypes.c_int32),
         ("table_budget", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -46,7 +48,9 @@ class MagPlanDesc(ctypes.Structure):
         ("L", ctypes.c_int32), ("m_prime", ctypes.c_int32), ("W", ctypes.c_int32),
         ("entry_bytes", ctypes.c_int32), ("map_kind", ctypes.c_int32), ("select", ctypes.c_int32),
         ("r", ctypes.c_uint32), ("m", ctypes.c_uint32), ("n_unique", ctypes.c_uint32),
+        ("dense", ctypes.c_int32), ("bloom_log2", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+        ("est_verif", ctypes.c_double),
     ]
 
 

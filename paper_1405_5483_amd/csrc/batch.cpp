@@ -82,7 +82,7 @@ mag_status mag_batch_create(mag_plan *const *plans, uint32_t njobs, mag_batch **
     for (uint32_t j = 0; j < njobs; ++j) {
         const mag_plan *p = plans[j];
         if (!p) return fail(MAG_E_INVALID, "plans[" + std::to_string(j) + "] is NULL");
-        if (p->r == 0) continue;               // no tiles are ever scanned for it
+        if (p->r == 0 || p->dense) continue;   // no filter state in these jobs
         if (p->W > 32 || p->k >= 32)
             return fail(MAG_E_UNSUPPORTED, "batched jobs need W = k*m' <= 32 and k < 32 (job " +
                                                std::to_string(j) + ")");
@@ -187,7 +187,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         std::memset(&J, 0, sizeof(J));
         const uint64_t kq = (uint64_t)p->k * p->q;
         const bool scans = p->r > 0 && n[j] >= p->m && n[j] >= (uint64_t)p->q;
-        const uint64_t X = scans ? (n[j] - p->q) / kq + 1 : 0;
+        // filter: samples; dense: start positions
+        const uint64_t X = !scans ? 0 : p->dense ? n[j] - p->m + 1 : (n[j] - p->q) / kq + 1;
         const uintptr_t t = reinterpret_cast<uintptr_t>(d_texts[j]);
         J.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
         J.delta = t & 15;
@@ -207,6 +208,13 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.w0 = ((uint32_t)p->mprime - 1 + 3) / 4 * 4;
         J.tlds = p->table.size() <= kBatchTableLds ? 1 : 0;
         J.table_vec = (uint32_t)((p->table.size() + 15) / 16);
+        J.dense = p->dense ? 1u : 0u;
+        if (p->dense) {
+            J.table = p->dev.bloom_batch;
+            J.tlds = 1;
+            J.table_vec = (uint32_t)(p->bloom_batch.size() * 4 / 16);
+            J.bshift = 32u - (uint32_t)std::min(p->bloom_log2, kBloomBatchLog2);
+        }
         ScanLaunch sl;
         sl.text = d_texts[j];
         sl.n = n[j];
@@ -232,7 +240,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     if (grid) {
         auto tile_weight = [&](uint32_t j, uint64_t t) {
             const uint64_t samples = t + 1 < tiles_of[j] ? (uint64_t)kBatchTileSamples : tail_samples[j];
-            return samples * jobs[j].kq + kTileOverheadBytes;
+            // a dense tile reads one byte per position but hashes every one of them
+            return samples * (jobs[j].dense ? 4 : jobs[j].kq) + kTileOverheadBytes;
         };
         long double total = 0;
         for (uint32_t j = 0; j < njobs; ++j)

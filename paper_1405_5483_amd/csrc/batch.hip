@@ -187,6 +187,7 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
     __amdgpu_buffer_rsrc_t trs = tile_rsrc(nullptr, 0);
     uint64_t delta = 0, n = 0, X = 0, tfirst = 0, tend = 0;
     uint32_t q = 1, k = 1, kq = 1, mprime = 1, W = 1, sp = 1, esz = 1, w0 = 0, tlds = 0, m = 1;
+    uint32_t dense = 0, bshift = 32, hw = 1, mw = 1, lastmask = 0;
 
     for (uint32_t slot = 0;; slot ^= 1) {
         const uint64_t g = uni64(s_ctl[slot]);
@@ -228,6 +229,11 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
             w0 = uni32(J.w0);
             tlds = uni32(J.tlds);
             m = uni32(J.v.m);
+            dense = uni32(J.dense);
+            bshift = uni32(J.bshift);
+            hw = uni32(J.v.hw);
+            mw = uni32(J.v.mw);
+            lastmask = uni32(J.v.lastmask);
             const uint32_t tvec = uni32(J.table_vec);
             const uint8_t *mu = uniptr(J.mu);
             const uint8_t *table = uniptr(reinterpret_cast<const uint8_t *>(J.table));
@@ -241,6 +247,31 @@ __global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs,
             }
         }
         const int64_t X0 = (int64_t)(g - tfirst) * kTS;
+        if (dense) {
+            // start positions X0 .. X0 + kTS - 1 against the Bloom bitmap in s_tab
+            int64_t e1 = X0 + kTS + 40;
+            if (e1 > (int64_t)n) e1 = (int64_t)n;
+            const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
+            const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;
+            const __amdgpu_buffer_rsrc_t drs = tile_rsrc(tbase + da0, (uint32_t)(da1 - da0));
+            __syncthreads();                // the bitmap is staged
+            if (wave == 0) {
+                uint64_t t = kNoTile;
+                if (!own_done) {
+                    const uint64_t c = __shfl(pending, 0);
+                    if (c < own_end) t = c;
+                    else own_done = true;
+                }
+                if (t == kNoTile) t = steal_tile(next, ranges, G, me, lane);
+                if (lane == 0) s_ctl[slot ^ 1] = t;
+            }
+            dense_tile<kBT>(drs, (uint32_t)(da1 - da0), (uint32_t)(delta + (uint64_t)X0 - da0), X0,
+                            (int64_t)n - (int64_t)m,
+                            reinterpret_cast<const uint32_t *>(s_tab), bshift, hw, mw, lastmask, queue,
+                            qn, vp, tid, lane, nver);
+            __syncthreads();                // s_ctl for the next tile
+            continue;
+        }
         // text bytes the tile's samples touch, warm-up included
         int64_t b0 = (X0 - (int64_t)w0) * kq;
         if (b0 < 0) b0 = 0;

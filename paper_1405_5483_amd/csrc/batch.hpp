@@ -5,19 +5,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dense.hpp"
 #include "mag_internal.hpp"
 #include "verify.hpp"
 
 namespace mag {
 
 constexpr int kBatchThreads = 512;               // threads per workgroup
-constexpr int kBatchTileSamples = 8192;          // samples per tile: 16 per thread
+constexpr int kBatchTileSamples = 8192;          // samples (dense jobs: start positions) per tile
 constexpr int kBatchMaxWarm = 32;                // warm-up entries before a tile (>= m' - 1)
 constexpr int kBatchQueue = 128;                 // per-wave queue of start positions
 // mask entries of one tile as u32, in whole groups of eight 16-byte vectors
 constexpr uint32_t kBatchEntryBytes =
     ((kBatchTileSamples + kBatchMaxWarm) * 4 + 127) / 128 * 128;
 constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
+static_assert(kBatchTileSamples == kDenseTilePositions && kBatchThreads == kDenseThreads,
+              "dense tiles of the batch kernel are the dense kernel's tiles");
+static_assert((1u << kBloomBatchLog2) / 8 <= kBatchTableLds, "batched Bloom bitmaps fit in LDS");
 // alphabet map, two claimed-tile slots, queues, entries, table
 constexpr uint32_t kBatchLdsBytes =
     256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + kBatchEntryBytes + kBatchTableLds;
@@ -34,6 +38,8 @@ struct JobDesc {
     uint32_t q, k, kq, mprime, W, sp, esz, w0;
     uint32_t tlds;             // table staged in LDS
     uint32_t table_vec;        // 16-byte vectors of the table
+    uint32_t dense;            // test every start position; `table` is then the Bloom bitmap
+    uint32_t bshift;           // 32 - log2(Bloom bits) of a dense job
     VerifyArgs v;              // verification, with the job number in key_or
 };
 

@@ -7,7 +7,9 @@
 #include <string>
 #include <vector>
 
+#include "dense.hpp"
 #include "mag_internal.hpp"
+#include "scan_args.hpp"
 
 namespace mag {
 
@@ -89,7 +91,9 @@ mag_status ensure_device(mag_plan *p) {
     const uint64_t o_pw = round16(o_slots + p->slots.size() * 8);
     const uint64_t o_ids0 = round16(o_pw + p->pwords.size() * 4 + 16);
     const uint64_t o_ids = round16(o_ids0 + p->idstart.size() * 4);
-    const uint64_t total = round16(o_ids + p->ids.size() * 4 + 16);
+    const uint64_t o_bloom = round16(o_ids + p->ids.size() * 4 + 16);
+    const uint64_t o_bloomb = round16(o_bloom + p->bloom.size() * 4);
+    const uint64_t total = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
     uint8_t *base = nullptr;
     e = hipMalloc(&base, total);
     if (e != hipSuccess) {
@@ -103,6 +107,9 @@ mag_status ensure_device(mag_plan *p) {
     if (!p->pwords.empty()) std::memcpy(&host[o_pw], p->pwords.data(), p->pwords.size() * 4);
     if (!p->idstart.empty()) std::memcpy(&host[o_ids0], p->idstart.data(), p->idstart.size() * 4);
     if (!p->ids.empty()) std::memcpy(&host[o_ids], p->ids.data(), p->ids.size() * 4);
+    if (!p->bloom.empty()) std::memcpy(&host[o_bloom], p->bloom.data(), p->bloom.size() * 4);
+    if (!p->bloom_batch.empty())
+        std::memcpy(&host[o_bloomb], p->bloom_batch.data(), p->bloom_batch.size() * 4);
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
@@ -115,6 +122,8 @@ mag_status ensure_device(mag_plan *p) {
     p->dev.pwords = reinterpret_cast<const uint32_t *>(base + o_pw);
     p->dev.idstart = reinterpret_cast<const uint32_t *>(base + o_ids0);
     p->dev.ids = reinterpret_cast<const uint32_t *>(base + o_ids);
+    p->dev.bloom = reinterpret_cast<const uint32_t *>(base + o_bloom);
+    p->dev.bloom_batch = reinterpret_cast<const uint32_t *>(base + o_bloomb);
 
     // fixed scratch: counters[4], the count and the stats of mag_scan
     Scratch &sc = p->scratch;
@@ -240,8 +249,11 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->r = p->r;
     d->m = p->m;
     d->n_unique = p->n_unique;
+    d->dense = p->dense;
+    d->bloom_log2 = p->bloom_log2;
     d->n_codes = p->n_codes;
     d->table_bytes = p->table.size();
+    d->est_verif = p->est_verif;
     return MAG_OK;
 }
 
@@ -285,7 +297,9 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     const int posbits = ceil_log2(n + 1 > 2 ? n + 1 : 2);
     if (idbits + posbits > 64) return fail(MAG_E_UNSUPPORTED, "positions and ids need more than 64 key bits");
     const uint64_t kq = (uint64_t)p->k * p->q;
-    const uint64_t samples = n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0;
+    // filter: q-grams read; dense: start positions tested
+    const uint64_t samples = p->dense ? (n >= p->m && p->r ? n - p->m + 1 : 0)
+                                      : (n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0);
 
     ScanLaunch sl;
     sl.text = d_text;
@@ -307,7 +321,23 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         }
         (void)hipEventRecord(rec.ev[0], stream);
     }
-    s = launch_scan(p, sl, stream);
+    if (p->dense) {
+        DenseArgs da{};
+        const uintptr_t t = reinterpret_cast<uintptr_t>(d_text);
+        da.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
+        da.delta = t & 15;
+        da.n = n;
+        da.last = (int64_t)n - (int64_t)p->m;
+        da.ntiles = samples ? (samples + kDenseTilePositions - 1) / kDenseTilePositions : 0;
+        da.bshift = 32u - (uint32_t)p->bloom_log2;
+        da.bloom_vec = (uint32_t)(p->bloom.size() * 4 / 16);
+        da.bloom = p->dev.bloom;
+        da.counters = p->scratch.counters;
+        da.v = make_verify_args(p, sl);
+        s = launch_dense(da, p->bloom.size() * 4, stream);
+    } else {
+        s = launch_scan(p, sl, stream);
+    }
     if (s != MAG_OK) return s;
     if (prof) (void)hipEventRecord(rec.ev[1], stream);
     if (idbits_out) *idbits_out = idbits;

@@ -1,0 +1,84 @@
+// Single-job dense scan: a persistent grid walks tiles of
+// kDenseTilePositions start positions with the Bloom bitmap staged in LDS
+// (see dense.hpp).
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "dense.hpp"
+
+namespace mag {
+namespace {
+
+using namespace dev;
+
+constexpr int kNT = kDenseThreads;
+constexpr int kQueue = 128;
+
+__global__ __launch_bounds__(kNT) void k_dense(DenseArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem);
+    uint32_t *s_bloom = reinterpret_cast<uint32_t *>(smem + (kNT / 64) * kQueue * 8);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the kernel's only argument is `a`, at the start of the argument segment
+    const VerifyArgs *vargs = (const VerifyArgs *)((const __attribute__((address_space(4))) char *)
+                                                       __builtin_amdgcn_kernarg_segment_ptr() +
+                                                   offsetof(DenseArgs, v));
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.bloom);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_bloom);
+        for (uint32_t v = tid; v < a.bloom_vec; v += kNT) dst[v] = src[v];
+    }
+    __syncthreads();
+    uint64_t *queue = s_queue + wave * kQueue;
+    uint32_t qn = 0;
+    uint64_t nhit = 0;
+    const uint32_t hw = a.v.hw, mw = a.v.mw, lastmask = a.v.lastmask;
+    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int64_t x0 = (int64_t)tile * kDenseTilePositions;
+        // bytes the tile's windows touch
+        int64_t b1 = x0 + kDenseTilePositions + 40;
+        if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
+        const uint64_t pa0 = (a.delta + (uint64_t)x0) & ~15ull;
+        const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
+        const uint32_t p0 = (uint32_t)(a.delta + (uint64_t)x0 - pa0);
+        dense_tile<kNT>(rs, (uint32_t)(pa1 - pa0), p0, x0, a.last, s_bloom, a.bshift, hw, mw, lastmask,
+                        queue, qn, vargs, tid, lane, nhit);
+    }
+    if (qn) drain_partial(vargs, queue, qn, lane);
+    unsigned long long nh = nhit;
+    for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
+    if (lane == 0 && nh) {
+        atomicAdd((unsigned long long *)&a.counters[1], nh);
+        atomicAdd((unsigned long long *)&a.counters[2], nh);
+    }
+}
+
+}  // namespace
+
+mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream) {
+    if (!a.ntiles) return MAG_OK;
+    const size_t shmem = (size_t)(kNT / 64) * kQueue * 8 + bloom_bytes;
+    static size_t configured = 0;
+    if (shmem > configured) {
+        // not every runtime needs the opt-in; a real LDS overflow fails the launch below
+        (void)hipFuncSetAttribute((const void *)k_dense, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shmem);
+        (void)hipGetLastError();
+        configured = shmem;
+    }
+    int dev = 0, ncu = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dense, kNT, shmem);
+    if (e != hipSuccess) return hip_fail(e, "dense scan sizing");
+    if (occ < 1) return fail(MAG_E_UNSUPPORTED, "dense scan does not fit on a compute unit");
+    uint64_t grid = (uint64_t)ncu * occ;
+    if (grid > a.ntiles) grid = a.ntiles;
+    hipLaunchKernelGGL(k_dense, dim3((uint32_t)grid), dim3(kNT), shmem, stream, a);
+    e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "dense scan launch");
+}
+
+}  // namespace mag

@@ -1,0 +1,104 @@
+// Dense mode: every start position is tested against a Bloom bitmap of the
+// patterns' first min(m, 16) bytes; those that pass go to the exact
+// verification of Section 3.2. This is the filter that passes every window
+// (sigma' = 1), done without per-window overhead: one hash and two LDS bit
+// tests per position. Shared by the single-job dense kernel and the batched
+// kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mag_internal.hpp"
+#include "scan_common.hpp"
+
+namespace mag {
+
+constexpr int kDenseThreads = 512;
+constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive positions per thread
+
+struct DenseArgs {
+    const uint8_t *tbase;      // text pointer rounded down to 16 bytes
+    uint64_t delta;            // text - tbase
+    uint64_t n;
+    int64_t last;              // last start position, n - m
+    uint64_t ntiles;
+    uint32_t bshift;           // 32 - log2(Bloom bits)
+    uint32_t bloom_vec;        // 16-byte vectors of the bitmap
+    const uint32_t *bloom;
+    uint64_t *counters;        // [1] positions past the bitmap [2] verifications
+    VerifyArgs v;
+};
+
+mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream);
+
+namespace dev {
+
+// One tile of the dense mode: start positions x0 .. x0 + 16*NT - 1 (those up
+// to `last`). Thread tid takes the 16 consecutive positions from
+// x0 + 16*tid: two 16-byte loads and one 8-byte load (consecutive lanes read
+// consecutive 16-byte blocks) give the bytes of all 16 windows. rs covers the
+// tile's bytes, nrec is its size and p0 the resource offset of position x0.
+// A thread whose 40 bytes reach past the resource (only at the end of a
+// text) loads single dwords, each range-checked on its own, so no text byte
+// comes back as an out-of-range zero. Positions that pass the bitmap go to
+// this wave's queue; full queues are verified at once.
+template <int NT>
+__device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t nrec, uint32_t p0,
+                                           int64_t x0, int64_t last, const uint32_t *s_bloom,
+                                           uint32_t bshift, uint32_t hw, uint32_t mw, uint32_t lastmask,
+                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int tid,
+                                           int lane, uint64_t &nhit) {
+    const uint32_t d = p0 & 3u;                 // the same for every lane
+    const uint32_t a = (p0 & ~3u) + 16u * (uint32_t)tid;
+    uint32_t W[10];                             // bytes [a, a + 40)
+    if (a + 40u <= nrec) {
+        const uint4 v0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)a, 0, 0));
+        const uint4 v1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(a + 16), 0, 0));
+        const uint2 v2 = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(a + 32), 0, 0));
+        W[0] = v0.x; W[1] = v0.y; W[2] = v0.z; W[3] = v0.w;
+        W[4] = v1.x; W[5] = v1.y; W[6] = v1.z; W[7] = v1.w;
+        W[8] = v2.x; W[9] = v2.y;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 10; ++t) W[t] = ld32(rs, a + 4u * t);
+    }
+    uint32_t V[9];                              // bytes from position x0 + 16*tid on
+#pragma unroll
+    for (int t = 0; t < 9; ++t) V[t] = __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
+    const int64_t xb = x0 + 16 * (int64_t)tid;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t x = xb + 4 * i + s;
+            uint32_t w[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                w[t] = s ? __builtin_amdgcn_alignbyte(V[i + t + 1], V[i + t], s) : V[i + t];
+            if (mw <= 4) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if ((uint32_t)t == mw - 1) w[t] &= lastmask;
+            }
+            const uint32_t h = prefilter_hash(w, (int)hw);
+            const uint32_t i1 = h >> bshift, i2 = bloom_second(h) >> bshift;
+            const bool hit = x <= last && ((s_bloom[i1 >> 5] >> (i1 & 31)) & 1u) &&
+                             ((s_bloom[i2 >> 5] >> (i2 & 31)) & 1u);
+            const uint64_t bal = __ballot(hit);
+            if (!bal) continue;
+            if (hit) {
+                queue[qn + lanes_below(bal)] = (uint64_t)x;
+                ++nhit;
+            }
+            qn += (uint32_t)__popcll(bal);
+            if (qn >= 64) {
+                qn -= 64;
+                drain64(vp, queue, qn, lane);
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace mag

@@ -42,6 +42,28 @@ __host__ __device__ inline uint32_t window_hash(const uint32_t *w, int nwords) {
     return h;
 }
 
+// Dense mode (every start position tested): a Bloom bitmap of 2^B bits over
+// the same first min(m, 16) bytes, two bits per distinct pattern. B grows with
+// the number of distinct patterns; batched scans use a copy with at most
+// kBloomBatchLog2 bits, built from the same hashes.
+constexpr int kBloomMinLog2 = 12;
+constexpr int kBloomMaxLog2 = 20;
+constexpr int kBloomBatchLog2 = 18;
+// MAG_MODE_AUTO scans densely when the filter is expected to verify at least
+// this many start positions per text byte.
+constexpr double kDenseVerifPerByte = 0.1;
+
+__host__ __device__ inline uint32_t prefilter_hash(const uint32_t *w, int nwords) {
+    uint32_t x = w[0];
+    if (nwords > 1) x ^= (w[1] << 7) | (w[1] >> 25);
+    if (nwords > 2) x ^= (w[2] << 14) | (w[2] >> 18);
+    if (nwords > 3) x ^= (w[3] << 21) | (w[3] >> 11);
+    return x * 0x9E3779B1u;
+}
+
+// The second Bloom bit comes from a remix of the same hash.
+__host__ __device__ inline uint32_t bloom_second(uint32_t h) { return (h ^ (h >> 15)) * 0x85EBCA77u; }
+
 // Everything a scan needs on the device. Plain pointers into one allocation.
 struct DeviceTables {
     uint8_t *base = nullptr;        // the single allocation
@@ -51,6 +73,8 @@ struct DeviceTables {
     const uint32_t *pwords = nullptr;  // n_unique * mw words
     const uint32_t *idstart = nullptr; // n_unique + 1
     const uint32_t *ids = nullptr;     // r
+    const uint32_t *bloom = nullptr;   // 2^bloom_log2 bits
+    const uint32_t *bloom_batch = nullptr;  // 2^min(bloom_log2, kBloomBatchLog2) bits
 };
 
 struct Scratch {
@@ -82,6 +106,11 @@ struct mag_plan {
     std::vector<uint32_t> pwords, idstart, ids;
     std::vector<uint64_t> slots;
 
+    // dense mode: test every start position against the Bloom bitmaps
+    int mode = MAG_MODE_AUTO, dense = 0, bloom_log2 = mag::kBloomMinLog2;
+    double est_verif = 0.0;          // estimated verifications per text byte of the filter
+    std::vector<uint32_t> bloom, bloom_batch;
+
     // device side
     std::mutex mtx;
     int device = -1;
@@ -102,6 +131,11 @@ mag_status ensure_device(mag_plan *p);
 // q of the fixed heuristic: log base max(sigma, 2) of r*m, rounded half up,
 // clamped to [1, min((m+1)/2, kMaxQ)] (plan.cpp).
 int heuristic_q(int sigma, uint32_t r, uint32_t m);
+
+// Verifications per text byte the filter of a built plan is expected to make,
+// from the class densities its mask table gives under the pattern-set byte
+// frequencies (plan.cpp); -1 when the table is too large to evaluate.
+double estimate_verifications(const mag_plan *p);
 
 // Host plan builder (plan.cpp).
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,

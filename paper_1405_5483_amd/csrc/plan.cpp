@@ -157,7 +157,62 @@ void build_verifier(mag_plan *p) {
     }
 }
 
+// Bloom bitmaps of the dense mode: bits prefilter_hash >> (32 - B) and
+// bloom_second(hash) >> (32 - B) of every distinct pattern's first min(m, 16)
+// bytes, for B = bloom_log2 and for the batched copy's smaller B.
+void build_bloom(mag_plan *p) {
+    int B = kBloomMinLog2;
+    while (B < kBloomMaxLog2 && (1ull << B) < 64ull * std::max<uint32_t>(p->n_unique, 1)) ++B;
+    p->bloom_log2 = B;
+    const int Bb = std::min(B, kBloomBatchLog2);
+    p->bloom.assign((1u << B) / 32, 0u);
+    p->bloom_batch.assign((1u << Bb) / 32, 0u);
+    const int hw = std::min<int>(p->mw, kHashWords);
+    for (uint32_t u = 0; u < p->n_unique; ++u) {
+        const uint32_t h = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
+        const uint32_t h2 = bloom_second(h);
+        for (uint32_t x : {h, h2}) {
+            const uint32_t i = x >> (32 - B), ib = x >> (32 - Bb);
+            p->bloom[i >> 5] |= 1u << (i & 31);
+            p->bloom_batch[ib >> 5] |= 1u << (ib & 31);
+        }
+    }
+}
+
 }  // namespace
+
+double estimate_verifications(const mag_plan *p) {
+    if (p->r == 0) return 0.0;
+    if (p->n_codes > (1ull << 22)) return -1.0;
+    const int sp = p->sigma_prime, q = p->q, W = p->W, k = p->k, esz = p->esz;
+    double byte_freq[256] = {0};
+    for (uint8_t c : p->patterns) byte_freq[c] += 1.0;
+    for (double &f : byte_freq) f /= (double)p->patterns.size();
+    std::vector<double> sym(sp, 0.0);
+    for (int c = 0; c < 256; ++c) sym[p->mu[c]] += byte_freq[c];
+    // p_b: probability that a text gram lies in class C[b]
+    std::vector<double> pb(W, 0.0);
+    const uint8_t *tb = p->table.data();
+    for (uint64_t code = 0; code < p->n_codes; ++code) {
+        double pr = 1.0;
+        uint64_t c = code;
+        for (int t = 0; t < q; ++t) {
+            pr *= sym[c % sp];
+            c /= sp;
+        }
+        if (pr == 0.0) continue;
+        for (int b = 0; b < W; ++b)
+            if (!(tb[code * esz + (b >> 3)] & (1u << (b & 7)))) pb[b] += pr;
+    }
+    // candidate windows per sample (every j of k), q starts each, one sample per kq bytes
+    double cand = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double prod = 1.0;
+        for (int h = 0; h < p->mprime; ++h) prod *= std::min(1.0, pb[j + h * k]);
+        cand += prod;
+    }
+    return cand * q / ((double)k * q);
+}
 
 int heuristic_q(int sigma, uint32_t r, uint32_t m) {
     const double s = std::max(sigma, 2);
@@ -175,6 +230,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (r > 0 && !patterns) return fail(MAG_E_INVALID, "patterns is NULL");
     if (prm.map_kind != MAG_MAP_GREEDY && prm.map_kind != MAG_MAP_RANK)
         return fail(MAG_E_INVALID, "unknown map_kind");
+    if (prm.mode < MAG_MODE_AUTO || prm.mode > MAG_MODE_DENSE) return fail(MAG_E_INVALID, "unknown mode");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
 
     p->r = r;
@@ -229,6 +285,11 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (p->map_kind == MAG_MAP_RANK) map_rank(p); else map_greedy(p);
     build_table(p);
     build_verifier(p);
+    build_bloom(p);
+    p->mode = prm.mode;
+    p->est_verif = estimate_verifications(p);
+    p->dense = prm.mode == MAG_MODE_DENSE ||
+               (prm.mode == MAG_MODE_AUTO && p->est_verif >= kDenseVerifPerByte);
     return MAG_OK;
 }
 

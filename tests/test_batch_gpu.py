@@ -71,8 +71,10 @@ def test_batch_mixed_jobs(torch_cuda, mag):
     t = gen_text(300_000, 20, rng=10)
     p = gen_patterns(t, 400, 16, 300, 20, rng=11)
     jobs.append(type(jobs[0])(t, p, {"big_table": True}))                  # table read from L2
-    plans = [mag.Plan(j.patterns) for j in jobs[:-1]]
-    plans.append(mag.Plan(jobs[-1].patterns, q=4, k=1, sigma_prime=20))
+    # every third job scans densely
+    plans = [mag.Plan(j.patterns, mode="dense" if i % 3 == 2 else "filter")
+             for i, j in enumerate(jobs[:-1])]
+    plans.append(mag.Plan(jobs[-1].patterns, q=4, k=1, sigma_prime=20, mode="filter"))
     assert plans[-1].info()["table_bytes"] > 32 * 1024
     # a plan shared by two jobs (same patterns, another text)
     t2 = gen_text(70_001, jobs[3].recipe["sigma"], rng=12)
@@ -118,7 +120,7 @@ def test_batch_device_wide_sort(torch_cuda, mag):
         jobs.append(make_job(1 << 18, 4, "uniform", 2000, 8, 0.5, 300 + s))
     total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
     assert total > 8192
-    plans = [mag.Plan(j.patterns) for j in jobs]
+    plans = [mag.Plan(j.patterns, mode="dense" if i % 2 else "filter") for i, j in enumerate(jobs)]
     texts = _upload(torch, [j.text for j in jobs], [1, 2, 3, 0])
     b = mag.Batch(plans)
     b.bind(texts, total + 100)
@@ -185,7 +187,7 @@ def test_batch_rebind_smaller(torch_cuda, mag):
 def test_batch_rejects_wide_plans(torch_cuda, mag):
     t = gen_text(10_000, 64, rng=1)
     p = gen_patterns(t, 10, 64, 5, 64, rng=2)
-    plan = mag.Plan(p, q=1, k=1, sigma_prime=64)       # W = 64
+    plan = mag.Plan(p, q=1, k=1, sigma_prime=64, mode="filter")       # W = 64
     with pytest.raises(mag.MagError):
         mag.Batch([plan])
 

@@ -128,3 +128,19 @@ def test_empty_pattern_set_is_valid():
     mag = _lib_or_skip()
     plan = mag.Plan(np.zeros((0, 8), dtype=np.uint8))
     assert plan.info()["r"] == 0
+
+
+def test_auto_mode_scans_densely_when_the_filter_cannot_prune():
+    import paper_1405_5483_amd as mag
+    from synth import make_job
+    # DNA, m = 8, 5000 patterns: every class holds almost every gram
+    sat = make_job(1 << 16, 4, "uniform", 5000, 8, 0.5, 1)
+    info = mag.Plan(sat.patterns).info()
+    assert info["dense"] == 1 and info["est_verif"] >= 0.1
+    assert 12 <= info["bloom_log2"] <= 20
+    # 64 symbols, m = 32, few patterns: a selective filter
+    sel = make_job(1 << 16, 64, "uniform", 50, 32, 0.5, 2)
+    info = mag.Plan(sel.patterns).info()
+    assert info["dense"] == 0 and 0 <= info["est_verif"] < 0.1
+    assert mag.Plan(sel.patterns, mode="dense").info()["dense"] == 1
+    assert mag.Plan(sat.patterns, mode="filter").info()["dense"] == 0

@@ -78,7 +78,7 @@ def test_parity_and_counts(torch_cuda, mag, case):
     sigma, n, r, m, q, k, sp, kind = case
     T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
     P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
-    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="filter")
     pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
     ref = om.occ_hashed(T, P)
     assert ref[0].size > 0
@@ -87,6 +87,23 @@ def test_parity_and_counts(torch_cuda, mag, case):
     assert st["samples"] == want["samples"]
     assert st["cand_windows"] == want["cand_windows"]
     assert st["verifications"] == want["verifications"]
+    assert st["matches"] == ref[0].size
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-r{c[2]}-m{c[3]}" for c in CASES])
+def test_dense_mode_parity(torch_cuda, mag, case):
+    """Every start position through the Bloom bitmap: the same occurrence
+    list; every occurring position passes the bitmap."""
+    sigma, n, r, m, q, k, sp, kind = case
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="dense")
+    assert plan.info()["dense"] == 1
+    pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+    ref = om.occ_hashed(T, P)
+    _assert_same(pos, ids, ref)
+    assert st["samples"] == n - m + 1
+    assert st["verifications"] == st["cand_windows"] >= np.unique(ref[0]).size
     assert st["matches"] == ref[0].size
 
 
@@ -201,7 +218,7 @@ def test_async_entry_point(torch_cuda, mag):
 def test_dna1m_workload(torch_cuda, mag, sel):
     job = workload("dna1m")
     kw = {} if sel == "heuristic" else dict(q=8, k=1, sigma_prime=4)
-    plan = mag.Plan(job.patterns, **kw)
+    plan = mag.Plan(job.patterns, mode="filter", **kw)
     pos, ids, st = _gpu_occ(torch_cuda, mag, job.text, plan, stats=True)
     ref = om.occ_hashed(job.text, job.patterns)
     _assert_same(pos, ids, ref)
@@ -214,13 +231,14 @@ def test_zipf256m_full_size(torch_cuda, mag):
     job = workload("zipf256m")
     ref = om.occ_hashed(job.text, job.patterns)
     buf = torch_cuda.from_numpy(job.text).cuda()
-    for kw in (dict(), dict(q=4, k=1, sigma_prime=16), dict(q=4, k=2, sigma_prime=16)):
+    for kw in (dict(mode="filter"), dict(q=4, k=1, sigma_prime=16), dict(q=4, k=2, sigma_prime=16),
+               dict(mode="dense")):
         plan = mag.Plan(job.patterns, **kw)
         occ = mag.scan(buf, plan).cpu().numpy()
         _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
     # counters on a prefix the numpy oracle finishes quickly
     pre = job.text[: 1 << 21]
-    plan = mag.Plan(job.patterns)
+    plan = mag.Plan(job.patterns, mode="filter")
     pos, ids, st = _gpu_occ(torch_cuda, mag, pre, plan, stats=True)
     _assert_same(pos, ids, om.occ_hashed(pre, job.patterns))
     info = plan.info()
@@ -232,7 +250,7 @@ def test_prot1g_full_size(torch_cuda, mag):
     job = workload("prot1g")
     ref = om.occ_hashed(job.text, job.patterns)
     buf = torch_cuda.from_numpy(job.text).cuda()
-    for kw in (dict(), dict(q=5, k=1, sigma_prime=20)):
+    for kw in (dict(mode="filter"), dict(q=5, k=1, sigma_prime=20), dict(mode="dense")):
         plan = mag.Plan(job.patterns, **kw)
         occ = mag.scan(buf, plan).cpu().numpy()
         _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
