@@ -34,17 +34,42 @@ __global__ __launch_bounds__(kNT) void k_dense(DenseArgs a) {
     uint32_t qn = 0;
     uint64_t nhit = 0;
     const uint32_t hw = a.v.hw, mw = a.v.mw, lastmask = a.v.lastmask;
-    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    // a tile's resource, size and the offset of its first position
+    auto tile_at = [&](uint64_t tile, __amdgpu_buffer_rsrc_t &rs, uint32_t &nrec, uint32_t &p0) {
         const int64_t x0 = (int64_t)tile * kDenseTilePositions;
-        // bytes the tile's windows touch
-        int64_t b1 = x0 + kDenseTilePositions + 40;
+        int64_t b1 = x0 + kDenseTilePositions + 40;       // bytes the tile's windows touch
         if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
         const uint64_t pa0 = (a.delta + (uint64_t)x0) & ~15ull;
         const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
-        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
-        const uint32_t p0 = (uint32_t)(a.delta + (uint64_t)x0 - pa0);
-        dense_tile<kNT>(rs, (uint32_t)(pa1 - pa0), p0, x0, a.last, s_bloom, a.bshift, hw, mw, lastmask,
-                        queue, qn, vargs, tid, lane, nhit);
+        rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
+        nrec = (uint32_t)(pa1 - pa0);
+        p0 = (uint32_t)(a.delta + (uint64_t)x0 - pa0);
+    };
+    // the next tile's bytes are loaded before the current tile's windows are tested
+    uint64_t tile = blockIdx.x;
+    uint32_t W[10], Wn[10];
+    uint32_t p0 = 0;
+    if (tile < a.ntiles) {
+        __amdgpu_buffer_rsrc_t rs;
+        uint32_t nrec;
+        tile_at(tile, rs, nrec, p0);
+        dense_load<kNT>(rs, nrec, p0, tid, W);
+    }
+    for (; tile < a.ntiles; tile += gridDim.x) {
+        const uint64_t nt = tile + gridDim.x;
+        uint32_t p0n = 0;
+        if (nt < a.ntiles) {
+            __amdgpu_buffer_rsrc_t rs;
+            uint32_t nrec;
+            tile_at(nt, rs, nrec, p0n);
+            dense_load<kNT>(rs, nrec, p0n, tid, Wn);
+        }
+        const int64_t x0 = (int64_t)tile * kDenseTilePositions;
+        dense_test(W, p0 & 3u, x0 + 16 * (int64_t)tid, a.last, s_bloom, a.bshift, hw, mw, lastmask, queue,
+                   qn, vargs, lane, nhit);
+#pragma unroll
+        for (int t = 0; t < 10; ++t) W[t] = Wn[t];
+        p0 = p0n;
     }
     if (qn) drain_partial(vargs, queue, qn, lane);
     unsigned long long nh = nhit;

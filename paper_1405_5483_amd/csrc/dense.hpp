@@ -43,15 +43,11 @@ namespace dev {
 // text) loads single dwords, each range-checked on its own, so no text byte
 // comes back as an out-of-range zero. Positions that pass the bitmap go to
 // this wave's queue; full queues are verified at once.
+// The 40 bytes thread tid needs, [a, a + 40) with a = (p0 & ~3) + 16*tid.
 template <int NT>
-__device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t nrec, uint32_t p0,
-                                           int64_t x0, int64_t last, const uint32_t *s_bloom,
-                                           uint32_t bshift, uint32_t hw, uint32_t mw, uint32_t lastmask,
-                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int tid,
-                                           int lane, uint64_t &nhit) {
-    const uint32_t d = p0 & 3u;                 // the same for every lane
+__device__ __forceinline__ void dense_load(__amdgpu_buffer_rsrc_t rs, uint32_t nrec, uint32_t p0, int tid,
+                                           uint32_t (&W)[10]) {
     const uint32_t a = (p0 & ~3u) + 16u * (uint32_t)tid;
-    uint32_t W[10];                             // bytes [a, a + 40)
     if (a + 40u <= nrec) {
         const uint4 v0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)a, 0, 0));
         const uint4 v1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(a + 16), 0, 0));
@@ -63,10 +59,17 @@ __device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t n
 #pragma unroll
         for (int t = 0; t < 10; ++t) W[t] = ld32(rs, a + 4u * t);
     }
-    uint32_t V[9];                              // bytes from position x0 + 16*tid on
+}
+
+// Tests the 16 windows of thread tid (positions xb .. xb + 15, xb = x0 +
+// 16*tid; d = p0 & 3) whose bytes are in W.
+__device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, int64_t xb, int64_t last,
+                                           const uint32_t *s_bloom, uint32_t bshift, uint32_t hw,
+                                           uint32_t mw, uint32_t lastmask, uint64_t *queue, uint32_t &qn,
+                                           const VerifyArgs *vp, int lane, uint64_t &nhit) {
+    uint32_t V[9];                              // bytes from position xb on
 #pragma unroll
     for (int t = 0; t < 9; ++t) V[t] = __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
-    const int64_t xb = x0 + 16 * (int64_t)tid;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -98,6 +101,21 @@ __device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t n
             }
         }
     }
+}
+
+// One whole tile: start positions x0 .. x0 + 16*NT - 1 (those up to `last`),
+// thread tid taking the 16 consecutive positions from x0 + 16*tid. rs covers
+// the tile's bytes, nrec is its size and p0 the resource offset of x0.
+template <int NT>
+__device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t nrec, uint32_t p0,
+                                           int64_t x0, int64_t last, const uint32_t *s_bloom,
+                                           uint32_t bshift, uint32_t hw, uint32_t mw, uint32_t lastmask,
+                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int tid,
+                                           int lane, uint64_t &nhit) {
+    uint32_t W[10];
+    dense_load<NT>(rs, nrec, p0, tid, W);
+    dense_test(W, p0 & 3u, x0 + 16 * (int64_t)tid, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp,
+               lane, nhit);
 }
 
 }  // namespace dev
