@@ -89,11 +89,41 @@ def map_greedy(patterns: np.ndarray, sigma_prime: int) -> np.ndarray:
     return mu
 
 
+def bits_shift(patterns: np.ndarray, sigma_prime: int) -> int:
+    """The shift s of the bit-field map (Section 3.3, combined alphabet mapping
+    and q-gram generation): sigma' = 2^l and mu(c) = (c >> s) & (2^l - 1).
+    Reading: s in 0..8-l is chosen so that the heaviest code carries the
+    least pattern-byte weight (ties to the smaller s); the paper's DNA example
+    shifts by one for the same reason (the low two bits of C and G agree)."""
+    l = sigma_prime.bit_length() - 1
+    if sigma_prime < 1 or (1 << l) != sigma_prime or l > 8:
+        raise ValueError("the bit-field map needs sigma' = 2^l with l <= 8")
+    hist = byte_histogram(patterns)
+    best, best_s = None, 0
+    for sh in range(0, 8 - l + 1):
+        load = [0] * sigma_prime
+        for c in range(256):
+            load[(c >> sh) & (sigma_prime - 1)] += int(hist[c])
+        if best is None or max(load) < best:
+            best, best_s = max(load), sh
+    return best_s
+
+
+def map_bits(patterns: np.ndarray, sigma_prime: int) -> np.ndarray:
+    """mu(c) = (c >> s) & (sigma' - 1), s from bits_shift: the gram code
+    sum_t mu(S[t]) sigma'^t is then the concatenation of l-bit fields of the
+    Section 3.3 formula, S[0] in the low bits."""
+    sh = bits_shift(patterns, sigma_prime)
+    return np.array([(c >> sh) & (sigma_prime - 1) for c in range(256)], dtype=np.uint8)
+
+
 def alphabet_map(patterns: np.ndarray, sigma_prime: int, kind: str = "greedy") -> np.ndarray:
     if kind == "greedy":
         return map_greedy(patterns, sigma_prime)
     if kind == "rank":
         return map_rank(patterns, sigma_prime)
+    if kind == "bits":
+        return map_bits(patterns, sigma_prime)
     raise ValueError(kind)
 
 

@@ -272,3 +272,29 @@ def test_heuristic_values_for_workloads():
     for name, want in expect.items():
         job = workload(name, n=1 << 20)
         assert mm.heuristic_params(job.patterns) == want, name
+
+
+# ------------------------------------------------- bit-field alphabet map
+
+def test_bits_map_matches_the_papers_dna_multiply_formula():
+    """Section 3.3 computes DNA 4-gram codes as
+    (((x >> 1) & 0x03030303) * 0x40100401) >> 24 with the first character in
+    the high bits. For ACGT patterns the bit-field map picks the same shift
+    (1), and our code is that value with its four 2-bit digits reversed."""
+    P = np.frombuffer(b"ACGTTGCAACGGTTCA", dtype=np.uint8).reshape(2, 8)
+    assert mm.bits_shift(P, 4) == 1
+    mu = mm.map_bits(P, 4)
+    for g in itertools.product(b"ACGTacgt", repeat=4):
+        x = g[0] | g[1] << 8 | g[2] << 16 | g[3] << 24
+        paper = ((((x >> 1) & 0x03030303) * 0x40100401) & 0xFFFFFFFF) >> 24
+        rev = sum(((paper >> (2 * (3 - t))) & 3) << (2 * t) for t in range(4))
+        assert mm.gram_code(bytes(g), mu, 4) == rev
+
+
+def test_bits_map_low_nibbles():
+    P = np.frombuffer(bytes(range(0x30, 0x70)), dtype=np.uint8).reshape(4, 16)
+    # every byte 0x30..0x6F once: the low nibble spreads them evenly (4 per code)
+    assert mm.bits_shift(P, 16) == 0
+    mu = mm.map_bits(P, 16)
+    assert [int(mu[c]) for c in (0x30, 0x4F, 0x6A)] == [0, 15, 10]
+    assert mm.gram_code(bytes([0x31, 0x32]), mu, 16) == 1 + 2 * 16
