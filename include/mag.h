@@ -71,7 +71,11 @@ typedef enum {
 /* Alphabet reduction mu: byte -> [0, sigma') (Section 3.3). */
 typedef enum {
     MAG_MAP_GREEDY = 0, /* equal-weight bins by longest-processing-time greedy */
-    MAG_MAP_RANK = 1    /* frequency rank; ranks >= sigma'-1 share the last code */
+    MAG_MAP_RANK = 1,   /* frequency rank; ranks >= sigma'-1 share the last code */
+    MAG_MAP_BITS = 2    /* bit fields (combined alphabet mapping and q-gram
+                           generation): sigma' = 2^l, mu(c) = (c >> s) & (2^l-1)
+                           with the shift s that spreads the pattern bytes most
+                           evenly; the scan computes codes without a map table */
 } mag_map_kind;
 
 typedef struct {
@@ -105,6 +109,8 @@ typedef struct {
     uint32_t n_unique;    /* distinct patterns                                  */
     int32_t dense;        /* 1: scans test every start position (mag_mode)      */
     int32_t bloom_log2;   /* bits of the dense mode's Bloom bitmap (log2)       */
+    int32_t bits_shift;   /* s of the bit-field map (MAG_MAP_BITS), else 0      */
+    int32_t reserved0;
     uint64_t n_codes;     /* sigma'^q mask-table entries                        */
     uint64_t table_bytes; /* n_codes * entry_bytes                              */
     double est_verif;     /* estimated verifications per text byte of the

@@ -20,7 +20,7 @@ MAG_E_DEVICE = -4
 MAG_E_OVERFLOW = -5
 
 SELECT = {"heuristic": 0, "explicit": 1, "learned": 2, "autotune": 3}
-MAP_KIND = {"greedy": 0, "rank": 1}
+MAP_KIND = {"greedy": 0, "rank": 1, "bits": 2}
 MODE = {"auto": 0, "filter": 1, "dense": 2}
 
 
@@ -49,6 +49,7 @@ class MagPlanDesc(ctypes.Structure):
         ("entry_bytes", ctypes.c_int32), ("map_kind", ctypes.c_int32), ("select", ctypes.c_int32),
         ("r", ctypes.c_uint32), ("m", ctypes.c_uint32), ("n_unique", ctypes.c_uint32),
         ("dense", ctypes.c_int32), ("bloom_log2", ctypes.c_int32),
+        ("bits_shift", ctypes.c_int32), ("reserved0", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("est_verif", ctypes.c_double),
     ]

@@ -251,6 +251,7 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->n_unique = p->n_unique;
     d->dense = p->dense;
     d->bloom_log2 = p->bloom_log2;
+    d->bits_shift = p->bits_shift;
     d->n_codes = p->n_codes;
     d->table_bytes = p->table.size();
     d->est_verif = p->est_verif;

@@ -97,6 +97,7 @@ struct mag_plan {
     // filter parameters
     int q = 1, k = 1, sigma_prime = 1, L = 0, mprime = 0, W = 0, esz = 1;
     int map_kind = MAG_MAP_GREEDY, select = MAG_SELECT_HEURISTIC;
+    int bits_shift = 0;              // s of the bit-field map
     uint8_t mu[256] = {0};
     uint64_t n_codes = 0;
     std::vector<uint8_t> table;      // n_codes * esz bytes

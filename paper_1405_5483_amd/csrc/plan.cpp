@@ -65,6 +65,30 @@ void map_greedy(mag_plan *p) {
     }
 }
 
+// mu(c) = (c >> s) & (sigma' - 1) for sigma' = 2^l, with the shift s in
+// 0..8-l that leaves the heaviest code the least pattern-byte weight (ties to
+// the smaller s).
+void map_bits(mag_plan *p) {
+    uint64_t hist[256] = {0};
+    for (uint8_t c : p->patterns) hist[c]++;
+    const int sp = p->sigma_prime;
+    int l = 0;
+    while ((1 << l) < sp) ++l;
+    uint64_t best = UINT64_MAX;
+    int best_s = 0;
+    for (int sh = 0; sh <= 8 - l; ++sh) {
+        std::vector<uint64_t> load(sp, 0);
+        for (int c = 0; c < 256; ++c) load[(c >> sh) & (sp - 1)] += hist[c];
+        const uint64_t mx = *std::max_element(load.begin(), load.end());
+        if (mx < best) {
+            best = mx;
+            best_s = sh;
+        }
+    }
+    p->bits_shift = best_s;
+    for (int c = 0; c < 256; ++c) p->mu[c] = (uint8_t)((c >> best_s) & (sp - 1));
+}
+
 void heuristic(const mag_plan *p, int budget, int &q, int &k, int &sp) {
     uint64_t hist[256];
     std::vector<int> order;
@@ -228,7 +252,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (m == 0) return fail(MAG_E_INVALID, "pattern length m must be >= 1");
     if (m > (uint32_t)kMaxM) return fail(MAG_E_UNSUPPORTED, "pattern length above 64");
     if (r > 0 && !patterns) return fail(MAG_E_INVALID, "patterns is NULL");
-    if (prm.map_kind != MAG_MAP_GREEDY && prm.map_kind != MAG_MAP_RANK)
+    if (prm.map_kind != MAG_MAP_GREEDY && prm.map_kind != MAG_MAP_RANK && prm.map_kind != MAG_MAP_BITS)
         return fail(MAG_E_INVALID, "unknown map_kind");
     if (prm.mode < MAG_MODE_AUTO || prm.mode > MAG_MODE_DENSE) return fail(MAG_E_INVALID, "unknown mode");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
@@ -269,6 +293,12 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (k < 1 || k > L) return fail(MAG_E_INVALID, "need 1 <= k <= L = (m-q+1)/q");
     if (k > kMaxK) return fail(MAG_E_UNSUPPORTED, "k above 32");
     if (sp < 1 || sp > 256) return fail(MAG_E_INVALID, "sigma' must be in [1, 256]");
+    if (prm.map_kind == MAG_MAP_BITS && (sp & (sp - 1))) {
+        // the bit-field map needs a power of two: the heuristic's sigma' is
+        // lowered to one, an explicit one must be one
+        if (prm.select == MAG_SELECT_EXPLICIT) return fail(MAG_E_INVALID, "the bit-field map needs sigma' = 2^l");
+        while (sp & (sp - 1)) sp &= sp - 1;
+    }
     double codes = std::pow((double)sp, q);
     p->q = q;
     p->k = k;
@@ -282,7 +312,9 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->n_codes = 1;
     for (int t = 0; t < q; ++t) p->n_codes *= (uint64_t)sp;
 
-    if (p->map_kind == MAG_MAP_RANK) map_rank(p); else map_greedy(p);
+    if (p->map_kind == MAG_MAP_RANK) map_rank(p);
+    else if (p->map_kind == MAG_MAP_BITS) map_bits(p);
+    else map_greedy(p);
     build_table(p);
     build_verifier(p);
     build_bloom(p);

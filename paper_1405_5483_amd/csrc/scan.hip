@@ -60,23 +60,37 @@ constexpr int kGroup = MAG_SCAN_GROUP;
 #ifndef MAG_SCAN_PREFETCH
 #define MAG_SCAN_PREFETCH 2
 #endif
+static_assert(MAG_SCAN_PREFETCH >= 1, "at least one round of loads in flight");
 constexpr int kPrefetch = MAG_SCAN_PREFETCH;   // rounds of loads in flight in phase A
 
-template <int G>
-__device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, int32_t p0,
-                                           int s, uint32_t kq) {
-#pragma unroll
-    for (int u = 0; u < G; ++u) w[u] = gram_words<Q>(rs, (uint32_t)(p0 + (s + u) * (int32_t)kq));
+// How phase A turns a gram into its code: Horner with 24-bit multiply-adds,
+// Horner with 32-bit ones, or the bit-field map's field extraction.
+constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2;
+
+template <int CODE>
+__device__ __forceinline__ uint32_t code_of(const GramWords &w, const uint8_t *s_mu, uint32_t sp,
+                                            uint32_t bshift, uint32_t blen) {
+    if constexpr (CODE == kCodeBits) return gram_code_bits<Q>(w, bshift, blen);
+    else return gram_code<Q, CODE == kCodeMul24>(w, s_mu, sp);
 }
 
-template <bool INTERIOR, bool MUL24, bool TLDS, int G, typename ET>
+// Words of G consecutive samples, the first at resource offset o.
+template <int G>
+__device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, uint32_t o,
+                                           uint32_t kq) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) w[u] = gram_words<Q>(rs, o + (uint32_t)u * kq);
+}
+
+template <bool INTERIOR, int CODE, bool TLDS, int G, typename ET>
 __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, int s, int W0,
-                                              uint32_t sp, const uint8_t *s_mu, const ET *s_tab,
-                                              const ET *g_tab, int64_t X0, uint64_t X) {
+                                              uint32_t sp, uint32_t bshift, uint32_t blen,
+                                              const uint8_t *s_mu, const ET *s_tab, const ET *g_tab,
+                                              int64_t X0, uint64_t X) {
     const ET none = (ET)~(ET)0;
     uint32_t g[G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) g[u] = gram_code<Q, MUL24>(w[u], s_mu, sp);
+    for (int u = 0; u < G; ++u) g[u] = code_of<CODE>(w[u], s_mu, sp, bshift, blen);
     ET e[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -90,43 +104,39 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     for (int u = 0; u < G; u += 4) store4(s_E + (s + W0 + u), e + u);
 }
 
-template <bool INTERIOR, bool MUL24, bool TLDS, typename ET>
+template <bool INTERIOR, int CODE, bool TLDS, typename ET>
 __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq,
-                                        uint32_t sp, const uint8_t *s_mu, const ET *s_tab,
+                                        uint32_t sp, uint32_t bshift, uint32_t blen,
+                                        const uint8_t *s_mu, const ET *s_tab,
                                         const ET *g_tab, int W0, uint32_t TS, int64_t X0, uint64_t X,
                                         int tid) {
     constexpr int G = kGroup;
+    constexpr int P = kPrefetch;
     const int step = G * kProducerThreads;
     int s = G * tid - W0;
-    if (kPrefetch >= 2) {
-        // two rounds in flight while a third is processed
-        GramWords b0[G], b1[G];
-        load_group<G>(b0, rs, p0, s, kq);
-        load_group<G>(b1, rs, p0, s + step, kq);
-        for (;;) {
-            if (s >= (int)TS) break;
-            process_group<INTERIOR, MUL24, TLDS, G>(b0, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
-            load_group<G>(b0, rs, p0, s + 2 * step, kq);
-            s += step;
-            if (s >= (int)TS) break;
-            process_group<INTERIOR, MUL24, TLDS, G>(b1, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
-            load_group<G>(b1, rs, p0, s + 2 * step, kq);
-            s += step;
-        }
-    } else {
-        GramWords cur[G];
-        load_group<G>(cur, rs, p0, s, kq);
-        for (; s < (int)TS; s += step) {
-            GramWords nxt[G];
-            load_group<G>(nxt, rs, p0, s + step, kq);
-            process_group<INTERIOR, MUL24, TLDS, G>(cur, s_E, s, W0, sp, s_mu, s_tab, g_tab, X0, X);
+    // P rounds of words in flight: round r is processed while rounds r+1 ..
+    // r+P-1 load, and its buffer is refilled with round r+P. Offsets advance
+    // by adds (one multiply per tile).
+    const uint32_t ostep = (uint32_t)step * kq;
+    uint32_t o = (uint32_t)(p0 + s * (int32_t)kq);
+    GramWords buf[P][G];
 #pragma unroll
-            for (int u = 0; u < G; ++u) cur[u] = nxt[u];
+    for (int r = 0; r < P; ++r) load_group<G>(buf[r], rs, o + (uint32_t)r * ostep, kq);
+    o += (uint32_t)P * ostep;
+    for (;;) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            if (s >= (int)TS) return;
+            process_group<INTERIOR, CODE, TLDS, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
+                                                  g_tab, X0, X);
+            load_group<G>(buf[r], rs, o, kq);
+            o += ostep;
+            s += step;
         }
     }
 }
 
-template <typename ET, typename DT, bool TLDS, bool MUL24>
+template <typename ET, typename DT, bool TLDS, int CODE>
 __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr int EPV = 16 / (int)sizeof(ET);            // entries per 16-byte LDS read
@@ -161,6 +171,7 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     const uint32_t topshift = a.W - a.k;
     // sigma' <= 256: the mask tells the compiler so, and Horner keeps 24-bit multiply-adds
     const uint32_t sp = a.sp & 0x1FFu, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
+    const uint32_t bshift = a.bshift & 7u, blen = a.blen & 15u;   // bit-field map (CODE == kCodeBits)
     const int W0 = (int)a.w0;                             // warm-up entries kept before a tile
     const int64_t last = (int64_t)a.n - (int64_t)a.m;   // last valid start position
 
@@ -186,9 +197,9 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
                 const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
                 ET *E = (it & 1) ? s_E1 : s_E0;
                 if (interior)
-                    phase_a<true, MUL24, TLDS>(E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<true, CODE, TLDS>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
                 else
-                    phase_a<false, MUL24, TLDS>(E, rs, p0, kq, sp, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<false, CODE, TLDS>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
             }
         } else if (it >= 1) {
             // Shift-Or over the lane's S samples. The W0 entries before them
@@ -281,9 +292,9 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     }
 }
 
-template <typename ET, typename DT, bool TLDS, bool MUL24>
+template <typename ET, typename DT, bool TLDS, int CODE>
 mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stream) {
-    auto fn = k_scan<ET, DT, TLDS, MUL24>;
+    auto fn = k_scan<ET, DT, TLDS, CODE>;
     static int configured_bytes = 0;    // per instantiation
     if ((int)shmem > configured_bytes) {
         // not every runtime needs the opt-in; a real LDS overflow fails the launch below
@@ -308,9 +319,12 @@ mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stre
 template <typename ET, typename DT>
 mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int ncu,
                      hipStream_t stream) {
-    if (tlds) return launch_one<ET, DT, true, true>(a, shmem, ncu, stream);   // LDS tables are small
-    return mul24 ? launch_one<ET, DT, false, true>(a, shmem, ncu, stream)
-                 : launch_one<ET, DT, false, false>(a, shmem, ncu, stream);
+    if (tlds) {   // LDS tables are small: 24-bit Horner steps always suffice
+        return a.blen ? launch_one<ET, DT, true, kCodeBits>(a, shmem, ncu, stream)
+                      : launch_one<ET, DT, true, kCodeMul24>(a, shmem, ncu, stream);
+    }
+    return mul24 ? launch_one<ET, DT, false, kCodeMul24>(a, shmem, ncu, stream)
+                 : launch_one<ET, DT, false, kCodeMul32>(a, shmem, ncu, stream);
 }
 
 }  // namespace

@@ -10,10 +10,10 @@
 namespace mag {
 
 #ifndef MAG_SCAN_THREADS
-#define MAG_SCAN_THREADS 512
+#define MAG_SCAN_THREADS 1024
 #endif
 #ifndef MAG_SCAN_PRODUCERS
-#define MAG_SCAN_PRODUCERS 6
+#define MAG_SCAN_PRODUCERS 12
 #endif
 constexpr int kScanThreads = MAG_SCAN_THREADS;        // threads per scan workgroup
 constexpr int kScanProducerWaves = MAG_SCAN_PRODUCERS; // waves that compute mask entries
@@ -29,6 +29,7 @@ struct ScanArgs {
     uint32_t e_lds;            // bytes of LDS for one buffer of a tile's mask entries
     uint32_t table_vec;        // 16-byte vectors of the mask table (LDS copy)
     uint32_t w0;               // entries kept before a tile's first sample (>= m'-1)
+    uint32_t bshift, blen;     // bit-field map: field shift and width l (blen 0: map table)
     const uint8_t *mu;
     const void *table;
     uint64_t *counters;        // [1] candidate windows [2] verifications

@@ -55,6 +55,23 @@ __device__ __forceinline__ uint32_t gram_code(const GramWords &gw, const uint8_t
     return g;
 }
 
+// Code of a q-gram under the bit-field map of Section 3.3: the l bits from
+// bit `shift` of every byte, S[0]'s field lowest. Equal to gram_code with
+// mu(c) = (c >> shift) & (2^l - 1), without the map table.
+template <int Q>
+__device__ __forceinline__ uint32_t gram_code_bits(const GramWords &gw, uint32_t shift, uint32_t l) {
+    const uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    const uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    uint32_t g = 0;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        const uint32_t field = t < 4 ? __builtin_amdgcn_ubfe(lo, 8 * t + shift, l)
+                                     : __builtin_amdgcn_ubfe(hi, 8 * (t - 4) + shift, l);
+        g |= field << (l * t);
+    }
+    return g;
+}
+
 // Raw buffer resource over [base, base + bytes). The operands are wave-uniform;
 // readfirstlane says so to the compiler, which otherwise may keep them in
 // vector registers and wrap every load in a loop over distinct values.

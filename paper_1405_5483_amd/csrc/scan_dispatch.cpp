@@ -84,6 +84,12 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
     // entries past them
     a.e_lds = (uint32_t)((((uint64_t)a.tile_samples + a.w0 + 16) * esz + 15) & ~15ull);
 
+    if (p->map_kind == MAG_MAP_BITS && p->sigma_prime > 1) {
+        a.bshift = (uint32_t)p->bits_shift;
+        uint32_t l = 0;
+        while ((1 << l) < p->sigma_prime) ++l;
+        a.blen = l;
+    }
     a.mu = p->dev.mu;
     a.table = p->dev.table;
     a.counters = s.counters;

@@ -55,6 +55,10 @@ CASES = [
     (64, 10, 64, 2, 7, 9, "rank"),         # W = 28 -> 4-byte entries
     (2, 5, 9, 5, 1, 2, "greedy"),
     (4, 8, 12, 4, 1, 1, "greedy"),
+    (4, 100, 16, 4, 1, 4, "bits"),         # bit-field map: DNA, two bits
+    (64, 40, 32, 4, 1, 16, "bits"),        # low nibbles of 0x30..0x6F
+    (20, 50, 16, 3, 2, 8, "bits"),
+    (64, 10, 64, 2, 7, 2, "bits"),
 ]
 
 
@@ -73,6 +77,8 @@ def test_plan_tables_equal_oracle(case):
     assert info["n_codes"] == f.n_codes
     mu, table = plan.export()
     assert np.array_equal(mu, f.mu)
+    if kind == "bits":
+        assert info["bits_shift"] == mm.bits_shift(P, sp)
     want = f.table()
     bits = 8 * info["entry_bytes"]
     mask = np.uint64((1 << bits) - 1) if bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -128,6 +134,17 @@ def test_empty_pattern_set_is_valid():
     mag = _lib_or_skip()
     plan = mag.Plan(np.zeros((0, 8), dtype=np.uint8))
     assert plan.info()["r"] == 0
+
+
+def test_bits_map_needs_a_power_of_two():
+    mag = _lib_or_skip()
+    T = gen_text(4096, 20, rng=1)
+    P = gen_patterns(T, 30, 16, 15, 20, rng=2)
+    with pytest.raises(mag.MagError):
+        mag.Plan(P, q=3, k=1, sigma_prime=12, map_kind="bits")
+    # the heuristic's sigma' is lowered to a power of two
+    sp = mag.Plan(P, map_kind="bits").info()["sigma_prime"]
+    assert sp & (sp - 1) == 0
 
 
 def test_auto_mode_scans_densely_when_the_filter_cannot_prune():

@@ -70,6 +70,11 @@ CASES = [
     (20, 150_000, 30, 15, 7, 1, 6, "greedy"),     # q = 7: grams straddle two words
     (20, 150_000, 30, 17, 8, 1, 5, "rank"),       # q = 8
     (4, 100_000, 20, 16, 1, 16, 4, "greedy"),     # k = L
+    (4, 200_003, 100, 16, 4, 1, 4, "bits"),       # bit-field map, DNA (shift 1)
+    (64, 250_000, 60, 32, 4, 1, 16, "bits"),      # low nibbles
+    (64, 180_001, 40, 32, 4, 2, 16, "bits"),
+    (20, 150_000, 30, 17, 8, 1, 4, "bits"),       # q = 8 from two words
+    (64, 120_000, 20, 32, 2, 3, 256, "bits"),     # l = 8: the byte itself
 ]
 
 
