@@ -36,6 +36,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources that determine the scan kernel's code; HBM traffic counted on an
+# earlier build is reported only while these are unchanged
+SCAN_SOURCES = ("scan.hip", "scan_common.hpp", "scan_args.hpp", "verify.hpp", "scan_dispatch.cpp")
+PMC_SUMMARY = "profiles/k_scan_{workload}_pmc.md"
 CPU_SHARE = 16          # host threads one GPU's share of the box may use
 SAMPLE_BYTES = 16 << 20 # text prefix the autotuner times candidates on
 
@@ -89,6 +93,50 @@ def scan_kernel_ms(mag, text, plan, out, cnt, repeats=2):
         best = min(best, mag.profile_read()["scan_ms"])
     mag.profile_enable(False)
     return best
+
+
+def scan_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in SCAN_SOURCES:
+        with open(os.path.join(ROOT, "paper_1405_5483_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str, info: dict):
+    """HBM bytes per scan launch from the committed rocprofv3 FETCH_SIZE and
+    WRITE_SIZE summary of this workload, each scaled by what the counter reads
+    for a copy of known size; None when the summary is missing, was taken with
+    other parameters, or the scan kernel's sources have changed since."""
+    path = os.path.join(ROOT, PMC_SUMMARY.format(workload=workload))
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+    if rec is None:
+        return None, "summary has no traffic record"
+    if [rec["q"], rec["k"], rec["sigma_prime"]] != [info["q"], info["k"], info["sigma_prime"]]:
+        return None, "counters were taken with other parameters"
+    if rec["src_sha256"] != scan_source_hash():
+        return None, "scan kernel changed since the counters were taken"
+    return rec["traffic_bytes"], path
+
+
+def copy_calibration(torch) -> None:
+    """Three device-to-device copies of 256 MiB: the reference kernel whose
+    FETCH_SIZE and WRITE_SIZE readings calibrate the counters."""
+    a = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    b = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    assert bool((b[:: 1 << 20] == 1).all())
+    del a, b
 
 
 def cpu_baseline(job, threads: int, max_bytes: int):
@@ -252,6 +300,8 @@ def main() -> int:
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned-vs-fixed, batch and other-workload sections")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -305,6 +355,12 @@ def main() -> int:
     alg_bytes = n                         # the filter kernel reads the text once
     achieved = alg_bytes / (scan_ms * 1e-3) / 1e9
 
+    traffic, traffic_src = profiled_traffic(args.workload, info)
+    log(f"HBM traffic per launch: {traffic} ({traffic_src})")
+    if args.copy_calibration:
+        log("copy calibration: 3 x 256 MiB")
+        copy_calibration(torch)
+
     # the same workload with the fixed heuristic's parameters
     fixed_plan = mag.Plan(job.patterns)
     finfo = fixed_plan.info()
@@ -356,7 +412,8 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": "k_scan", "kernel_ms": round(scan_ms, 5),
                      "alg_bytes_per_launch": alg_bytes},
         "fixed_params": fixed,
