@@ -9,7 +9,9 @@ it.
   every ``(i, id)`` with ``T[i..i+m) == P_id``, from C (``occ.c``): a brute
   force double loop and a chained-hash matcher.
 * ``oracle.method`` - the filter's intermediate objects written from their
-  definitions (Sections 2-3): alphabet maps, the fixed parameter heuristic,
+  definitions (Sections 2-3): alphabet maps (per byte, and on whole q-grams
+  through a 64-bit hash whose constants are a reading: the paper names no
+  hash), the fixed parameter heuristic,
   superimposed q-gram classes, the Shift-Or mask table and the set of
   candidate windows, plus the class-density estimate of Section 2.
 * ``oracle.mlp``    - float64 forward/backward/Adam of the parameter-selector

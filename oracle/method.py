@@ -12,7 +12,9 @@ Notation (Sections 2 and 3):
   shift s = 0..q-1 (Section 2, non-overlapping q-grams). All shifts share
   ``L = (m - q + 1) // q`` gram positions.
 * gram code of ``S[0..q)``: ``sum_t mu(S[t]) * sigma'**t`` (Section 3.2,
-  "Implementation"; S[0] is the least significant digit).
+  "Implementation"; S[0] is the least significant digit). Under the alphabet
+  mapping on q-grams (Section 3.3) the gram itself is mapped instead: its
+  code is the top log2(sigma') bits of a 64-bit hash of its raw bytes.
 * superimposed class at gram position b: ``C[b] = {code(P_i[s+bq .. s+bq+q)) :
   i < r, s < q}`` (Section 2, superimposition).
 * ``k``: the sampling parameter of Section 3.1; sub-pattern j takes gram
@@ -117,6 +119,76 @@ def map_bits(patterns: np.ndarray, sigma_prime: int) -> np.ndarray:
     return np.array([(c >> sh) & (sigma_prime - 1) for c in range(256)], dtype=np.uint8)
 
 
+# --------------------------------------------- alphabet mapping on q-grams
+
+MASK64 = (1 << 64) - 1
+FMIX_C1 = 0xFF51AFD7ED558CCD
+FMIX_C2 = 0xC4CEB9FE1A85EC53
+
+
+def fmix64(x: int) -> int:
+    """MurmurHash3's 64-bit finalizer (A. Appleby, public domain): three
+    xor-shifts by 33 with two odd multiplies between them, modulo 2^64."""
+    x &= MASK64
+    x ^= x >> 33
+    x = (x * FMIX_C1) & MASK64
+    x ^= x >> 33
+    x = (x * FMIX_C2) & MASK64
+    x ^= x >> 33
+    return x
+
+
+def gram_key(seq) -> int:
+    """The raw bytes of a q-gram (q <= 8) as one integer, S[0] in the low byte."""
+    key = 0
+    for t, c in enumerate(seq):
+        key |= int(c) << (8 * t)
+    return key
+
+
+def qgram_code(seq, log2_sigma_prime: int) -> int:
+    """Code of a q-gram under the alphabet mapping on q-grams (Section 3.3,
+    "Alphabet mapping on the q-grams"): the mapped q-gram alphabet has
+    sigma' = 2^b symbols and a gram's symbol is the top b bits of
+    fmix64(key). Reading: the paper leaves the mapping method open (bin
+    packing is one example) and stores the mapping by hashing; here the
+    hash itself is the mapping, which fixes the table at exactly sigma'
+    entries for any q, needs no stored keys, and keeps every gram of the
+    text mappable. q is limited to 8 so that a gram is one 64-bit key."""
+    b = log2_sigma_prime
+    if b == 0:
+        return 0
+    return fmix64(gram_key(seq)) >> (64 - b)
+
+
+def qgram_codes(grams: np.ndarray, log2_sigma_prime: int) -> np.ndarray:
+    """qgram_code of every row of an [N, q] byte array, as int64."""
+    g = np.asarray(grams, dtype=np.uint8)
+    n, q = g.shape
+    if q > 8:
+        raise ValueError("q-grams of the q-gram map hold at most 8 bytes")
+    b = log2_sigma_prime
+    if b == 0 or n == 0:
+        return np.zeros(n, dtype=np.int64)
+    x = np.zeros(n, dtype=np.uint64)
+    for t in range(q):
+        x |= g[:, t].astype(np.uint64) << np.uint64(8 * t)
+    s33 = np.uint64(33)
+    x ^= x >> s33
+    x *= np.uint64(FMIX_C1)          # wraps modulo 2^64
+    x ^= x >> s33
+    x *= np.uint64(FMIX_C2)
+    x ^= x >> s33
+    return (x >> np.uint64(64 - b)).astype(np.int64)
+
+
+def log2_exact(v: int) -> int:
+    b = int(v).bit_length() - 1
+    if v < 1 or (1 << b) != v:
+        raise ValueError("sigma' of this map must be a power of two")
+    return b
+
+
 def alphabet_map(patterns: np.ndarray, sigma_prime: int, kind: str = "greedy") -> np.ndarray:
     if kind == "greedy":
         return map_greedy(patterns, sigma_prime)
@@ -149,6 +221,14 @@ def entry_bytes(W: int) -> int:
         if W <= 8 * b:
             return b
     raise ValueError("W > 64")
+
+
+def entry_bits(W: int, kind: str) -> int:
+    """Bits one stored mask-table entry takes: tables of the q-gram map with
+    W <= 4 are packed (1, 2 or 4 bits per entry), all others use whole bytes."""
+    if kind == "qgram" and W <= 4:
+        return 1 if W <= 1 else 2 if W <= 2 else 4
+    return 8 * entry_bytes(W)
 
 
 def heuristic_q(sigma: int, r: int, m: int) -> int:
@@ -193,6 +273,48 @@ def heuristic_params(patterns: np.ndarray, table_budget: int = DEFAULT_TABLE_BUD
     while sig > 1 and sig ** q * eb > table_budget:
         sig -= 1
     return q, k, sig
+
+
+QGRAM_TABLE_BUDGET = 4 << 20     # bytes the q-gram map's heuristic allows for the mask table
+QGRAM_LOAD = 32                  # target codes per distinct gram of the fullest class
+
+
+def class_grams(patterns: np.ndarray, q: int, W: int) -> list[set]:
+    """For b < W, the distinct raw q-grams (as bytes) of every pattern's
+    shift-s gram at position b, over all q shifts: the classes before any
+    alphabet mapping."""
+    p = np.asarray(patterns, dtype=np.uint8)
+    out = []
+    for b in range(W):
+        grams = set()
+        for s in range(q):
+            off = s + b * q
+            grams.update(bytes(row) for row in p[:, off:off + q])
+        out.append(grams)
+    return out
+
+
+def heuristic_params_qgram(patterns: np.ndarray, table_budget: int = QGRAM_TABLE_BUDGET):
+    """(q, k, sigma') for the q-gram map. Reading (the paper gives none for
+    this variant; Section 3.3 only says q may be large and sigma' is chosen to
+    control the table): q is the largest allowed (min(8, (m+1)//2)), k = 1
+    (the longest sub-pattern), and sigma' is the smallest power of two with
+    at least QGRAM_LOAD codes per distinct gram of the fullest class, halved
+    while the table exceeds the budget (sigma' >= 2)."""
+    p = np.asarray(patterns, dtype=np.uint8)
+    r, m = p.shape
+    q = max(1, min(MAX_Q, (m + 1) // 2))
+    L = gram_positions(m, q)
+    k = 1
+    W = k * sub_pattern_length(L, k)
+    D = max((len(c) for c in class_grams(p, q, W)), default=0) if r else 0
+    eb = entry_bits(W, "qgram")
+    sp = 2
+    while sp < QGRAM_LOAD * D:
+        sp *= 2
+    while sp > 2 and sp * eb > 8 * table_budget:
+        sp //= 2
+    return q, k, sp
 
 
 # ----------------------------------------------------------- q-gram classes
@@ -269,9 +391,21 @@ class Filter:
             raise ValueError("need 1 <= k <= L")
         self.mprime = sub_pattern_length(self.L, k)
         self.W = k * self.mprime
-        self.mu = alphabet_map(p, sigma_prime, kind)
-        self.n_codes = sigma_prime ** q
-        self.C = classes(p, self.mu, sigma_prime, q, self.W)
+        self.kind = kind
+        if kind == "qgram":
+            if q > MAX_Q:
+                raise ValueError("q above 8")
+            self.log2_sp = log2_exact(sigma_prime)
+            self.mu = None
+            self.n_codes = sigma_prime
+            self.C = [set(int(c) for c in qgram_codes(
+                np.frombuffer(b"".join(sorted(g)), dtype=np.uint8).reshape(-1, q), self.log2_sp))
+                for g in class_grams(p, q, self.W)]
+        else:
+            self.mu = alphabet_map(p, sigma_prime, kind)
+            self.n_codes = sigma_prime ** q
+            self.C = classes(p, self.mu, sigma_prime, q, self.W)
+        self.entry_bits = entry_bits(self.W, kind)
 
     def table(self) -> np.ndarray:
         return mask_table(self.C, self.W, self.n_codes)
@@ -286,6 +420,9 @@ class Filter:
         t = np.asarray(text, dtype=np.uint8)
         X = self.n_samples(t.size)
         kq = self.k * self.q
+        if self.kind == "qgram":
+            idx = np.arange(X, dtype=np.int64)[:, None] * kq + np.arange(self.q)[None, :]
+            return qgram_codes(t[idx].reshape(X, self.q), self.log2_sp)
         codes = np.zeros(X, dtype=np.int64)
         for d in range(self.q):
             codes += self.mu[t[np.arange(X, dtype=np.int64) * kq + d]].astype(np.int64) * self.sigma_prime ** d

@@ -10,6 +10,7 @@ Graham's bound for the greedy bin packing.
 """
 
 import itertools
+import math
 import json
 import os
 
@@ -182,6 +183,11 @@ CASES = [
     (64, 3000, 20, 32, 2, 3, 16, "greedy"),
     (2, 2000, 5, 9, 5, 1, 2, "greedy"),
     (4, 2000, 8, 12, 4, 1, 1, "greedy"),
+    (20, 3000, 30, 16, 8, 1, 1 << 12, "qgram"),     # q-gram map, W = 1
+    (4, 3000, 10, 16, 5, 1, 1 << 10, "qgram"),      # W = 2
+    (64, 3000, 20, 32, 6, 2, 1 << 9, "qgram"),      # W = 4
+    (64, 3000, 20, 32, 3, 3, 1 << 6, "qgram"),      # W = 9: whole-byte entries
+    (20, 2000, 12, 16, 4, 1, 2, "qgram"),
 ]
 
 
@@ -298,3 +304,94 @@ def test_bits_map_low_nibbles():
     mu = mm.map_bits(P, 16)
     assert [int(mu[c]) for c in (0x30, 0x4F, 0x6A)] == [0, 15, 10]
     assert mm.gram_code(bytes([0x31, 0x32]), mu, 16) == 1 + 2 * 16
+
+
+# ------------------------------------------------ alphabet mapping on q-grams
+
+def _unxorshift33(y):
+    # x ^ (x >> 33) keeps the top 33 bits, so applying it again restores x
+    return y ^ (y >> 33)
+
+
+def test_fmix64_is_a_bijection():
+    # invert each step from the mathematics: odd multipliers have inverses
+    # modulo 2^64 and the 33-bit xor-shift is its own inverse
+    inv1 = pow(mm.FMIX_C1, -1, 1 << 64)
+    inv2 = pow(mm.FMIX_C2, -1, 1 << 64)
+    rng = np.random.default_rng(11)
+    for x in [0, 1, 2, (1 << 64) - 1, 1 << 63] + [int(v) for v in rng.integers(0, 1 << 63, 500)]:
+        y = mm.fmix64(x)
+        y = _unxorshift33(y)
+        y = (y * inv2) % (1 << 64)
+        y = _unxorshift33(y)
+        y = (y * inv1) % (1 << 64)
+        assert _unxorshift33(y) == x
+    assert mm.FMIX_C1 % 2 == 1 and mm.FMIX_C2 % 2 == 1
+
+
+def test_fmix64_avalanche():
+    # the finalizer's purpose: flipping any input bit flips every output bit
+    # with probability near 1/2 (a dropped or mistyped step breaks this)
+    rng = np.random.default_rng(12)
+    keys = [int(v) for v in rng.integers(0, 1 << 63, 4000, dtype=np.int64)]
+    keys = [k | (int(rng.integers(0, 2)) << 63) for k in keys]
+    flips = np.zeros((64, 64))
+    for k in keys:
+        h = mm.fmix64(k)
+        for i in range(64):
+            d = h ^ mm.fmix64(k ^ (1 << i))
+            flips[i] += [(d >> j) & 1 for j in range(64)]
+    bias = np.abs(flips / len(keys) - 0.5)
+    assert bias.max() < 0.04, bias.max()
+
+
+def test_qgram_codes_vectorized_equal_scalar():
+    rng = np.random.default_rng(13)
+    for q in range(1, 9):
+        g = rng.integers(0, 256, (300, q), dtype=np.uint8)
+        for b in (0, 1, 7, 16, 28):
+            want = [mm.qgram_code(row, b) for row in g]
+            assert mm.qgram_codes(g, b).tolist() == want
+    assert mm.gram_key(b"\x01\x02") == 0x0201
+
+
+def test_qgram_class_occupancy_is_balls_in_bins():
+    # D distinct grams hashed into sigma' codes occupy sigma'(1-(1-1/sigma')^D)
+    # codes on average (variance below the mean)
+    T = gen_text(200_000, 20, rng=14)
+    P = gen_patterns(T, 2000, 16, 1000, 20, rng=15)
+    for b in (10, 12, 14):
+        f = mm.Filter(P, 8, 1, 1 << b, "qgram")
+        D = len(mm.class_grams(P, 8, 1)[0])
+        sp = 1 << b
+        expect = sp * (1 - (1 - 1 / sp) ** D)
+        got = len(f.C[0])
+        assert abs(got - expect) < 4 * math.sqrt(expect) + 2, (b, got, expect)
+        assert max(f.C[0]) < sp
+
+
+def test_qgram_candidate_rate():
+    # uniform text over 20 symbols with q = 8: text grams almost never equal a
+    # pattern gram, so a sample passes with probability |C[0]| / sigma'
+    T = gen_text(300_000, 20, rng=16)
+    P = gen_patterns(gen_text(50_000, 20, rng=17), 500, 16, 500, 20, rng=18)
+    f = mm.Filter(P, 8, 1, 1 << 14, "qgram")
+    cnt = f.counts(T)
+    rate = cnt["cand_windows"] / cnt["samples"]
+    expect = len(f.C[0]) / f.n_codes
+    assert abs(rate - expect) < 5 * math.sqrt(expect / cnt["samples"]) + 1e-3, (rate, expect)
+
+
+def test_qgram_heuristic_invariants():
+    for sigma, r, m in ((4, 100, 16), (64, 1000, 32), (20, 3000, 16), (20, 50, 8), (2, 20, 5)):
+        T = gen_text(30_000, sigma, rng=r)
+        P = gen_patterns(T, r, m, r // 2, sigma, rng=m)
+        q, k, sp = mm.heuristic_params_qgram(P)
+        assert q == min(8, (m + 1) // 2) and k == 1
+        f = mm.Filter(P, q, k, sp, "qgram")
+        D = max(len(c) for c in mm.class_grams(P, q, f.W))
+        assert sp & (sp - 1) == 0
+        eb = mm.entry_bits(f.W, "qgram")
+        assert sp * eb <= 8 * mm.QGRAM_TABLE_BUDGET
+        assert sp >= mm.QGRAM_LOAD * D or 2 * sp * eb > 8 * mm.QGRAM_TABLE_BUDGET
+        assert sp == 2 or sp < 2 * mm.QGRAM_LOAD * D
