@@ -18,7 +18,8 @@ measurements:
 * batch: the 512-job workload (about 1.1 GB of text) as per-job scans with
   fixed parameters, and batched (one persistent launch, graph replay) with
   fixed and with learned parameters, every job checked against the oracle;
-* workloads: the 1 MiB DNA and the 1 GiB protein-like scans.
+* workloads: the 1 MiB DNA and the 1 GiB protein-like scans, each with the
+  heuristic's, the selector's and the q-gram map heuristic's plan.
 """
 
 from __future__ import annotations
@@ -59,6 +60,8 @@ def plan_for(mag, patterns, select: str, text=None, selector=None):
         log(f"autotune picked {best}")
         return mag.Plan(patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
                         map_kind=best["map_kind"])
+    if select == "qgram":
+        return mag.Plan(patterns, map_kind="qgram")
     if select.startswith("explicit:"):
         q, k, sp = (int(v) for v in select.split(":")[1].split(","))
         return mag.Plan(patterns, q=q, k=k, sigma_prime=sp)
@@ -271,7 +274,7 @@ def single_workload(torch, mag, selector, name: str, steps: int):
     text = torch.from_numpy(job.text).cuda()
     ref = om.occ_hashed(job.text, job.patterns, threads=CPU_SHARE)
     res = {"text_bytes": job.n, "r": job.r, "m": job.m}
-    for sel in ("heuristic", "learned"):
+    for sel in ("heuristic", "learned", "qgram"):
         plan = plan_for(mag, job.patterns, sel, text, selector)
         info = plan.info()
         occ = mag.scan(text, plan, out_cap=ref[0].size + 1024)
@@ -282,9 +285,13 @@ def single_workload(torch, mag, selector, name: str, steps: int):
         res[sel] = {"GBps": round(job.n / (ms * 1e-3) / 1e9, 2), "ms_per_step": round(ms, 4),
                     "scan_kernel_ms": round(prof["scan_ms"] / max(prof["launches"], 1), 4),
                     "q": info["q"], "k": info["k"], "sigma_prime": info["sigma_prime"],
+                    "map": _MAP_NAMES[info["map_kind"]], "dense": bool(info["dense"]),
                     "bit_exact": exact}
         plan.close()
     return res
+
+
+_MAP_NAMES = {0: "greedy", 1: "rank", 2: "bits", 3: "qgram"}
 
 
 def main() -> int:
@@ -294,7 +301,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf256m")
     ap.add_argument("--select", default="learned",
-                    help="learned | heuristic | autotune | explicit:q,k,sigma'")
+                    help="learned | heuristic | qgram | autotune | explicit:q,k,sigma'")
     ap.add_argument("--eval-sets", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")

@@ -68,14 +68,37 @@ typedef enum {
                             filter that passes every window, Section 3.2)      */
 } mag_mode;
 
+/* Where filter survivors are verified (Section 3.2's exact check). */
+typedef enum {
+    MAG_VERIFY_AUTO = 0,     /* deferred when a filter scan is expected to
+                                verify at least 2^24 start positions, else
+                                inline (the dense mode always inline)          */
+    MAG_VERIFY_INLINE = 1,   /* by the filter kernel's own waves               */
+    MAG_VERIFY_DEFERRED = 2  /* the filter kernel appends the start positions
+                                to a device buffer and a verification kernel
+                                with a full-occupancy grid checks them; starts
+                                past the buffer's capacity are verified inline,
+                                so the result never depends on it              */
+} mag_verify;
+
 /* Alphabet reduction mu: byte -> [0, sigma') (Section 3.3). */
 typedef enum {
     MAG_MAP_GREEDY = 0, /* equal-weight bins by longest-processing-time greedy */
     MAG_MAP_RANK = 1,   /* frequency rank; ranks >= sigma'-1 share the last code */
-    MAG_MAP_BITS = 2    /* bit fields (combined alphabet mapping and q-gram
+    MAG_MAP_BITS = 2,   /* bit fields (combined alphabet mapping and q-gram
                            generation): sigma' = 2^l, mu(c) = (c >> s) & (2^l-1)
                            with the shift s that spreads the pattern bytes most
                            evenly; the scan computes codes without a map table */
+    MAG_MAP_QGRAM = 3   /* alphabet mapping on q-grams (Section 3.3): the whole
+                           gram (its q <= 8 raw bytes, S[0] in the low byte of a
+                           64-bit key) is mapped to the top log2(sigma') bits of
+                           MurmurHash3's 64-bit finalizer. sigma' is a power of
+                           two in [1, 2^28] and counts table entries directly
+                           (not sigma'^q); tables with W <= 4 are packed at 1, 2
+                           or 4 bits per entry. The heuristic takes the largest
+                           q, k = 1 and sigma' >= 32 codes per distinct gram of
+                           the fullest class within table_budget (0 = 8 MiB).
+                           Not accepted by mag_batch_create unless dense.      */
 } mag_map_kind;
 
 typedef struct {
@@ -85,9 +108,12 @@ typedef struct {
     int32_t k;            /* sampling parameter (explicit selection)            */
     int32_t sigma_prime;  /* reduced alphabet size (explicit selection)         */
     int32_t table_budget; /* bytes the heuristic allows for the mask table;
-                             0 = 96 KiB                                         */
+                             0 = 96 KiB (8 MiB for MAG_MAP_QGRAM)                */
     int32_t mode;         /* mag_mode                                           */
-    int32_t reserved[5];  /* must be zero                                       */
+    int32_t verify;       /* mag_verify                                         */
+    int32_t verify_buffer;/* entries of the deferred-start buffer; 0 = sized
+                             from the expected verifications (2^20 .. 2^26)     */
+    int32_t reserved[3];  /* must be zero                                       */
 } mag_params;
 
 typedef struct {
@@ -110,9 +136,11 @@ typedef struct {
     int32_t dense;        /* 1: scans test every start position (mag_mode)      */
     int32_t bloom_log2;   /* bits of the dense mode's Bloom bitmap (log2)       */
     int32_t bits_shift;   /* s of the bit-field map (MAG_MAP_BITS), else 0      */
-    int32_t reserved0;
-    uint64_t n_codes;     /* sigma'^q mask-table entries                        */
-    uint64_t table_bytes; /* n_codes * entry_bytes                              */
+    int32_t entry_bits;   /* bits a stored table entry takes: 1, 2 or 4 when
+                             packed (MAG_MAP_QGRAM with W <= 4), else
+                             8 * entry_bytes                                    */
+    uint64_t n_codes;     /* mask-table entries: sigma'^q (sigma' for QGRAM)    */
+    uint64_t table_bytes; /* n_codes * entry_bits / 8, padded to 16 bytes       */
     double est_verif;     /* estimated verifications per text byte of the
                              filter (-1: not evaluated)                        */
 } mag_plan_desc;
@@ -131,7 +159,8 @@ typedef struct mag_plan mag_plan;
  * copied, so the caller may free it on return). params may be NULL (heuristic,
  * greedy map). Host-only work: device tables are uploaded on first use.
  * Errors: m == 0 or m > 64, explicit q with 2q-1 > m, k outside [1, L],
- * sigma' outside [1, 256] or a mask table above 1 GiB -> MAG_E_INVALID /
+ * sigma' outside [1, 256] (for MAG_MAP_QGRAM: not a power of two in
+ * [1, 2^28]) or a mask table above 1 GiB -> MAG_E_INVALID /
  * MAG_E_UNSUPPORTED. r == 0 is valid (every scan returns no match). */
 mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
                            const mag_params *params, mag_plan **out);
@@ -143,9 +172,12 @@ void mag_plan_destroy(mag_plan *plan);
 /* Resolved parameters and table sizes of a plan. */
 mag_status mag_plan_info(const mag_plan *plan, mag_plan_desc *desc);
 
-/* Host copies of the plan's alphabet map (256 bytes) and mask table
- * (desc.table_bytes bytes, little-endian entries of desc.entry_bytes). Either
- * output may be NULL. table_cap is the capacity of table_out in bytes. */
+/* Host copies of the plan's alphabet map (256 bytes; all zero for
+ * MAG_MAP_QGRAM, which has none) and mask table (desc.table_bytes bytes,
+ * little-endian entries of desc.entry_bytes; packed tables hold entry c in
+ * bits [c * entry_bits, (c + 1) * entry_bits) of the little-endian bit
+ * stream). Either output may be NULL. table_cap is the capacity of table_out
+ * in bytes. */
 mag_status mag_plan_export(const mag_plan *plan, uint8_t *mu_out, void *table_out,
                            uint64_t table_cap);
 

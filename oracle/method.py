@@ -275,7 +275,7 @@ def heuristic_params(patterns: np.ndarray, table_budget: int = DEFAULT_TABLE_BUD
     return q, k, sig
 
 
-QGRAM_TABLE_BUDGET = 4 << 20     # bytes the q-gram map's heuristic allows for the mask table
+QGRAM_TABLE_BUDGET = 8 << 20     # bytes the q-gram map's heuristic allows for the mask table
 QGRAM_LOAD = 32                  # target codes per distinct gram of the fullest class
 
 

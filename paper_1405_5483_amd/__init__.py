@@ -18,7 +18,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, MagError, MagParams, MagPlanDesc,
+from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, VERIFY, MagError, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
 __all__ = ["Plan", "Batch", "Selector", "scan", "scan_async", "scan_batch", "autotune",
@@ -48,7 +48,7 @@ class Plan:
     def __init__(self, patterns, *, select: str = "heuristic", q: int | None = None,
                  k: int | None = None, sigma_prime: int | None = None,
                  map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
-                 candidate: int | None = None):
+                 verify: str = "auto", verify_buffer: int = 0, candidate: int | None = None):
         p = _as_patterns(patterns)
         self.r, self.m = int(p.shape[0]), int(p.shape[1])
         self.candidate = candidate        # selector grid index of a learned pick (informational)
@@ -63,6 +63,8 @@ class Plan:
         prm.sigma_prime = int(sigma_prime or 0)
         prm.table_budget = int(table_budget)
         prm.mode = MODE[mode]
+        prm.verify = VERIFY[verify]
+        prm.verify_buffer = int(verify_buffer)
         handle = ctypes.c_void_p()
         self._h = None
         check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,
@@ -80,10 +82,24 @@ class Plan:
         check(lib().mag_plan_info(self.handle, ctypes.byref(d)), "mag_plan_info")
         return {name: getattr(d, name) for name, _ in MagPlanDesc._fields_}
 
-    def export(self):
-        """(mu [256] uint8, mask table [sigma'^q] of the entry dtype)."""
+    def export(self, raw: bool = False):
+        """(mu [256] uint8, mask table with one entry per code in the entry
+        dtype). Packed tables (entry_bits < 8) are unpacked to uint8 entries
+        whose bits above entry_bits are 1, or returned as the stored bytes
+        with raw=True."""
         info = self.info()
         mu = np.empty(256, dtype=np.uint8)
+        eb = info["entry_bits"]
+        if eb < 8:
+            buf = np.empty(info["table_bytes"], dtype=np.uint8)
+            check(lib().mag_plan_export(self.handle, mu.ctypes.data, buf.ctypes.data,
+                                        buf.nbytes), "mag_plan_export")
+            if raw:
+                return mu, buf
+            n = info["n_codes"]
+            bits = np.unpackbits(buf, bitorder="little")[: n * eb].reshape(n, eb).astype(np.uint16)
+            vals = (bits << np.arange(eb, dtype=np.uint16)).sum(axis=1)
+            return mu, (vals | ((0xFF << eb) & 0xFF)).astype(np.uint8)
         table = np.empty(info["n_codes"], dtype=_ENTRY_DTYPE[info["entry_bytes"]])
         check(lib().mag_plan_export(self.handle, mu.ctypes.data, table.ctypes.data,
                                     table.nbytes), "mag_plan_export")

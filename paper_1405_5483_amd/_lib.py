@@ -20,7 +20,8 @@ MAG_E_DEVICE = -4
 MAG_E_OVERFLOW = -5
 
 SELECT = {"heuristic": 0, "explicit": 1, "learned": 2, "autotune": 3}
-MAP_KIND = {"greedy": 0, "rank": 1, "bits": 2}
+MAP_KIND = {"greedy": 0, "rank": 1, "bits": 2, "qgram": 3}
+VERIFY = {"auto": 0, "inline": 1, "deferred": 2}
 MODE = {"auto": 0, "filter": 1, "dense": 2}
 
 
@@ -33,7 +34,9 @@ class MagParams(ctypes.Structure):
         ("sigma_prime", ctypes.c_int32),
         ("table_budget", ctypes.c_int32),
         ("mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("verify", ctypes.c_int32),
+        ("verify_buffer", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -49,7 +52,7 @@ class MagPlanDesc(ctypes.Structure):
         ("entry_bytes", ctypes.c_int32), ("map_kind", ctypes.c_int32), ("select", ctypes.c_int32),
         ("r", ctypes.c_uint32), ("m", ctypes.c_uint32), ("n_unique", ctypes.c_uint32),
         ("dense", ctypes.c_int32), ("bloom_log2", ctypes.c_int32),
-        ("bits_shift", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("bits_shift", ctypes.c_int32), ("entry_bits", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("est_verif", ctypes.c_double),
     ]

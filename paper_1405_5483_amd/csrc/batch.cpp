@@ -83,6 +83,9 @@ mag_status mag_batch_create(mag_plan *const *plans, uint32_t njobs, mag_batch **
         const mag_plan *p = plans[j];
         if (!p) return fail(MAG_E_INVALID, "plans[" + std::to_string(j) + "] is NULL");
         if (p->r == 0 || p->dense) continue;   // no filter state in these jobs
+        if (p->map_kind == MAG_MAP_QGRAM)
+            return fail(MAG_E_UNSUPPORTED, "batched filter jobs need a per-byte alphabet map (job " +
+                                               std::to_string(j) + " maps q-grams)");
         if (p->W > 32 || p->k >= 32)
             return fail(MAG_E_UNSUPPORTED, "batched jobs need W = k*m' <= 32 and k < 32 (job " +
                                                std::to_string(j) + ")");

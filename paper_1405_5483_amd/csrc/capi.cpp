@@ -2,6 +2,7 @@
 // device upload, scratch management and the scan entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -61,6 +62,43 @@ mag_status ensure_keys(mag_plan *p, uint64_t cap, hipStream_t stream) {
     }
     sc.keys_cap = want;
     return MAG_OK;
+}
+
+// Pending-start buffer of at least `cap` entries (grown like the key buffers).
+mag_status ensure_pending(mag_plan *p, uint64_t cap, hipStream_t stream) {
+    Scratch &sc = p->scratch;
+    if (sc.pending_cap >= cap && sc.pending) return MAG_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (sc.pending) {
+        (void)hipFree(sc.pending);
+        sc.pending = nullptr;
+        sc.pending_cap = 0;
+    }
+    e = hipMalloc(&sc.pending, cap * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of the deferred-start buffer failed");
+    }
+    sc.pending_cap = cap;
+    if (!sc.seg_count) {
+        // zero once here; afterwards the finishing kernel of every scan clears them
+        e = hipMalloc(&sc.seg_count, kPendingSegments * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMemsetAsync(sc.seg_count, 0, kPendingSegments * sizeof(uint64_t), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "deferred-start counters");
+    }
+    return MAG_OK;
+}
+
+// Capacity of the deferred-start buffer for a scan expected to verify
+// `expect` start positions, or 0 to verify inline.
+uint64_t pending_capacity(double expect) {
+    if (expect >= 0.0 && expect < (double)(1 << 20)) return 0;
+    const double want = expect < 0.0 ? (double)(1ull << 24) : 2.0 * expect;
+    uint64_t cap = 1ull << 20;
+    while ((double)cap < want && cap < kPendingMax) cap <<= 1;
+    return cap;
 }
 
 }  // namespace
@@ -229,6 +267,8 @@ void mag_plan_destroy(mag_plan *p) {
         (void)hipFree(p->scratch.hist);
         (void)hipFree(p->scratch.radix_off);
         (void)hipFree(p->scratch.keys);
+        (void)hipFree(p->scratch.pending);
+        (void)hipFree(p->scratch.seg_count);
         (void)hipSetDevice(cur);
     }
     delete p;
@@ -252,6 +292,7 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->dense = p->dense;
     d->bloom_log2 = p->bloom_log2;
     d->bits_shift = p->bits_shift;
+    d->entry_bits = p->entry_bits;
     d->n_codes = p->n_codes;
     d->table_bytes = p->table.size();
     d->est_verif = p->est_verif;
@@ -302,6 +343,22 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     const uint64_t samples = p->dense ? (n >= p->m && p->r ? n - p->m + 1 : 0)
                                       : (n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0);
 
+    // many expected verifications: the filter kernels defer them
+    const double expect = p->r == 0 ? 0.0
+                          : p->dense ? p->bloom_fp * (double)samples
+                          : p->est_verif < 0.0 ? -1.0 : p->est_verif * (double)n;
+    uint64_t pcap = 0;
+    const bool defer = p->verify == MAG_VERIFY_DEFERRED ||
+                       (p->verify == MAG_VERIFY_AUTO && !p->dense &&
+                        (expect < 0.0 || expect >= kDeferMinVerifications));
+    if (samples && defer)
+        pcap = p->verify_buffer ? p->verify_buffer
+                                : pending_capacity(expect < 0.0 ? expect : std::max(expect, (double)(1 << 20)));
+    if (pcap) {
+        s = ensure_pending(p, pcap, stream);
+        if (s != MAG_OK) return s;
+    }
+
     ScanLaunch sl;
     sl.text = d_text;
     sl.n = n;
@@ -309,6 +366,9 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     sl.cap = out_cap;
     sl.counters = p->scratch.counters;
     sl.idbits = idbits;
+    sl.pending = pcap ? p->scratch.pending : nullptr;
+    sl.pending_cap = pcap ? p->scratch.pending_cap : 0;
+    sl.seg_count = pcap ? p->scratch.seg_count : nullptr;
     ProfileRecord rec{{nullptr, nullptr, nullptr}};
     bool prof;
     {
@@ -339,6 +399,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     } else {
         s = launch_scan(p, sl, stream);
     }
+    if (s == MAG_OK && sl.pending) s = launch_verify(make_verify_args(p, sl), stream);
     if (s != MAG_OK) return s;
     if (prof) (void)hipEventRecord(rec.ev[1], stream);
     if (idbits_out) *idbits_out = idbits;

@@ -20,6 +20,19 @@ constexpr int kMaxW = 64;           // automaton bits
 constexpr int kMaxK = 32;           // candidate mask of one window fits 32 bits
 constexpr uint64_t kMaxTableBytes = 1ull << 30;
 constexpr int kDefaultTableBudget = 96 * 1024;
+// alphabet mapping on q-grams: sigma' = 2^b codes with b <= 28; the heuristic
+// aims at kQgramLoad codes per distinct gram of the fullest class within
+// kQgramTableBudget bytes of table
+constexpr int kMaxQgramLog2 = 28;
+constexpr int kQgramTableBudget = 8 << 20;
+constexpr int kQgramLoad = 32;
+// filter scans expected to verify at least this many start positions defer
+// them to the verification kernel (measured: below it, and for the dense
+// mode, whose verification overlaps its ALU-bound position tests, inline
+// verification is as fast or faster)
+constexpr double kDeferMinVerifications = 1 << 24;
+constexpr uint64_t kPendingMax = 1ull << 26;
+constexpr uint32_t kPendingSegments = 256;   // deferred-start buffer segments, one counter each
 constexpr int kHashWords = 4;       // the verification hash reads the first 16 bytes
 // Scratch counters: [0] occurrences [1] candidate windows [2] verifications,
 // [4] and [8..11] the count and stats that mag_scan reads back, and
@@ -85,6 +98,9 @@ struct Scratch {
     uint32_t *hist = nullptr;       // device-wide radix sort: digit counts [256][chunks]
     uint64_t *radix_off = nullptr;  // their start offsets [256][chunks], then 256 digit totals
     uint64_t radix_chunks = 0;
+    uint64_t *pending = nullptr;    // start positions deferred to the verification kernel
+    uint64_t pending_cap = 0;
+    uint64_t *seg_count = nullptr;  // kPendingSegments counters (cleared by the finishing kernel)
 };
 
 }  // namespace mag
@@ -98,9 +114,11 @@ struct mag_plan {
     int q = 1, k = 1, sigma_prime = 1, L = 0, mprime = 0, W = 0, esz = 1;
     int map_kind = MAG_MAP_GREEDY, select = MAG_SELECT_HEURISTIC;
     int bits_shift = 0;              // s of the bit-field map
+    int qbits = 0;                   // log2 sigma' of the q-gram map
+    int entry_bits = 8;              // stored bits per table entry (1, 2, 4: packed)
     uint8_t mu[256] = {0};
     uint64_t n_codes = 0;
-    std::vector<uint8_t> table;      // n_codes * esz bytes
+    std::vector<uint8_t> table;      // n_codes * esz bytes, or packed entries
 
     // verification set: distinct patterns, their ids, and a probe table
     uint32_t n_unique = 0, slot_bits = 1;
@@ -110,6 +128,9 @@ struct mag_plan {
     // dense mode: test every start position against the Bloom bitmaps
     int mode = MAG_MODE_AUTO, dense = 0, bloom_log2 = mag::kBloomMinLog2;
     double est_verif = 0.0;          // estimated verifications per text byte of the filter
+    double bloom_fp = 0.0;           // estimated share of start positions the Bloom bitmap passes
+    int verify = MAG_VERIFY_AUTO;    // inline or deferred verification
+    uint64_t verify_buffer = 0;      // deferred-start buffer entries (0: sized per scan)
     std::vector<uint32_t> bloom, bloom_batch;
 
     // device side
@@ -143,15 +164,23 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
                       const mag_params *params);
 
 // Kernel launches (scan.hip, sort.hip).
+struct VerifyArgs;
 struct ScanLaunch {
-    const uint8_t *text;
-    uint64_t n;
-    uint64_t *keys;       // key output, capacity cap
-    uint64_t cap;
-    uint64_t *counters;   // [0] occurrences [1] candidate windows [2] verifications
-    int idbits;
+    const uint8_t *text = nullptr;
+    uint64_t n = 0;
+    uint64_t *keys = nullptr;      // key output, capacity cap
+    uint64_t cap = 0;
+    uint64_t *counters = nullptr;  // [0] occurrences [1] candidate windows [2] verifications
+                                   // [3] deferred starts
+    int idbits = 0;
+    uint64_t *pending = nullptr;   // deferred start positions (NULL: verify inline)
+    uint64_t pending_cap = 0;      // entries, split into kPendingSegments segments
+    uint64_t *seg_count = nullptr;
 };
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream);
+// Verifies the start positions a filter kernel deferred to v.pending
+// (segment counts in v.seg_count) with a full-occupancy grid (verify.hip).
+mag_status launch_verify(const VerifyArgs &v, hipStream_t stream);
 mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStream_t stream);
 // Occurrence counts up to this many are sorted inside the finishing kernel.
 uint32_t small_sort_max();

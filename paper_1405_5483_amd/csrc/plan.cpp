@@ -6,6 +6,7 @@
 //  - q-gram classes over all q shifts, superimposed Section 2
 //  - k interleaved sub-patterns, Shift-Or masks     Sections 3.1-3.2
 //  - exact verification set                         Section 3.2
+//  - alphabet mapping on whole q-grams (hashed)     Section 3.3
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -89,6 +90,60 @@ void map_bits(mag_plan *p) {
     for (int c = 0; c < 256; ++c) p->mu[c] = (uint8_t)((c >> best_s) & (sp - 1));
 }
 
+// MurmurHash3's 64-bit finalizer: the q-gram map's hash.
+uint64_t fmix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xFF51AFD7ED558CCDull;
+    x ^= x >> 33;
+    x *= 0xC4CEB9FE1A85EC53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+// Code of the q raw bytes at g under the q-gram map with sigma' = 2^qbits.
+uint64_t qgram_code(const uint8_t *g, int q, int qbits) {
+    if (qbits == 0) return 0;
+    uint64_t key = 0;
+    for (int t = 0; t < q; ++t) key |= (uint64_t)g[t] << (8 * t);
+    return fmix64(key) >> (64 - qbits);
+}
+
+int packed_bits(int W) { return W <= 1 ? 1 : W <= 2 ? 2 : 4; }
+
+// Distinct raw grams of class b (all q shifts), as 64-bit keys.
+std::vector<uint64_t> class_keys(const mag_plan *p, int q, int b) {
+    std::vector<uint64_t> keys;
+    keys.reserve((size_t)p->r * q);
+    for (uint32_t i = 0; i < p->r; ++i) {
+        const uint8_t *pat = p->patterns.data() + (size_t)i * p->m;
+        for (int s = 0; s < q; ++s) {
+            uint64_t key = 0;
+            for (int t = 0; t < q; ++t) key |= (uint64_t)pat[s + b * q + t] << (8 * t);
+            keys.push_back(key);
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    return keys;
+}
+
+// (q, k, sigma') of the q-gram map: the largest q, k = 1, and the smallest
+// sigma' = 2^b with kQgramLoad codes per distinct gram of the fullest class,
+// halved while the table exceeds the budget.
+void heuristic_qgram(const mag_plan *p, int budget, int &q, int &k, int &sp) {
+    q = std::max(1, std::min<int>(kMaxQ, ((int)p->m + 1) / 2));
+    k = 1;
+    const int L = ((int)p->m - q + 1) / q;
+    const int W = std::min(L, kMaxW);
+    const int eb = W <= 4 ? packed_bits(W) : 8 * entry_bytes_for(W);
+    uint64_t D = 0;
+    for (int b = 0; p->r && b < W; ++b) D = std::max<uint64_t>(D, class_keys(p, q, b).size());
+    uint64_t s = 2;
+    while (s < (uint64_t)kQgramLoad * D && s < (1ull << kMaxQgramLog2)) s *= 2;
+    while (s > 2 && s * (uint64_t)eb > 8ull * (uint64_t)budget) s /= 2;
+    sp = (int)s;
+}
+
 void heuristic(const mag_plan *p, int budget, int &q, int &k, int &sp) {
     uint64_t hist[256];
     std::vector<int> order;
@@ -121,7 +176,28 @@ void heuristic(const mag_plan *p, int budget, int &q, int &k, int &sp) {
     while (sp > 1 && !fits(sp)) --sp;
 }
 
+// Mask table of the q-gram map. Packed tables hold entry c in bits
+// [c*eb, (c+1)*eb) of the little-endian bit stream, padded to 16 bytes.
+void build_table_qgram(mag_plan *p) {
+    const int q = p->q, W = p->W, eb = p->entry_bits;
+    const uint64_t bytes = eb < 8 ? ((p->n_codes * (uint64_t)eb + 127) / 128) * 16
+                                  : p->n_codes * (uint64_t)p->esz;
+    p->table.assign(bytes, 0xFF);
+    uint8_t *tb = p->table.data();
+    for (int b = 0; b < W; ++b) {
+        for (uint64_t key : class_keys(p, q, b)) {
+            uint8_t g[8];
+            for (int t = 0; t < 8; ++t) g[t] = (uint8_t)(key >> (8 * t));
+            const uint64_t code = qgram_code(g, q, p->qbits);
+            const uint64_t bit = eb < 8 ? code * (uint64_t)eb + (uint64_t)b
+                                        : code * 8ull * (uint64_t)p->esz + (uint64_t)b;
+            tb[bit >> 3] &= (uint8_t)~(1u << (bit & 7));
+        }
+    }
+}
+
 void build_table(mag_plan *p) {
+    if (p->map_kind == MAG_MAP_QGRAM) return build_table_qgram(p);
     const int q = p->q, sp = p->sigma_prime, W = p->W, esz = p->esz;
     p->table.assign(p->n_codes * esz, 0xFF);
     uint8_t *tb = p->table.data();
@@ -188,6 +264,10 @@ void build_bloom(mag_plan *p) {
     int B = kBloomMinLog2;
     while (B < kBloomMaxLog2 && (1ull << B) < 64ull * std::max<uint32_t>(p->n_unique, 1)) ++B;
     p->bloom_log2 = B;
+    // two bits per distinct pattern: a random position passes with the
+    // square of the bitmap's fill
+    const double fill = 1.0 - std::exp(-2.0 * (double)p->n_unique / (double)(1ull << B));
+    p->bloom_fp = fill * fill;
     const int Bb = std::min(B, kBloomBatchLog2);
     p->bloom.assign((1u << B) / 32, 0u);
     p->bloom_batch.assign((1u << Bb) / 32, 0u);
@@ -205,8 +285,48 @@ void build_bloom(mag_plan *p) {
 
 }  // namespace
 
+namespace {
+
+// p_b of the q-gram map: the probability that a text gram (bytes drawn
+// independently by the pattern-set byte frequencies) is one of the class's
+// grams, plus, for every other gram, the share of codes the class occupies.
+double qgram_class_probability(const mag_plan *p, const double *freq, int b) {
+    double exact = 0.0;
+    std::vector<uint64_t> codes;
+    for (uint64_t key : class_keys(p, p->q, b)) {
+        double pr = 1.0;
+        uint8_t g[8];
+        for (int t = 0; t < p->q; ++t) {
+            g[t] = (uint8_t)(key >> (8 * t));
+            pr *= freq[g[t]];
+        }
+        exact += pr;
+        codes.push_back(qgram_code(g, p->q, p->qbits));
+    }
+    std::sort(codes.begin(), codes.end());
+    const double occupied = (double)(std::unique(codes.begin(), codes.end()) - codes.begin());
+    const double share = occupied / (double)p->n_codes;
+    return std::min(1.0, exact + (1.0 - std::min(exact, 1.0)) * share);
+}
+
+}  // namespace
+
 double estimate_verifications(const mag_plan *p) {
     if (p->r == 0) return 0.0;
+    if (p->map_kind == MAG_MAP_QGRAM) {
+        double freq[256] = {0};
+        for (uint8_t c : p->patterns) freq[c] += 1.0;
+        for (double &f : freq) f /= (double)p->patterns.size();
+        std::vector<double> pb(p->W);
+        for (int b = 0; b < p->W; ++b) pb[b] = qgram_class_probability(p, freq, b);
+        double cand = 0.0;
+        for (int j = 0; j < p->k; ++j) {
+            double prod = 1.0;
+            for (int h = 0; h < p->mprime; ++h) prod *= pb[j + h * p->k];
+            cand += prod;
+        }
+        return cand / (double)p->k;
+    }
     if (p->n_codes > (1ull << 22)) return -1.0;
     const int sp = p->sigma_prime, q = p->q, W = p->W, k = p->k, esz = p->esz;
     double byte_freq[256] = {0};
@@ -252,9 +372,13 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (m == 0) return fail(MAG_E_INVALID, "pattern length m must be >= 1");
     if (m > (uint32_t)kMaxM) return fail(MAG_E_UNSUPPORTED, "pattern length above 64");
     if (r > 0 && !patterns) return fail(MAG_E_INVALID, "patterns is NULL");
-    if (prm.map_kind != MAG_MAP_GREEDY && prm.map_kind != MAG_MAP_RANK && prm.map_kind != MAG_MAP_BITS)
+    if (prm.map_kind < MAG_MAP_GREEDY || prm.map_kind > MAG_MAP_QGRAM)
         return fail(MAG_E_INVALID, "unknown map_kind");
+    const bool qgram = prm.map_kind == MAG_MAP_QGRAM;
     if (prm.mode < MAG_MODE_AUTO || prm.mode > MAG_MODE_DENSE) return fail(MAG_E_INVALID, "unknown mode");
+    if (prm.verify < MAG_VERIFY_AUTO || prm.verify > MAG_VERIFY_DEFERRED)
+        return fail(MAG_E_INVALID, "unknown verify");
+    if (prm.verify_buffer < 0) return fail(MAG_E_INVALID, "verify_buffer must be >= 0");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
 
     p->r = r;
@@ -265,6 +389,12 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->select = prm.select;
 
     int q, k, sp;
+    const int budget = prm.table_budget > 0 ? prm.table_budget
+                                            : (qgram ? kQgramTableBudget : kDefaultTableBudget);
+    auto pick = [&]() {
+        if (qgram) heuristic_qgram(p, budget, q, k, sp);
+        else heuristic(p, budget, q, k, sp);
+    };
     switch (prm.select) {
         case MAG_SELECT_LEARNED:    // a pick resolved by mag_select_learned
             if (prm.q > 0 && prm.k > 0 && prm.sigma_prime > 0) {
@@ -273,11 +403,11 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
                 sp = prm.sigma_prime;
                 break;
             }
-            heuristic(p, prm.table_budget > 0 ? prm.table_budget : kDefaultTableBudget, q, k, sp);
+            pick();
             break;
         case MAG_SELECT_HEURISTIC:
         case MAG_SELECT_AUTOTUNE:   // mag_autotune returns its pick as explicit parameters
-            heuristic(p, prm.table_budget > 0 ? prm.table_budget : kDefaultTableBudget, q, k, sp);
+            pick();
             break;
         case MAG_SELECT_EXPLICIT:
             q = prm.q;
@@ -292,14 +422,19 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     const int L = ((int)m - q + 1) / q;
     if (k < 1 || k > L) return fail(MAG_E_INVALID, "need 1 <= k <= L = (m-q+1)/q");
     if (k > kMaxK) return fail(MAG_E_UNSUPPORTED, "k above 32");
-    if (sp < 1 || sp > 256) return fail(MAG_E_INVALID, "sigma' must be in [1, 256]");
+    if (qgram) {
+        if (sp < 1 || sp > (1 << kMaxQgramLog2) || (sp & (sp - 1)))
+            return fail(MAG_E_INVALID, "the q-gram map needs sigma' = 2^b with b <= 28");
+    } else if (sp < 1 || sp > 256) {
+        return fail(MAG_E_INVALID, "sigma' must be in [1, 256]");
+    }
     if (prm.map_kind == MAG_MAP_BITS && (sp & (sp - 1))) {
         // the bit-field map needs a power of two: the heuristic's sigma' is
         // lowered to one, an explicit one must be one
         if (prm.select == MAG_SELECT_EXPLICIT) return fail(MAG_E_INVALID, "the bit-field map needs sigma' = 2^l");
         while (sp & (sp - 1)) sp &= sp - 1;
     }
-    double codes = std::pow((double)sp, q);
+    double codes = qgram ? (double)sp : std::pow((double)sp, q);
     p->q = q;
     p->k = k;
     p->sigma_prime = sp;
@@ -307,18 +442,28 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->mprime = std::min(L / k, kMaxW / k);
     p->W = k * p->mprime;
     p->esz = entry_bytes_for(p->W);
-    if (codes * p->esz > (double)kMaxTableBytes)
+    p->entry_bits = qgram && p->W <= 4 ? packed_bits(p->W) : 8 * p->esz;
+    if (codes * p->entry_bits / 8.0 > (double)kMaxTableBytes)
         return fail(MAG_E_UNSUPPORTED, "mask table above 1 GiB");
     p->n_codes = 1;
-    for (int t = 0; t < q; ++t) p->n_codes *= (uint64_t)sp;
+    if (qgram) {
+        p->n_codes = (uint64_t)sp;
+        p->qbits = 0;
+        while ((1 << p->qbits) < sp) ++p->qbits;
+    } else {
+        for (int t = 0; t < q; ++t) p->n_codes *= (uint64_t)sp;
+    }
 
     if (p->map_kind == MAG_MAP_RANK) map_rank(p);
     else if (p->map_kind == MAG_MAP_BITS) map_bits(p);
+    else if (qgram) std::memset(p->mu, 0, sizeof(p->mu));
     else map_greedy(p);
     build_table(p);
     build_verifier(p);
     build_bloom(p);
     p->mode = prm.mode;
+    p->verify = prm.verify;
+    p->verify_buffer = (uint64_t)prm.verify_buffer;
     p->est_verif = estimate_verifications(p);
     p->dense = prm.mode == MAG_MODE_DENSE ||
                (prm.mode == MAG_MODE_AUTO && p->est_verif >= kDenseVerifPerByte);

@@ -12,8 +12,11 @@
 // working one tile apart on two LDS buffers of mask entries E:
 //  - producer waves take consecutive samples (coalesced 32-bit buffer loads of
 //    the q bytes, range-checked so any text alignment works; the next rounds'
-//    words are prefetched), map the bytes through mu, look the code up in the
-//    mask table (LDS when it fits, else global/L2) and store the entry in E;
+//    words are prefetched), turn the bytes into the gram's code (Horner over
+//    mu, the bit fields of the bit-field map, or the hash of the alphabet
+//    mapping on q-grams), look the code up in the mask table (LDS when it
+//    fits, else global/L2; whole or packed 1/2/4-bit entries) and store the
+//    entry in E;
 //    no sample depends on another, so every lookup can be in flight;
 //  - consumer lanes run the Shift-Or recurrence over a contiguous run of S
 //    entries of the previous tile's E, after the W0 entries before it (warm-up:
@@ -64,13 +67,15 @@ static_assert(MAG_SCAN_PREFETCH >= 1, "at least one round of loads in flight");
 constexpr int kPrefetch = MAG_SCAN_PREFETCH;   // rounds of loads in flight in phase A
 
 // How phase A turns a gram into its code: Horner with 24-bit multiply-adds,
-// Horner with 32-bit ones, or the bit-field map's field extraction.
-constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2;
+// Horner with 32-bit ones, the bit-field map's field extraction, or the hash
+// of the alphabet mapping on q-grams (blen = log2 sigma').
+constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2, kCodeHash = 3;
 
 template <int CODE>
 __device__ __forceinline__ uint32_t code_of(const GramWords &w, const uint8_t *s_mu, uint32_t sp,
                                             uint32_t bshift, uint32_t blen) {
     if constexpr (CODE == kCodeBits) return gram_code_bits<Q>(w, bshift, blen);
+    else if constexpr (CODE == kCodeHash) return gram_code_hash<Q>(w, blen);
     else return gram_code<Q, CODE == kCodeMul24>(w, s_mu, sp);
 }
 
@@ -82,7 +87,7 @@ __device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rs
     for (int u = 0; u < G; ++u) w[u] = gram_words<Q>(rs, o + (uint32_t)u * kq);
 }
 
-template <bool INTERIOR, int CODE, bool TLDS, int G, typename ET>
+template <bool INTERIOR, int CODE, bool TLDS, int PB, int G, typename ET>
 __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, int s, int W0,
                                               uint32_t sp, uint32_t bshift, uint32_t blen,
                                               const uint8_t *s_mu, const ET *s_tab, const ET *g_tab,
@@ -94,7 +99,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     ET e[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-        e[u] = TLDS ? s_tab[g[u]] : g_tab[g[u]];
+        e[u] = table_entry<PB>(TLDS ? s_tab : g_tab, g[u]);
         if (!INTERIOR) {
             const int64_t x = X0 + s + u;
             if (x < 0 || x >= (int64_t)X) e[u] = none;
@@ -104,7 +109,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     for (int u = 0; u < G; u += 4) store4(s_E + (s + W0 + u), e + u);
 }
 
-template <bool INTERIOR, int CODE, bool TLDS, typename ET>
+template <bool INTERIOR, int CODE, bool TLDS, int PB, typename ET>
 __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq,
                                         uint32_t sp, uint32_t bshift, uint32_t blen,
                                         const uint8_t *s_mu, const ET *s_tab,
@@ -127,7 +132,7 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             if (s >= (int)TS) return;
-            process_group<INTERIOR, CODE, TLDS, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
+            process_group<INTERIOR, CODE, TLDS, PB, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
                                                   g_tab, X0, X);
             load_group<G>(buf[r], rs, o, kq);
             o += ostep;
@@ -136,7 +141,7 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
     }
 }
 
-template <typename ET, typename DT, bool TLDS, int CODE>
+template <typename ET, typename DT, bool TLDS, int CODE, int PB>
 __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr int EPV = 16 / (int)sizeof(ET);            // entries per 16-byte LDS read
@@ -171,7 +176,8 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     const uint32_t topshift = a.W - a.k;
     // sigma' <= 256: the mask tells the compiler so, and Horner keeps 24-bit multiply-adds
     const uint32_t sp = a.sp & 0x1FFu, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
-    const uint32_t bshift = a.bshift & 7u, blen = a.blen & 15u;   // bit-field map (CODE == kCodeBits)
+    const uint32_t bshift = a.bshift & 7u;                // bit-field map (CODE == kCodeBits)
+    const uint32_t blen = a.blen & 31u;                   // field width, or log2 sigma' (kCodeHash)
     const int W0 = (int)a.w0;                             // warm-up entries kept before a tile
     const int64_t last = (int64_t)a.n - (int64_t)a.m;   // last valid start position
 
@@ -197,9 +203,9 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
                 const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
                 ET *E = (it & 1) ? s_E1 : s_E0;
                 if (interior)
-                    phase_a<true, CODE, TLDS>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<true, CODE, TLDS, PB>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
                 else
-                    phase_a<false, CODE, TLDS>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<false, CODE, TLDS, PB>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
             }
         } else if (it >= 1) {
             // Shift-Or over the lane's S samples. The W0 entries before them
@@ -292,9 +298,9 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     }
 }
 
-template <typename ET, typename DT, bool TLDS, int CODE>
+template <typename ET, typename DT, bool TLDS, int CODE, int PB = 0>
 mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stream) {
-    auto fn = k_scan<ET, DT, TLDS, CODE>;
+    auto fn = k_scan<ET, DT, TLDS, CODE, PB>;
     static int configured_bytes = 0;    // per instantiation
     if ((int)shmem > configured_bytes) {
         // not every runtime needs the opt-in; a real LDS overflow fails the launch below
@@ -316,9 +322,24 @@ mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stre
     return MAG_OK;
 }
 
+template <typename ET, typename DT, int PB>
+mag_status launch_hash(const ScanArgs &a, bool tlds, size_t shmem, int ncu, hipStream_t stream) {
+    return tlds ? launch_one<ET, DT, true, kCodeHash, PB>(a, shmem, ncu, stream)
+                : launch_one<ET, DT, false, kCodeHash, PB>(a, shmem, ncu, stream);
+}
+
 template <typename ET, typename DT>
 mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int ncu,
                      hipStream_t stream) {
+    if (a.qgram) {   // alphabet mapping on q-grams: packed tables hold 1-byte entries
+        if constexpr (sizeof(ET) == 1) {
+            if (a.pbits == 1) return launch_hash<ET, DT, 1>(a, tlds, shmem, ncu, stream);
+            if (a.pbits == 2) return launch_hash<ET, DT, 2>(a, tlds, shmem, ncu, stream);
+            if (a.pbits == 4) return launch_hash<ET, DT, 4>(a, tlds, shmem, ncu, stream);
+        }
+        if (a.pbits) return fail(MAG_E_UNSUPPORTED, "packed mask entries need W <= 4");
+        return launch_hash<ET, DT, 0>(a, tlds, shmem, ncu, stream);
+    }
     if (tlds) {   // LDS tables are small: 24-bit Horner steps always suffice
         return a.blen ? launch_one<ET, DT, true, kCodeBits>(a, shmem, ncu, stream)
                       : launch_one<ET, DT, true, kCodeMul24>(a, shmem, ncu, stream);

@@ -29,7 +29,10 @@ struct ScanArgs {
     uint32_t e_lds;            // bytes of LDS for one buffer of a tile's mask entries
     uint32_t table_vec;        // 16-byte vectors of the mask table (LDS copy)
     uint32_t w0;               // entries kept before a tile's first sample (>= m'-1)
-    uint32_t bshift, blen;     // bit-field map: field shift and width l (blen 0: map table)
+    uint32_t bshift, blen;     // bit-field map: field shift and width l (blen 0: map table);
+                               // q-gram map: blen = log2 sigma'
+    uint32_t qgram;            // 1: codes are hashed q-grams (no mu)
+    uint32_t pbits;            // bits per packed table entry (1, 2, 4), 0: whole entries
     const uint8_t *mu;
     const void *table;
     uint64_t *counters;        // [1] candidate windows [2] verifications

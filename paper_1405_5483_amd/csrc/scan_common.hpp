@@ -72,6 +72,39 @@ __device__ __forceinline__ uint32_t gram_code_bits(const GramWords &gw, uint32_t
     return g;
 }
 
+// Code of a q-gram under the alphabet mapping on q-grams (Section 3.3): the
+// top hbits (<= 28) bits of MurmurHash3's 64-bit finalizer of the gram's raw
+// bytes (S[0] in the low byte). The finalizer's last xor-shift leaves the high
+// word alone, so only the high word of the second product is formed.
+template <int Q>
+__device__ __forceinline__ uint32_t gram_code_hash(const GramWords &gw, uint32_t hbits) {
+    uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    if (Q < 4) lo &= (1u << (8 * Q)) - 1u;
+    if (Q > 4 && Q < 8) hi &= (1u << (8 * (Q - 4))) - 1u;
+    lo ^= hi >> 1;                                                     // x ^= x >> 33
+    const uint64_t x = (((uint64_t)hi << 32) | lo) * 0xFF51AFD7ED558CCDull;
+    const uint32_t xh = (uint32_t)(x >> 32);
+    const uint32_t xl = (uint32_t)x ^ (xh >> 1);                       // x ^= x >> 33
+    constexpr uint32_t c2lo = 0x1A85EC53u, c2hi = 0xC4CEB9FEu;
+    const uint32_t top = __umulhi(xl, c2lo) + xl * c2hi + xh * c2lo;   // high word of x * C2
+    return hbits ? top >> (32u - hbits) : 0u;
+}
+
+// Entry g of a mask table: whole entries of type ET, or (PB = 1, 2, 4) PB-bit
+// entries packed little-endian into 32-bit words, returned with the bits
+// above PB set (they are past W).
+template <int PB, typename ET>
+__device__ __forceinline__ ET table_entry(const ET *tab, uint32_t g) {
+    if constexpr (PB == 0) {
+        return tab[g];
+    } else {
+        constexpr uint32_t kPer = 32 / PB;
+        const uint32_t word = reinterpret_cast<const uint32_t *>(tab)[g / kPer];
+        return (ET)(((word >> ((g % kPer) * PB)) & ((1u << PB) - 1u)) | (0xFFu << PB));
+    }
+}
+
 // Raw buffer resource over [base, base + bytes). The operands are wave-uniform;
 // readfirstlane says so to the compiler, which otherwise may keep them in
 // vector registers and wrap every load in a loop over distinct values.
@@ -89,11 +122,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const uint8_t *base,
 // every lane must call it). `v` points at the verification arguments in
 // memory (the scan kernel passes their place in its kernel-argument segment,
 // the batched kernel its job table), so they are read on this cold path and
-// occupy no registers in the scan loops.
+// occupy no registers in the scan loops. With a pending buffer the starts are
+// appended to it (one atomic per wave) for the verification kernel; lanes
+// whose slot falls past its capacity verify here instead.
 __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v, uint64_t i0,
                                                             bool active) {
     VerifyArgs args;
     __builtin_memcpy(&args, v, sizeof(args));
+    if (args.pending) {
+        const uint64_t mask = __ballot(active);
+        if (!mask) return;
+        const uint32_t cnt = (uint32_t)__popcll(mask);
+        const uint32_t lane = __lane_id();
+        const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(true));
+        // one counter per segment keeps the atomics of different workgroups apart
+        const uint32_t seg = blockIdx.x % kPendingSegments;
+        unsigned long long got = 0;
+        if (lane == first) got = atomicAdd((unsigned long long *)&args.seg_count[seg], (unsigned long long)cnt);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+        const uint64_t base = ((uint64_t)hi << 32) | lo;
+        const uint64_t slot = base + lanes_below(mask);
+        const bool stored = active && slot < args.seg_cap;
+        if (stored) args.pending[(uint64_t)seg * args.seg_cap + slot] = i0;
+        if (base + cnt <= args.seg_cap) return;
+        active = active && !stored;
+    }
     verify_wave(args, i0, active);
 }
 

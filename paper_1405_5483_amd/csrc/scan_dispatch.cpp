@@ -45,6 +45,9 @@ VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
     v.keys = s.keys;
     v.cap = s.cap;
     v.counters = s.counters;
+    v.pending = s.pending;
+    v.seg_count = s.seg_count;
+    v.seg_cap = s.pending_cap / kPendingSegments;
     return v;
 }
 
@@ -89,6 +92,11 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
         uint32_t l = 0;
         while ((1 << l) < p->sigma_prime) ++l;
         a.blen = l;
+    }
+    if (p->map_kind == MAG_MAP_QGRAM) {
+        a.qgram = 1;
+        a.blen = (uint32_t)p->qbits;
+        a.pbits = p->entry_bits < 8 ? (uint32_t)p->entry_bits : 0u;
     }
     a.mu = p->dev.mu;
     a.table = p->dev.table;

@@ -124,6 +124,7 @@ struct FinishArgs {
     mag_match *out;
     uint64_t *sorted;      // optional: the sorted keys of small outputs too
     uint64_t posmask;
+    uint64_t *seg_count;   // optional: deferred-start segment counters, returned to zero
     int idbits;
 };
 
@@ -150,6 +151,9 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
         a.counters[2] = 0;
         a.counters[3] = 0;
     }
+    // the verification kernel has read the segment counts (it ran before)
+    if (a.seg_count)
+        for (uint32_t i = tid; i < kPendingSegments; i += kFinishThreads) a.seg_count[i] = 0;
     if (z > a.cap || z == 0 || z > kSmallMax) return;
 
     if (z <= kRankMax) {
@@ -323,6 +327,7 @@ mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *
     a.out = out;
     a.sorted = sorted;
     a.posmask = posmask;
+    a.seg_count = sc.seg_count;
     a.idbits = idbits;
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, stream, a);
     hipError_t e = hipGetLastError();

@@ -1,7 +1,7 @@
 // Exact verification of one start position (Section 3.2: the filter only
-// prunes; every surviving position is checked against the patterns). Shared by
-// the scan kernel (fallback when the candidate buffer is full) and the
-// verification kernel.
+// prunes; every surviving position is checked against the patterns). Used
+// inline by the filter kernels and by the verification kernel that drains the
+// start positions they defer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +23,10 @@ struct VerifyArgs {
     uint64_t cap;
     uint64_t key_or;           // batched scans: the job number in the key's top bits
     uint64_t *counters;        // [0] = occurrences found
+    uint64_t *pending;         // deferred start positions (NULL: verify inline), kPendingSegments
+                               // segments of seg_cap entries; workgroup g appends to g % segments
+    uint64_t *seg_count;       // starts appended to each segment (may exceed seg_cap)
+    uint64_t seg_cap;
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {

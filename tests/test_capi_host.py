@@ -59,6 +59,13 @@ CASES = [
     (64, 40, 32, 4, 1, 16, "bits"),        # low nibbles of 0x30..0x6F
     (20, 50, 16, 3, 2, 8, "bits"),
     (64, 10, 64, 2, 7, 2, "bits"),
+    (20, 300, 16, 8, 1, 1 << 12, "qgram"),   # alphabet mapping on q-grams: 1-bit entries
+    (4, 100, 16, 5, 1, 1 << 10, "qgram"),    # W = 2: 2-bit entries
+    (64, 40, 32, 6, 2, 1 << 9, "qgram"),     # W = 4: 4-bit entries
+    (64, 40, 32, 3, 3, 1 << 6, "qgram"),     # W = 9: 2-byte entries
+    (64, 10, 64, 1, 1, 1 << 5, "qgram"),     # W = 64: 8-byte entries
+    (20, 50, 16, 4, 1, 1, "qgram"),          # sigma' = 1: every gram is code 0
+    (4, 20, 8, 3, 1, 1 << 20, "qgram"),      # table larger than LDS
 ]
 
 
@@ -76,7 +83,14 @@ def test_plan_tables_equal_oracle(case):
     assert info["entry_bytes"] == mm.entry_bytes(f.W)
     assert info["n_codes"] == f.n_codes
     mu, table = plan.export()
-    assert np.array_equal(mu, f.mu)
+    if kind == "qgram":
+        assert not mu.any()
+        assert info["entry_bits"] == f.entry_bits
+        assert info["table_bytes"] == (-(-f.n_codes * f.entry_bits // 128) * 16
+                                       if f.entry_bits < 8 else f.n_codes * info["entry_bytes"])
+    else:
+        assert np.array_equal(mu, f.mu)
+        assert info["entry_bits"] == 8 * info["entry_bytes"]
     if kind == "bits":
         assert info["bits_shift"] == mm.bits_shift(P, sp)
     want = f.table()
@@ -100,6 +114,32 @@ def test_heuristic_equals_oracle(seed):
         info = plan.info()
         want = mm.heuristic_params(P, budget or mm.DEFAULT_TABLE_BUDGET)
         assert (info["q"], info["k"], info["sigma_prime"]) == want
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_qgram_heuristic_equals_oracle(seed):
+    mag = _lib_or_skip()
+    rng = np.random.default_rng(100 + seed)
+    sigma = int(rng.choice([2, 4, 20, 64]))
+    r = int(round(10 ** rng.uniform(0.5, 4.0)))
+    m = int(rng.choice([4, 8, 16, 32, 64]))
+    T = gen_text(8192, sigma, rng=seed)
+    P = gen_patterns(T, r, m, r // 2, sigma, rng=seed + 1)
+    for budget in (0, 4096, 1 << 16):
+        plan = mag.Plan(P, map_kind="qgram", table_budget=budget)
+        info = plan.info()
+        want = mm.heuristic_params_qgram(P, budget or mm.QGRAM_TABLE_BUDGET)
+        assert (info["q"], info["k"], info["sigma_prime"]) == want
+
+
+def test_qgram_map_needs_a_power_of_two():
+    mag = _lib_or_skip()
+    T = gen_text(4096, 20, rng=1)
+    P = gen_patterns(T, 30, 16, 15, 20, rng=2)
+    for sp in (3, 1000, 1 << 29):
+        with pytest.raises(mag.MagError):
+            mag.Plan(P, q=4, k=1, sigma_prime=sp, map_kind="qgram")
+    assert mag.Plan(P, q=8, k=1, sigma_prime=1 << 28, map_kind="qgram").info()["n_codes"] == 1 << 28
 
 
 def test_workload_heuristics():
@@ -128,6 +168,20 @@ def test_invalid_parameters():
     with pytest.raises(mag.MagError) as ei:
         mag.Plan(np.zeros((1, 65), dtype=np.uint8))
     assert ei.value.status == -2
+
+
+def test_invalid_verify_parameters():
+    mag = _lib_or_skip()
+    P = np.frombuffer(b"ABCDEFGHIJKLMNOP", dtype=np.uint8).reshape(1, 16)
+    from paper_1405_5483_amd._lib import MagParams
+    import ctypes
+    from paper_1405_5483_amd._lib import lib
+    for field, value in (("verify", 3), ("verify", -1), ("verify_buffer", -5)):
+        prm = MagParams()
+        setattr(prm, field, value)
+        h = ctypes.c_void_p()
+        assert lib().mag_plan_create(P.ctypes.data, 1, 16, ctypes.byref(prm), ctypes.byref(h)) == -1
+    assert mag.Plan(P, verify="deferred", verify_buffer=64).info()["r"] == 1
 
 
 def test_empty_pattern_set_is_valid():

@@ -75,6 +75,17 @@ CASES = [
     (64, 180_001, 40, 32, 4, 2, 16, "bits"),
     (20, 150_000, 30, 17, 8, 1, 4, "bits"),       # q = 8 from two words
     (64, 120_000, 20, 32, 2, 3, 256, "bits"),     # l = 8: the byte itself
+    (20, 200_003, 300, 16, 8, 1, 1 << 12, "qgram"),  # q-gram map: 1-bit entries in LDS
+    (4, 150_001, 100, 16, 5, 1, 1 << 10, "qgram"),   # W = 2: 2-bit entries
+    (64, 200_000, 40, 32, 6, 2, 1 << 9, "qgram"),    # W = 4: 4-bit entries
+    (64, 180_000, 40, 32, 3, 3, 1 << 6, "qgram"),    # W = 9: 2-byte entries
+    (64, 100_000, 10, 64, 1, 1, 1 << 5, "qgram"),    # W = 64, q = 1
+    (20, 150_000, 30, 16, 2, 3, 1 << 8, "qgram"),    # q = 2
+    (20, 150_000, 30, 15, 7, 1, 1 << 14, "qgram"),   # q = 7
+    (4, 120_000, 20, 8, 3, 1, 1 << 20, "qgram"),     # 2-bit entries, table in global memory
+    (20, 150_000, 60, 16, 4, 1, 1 << 22, "qgram"),   # 4-bit entries, 2 MiB table
+    (64, 100_000, 20, 32, 4, 1, 1 << 17, "qgram"),   # W = 7: whole bytes, 128 KiB table
+    (20, 100_000, 20, 16, 4, 1, 1, "qgram"),         # sigma' = 1: every window verified
 ]
 
 
@@ -110,6 +121,41 @@ def test_dense_mode_parity(torch_cuda, mag, case):
     assert st["samples"] == n - m + 1
     assert st["verifications"] == st["cand_windows"] >= np.unique(ref[0]).size
     assert st["matches"] == ref[0].size
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-r{c[2]}-m{c[3]}-q{c[4]}-{c[7]}" for c in CASES])
+def test_deferred_verification_parity(torch_cuda, mag, case):
+    """Starts deferred to the verification kernel: the same list and the same
+    counters; with a 4096-entry buffer every case that verifies more starts
+    than that also takes the inline fallback for the overflow."""
+    sigma, n, r, m, q, k, sp, kind = case
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
+    ref = om.occ_hashed(T, P)
+    want = mm.Filter(P, q, k, sp, kind).counts(T)
+    for buf in (0, 4096):
+        plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="filter",
+                        verify="deferred", verify_buffer=buf)
+        pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+        _assert_same(pos, ids, ref)
+        assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
+    # the dense mode defers its Bloom-bitmap survivors the same way
+    plan = mag.Plan(P, mode="dense", verify="deferred", verify_buffer=4096)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+    _assert_same(pos, ids, ref)
+
+
+def test_deferred_overflow_and_repeat(torch_cuda, mag):
+    """sigma' = 1 verifies every start: 300 000 deferred starts through a
+    4096-entry buffer, twice in a row on the same plan (the deferred count
+    must return to zero between scans), then a smaller text."""
+    T = gen_text(300_000, 4, rng=77)
+    P = gen_patterns(T, 40, 12, 30, 4, rng=78)
+    plan = mag.Plan(P, q=4, k=1, sigma_prime=1, mode="filter", verify="deferred", verify_buffer=4096)
+    for t in (T, T, T[:5000]):
+        pos, ids, st = _gpu_occ(torch_cuda, mag, t, plan, stats=True)
+        _assert_same(pos, ids, om.occ_hashed(t, P))
+        assert st["verifications"] == t.size - 12 + 1
 
 
 @pytest.mark.parametrize("offset", [0, 1, 3, 7, 13])
@@ -255,7 +301,8 @@ def test_prot1g_full_size(torch_cuda, mag):
     job = workload("prot1g")
     ref = om.occ_hashed(job.text, job.patterns)
     buf = torch_cuda.from_numpy(job.text).cuda()
-    for kw in (dict(mode="filter"), dict(q=5, k=1, sigma_prime=20), dict(mode="dense")):
+    for kw in (dict(mode="filter"), dict(q=5, k=1, sigma_prime=20), dict(mode="dense"),
+               dict(map_kind="qgram", mode="filter")):
         plan = mag.Plan(job.patterns, **kw)
         occ = mag.scan(buf, plan).cpu().numpy()
         _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
