@@ -428,6 +428,26 @@ class Filter:
             codes += self.mu[t[np.arange(X, dtype=np.int64) * kq + d]].astype(np.int64) * self.sigma_prime ** d
         return codes
 
+    def n_grams(self, n: int) -> int:
+        """Complete non-overlapping text q-grams T[yq .. yq+q)."""
+        return 0 if n < self.q else (n - self.q) // self.q + 1
+
+    def encode(self, text: np.ndarray) -> np.ndarray:
+        """The encoded text of the SMAG variant (Section 3.2,
+        "Implementation"): the code of every complete non-overlapping q-gram
+        T[yq .. yq+q), y = 0 .. (n-q)//q, computed before the search. The
+        filter's sample x is entry x*k of it."""
+        t = np.asarray(text, dtype=np.uint8)
+        G = self.n_grams(t.size)
+        idx = np.arange(G, dtype=np.int64)[:, None] * self.q + np.arange(self.q)[None, :]
+        grams = t[idx].reshape(G, self.q)
+        if self.kind == "qgram":
+            return qgram_codes(grams, self.log2_sp)
+        codes = np.zeros(G, dtype=np.int64)
+        for d in range(self.q):
+            codes += self.mu[grams[:, d]].astype(np.int64) * self.sigma_prime ** d
+        return codes
+
     def candidates(self, text: np.ndarray) -> np.ndarray:
         """Boolean [X, k]: window (x, j) passes the filter."""
         g = self.sample_codes(text)

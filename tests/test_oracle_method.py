@@ -395,3 +395,37 @@ def test_qgram_heuristic_invariants():
         assert sp * eb <= 8 * mm.QGRAM_TABLE_BUDGET
         assert sp >= mm.QGRAM_LOAD * D or 2 * sp * eb > 8 * mm.QGRAM_TABLE_BUDGET
         assert sp == 2 or sp < 2 * mm.QGRAM_LOAD * D
+
+
+# ------------------------------------------------------ SMAG: encoded text
+
+@pytest.mark.parametrize("kind", ["greedy", "rank", "bits", "qgram"])
+def test_encoded_text_digits_are_the_mapped_bytes(kind):
+    # decode every code: for the per-byte maps its base-sigma' digits, least
+    # significant first, must be mu of the gram's bytes; for the q-gram map
+    # each code must equal the scalar hash of its gram
+    T = gen_text(3001, 20, rng=31)
+    P = gen_patterns(T, 30, 16, 20, 20, rng=32)
+    q, sp = 3, (8 if kind == "bits" else 1 << 12 if kind == "qgram" else 7)
+    f = mm.Filter(P, q, 1, sp, kind)
+    codes = f.encode(T)
+    assert codes.size == (T.size - q) // q + 1
+    for y in range(0, codes.size, 37):
+        gram = T[y * q:y * q + q]
+        if kind == "qgram":
+            assert codes[y] == mm.qgram_code(gram, 12)
+        else:
+            c = int(codes[y])
+            digits = [(c // sp ** t) % sp for t in range(q)]
+            assert digits == [int(f.mu[b]) for b in gram]
+
+
+def test_encoded_text_holds_the_filter_samples():
+    # sample x of the sampled filter (byte x*k*q) is entry x*k of the encoded text
+    T = gen_text(5000, 4, rng=33)
+    P = gen_patterns(T, 10, 16, 5, 4, rng=34)
+    for q, k in ((2, 3), (4, 2), (5, 1)):
+        f = mm.Filter(P, q, k, 4)
+        enc = f.encode(T)
+        assert np.array_equal(f.sample_codes(T), enc[::k][: f.n_samples(T.size)])
+    assert mm.Filter(P, 4, 1, 4).encode(T[:3]).size == 0
