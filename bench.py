@@ -13,6 +13,7 @@ scan kernel, timed with HIP events recorded by the library on the scan's own
 stream), the CPU oracle timed on the host's cores, and three further
 measurements:
 
+* mag_vs_smag: the same scan with the text encoded first (SMAG);
 * learned_vs_fixed: held-out pattern sets over 64 MiB texts, scan-kernel time
   with the heuristic's parameters and with the selector's pick;
 * batch: the 512-job workload (about 1.1 GB of text) as per-job scans with
@@ -266,6 +267,26 @@ def batch_section(torch, mag, selector, steps: int):
             "timing": "graph replays of bind-time launches; per-job scans wall clock"}
 
 
+def mag_vs_smag(torch, mag, job, text, plan_for, select, selector, out, cnt, steps, warmup, mag_gbps):
+    """The timed workload with the same parameters, but each scan first
+    encodes the whole text (SMAG, Section 3.2): the paper reports the
+    on-the-fly variant (MAG) as generally faster."""
+    plan = plan_for(mag, job.patterns, select, text, selector)
+    info = plan.info()
+    smag = mag.Plan(job.patterns, q=info["q"], k=info["k"], sigma_prime=info["sigma_prime"],
+                    map_kind={0: "greedy", 1: "rank", 2: "bits", 3: "qgram"}[info["map_kind"]],
+                    encode=True, mode="filter")
+    plan.close()
+    ms, prof = time_scans(torch, mag, text, smag, out, cnt, steps, warmup)
+    z = int(cnt.item())
+    smag.close()
+    gbps = job.n / (ms * 1e-3) / 1e9
+    return {"smag_GBps": round(gbps, 2), "smag_ms_per_step": round(ms, 5),
+            "smag_kernels_ms": round(prof["scan_ms"] / max(prof["launches"], 1), 5),
+            "mag_GBps": round(mag_gbps, 2), "mag_over_smag": round(mag_gbps / gbps, 3),
+            "occurrences": z}
+
+
 def single_workload(torch, mag, selector, name: str, steps: int):
     import numpy as np
     from oracle import match as om
@@ -380,6 +401,10 @@ def main() -> int:
 
     extras = {}
     if not args.no_extras:
+        log("MAG vs SMAG (text encoded before the search) with the same plan")
+        extras["mag_vs_smag"] = mag_vs_smag(torch, mag, job, text, plan_for, args.select, selector,
+                                            out, cnt, args.steps, args.warmup, value)
+        log(f"mag_vs_smag: {extras['mag_vs_smag']}")
         log(f"learned vs fixed on {args.eval_sets} held-out sets")
         extras["learned_vs_fixed"] = learned_vs_fixed(torch, mag, selector, args.eval_sets, 64 << 20)
         log(f"learned vs fixed: {extras['learned_vs_fixed']}")

@@ -113,7 +113,14 @@ typedef struct {
     int32_t verify;       /* mag_verify                                         */
     int32_t verify_buffer;/* entries of the deferred-start buffer; 0 = sized
                              from the expected verifications (2^20 .. 2^26)     */
-    int32_t reserved[3];  /* must be zero                                       */
+    int32_t encode;       /* 0: MAG, q-gram codes computed on the fly while
+                             scanning; 1: SMAG, each scan first encodes the
+                             whole text (mag_encode's codes, kept in 16 bits
+                             when sigma'^q <= 2^16) and the filter reads them
+                             (Section 3.2, "Implementation"). Same results;
+                             the dense mode and batches always compute on the
+                             fly                                               */
+    int32_t reserved[2];  /* must be zero                                       */
 } mag_params;
 
 typedef struct {
@@ -180,6 +187,16 @@ mag_status mag_plan_info(const mag_plan *plan, mag_plan_desc *desc);
  * in bytes. */
 mag_status mag_plan_export(const mag_plan *plan, uint8_t *mu_out, void *table_out,
                            uint64_t table_cap);
+
+/* SMAG's encoding pass on its own (Section 3.2, "Implementation"): writes to
+ * d_codes (device, capacity cap entries) the plan's code of every complete
+ * non-overlapping q-gram d_text[y*q .. y*q+q), y = 0 .. (n-q)/q, and their
+ * number to *n_codes (host). The codes are those the filter looks up: the
+ * Horner value of the mapped bytes, sigma'^t weighting byte t, or the q-gram
+ * map's hash. Enqueued on `stream`; no wait. n < q writes nothing. Errors:
+ * NULL arguments, cap below the count -> MAG_E_INVALID. */
+mag_status mag_encode(mag_plan *plan, const uint8_t *d_text, uint64_t n, uint32_t *d_codes,
+                      uint64_t cap, uint64_t *n_codes, void *stream);
 
 /* Scans d_text[0..n) and enqueues everything on `stream` without waiting:
  * filter, verification and the final sort. Writes min(z, out_cap) sorted

@@ -48,7 +48,8 @@ class Plan:
     def __init__(self, patterns, *, select: str = "heuristic", q: int | None = None,
                  k: int | None = None, sigma_prime: int | None = None,
                  map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
-                 verify: str = "auto", verify_buffer: int = 0, candidate: int | None = None):
+                 verify: str = "auto", verify_buffer: int = 0, encode: bool = False,
+                 candidate: int | None = None):
         p = _as_patterns(patterns)
         self.r, self.m = int(p.shape[0]), int(p.shape[1])
         self.candidate = candidate        # selector grid index of a learned pick (informational)
@@ -65,6 +66,7 @@ class Plan:
         prm.mode = MODE[mode]
         prm.verify = VERIFY[verify]
         prm.verify_buffer = int(verify_buffer)
+        prm.encode = 1 if encode else 0
         handle = ctypes.c_void_p()
         self._h = None
         check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,
@@ -155,6 +157,24 @@ def scan(text, plan: Plan, out_cap: int | None = None, stats: bool = False, stre
     if stats:
         return res, {name: int(getattr(st, name)) for name, _ in MagStats._fields_}
     return res
+
+
+def encode(text, plan: Plan, stream=None):
+    """SMAG's encoded text (``mag_encode``): the plan's code of every complete
+    non-overlapping q-gram of ``text``, as an int32 CUDA tensor (codes are
+    below 2^28, so the unsigned values read the same)."""
+    import torch
+    _check_text(text)
+    n = text.numel()
+    q = plan.info()["q"]
+    G = (n - q) // q + 1 if n >= q else 0
+    out = torch.empty(max(G, 1), dtype=torch.int32, device=text.device)
+    got = ctypes.c_uint64(0)
+    check(lib().mag_encode(plan.handle, ctypes.c_void_p(text.data_ptr()) if n else None, n,
+                           ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(got),
+                           _stream_ptr(stream)), "mag_encode")
+    assert got.value == G
+    return out[:G]
 
 
 def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> None:

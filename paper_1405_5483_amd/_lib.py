@@ -36,7 +36,8 @@ class MagParams(ctypes.Structure):
         ("mode", ctypes.c_int32),
         ("verify", ctypes.c_int32),
         ("verify_buffer", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("encode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -79,6 +80,9 @@ SIGNATURES = {
     "mag_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MagPlanDesc)]),
     "mag_plan_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint64]),
+    "mag_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "mag_scan_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                       ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),

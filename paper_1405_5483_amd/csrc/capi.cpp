@@ -91,6 +91,26 @@ mag_status ensure_pending(mag_plan *p, uint64_t cap, hipStream_t stream) {
     return MAG_OK;
 }
 
+// Encoded-text buffer of at least `bytes` bytes (SMAG).
+mag_status ensure_codes(mag_plan *p, uint64_t bytes, hipStream_t stream) {
+    Scratch &sc = p->scratch;
+    if (sc.codes_bytes >= bytes && sc.codes) return MAG_OK;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (sc.codes) {
+        (void)hipFree(sc.codes);
+        sc.codes = nullptr;
+        sc.codes_bytes = 0;
+    }
+    e = hipMalloc(&sc.codes, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MAG_E_NOMEM, "device allocation of the encoded text failed");
+    }
+    sc.codes_bytes = bytes;
+    return MAG_OK;
+}
+
 // Capacity of the deferred-start buffer for a scan expected to verify
 // `expect` start positions, or 0 to verify inline.
 uint64_t pending_capacity(double expect) {
@@ -269,6 +289,7 @@ void mag_plan_destroy(mag_plan *p) {
         (void)hipFree(p->scratch.keys);
         (void)hipFree(p->scratch.pending);
         (void)hipFree(p->scratch.seg_count);
+        (void)hipFree(p->scratch.codes);
         (void)hipSetDevice(cur);
     }
     delete p;
@@ -369,6 +390,14 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     sl.pending = pcap ? p->scratch.pending : nullptr;
     sl.pending_cap = pcap ? p->scratch.pending_cap : 0;
     sl.seg_count = pcap ? p->scratch.seg_count : nullptr;
+    const bool smag = p->encode && !p->dense && p->r && n >= (uint64_t)p->q;
+    if (smag) {
+        sl.csz = encoded_code_bytes(p);
+        // 16 bytes of slack: phase A reads the 32-bit word holding each code
+        s = ensure_codes(p, ((n - p->q) / p->q + 1) * (uint64_t)sl.csz + 16, stream);
+        if (s != MAG_OK) return s;
+        sl.codes = p->scratch.codes;
+    }
     ProfileRecord rec{{nullptr, nullptr, nullptr}};
     bool prof;
     {
@@ -397,7 +426,8 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         da.v = make_verify_args(p, sl);
         s = launch_dense(da, p->bloom.size() * 4, stream);
     } else {
-        s = launch_scan(p, sl, stream);
+        if (smag) s = launch_encode(p, d_text, n, p->scratch.codes, sl.csz, stream);
+        if (s == MAG_OK) s = launch_scan(p, sl, stream);
     }
     if (s == MAG_OK && sl.pending) s = launch_verify(make_verify_args(p, sl), stream);
     if (s != MAG_OK) return s;
@@ -425,6 +455,20 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
 }  // namespace mag
 
 extern "C" {
+
+mag_status mag_encode(mag_plan *p, const uint8_t *d_text, uint64_t n, uint32_t *d_codes,
+                      uint64_t cap, uint64_t *n_codes, void *stream) {
+    if (!p || !n_codes) return fail(MAG_E_INVALID, "NULL argument");
+    const uint64_t G = n >= (uint64_t)p->q ? (n - p->q) / p->q + 1 : 0;
+    *n_codes = G;
+    if (G == 0) return MAG_OK;
+    if (!d_text || !d_codes) return fail(MAG_E_INVALID, "d_text or d_codes is NULL");
+    if (cap < G) return fail(MAG_E_INVALID, "d_codes holds fewer entries than there are q-grams");
+    std::lock_guard<std::mutex> lock(p->mtx);
+    mag_status s = ensure_device(p);
+    if (s != MAG_OK) return s;
+    return launch_encode(p, d_text, n, d_codes, 4, reinterpret_cast<hipStream_t>(stream));
+}
 
 mag_status mag_scan_async(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                           uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream) {

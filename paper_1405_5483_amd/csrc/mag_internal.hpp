@@ -101,6 +101,8 @@ struct Scratch {
     uint64_t *pending = nullptr;    // start positions deferred to the verification kernel
     uint64_t pending_cap = 0;
     uint64_t *seg_count = nullptr;  // kPendingSegments counters (cleared by the finishing kernel)
+    void *codes = nullptr;          // SMAG: the encoded text
+    uint64_t codes_bytes = 0;
 };
 
 }  // namespace mag
@@ -130,6 +132,7 @@ struct mag_plan {
     double est_verif = 0.0;          // estimated verifications per text byte of the filter
     double bloom_fp = 0.0;           // estimated share of start positions the Bloom bitmap passes
     int verify = MAG_VERIFY_AUTO;    // inline or deferred verification
+    int encode = 0;                  // 1: SMAG, the text is encoded before the search
     uint64_t verify_buffer = 0;      // deferred-start buffer entries (0: sized per scan)
     std::vector<uint32_t> bloom, bloom_batch;
 
@@ -176,8 +179,16 @@ struct ScanLaunch {
     uint64_t *pending = nullptr;   // deferred start positions (NULL: verify inline)
     uint64_t pending_cap = 0;      // entries, split into kPendingSegments segments
     uint64_t *seg_count = nullptr;
+    const void *codes = nullptr;   // SMAG: the encoded text (NULL: codes on the fly)
+    int csz = 0;                   // bytes per encoded code (2 or 4)
 };
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream);
+// SMAG: writes the code of every complete non-overlapping q-gram of
+// text[0..n) to codes, csz (2 or 4) bytes each (scan_dispatch.cpp).
+mag_status launch_encode(const mag_plan *p, const uint8_t *text, uint64_t n, void *codes, int csz,
+                         hipStream_t stream);
+// Bytes per encoded code of a plan: 2 when every code fits 16 bits, else 4.
+int encoded_code_bytes(const mag_plan *p);
 // Verifies the start positions a filter kernel deferred to v.pending
 // (segment counts in v.seg_count) with a full-occupancy grid (verify.hip).
 mag_status launch_verify(const VerifyArgs &v, hipStream_t stream);

@@ -379,6 +379,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     if (prm.verify < MAG_VERIFY_AUTO || prm.verify > MAG_VERIFY_DEFERRED)
         return fail(MAG_E_INVALID, "unknown verify");
     if (prm.verify_buffer < 0) return fail(MAG_E_INVALID, "verify_buffer must be >= 0");
+    if (prm.encode != 0 && prm.encode != 1) return fail(MAG_E_INVALID, "encode must be 0 or 1");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
 
     p->r = r;
@@ -464,6 +465,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->mode = prm.mode;
     p->verify = prm.verify;
     p->verify_buffer = (uint64_t)prm.verify_buffer;
+    p->encode = prm.encode;
     p->est_verif = estimate_verifications(p);
     p->dense = prm.mode == MAG_MODE_DENSE ||
                (prm.mode == MAG_MODE_AUTO && p->est_verif >= kDenseVerifPerByte);

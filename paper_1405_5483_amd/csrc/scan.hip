@@ -67,24 +67,43 @@ static_assert(MAG_SCAN_PREFETCH >= 1, "at least one round of loads in flight");
 constexpr int kPrefetch = MAG_SCAN_PREFETCH;   // rounds of loads in flight in phase A
 
 // How phase A turns a gram into its code: Horner with 24-bit multiply-adds,
-// Horner with 32-bit ones, the bit-field map's field extraction, or the hash
-// of the alphabet mapping on q-grams (blen = log2 sigma').
+// Horner with 32-bit ones, the bit-field map's field extraction, the hash of
+// the alphabet mapping on q-grams (blen = log2 sigma'), or (SMAG) a code the
+// encoding kernel already wrote, 16 or 32 bits wide.
 constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2, kCodeHash = 3;
+constexpr int kCodePre16 = 4, kCodePre32 = 5;
+constexpr bool is_pre(int code) { return code == kCodePre16 || code == kCodePre32; }
 
 template <int CODE>
 __device__ __forceinline__ uint32_t code_of(const GramWords &w, const uint8_t *s_mu, uint32_t sp,
                                             uint32_t bshift, uint32_t blen) {
     if constexpr (CODE == kCodeBits) return gram_code_bits<Q>(w, bshift, blen);
     else if constexpr (CODE == kCodeHash) return gram_code_hash<Q>(w, blen);
+    // encoded codes arrive through a resource that may extend into the
+    // buffer's unwritten tail (samples past the last one read it before their
+    // entry is discarded): clamp to the largest valid code, carried in sp
+    else if constexpr (CODE == kCodePre16) return min((w.w0 >> (8u * w.sh)) & 0xFFFFu, sp);
+    else if constexpr (CODE == kCodePre32) return min(w.w0, sp);
     else return gram_code<Q, CODE == kCodeMul24>(w, s_mu, sp);
 }
 
-// Words of G consecutive samples, the first at resource offset o.
-template <int G>
+// Source words of G consecutive samples, the first at resource offset o and
+// the others `stride` bytes apart: the text words of each q-gram, or the
+// word holding each encoded code.
+template <int CODE, int G>
 __device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, uint32_t o,
-                                           uint32_t kq) {
+                                           uint32_t stride) {
 #pragma unroll
-    for (int u = 0; u < G; ++u) w[u] = gram_words<Q>(rs, o + (uint32_t)u * kq);
+    for (int u = 0; u < G; ++u) {
+        const uint32_t at = o + (uint32_t)u * stride;
+        if constexpr (is_pre(CODE)) {
+            w[u].w0 = ld32(rs, at & ~3u);
+            w[u].sh = at & 3u;
+            w[u].w1 = w[u].w2 = 0u;
+        } else {
+            w[u] = gram_words<Q>(rs, at);
+        }
+    }
 }
 
 template <bool INTERIOR, int CODE, bool TLDS, int PB, int G, typename ET>
@@ -110,7 +129,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
 }
 
 template <bool INTERIOR, int CODE, bool TLDS, int PB, typename ET>
-__device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq,
+__device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq /* source stride */,
                                         uint32_t sp, uint32_t bshift, uint32_t blen,
                                         const uint8_t *s_mu, const ET *s_tab,
                                         const ET *g_tab, int W0, uint32_t TS, int64_t X0, uint64_t X,
@@ -126,7 +145,7 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
     uint32_t o = (uint32_t)(p0 + s * (int32_t)kq);
     GramWords buf[P][G];
 #pragma unroll
-    for (int r = 0; r < P; ++r) load_group<G>(buf[r], rs, o + (uint32_t)r * ostep, kq);
+    for (int r = 0; r < P; ++r) load_group<CODE, G>(buf[r], rs, o + (uint32_t)r * ostep, kq);
     o += (uint32_t)P * ostep;
     for (;;) {
 #pragma unroll
@@ -134,7 +153,7 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
             if (s >= (int)TS) return;
             process_group<INTERIOR, CODE, TLDS, PB, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
                                                   g_tab, X0, X);
-            load_group<G>(buf[r], rs, o, kq);
+            load_group<CODE, G>(buf[r], rs, o, kq);
             o += ostep;
             s += step;
         }
@@ -175,7 +194,10 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     const uint32_t kmask = a.k >= 32 ? 0xFFFFFFFFu : ((1u << a.k) - 1u);
     const uint32_t topshift = a.W - a.k;
     // sigma' <= 256: the mask tells the compiler so, and Horner keeps 24-bit multiply-adds
-    const uint32_t sp = a.sp & 0x1FFu, k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
+    // sigma' (Horner codes, <= 256), or the largest valid code (encoded codes)
+    const uint32_t sp = is_pre(CODE) ? a.maxcode : (a.sp & 0x1FFu);
+    const uint32_t k = a.k, kq = a.kq, S = a.S, TS = a.tile_samples;
+    const uint32_t stride = a.stride;                     // source bytes from one sample to the next
     const uint32_t bshift = a.bshift & 7u;                // bit-field map (CODE == kCodeBits)
     const uint32_t blen = a.blen & 31u;                   // field width, or log2 sigma' (kCodeHash)
     const int W0 = (int)a.w0;                             // warm-up entries kept before a tile
@@ -190,22 +212,22 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
             if (it < nlocal) {
                 const int64_t X0 = (int64_t)(blockIdx.x + it * gridDim.x) * TS;
                 // text bytes the tile's samples touch, warm-up included
-                int64_t b0 = (X0 - (int64_t)W0) * kq;
+                int64_t b0 = (X0 - (int64_t)W0) * stride;
                 if (b0 < 0) b0 = 0;
-                int64_t b1 = (X0 + (int64_t)TS) * kq + kMaxQ;
-                if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
+                int64_t b1 = (X0 + (int64_t)TS) * stride + kMaxQ;
+                if (b1 > (int64_t)a.src_bytes) b1 = (int64_t)a.src_bytes;
                 if (b1 < b0) b1 = b0;
                 const uint64_t pa0 = (a.delta + (uint64_t)b0) & ~15ull;
                 const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
                 const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
                 const int64_t pbase = (int64_t)a.delta - (int64_t)pa0;
                 const bool interior = X0 - W0 >= 0 && X0 + (int64_t)TS <= (int64_t)a.X;
-                const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)kq);   // resource offset of sample X0
+                const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)stride);   // resource offset of sample X0
                 ET *E = (it & 1) ? s_E1 : s_E0;
                 if (interior)
-                    phase_a<true, CODE, TLDS, PB>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<true, CODE, TLDS, PB>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
                 else
-                    phase_a<false, CODE, TLDS, PB>(E, rs, p0, kq, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    phase_a<false, CODE, TLDS, PB>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
             }
         } else if (it >= 1) {
             // Shift-Or over the lane's S samples. The W0 entries before them
@@ -322,24 +344,32 @@ mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stre
     return MAG_OK;
 }
 
-template <typename ET, typename DT, int PB>
-mag_status launch_hash(const ScanArgs &a, bool tlds, size_t shmem, int ncu, hipStream_t stream) {
-    return tlds ? launch_one<ET, DT, true, kCodeHash, PB>(a, shmem, ncu, stream)
-                : launch_one<ET, DT, false, kCodeHash, PB>(a, shmem, ncu, stream);
+// Chooses the table form: packed 1/2/4-bit entries (1-byte entry types
+// only) or whole entries, staged in LDS or read from global memory.
+template <typename ET, typename DT, int CODE>
+mag_status launch_tables(const ScanArgs &a, bool tlds, size_t shmem, int ncu, hipStream_t stream) {
+    if constexpr (sizeof(ET) == 1) {
+        if (a.pbits == 1)
+            return tlds ? launch_one<ET, DT, true, CODE, 1>(a, shmem, ncu, stream)
+                        : launch_one<ET, DT, false, CODE, 1>(a, shmem, ncu, stream);
+        if (a.pbits == 2)
+            return tlds ? launch_one<ET, DT, true, CODE, 2>(a, shmem, ncu, stream)
+                        : launch_one<ET, DT, false, CODE, 2>(a, shmem, ncu, stream);
+        if (a.pbits == 4)
+            return tlds ? launch_one<ET, DT, true, CODE, 4>(a, shmem, ncu, stream)
+                        : launch_one<ET, DT, false, CODE, 4>(a, shmem, ncu, stream);
+    }
+    if (a.pbits) return fail(MAG_E_UNSUPPORTED, "packed mask entries need W <= 4");
+    return tlds ? launch_one<ET, DT, true, CODE, 0>(a, shmem, ncu, stream)
+                : launch_one<ET, DT, false, CODE, 0>(a, shmem, ncu, stream);
 }
 
 template <typename ET, typename DT>
 mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int ncu,
                      hipStream_t stream) {
-    if (a.qgram) {   // alphabet mapping on q-grams: packed tables hold 1-byte entries
-        if constexpr (sizeof(ET) == 1) {
-            if (a.pbits == 1) return launch_hash<ET, DT, 1>(a, tlds, shmem, ncu, stream);
-            if (a.pbits == 2) return launch_hash<ET, DT, 2>(a, tlds, shmem, ncu, stream);
-            if (a.pbits == 4) return launch_hash<ET, DT, 4>(a, tlds, shmem, ncu, stream);
-        }
-        if (a.pbits) return fail(MAG_E_UNSUPPORTED, "packed mask entries need W <= 4");
-        return launch_hash<ET, DT, 0>(a, tlds, shmem, ncu, stream);
-    }
+    if (a.pre == 2) return launch_tables<ET, DT, kCodePre16>(a, tlds, shmem, ncu, stream);
+    if (a.pre == 4) return launch_tables<ET, DT, kCodePre32>(a, tlds, shmem, ncu, stream);
+    if (a.qgram) return launch_tables<ET, DT, kCodeHash>(a, tlds, shmem, ncu, stream);
     if (tlds) {   // LDS tables are small: 24-bit Horner steps always suffice
         return a.blen ? launch_one<ET, DT, true, kCodeBits>(a, shmem, ncu, stream)
                       : launch_one<ET, DT, true, kCodeMul24>(a, shmem, ncu, stream);
@@ -348,10 +378,64 @@ mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int
                  : launch_one<ET, DT, false, kCodeMul32>(a, shmem, ncu, stream);
 }
 
+// SMAG's encoding pass (Section 3.2, "Implementation"): the code of every
+// complete non-overlapping q-gram T[yQ .. yQ+Q), written as CT. A block takes
+// kEncodeThreads * kEncodePerThread consecutive grams per step; thread t
+// writes grams t, t + kEncodeThreads, ... of the step, so stores coalesce.
+constexpr int kEncodeThreads = 256, kEncodePerThread = 4;
+
+template <int CODE, typename CT>
+__global__ __launch_bounds__(kEncodeThreads) void k_encode(EncodeArgs e) {
+    __shared__ uint8_t s_mu[256];
+    for (int i = threadIdx.x; i < 256; i += kEncodeThreads) s_mu[i] = e.mu[i];
+    __syncthreads();
+    constexpr uint64_t kBlockGrams = (uint64_t)kEncodeThreads * kEncodePerThread;
+    const uint32_t sp = e.sp & 0x1FFu, bshift = e.bshift & 7u, blen = e.blen & 31u;
+    CT *out = reinterpret_cast<CT *>(e.codes);
+    for (uint64_t y0 = (uint64_t)blockIdx.x * kBlockGrams; y0 < e.G; y0 += (uint64_t)gridDim.x * kBlockGrams) {
+        // the step's text bytes (and the word after the last gram); loads
+        // past the resource read zeros and belong to no complete gram
+        const uint64_t b0 = y0 * Q;
+        uint64_t b1 = (y0 + kBlockGrams) * Q + 8;
+        if (b1 > e.n) b1 = e.n;
+        const uint64_t pa0 = (e.delta + b0) & ~15ull;
+        const uint64_t pa1 = (e.delta + b1 + 15) & ~15ull;
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(e.tbase + pa0, (uint32_t)(pa1 - pa0));
+        const uint32_t pbase = (uint32_t)(e.delta + b0 - pa0);
+#pragma unroll
+        for (int u = 0; u < kEncodePerThread; ++u) {
+            const uint64_t y = y0 + (uint64_t)u * kEncodeThreads + threadIdx.x;
+            if (y < e.G) {
+                const GramWords w = gram_words<Q>(rs, pbase + (uint32_t)((y - y0) * Q));
+                out[y] = (CT)code_of<CODE>(w, s_mu, sp, bshift, blen);
+            }
+        }
+    }
+}
+
+template <int CODE>
+mag_status launch_encode_code(const EncodeArgs &e, int csz, hipStream_t stream) {
+    const uint64_t steps = (e.G + kEncodeThreads * kEncodePerThread - 1) / (kEncodeThreads * kEncodePerThread);
+    const uint32_t grid = (uint32_t)(steps < (1u << 20) ? steps : (1u << 20));
+    if (csz == 2) hipLaunchKernelGGL((k_encode<CODE, uint16_t>), dim3(grid), dim3(kEncodeThreads), 0, stream, e);
+    else hipLaunchKernelGGL((k_encode<CODE, uint32_t>), dim3(grid), dim3(kEncodeThreads), 0, stream, e);
+    const hipError_t err = hipGetLastError();
+    return err == hipSuccess ? MAG_OK : hip_fail(err, "encode launch");
+}
+
 }  // namespace
 
 #define MAG_CAT2(a, b) a##b
 #define MAG_CAT(a, b) MAG_CAT2(a, b)
+
+mag_status MAG_CAT(launch_encode_q, MAG_SCAN_Q)(const EncodeArgs &e, int csz, bool mul24,
+                                               hipStream_t stream) {
+    if (e.G == 0) return MAG_OK;
+    if (e.qgram) return launch_encode_code<kCodeHash>(e, csz, stream);
+    if (e.blen) return launch_encode_code<kCodeBits>(e, csz, stream);
+    return mul24 ? launch_encode_code<kCodeMul24>(e, csz, stream)
+                 : launch_encode_code<kCodeMul32>(e, csz, stream);
+}
 
 mag_status MAG_CAT(launch_scan_q, MAG_SCAN_Q)(const ScanArgs &a, int esz, bool wide, bool tlds,
                                              bool mul24, size_t shmem, int ncu, hipStream_t stream) {

@@ -51,6 +51,52 @@ VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
     return v;
 }
 
+int encoded_code_bytes(const mag_plan *p) { return p->n_codes <= 65536 ? 2 : 4; }
+
+namespace {
+// 24-bit Horner steps are exact when every partial code stays below 2^24
+bool horner_mul24(const mag_plan *p) {
+    uint64_t partial = 1;
+    for (int t = 0; t + 1 < p->q; ++t) partial *= (uint64_t)p->sigma_prime;
+    return partial < (1ull << 24);
+}
+}  // namespace
+
+mag_status launch_encode(const mag_plan *p, const uint8_t *text, uint64_t n, void *codes, int csz,
+                         hipStream_t stream) {
+    if (n < (uint64_t)p->q) return MAG_OK;
+    EncodeArgs e{};
+    const uintptr_t t = reinterpret_cast<uintptr_t>(text);
+    e.tbase = reinterpret_cast<const uint8_t *>(t & ~(uintptr_t)15);
+    e.delta = t & 15;
+    e.n = n;
+    e.G = (n - p->q) / p->q + 1;
+    e.codes = codes;
+    e.mu = p->dev.mu;
+    e.sp = (uint32_t)p->sigma_prime;
+    if (p->map_kind == MAG_MAP_QGRAM) {
+        e.qgram = 1;
+        e.blen = (uint32_t)p->qbits;
+    } else if (p->map_kind == MAG_MAP_BITS && p->sigma_prime > 1) {
+        e.bshift = (uint32_t)p->bits_shift;
+        uint32_t l = 0;
+        while ((1 << l) < p->sigma_prime) ++l;
+        e.blen = l;
+    }
+    const bool mul24 = horner_mul24(p);
+    switch (p->q) {
+        case 1: return launch_encode_q1(e, csz, mul24, stream);
+        case 2: return launch_encode_q2(e, csz, mul24, stream);
+        case 3: return launch_encode_q3(e, csz, mul24, stream);
+        case 4: return launch_encode_q4(e, csz, mul24, stream);
+        case 5: return launch_encode_q5(e, csz, mul24, stream);
+        case 6: return launch_encode_q6(e, csz, mul24, stream);
+        case 7: return launch_encode_q7(e, csz, mul24, stream);
+        case 8: return launch_encode_q8(e, csz, mul24, stream);
+        default: return fail(MAG_E_UNSUPPORTED, "q outside [1, 8]");
+    }
+}
+
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream) {
     if (s.n < (uint64_t)p->q || p->r == 0) return MAG_OK;
     const int ncu = compute_units();
@@ -67,6 +113,17 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
     a.sp = p->sigma_prime;
     a.m = p->m;
     a.X = (s.n - p->q) / a.kq + 1;
+    a.src_bytes = s.n;
+    a.stride = a.kq;
+    if (s.codes) {
+        // SMAG: phase A reads sample x's code at entry x*k of the encoded text
+        a.tbase = static_cast<const uint8_t *>(s.codes);
+        a.delta = 0;
+        a.src_bytes = ((s.n - p->q) / p->q + 1) * (uint64_t)s.csz;
+        a.stride = p->k * (uint32_t)s.csz;
+        a.pre = (uint32_t)s.csz;
+        a.maxcode = (uint32_t)(p->n_codes - 1);
+    }
 
     const uint32_t esz = (uint32_t)p->esz;
     const uint32_t epv = 16 / esz;                      // entries per 16-byte LDS read
@@ -109,10 +166,7 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
     const size_t shmem = 256 + (size_t)(kScanConsumerLanes / 64) * 128 * 8 + 2 * (size_t)a.e_lds +
                          (tlds ? (size_t)a.table_vec * 16 : 0);
     const bool wide = p->W > 32 || p->k >= 32;
-    // 24-bit Horner steps are exact when every partial code stays below 2^24
-    uint64_t partial = 1;
-    for (int t = 0; t + 1 < p->q; ++t) partial *= (uint64_t)p->sigma_prime;
-    const bool mul24 = partial < (1ull << 24);
+    const bool mul24 = horner_mul24(p);
     switch (p->q) {
         case 1: return launch_scan_q1(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);
         case 2: return launch_scan_q2(a, p->esz, wide, tlds, mul24, shmem, ncu, stream);

@@ -176,7 +176,7 @@ def test_invalid_verify_parameters():
     from paper_1405_5483_amd._lib import MagParams
     import ctypes
     from paper_1405_5483_amd._lib import lib
-    for field, value in (("verify", 3), ("verify", -1), ("verify_buffer", -5)):
+    for field, value in (("verify", 3), ("verify", -1), ("verify_buffer", -5), ("encode", 2)):
         prm = MagParams()
         setattr(prm, field, value)
         h = ctypes.c_void_p()

@@ -158,6 +158,58 @@ def test_deferred_overflow_and_repeat(torch_cuda, mag):
         assert st["verifications"] == t.size - 12 + 1
 
 
+def _upload(torch, t, offset=0):
+    buf = torch.empty(t.size + offset + 16, dtype=torch.uint8, device="cuda")
+    view = buf[offset:offset + t.size]
+    if t.size:
+        view.copy_(torch.from_numpy(t))
+    return view
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-q{c[4]}-k{c[5]}-sp{c[6]}-{c[7]}" for c in CASES])
+def test_encoded_text_equals_oracle(torch_cuda, mag, case):
+    """SMAG's encoding pass: every q-gram code, bit-exact, at two text
+    alignments."""
+    sigma, n, r, m, q, k, sp, kind = case
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind)
+    want = mm.Filter(P, q, k, sp, kind).encode(T)
+    for offset in (0, 3):
+        got = mag.encode(_upload(torch_cuda, T, offset), plan).cpu().numpy().astype(np.uint32)
+        assert got.size == want.size
+        assert np.array_equal(got, want.astype(np.uint32))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-q{c[4]}-k{c[5]}-sp{c[6]}-{c[7]}" for c in CASES])
+def test_smag_parity_and_counts(torch_cuda, mag, case):
+    """The text encoded first (SMAG), then filtered from the codes: the same
+    occurrence list and the same work counters as the definitions give."""
+    sigma, n, r, m, q, k, sp, kind = case
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="filter", encode=True)
+    pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, offset=5, stats=True)
+    ref = om.occ_hashed(T, P)
+    _assert_same(pos, ids, ref)
+    want = mm.Filter(P, q, k, sp, kind).counts(T)
+    assert (st["samples"], st["cand_windows"], st["verifications"]) == \
+        (want["samples"], want["cand_windows"], want["verifications"])
+
+
+def test_smag_edges(torch_cuda, mag):
+    """Texts shorter than q, exactly q, and a deferred-verification SMAG scan
+    whose codes need 32 bits."""
+    T = gen_text(100_000, 20, rng=91)
+    P = gen_patterns(T, 200, 16, 150, 20, rng=92)
+    plan = mag.Plan(P, q=5, k=1, sigma_prime=20, mode="filter", encode=True, verify="deferred")
+    assert plan.info()["n_codes"] > 65536
+    for t in (T[:3], T[:5], T[:16], T[:16 + 5 * 7 + 2], T):
+        pos, ids, _ = _gpu_occ(torch_cuda, mag, t, plan)
+        _assert_same(pos, ids, om.occ_hashed(t, P))
+    assert mag.encode(_upload(torch_cuda, T[:4]), plan).numel() == 0
+
+
 @pytest.mark.parametrize("offset", [0, 1, 3, 7, 13])
 def test_unaligned_text(torch_cuda, mag, offset):
     T = gen_text(100_003, 4, rng=offset)
