@@ -2,6 +2,8 @@
 
 ``occ_hashed`` and ``occ_brute`` return the occurrence set of Section 1,
 ``{(i, id) : T[i..i+m) == P_id}``, as two arrays sorted by ``(i, id)``.
+``occ_var`` and ``occ_var_python`` drop the equal-length requirement (the
+introduction notes it may be removed): ``{(i, id) : T[i..i+m_id) == P_id}``.
 """
 
 from __future__ import annotations
@@ -121,3 +123,43 @@ def occ_at(text, patterns, i: int) -> np.ndarray:
     if i < 0 or i + m > t.size:
         return np.empty(0, dtype=np.uint32)
     return np.nonzero((p == t[i:i + m][None, :]).all(axis=1))[0].astype(np.uint32)
+
+
+def occ_var(text, patterns, threads: int | None = None):
+    """Occurrences of patterns of unequal lengths (a list of byte strings or
+    uint8 arrays): the equal-length matcher run on each group of patterns of
+    one length, its ids mapped back to the list's, merged and sorted by
+    (pos, id)."""
+    pats = [np.frombuffer(bytes(p), dtype=np.uint8) if not isinstance(p, np.ndarray)
+            else np.asarray(p, dtype=np.uint8) for p in patterns]
+    by_len: dict[int, list[int]] = {}
+    for pid, pat in enumerate(pats):
+        if pat.size == 0:
+            raise ValueError("empty pattern")
+        by_len.setdefault(int(pat.size), []).append(pid)
+    allpos, allids = [], []
+    for length, members in sorted(by_len.items()):
+        group = np.stack([pats[pid] for pid in members])
+        pos, ids = occ_hashed(text, group, threads)
+        allpos.append(pos)
+        allids.append(np.asarray(members, dtype=np.uint32)[ids.astype(np.int64)])
+    if not allpos:
+        return np.empty(0, dtype=np.uint64), np.empty(0, dtype=np.uint32)
+    pos = np.concatenate(allpos)
+    ids = np.concatenate(allids)
+    order = np.lexsort((ids, pos))
+    return pos[order], ids[order]
+
+
+def occ_var_python(text, patterns):
+    """Pure-Python double loop over start positions and patterns of any
+    lengths, for the smallest cases."""
+    t = bytes(np.asarray(text, dtype=np.uint8))
+    pats = [bytes(p) for p in patterns]
+    pos, ids = [], []
+    for i in range(len(t)):
+        for pid, pat in enumerate(pats):
+            if i + len(pat) <= len(t) and t[i:i + len(pat)] == pat:
+                pos.append(i)
+                ids.append(pid)
+    return np.array(pos, dtype=np.uint64), np.array(ids, dtype=np.uint32)

@@ -506,3 +506,17 @@ def class_hit_probability(alphabet: int, items: int) -> float:
 
 def expected_class_size(alphabet: int, items: int) -> float:
     return alphabet * class_hit_probability(alphabet, items)
+
+
+# ------------------------------------------------- unequal pattern lengths
+
+def prefix_set(patterns) -> np.ndarray:
+    """Patterns of unequal lengths filter as the set of their first m_min
+    bytes (m_min the shortest length): an occurrence of P_id at i contains
+    an occurrence of its prefix at i, so the equal-length filter over the
+    prefixes never drops it. Reading of the introduction's remark that the
+    equal-length requirement may be removed; verification then checks each
+    pattern over its full length."""
+    pats = [np.asarray(np.frombuffer(bytes(p), dtype=np.uint8)) for p in patterns]
+    m_min = min(p.size for p in pats)
+    return np.stack([p[:m_min] for p in pats])

@@ -108,3 +108,62 @@ def test_occ_at_matches_list():
     pos, ids = om.occ_hashed(T, P)
     for i in range(0, 4995, 7):
         assert om.occ_at(T, P, i).tolist() == ids[pos == i].tolist()
+
+
+# ------------------------------------------------- unequal pattern lengths
+
+def _var_set(rng, text, r, lens, planted):
+    pats = []
+    for i in range(r):
+        L = int(rng.choice(lens))
+        if i < planted and text.size >= L:
+            u = int(rng.integers(0, text.size - L + 1))
+            pats.append(bytes(text[u:u + L]))
+        else:
+            pats.append(bytes(rng.integers(0, 4, L, dtype=np.uint8) + ord("A")))
+    return pats
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_occ_var_equals_python_double_loop(seed):
+    rng = np.random.default_rng(700 + seed)
+    T = (rng.integers(0, 4, int(rng.integers(0, 400)), dtype=np.uint8) + ord("A"))
+    pats = _var_set(rng, T, int(rng.integers(1, 12)), [1, 2, 3, 5, 8], 6)
+    if rng.random() < 0.5 and pats:
+        pats.append(pats[0])                      # a duplicate
+        pats.append(pats[0] + b"A")               # an extension of another pattern
+    want = om.occ_var_python(T, pats)
+    got = om.occ_var(T, pats)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def test_occ_var_nested_patterns_closed_form():
+    # text a^n; patterns a^1 .. a^5: a^L occurs at every i <= n-L
+    n = 50
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    pats = [b"a" * L for L in (3, 1, 5, 2, 4)]
+    pos, ids = om.occ_var(T, pats)
+    expect = sorted((i, pid) for pid, p in enumerate(pats) for i in range(n - len(p) + 1))
+    assert list(zip(pos.tolist(), ids.tolist())) == expect
+
+
+def test_occ_var_equal_lengths_reduce_to_occ_hashed():
+    rng = np.random.default_rng(9)
+    T = rng.integers(0, 4, 5000, dtype=np.uint8)
+    P = np.stack([T[u:u + 8] for u in rng.integers(0, 4990, 20)])
+    a = om.occ_var(T, [bytes(row) for row in P])
+    b = om.occ_hashed(T, P)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_prefix_filter_never_drops_a_match():
+    from oracle import method as mm
+    rng = np.random.default_rng(10)
+    T = rng.integers(0, 4, 20_000, dtype=np.uint8) + ord("A")
+    pats = _var_set(rng, T, 40, [9, 12, 16, 23], 30)
+    pre = mm.prefix_set(pats)
+    assert pre.shape == (40, 9)
+    f = mm.Filter(pre, 3, 2, 4)
+    starts = set(f.verification_starts(T).tolist())
+    pos, _ = om.occ_var(T, pats)
+    assert pos.size > 0 and set(pos.tolist()) <= starts
