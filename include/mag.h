@@ -150,6 +150,10 @@ typedef struct {
     uint64_t table_bytes; /* n_codes * entry_bits / 8, padded to 16 bytes       */
     double est_verif;     /* estimated verifications per text byte of the
                              filter (-1: not evaluated)                        */
+    uint32_t m_max;       /* longest pattern (m for equal lengths)             */
+    uint32_t var;         /* 1: built by mag_plan_create_var; m is the shortest
+                             length and the filter sees every pattern's first
+                             m bytes                                           */
 } mag_plan_desc;
 
 /* Work counters of one scan (integers; equal to the oracle's counts). */
@@ -171,6 +175,22 @@ typedef struct mag_plan mag_plan;
  * MAG_E_UNSUPPORTED. r == 0 is valid (every scan returns no match). */
 mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
                            const mag_params *params, mag_plan **out);
+
+/* Builds a plan for r patterns of unequal lengths (the introduction notes
+ * the equal-length requirement may be removed): pattern i is
+ * bytes[offsets[i] .. offsets[i+1]) (host arrays, copied), 1 to 64 bytes.
+ * The filter is the one mag_plan_create builds for the patterns' first m_min
+ * bytes (m_min = the shortest length; every occurrence contains an
+ * occurrence of its prefix, so none is lost); verification checks each
+ * candidate start against every distinct pattern with that prefix over its
+ * full length, and a pattern only matches where it ends inside the text.
+ * Results: every (i, id) with T[i .. i + len_id) == P_id, sorted. Equal
+ * lengths give the same plan as mag_plan_create. Errors: r == 0, NULL
+ * arrays, decreasing offsets, an empty pattern -> MAG_E_INVALID; a pattern
+ * above 64 bytes -> MAG_E_UNSUPPORTED; params as for mag_plan_create. Such
+ * plans are rejected by mag_batch_create. */
+mag_status mag_plan_create_var(const uint8_t *bytes, const uint64_t *offsets, uint32_t r,
+                               const mag_params *params, mag_plan **out);
 
 /* Releases the plan and its device tables. NULL is ignored. The caller must
  * not destroy a plan while a stream still runs work that uses it. */

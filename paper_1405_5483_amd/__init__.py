@@ -5,7 +5,8 @@ marshals arguments. Every step of the scan runs in the library's HIP kernels;
 PyTorch supplies device memory and streams.
 
     import torch, paper_1405_5483_amd as mag
-    plan = mag.Plan(patterns)                 # [r, m] uint8 (numpy / bytes list)
+    plan = mag.Plan(patterns)                 # [r, m] uint8 (numpy / bytes list;
+                                              #  a list of unequal lengths also works)
     occ = mag.scan(text_cuda_u8, plan)        # int64 [z, 2]: (pos, pattern id)
 
 The occurrence set is the one of Section 1 of the paper: every (i, id) with
@@ -42,6 +43,19 @@ def _as_patterns(patterns) -> np.ndarray:
     return p
 
 
+def _unequal(patterns):
+    """(concatenated bytes, offsets) when ``patterns`` is a list whose
+    entries differ in length, else None."""
+    if not isinstance(patterns, (list, tuple)) or not patterns:
+        return None
+    rows = [np.frombuffer(bytes(p), dtype=np.uint8) for p in patterns]
+    if len({r.size for r in rows}) == 1:
+        return None
+    offsets = np.zeros(len(rows) + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum([r.size for r in rows])
+    return np.ascontiguousarray(np.concatenate(rows)), offsets
+
+
 class Plan:
     """A pattern set prepared for scanning (``mag_plan_create``)."""
 
@@ -50,8 +64,13 @@ class Plan:
                  map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
                  verify: str = "auto", verify_buffer: int = 0, encode: bool = False,
                  candidate: int | None = None):
-        p = _as_patterns(patterns)
-        self.r, self.m = int(p.shape[0]), int(p.shape[1])
+        var = _unequal(patterns)
+        if var is None:
+            p = _as_patterns(patterns)
+            self.r, self.m = int(p.shape[0]), int(p.shape[1])
+        else:
+            data, offsets = var
+            self.r, self.m = int(offsets.size - 1), int(np.diff(offsets).min())
         self.candidate = candidate        # selector grid index of a learned pick (informational)
         prm = MagParams()
         if q is not None or k is not None or sigma_prime is not None:
@@ -69,8 +88,13 @@ class Plan:
         prm.encode = 1 if encode else 0
         handle = ctypes.c_void_p()
         self._h = None
-        check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,
-                                    ctypes.byref(prm), ctypes.byref(handle)), "mag_plan_create")
+        if var is None:
+            check(lib().mag_plan_create(p.ctypes.data if p.size else None, self.r, self.m,
+                                        ctypes.byref(prm), ctypes.byref(handle)), "mag_plan_create")
+        else:
+            check(lib().mag_plan_create_var(data.ctypes.data, offsets.ctypes.data, self.r,
+                                            ctypes.byref(prm), ctypes.byref(handle)),
+                  "mag_plan_create_var")
         self._h = handle
 
     @property

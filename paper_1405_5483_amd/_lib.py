@@ -55,7 +55,7 @@ class MagPlanDesc(ctypes.Structure):
         ("dense", ctypes.c_int32), ("bloom_log2", ctypes.c_int32),
         ("bits_shift", ctypes.c_int32), ("entry_bits", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
-        ("est_verif", ctypes.c_double),
+        ("est_verif", ctypes.c_double), ("m_max", ctypes.c_uint32), ("var", ctypes.c_uint32),
     ]
 
 
@@ -80,6 +80,8 @@ SIGNATURES = {
     "mag_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MagPlanDesc)]),
     "mag_plan_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint64]),
+    "mag_plan_create_var": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "mag_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                   ctypes.c_void_p]),

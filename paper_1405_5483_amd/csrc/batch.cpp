@@ -82,6 +82,9 @@ mag_status mag_batch_create(mag_plan *const *plans, uint32_t njobs, mag_batch **
     for (uint32_t j = 0; j < njobs; ++j) {
         const mag_plan *p = plans[j];
         if (!p) return fail(MAG_E_INVALID, "plans[" + std::to_string(j) + "] is NULL");
+        if (p->var)
+            return fail(MAG_E_UNSUPPORTED, "batched jobs need patterns of one length (job " +
+                                               std::to_string(j) + ")");
         if (p->r == 0 || p->dense) continue;   // no filter state in these jobs
         if (p->map_kind == MAG_MAP_QGRAM)
             return fail(MAG_E_UNSUPPORTED, "batched filter jobs need a per-byte alphabet map (job " +

@@ -151,7 +151,10 @@ mag_status ensure_device(mag_plan *p) {
     const uint64_t o_ids = round16(o_ids0 + p->idstart.size() * 4);
     const uint64_t o_bloom = round16(o_ids + p->ids.size() * 4 + 16);
     const uint64_t o_bloomb = round16(o_bloom + p->bloom.size() * 4);
-    const uint64_t total = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
+    const uint64_t o_pwoff = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
+    const uint64_t o_plen = round16(o_pwoff + p->pwoff.size() * 4);
+    const uint64_t o_gstart = round16(o_plen + p->plen.size() * 4);
+    const uint64_t total = round16(o_gstart + p->gstart.size() * 4 + 16);
     uint8_t *base = nullptr;
     e = hipMalloc(&base, total);
     if (e != hipSuccess) {
@@ -168,6 +171,9 @@ mag_status ensure_device(mag_plan *p) {
     if (!p->bloom.empty()) std::memcpy(&host[o_bloom], p->bloom.data(), p->bloom.size() * 4);
     if (!p->bloom_batch.empty())
         std::memcpy(&host[o_bloomb], p->bloom_batch.data(), p->bloom_batch.size() * 4);
+    if (!p->pwoff.empty()) std::memcpy(&host[o_pwoff], p->pwoff.data(), p->pwoff.size() * 4);
+    if (!p->plen.empty()) std::memcpy(&host[o_plen], p->plen.data(), p->plen.size() * 4);
+    if (!p->gstart.empty()) std::memcpy(&host[o_gstart], p->gstart.data(), p->gstart.size() * 4);
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
@@ -182,6 +188,9 @@ mag_status ensure_device(mag_plan *p) {
     p->dev.ids = reinterpret_cast<const uint32_t *>(base + o_ids);
     p->dev.bloom = reinterpret_cast<const uint32_t *>(base + o_bloom);
     p->dev.bloom_batch = reinterpret_cast<const uint32_t *>(base + o_bloomb);
+    p->dev.pwoff = reinterpret_cast<const uint32_t *>(base + o_pwoff);
+    p->dev.plen = reinterpret_cast<const uint32_t *>(base + o_plen);
+    p->dev.gstart = reinterpret_cast<const uint32_t *>(base + o_gstart);
 
     // fixed scratch: counters[4], the count and the stats of mag_scan
     Scratch &sc = p->scratch;
@@ -276,6 +285,30 @@ mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
     return MAG_OK;
 }
 
+mag_status mag_plan_create_var(const uint8_t *bytes, const uint64_t *offsets, uint32_t r,
+                               const mag_params *params, mag_plan **out) {
+    if (!out) return fail(MAG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (params) {
+        for (int v : params->reserved)
+            if (v) return fail(MAG_E_INVALID, "mag_params.reserved must be zero");
+    }
+    mag_plan *p = new (std::nothrow) mag_plan();
+    if (!p) return fail(MAG_E_NOMEM, "host allocation failed");
+    mag_status s;
+    try {
+        s = build_plan_var(p, bytes, offsets, r, params);
+    } catch (const std::bad_alloc &) {
+        s = fail(MAG_E_NOMEM, "host allocation failed while building the plan");
+    }
+    if (s != MAG_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return MAG_OK;
+}
+
 void mag_plan_destroy(mag_plan *p) {
     if (!p) return;
     if (p->device >= 0) {
@@ -317,6 +350,8 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->n_codes = p->n_codes;
     d->table_bytes = p->table.size();
     d->est_verif = p->est_verif;
+    d->m_max = p->m_max;
+    d->var = (uint32_t)p->var;
     return MAG_OK;
 }
 

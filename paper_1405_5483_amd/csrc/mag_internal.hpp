@@ -88,6 +88,9 @@ struct DeviceTables {
     const uint32_t *ids = nullptr;     // r
     const uint32_t *bloom = nullptr;   // 2^bloom_log2 bits
     const uint32_t *bloom_batch = nullptr;  // 2^min(bloom_log2, kBloomBatchLog2) bits
+    const uint32_t *pwoff = nullptr;   // unequal lengths: word offset of each distinct pattern
+    const uint32_t *plen = nullptr;    //   its length
+    const uint32_t *gstart = nullptr;  //   first distinct pattern of each prefix group (+ end)
 };
 
 struct Scratch {
@@ -133,6 +136,13 @@ struct mag_plan {
     double bloom_fp = 0.0;           // estimated share of start positions the Bloom bitmap passes
     int verify = MAG_VERIFY_AUTO;    // inline or deferred verification
     int encode = 0;                  // 1: SMAG, the text is encoded before the search
+    // unequal lengths: m is the shortest length and the filter sees every
+    // pattern's first m bytes; verification uses the full patterns
+    int var = 0;
+    uint32_t m_max = 0;
+    std::vector<uint8_t> fbytes;     // the full patterns, concatenated
+    std::vector<uint64_t> foff;      // r + 1 offsets into fbytes
+    std::vector<uint32_t> pwoff, plen, gstart;
     uint64_t verify_buffer = 0;      // deferred-start buffer entries (0: sized per scan)
     std::vector<uint32_t> bloom, bloom_batch;
 
@@ -165,6 +175,9 @@ double estimate_verifications(const mag_plan *p);
 // Host plan builder (plan.cpp).
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
                       const mag_params *params);
+// Patterns of unequal lengths: bytes[offsets[i] .. offsets[i+1]) is pattern i.
+mag_status build_plan_var(mag_plan *p, const uint8_t *bytes, const uint64_t *offsets, uint32_t r,
+                          const mag_params *params);
 
 // Kernel launches (scan.hip, sort.hip).
 struct VerifyArgs;

@@ -384,6 +384,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
 
     p->r = r;
     p->m = m;
+    p->m_max = m;
     p->mw = (m + 3) / 4;
     p->patterns.assign(patterns, patterns + (size_t)r * m);
     p->map_kind = prm.map_kind;
@@ -469,6 +470,101 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->est_verif = estimate_verifications(p);
     p->dense = prm.mode == MAG_MODE_DENSE ||
                (prm.mode == MAG_MODE_AUTO && p->est_verif >= kDenseVerifPerByte);
+    return MAG_OK;
+}
+
+namespace {
+
+// Verification set of a plan with unequal lengths. Ids are ordered by
+// (first m bytes, length, bytes, id): equal patterns form one run of ids per
+// distinct pattern u, and distinct patterns sharing their first m bytes form
+// one group, which the probe table indexes by the hash of those bytes.
+void build_verifier_var(mag_plan *p) {
+    const uint32_t r = p->r, m = p->m;
+    const uint8_t *B = p->fbytes.data();
+    auto len = [&](uint32_t i) { return (uint32_t)(p->foff[i + 1] - p->foff[i]); };
+    auto at = [&](uint32_t i) { return B + p->foff[i]; };
+    std::vector<uint32_t> order(r);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const int c = std::memcmp(at(a), at(b), m);
+        if (c) return c < 0;
+        if (len(a) != len(b)) return len(a) < len(b);
+        return std::memcmp(at(a), at(b), len(a)) < 0;
+    });
+    p->ids = order;
+    p->idstart.clear();
+    p->pwords.clear();
+    p->pwoff.clear();
+    p->plen.clear();
+    p->gstart.clear();
+    for (uint32_t i = 0; i < r; ++i) {
+        const uint32_t a = order[i];
+        const bool new_u = i == 0 || len(a) != len(order[i - 1]) ||
+                           std::memcmp(at(a), at(order[i - 1]), len(a)) != 0;
+        if (!new_u) continue;
+        const bool new_g = i == 0 || std::memcmp(at(a), at(order[i - 1]), m) != 0;
+        if (new_g) p->gstart.push_back((uint32_t)p->idstart.size());
+        p->idstart.push_back(i);
+        p->pwoff.push_back((uint32_t)p->pwords.size());
+        p->plen.push_back(len(a));
+        for (uint32_t t = 0; t < (len(a) + 3) / 4; ++t) {
+            uint32_t w = 0;
+            for (uint32_t b = 0; b < 4; ++b)
+                if (4 * t + b < len(a)) w |= (uint32_t)at(a)[4 * t + b] << (8 * b);
+            p->pwords.push_back(w);
+        }
+    }
+    p->n_unique = (uint32_t)p->idstart.size();
+    p->idstart.push_back(r);
+    const uint32_t groups = (uint32_t)p->gstart.size();
+    p->gstart.push_back(p->n_unique);
+
+    uint32_t bits = 1;
+    while ((1ull << bits) < 2ull * std::max<uint32_t>(groups, 1)) ++bits;
+    p->slot_bits = bits;
+    p->slots.assign(1ull << bits, 0);
+    const uint64_t mask = (1ull << bits) - 1;
+    const int hw = std::min<int>(p->mw, kHashWords);
+    const uint32_t lastmask = (m & 3) ? ((1u << (8 * (m & 3))) - 1u) : 0xFFFFFFFFu;
+    for (uint32_t g = 0; g < groups; ++g) {
+        uint32_t hv[kHashWords] = {0};
+        const uint32_t *pw = &p->pwords[p->pwoff[p->gstart[g]]];
+        for (int t = 0; t < hw; ++t) hv[t] = (t == (int)p->mw - 1) ? (pw[t] & lastmask) : pw[t];
+        const uint32_t h = window_hash(hv, hw);
+        uint64_t s = (uint64_t)(h >> (32 - bits));
+        while (p->slots[s]) s = (s + 1) & mask;
+        p->slots[s] = ((uint64_t)h << 32) | (uint64_t)(g + 1);
+    }
+}
+
+}  // namespace
+
+mag_status build_plan_var(mag_plan *p, const uint8_t *bytes, const uint64_t *offsets, uint32_t r,
+                          const mag_params *params) {
+    if (r == 0) return fail(MAG_E_INVALID, "unequal-length plans need at least one pattern");
+    if (!bytes || !offsets) return fail(MAG_E_INVALID, "bytes or offsets is NULL");
+    uint32_t m_min = UINT32_MAX, m_max = 0;
+    for (uint32_t i = 0; i < r; ++i) {
+        if (offsets[i + 1] < offsets[i]) return fail(MAG_E_INVALID, "offsets must not decrease");
+        const uint64_t L = offsets[i + 1] - offsets[i];
+        if (L == 0) return fail(MAG_E_INVALID, "pattern length must be >= 1");
+        if (L > (uint64_t)kMaxM) return fail(MAG_E_UNSUPPORTED, "pattern length above 64");
+        m_min = std::min<uint32_t>(m_min, (uint32_t)L);
+        m_max = std::max<uint32_t>(m_max, (uint32_t)L);
+    }
+    // the filter's view: every pattern's first m_min bytes
+    std::vector<uint8_t> prefixes((size_t)r * m_min);
+    for (uint32_t i = 0; i < r; ++i)
+        std::memcpy(&prefixes[(size_t)i * m_min], bytes + offsets[i], m_min);
+    mag_status s = build_plan(p, prefixes.data(), r, m_min, params);
+    if (s != MAG_OK) return s;
+    p->var = 1;
+    p->m_max = m_max;
+    p->fbytes.assign(bytes + offsets[0], bytes + offsets[r]);
+    p->foff.resize(r + 1);
+    for (uint32_t i = 0; i <= r; ++i) p->foff[i] = offsets[i] - offsets[0];
+    build_verifier_var(p);
     return MAG_OK;
 }
 

@@ -48,6 +48,11 @@ VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
     v.pending = s.pending;
     v.seg_count = s.seg_count;
     v.seg_cap = s.pending_cap / kPendingSegments;
+    v.n = s.n;
+    v.var = (uint32_t)p->var;
+    v.pwoff = p->dev.pwoff;
+    v.plen = p->dev.plen;
+    v.gstart = p->dev.gstart;
     return v;
 }
 

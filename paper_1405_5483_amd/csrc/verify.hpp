@@ -27,6 +27,13 @@ struct VerifyArgs {
                                // segments of seg_cap entries; workgroup g appends to g % segments
     uint64_t *seg_count;       // starts appended to each segment (may exceed seg_cap)
     uint64_t seg_cap;
+    // patterns of unequal lengths (var = 1): slots lead to groups of distinct
+    // patterns that share their first m bytes (m = the shortest length);
+    // group g is distinct patterns gstart[g] .. gstart[g+1]-1, pattern u has
+    // plen[u] bytes in words pwords[pwoff[u] ..]
+    uint64_t n;                // text bytes
+    const uint32_t *pwoff, *plen, *gstart;
+    uint32_t var, pad2_;
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
@@ -87,6 +94,113 @@ __device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
     }
 }
 
+// Unequal lengths: index + 1 of the group whose shared first m bytes equal
+// the window's, or 0.
+__device__ inline uint32_t find_group(const VerifyArgs &a, uint64_t i0) {
+    const uint64_t p = a.delta + i0;
+    const uint64_t base = p & ~3ull;
+    const uint32_t sh = (uint32_t)(p & 3);
+    uint32_t hv[kHashWords];
+    uint32_t lo = gword(a, base);
+#pragma unroll
+    for (int t = 0; t < kHashWords; ++t) {
+        uint32_t x = 0;
+        if (t < (int)a.hw) {
+            const uint32_t hi = gword(a, base + 4 * t + 4);
+            x = __builtin_amdgcn_alignbyte(hi, lo, sh);
+            lo = hi;
+            if (t == (int)a.mw - 1) x &= a.lastmask;
+        }
+        hv[t] = x;
+    }
+    const uint32_t h = window_hash(hv, (int)a.hw);
+    uint32_t slot = h >> a.slot_shift;
+    for (;;) {
+        const uint64_t e = a.slots[slot];
+        if (e == 0) return 0;
+        if ((uint32_t)(e >> 32) == h) {
+            const uint32_t g = (uint32_t)e - 1u;
+            const uint32_t *pw = a.pwords + a.pwoff[a.gstart[g]];
+            bool eq = true;
+            uint32_t w0 = gword(a, base);
+            for (uint32_t t = 0; t < a.mw; ++t) {
+                const uint32_t w1 = gword(a, base + 4 * t + 4);
+                uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, sh);
+                w0 = w1;
+                uint32_t y = pw[t];
+                if (t == a.mw - 1) {
+                    x &= a.lastmask;
+                    y &= a.lastmask;
+                }
+                if (x != y) { eq = false; break; }
+            }
+            if (eq) return g + 1;     // groups have distinct prefixes
+        }
+        slot = (slot + 1) & a.slot_mask;
+    }
+}
+
+// Unequal lengths: does distinct pattern u occur at start position i0?
+__device__ inline bool member_matches(const VerifyArgs &a, uint64_t i0, uint32_t u) {
+    const uint32_t len = a.plen[u];
+    if (i0 + len > a.n) return false;
+    const uint32_t *pw = a.pwords + a.pwoff[u];
+    const uint64_t p = a.delta + i0;
+    const uint64_t base = p & ~3ull;
+    const uint32_t sh = (uint32_t)(p & 3);
+    const uint32_t words = (len + 3) / 4;
+    const uint32_t lastmask = (len & 3) ? ((1u << (8 * (len & 3))) - 1u) : 0xFFFFFFFFu;
+    uint32_t w0 = gword(a, base);
+    for (uint32_t t = 0; t < words; ++t) {
+        const uint32_t w1 = gword(a, base + 4 * t + 4);
+        uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, sh);
+        w0 = w1;
+        if (t == words - 1) x &= lastmask;
+        if (x != pw[t]) return false;
+    }
+    return true;
+}
+
+// Unequal lengths: every member of the window's group that fits before the
+// text's end and equals the text there emits all its ids. Lanes walk their
+// own groups in step; each step's ids leave in ballot rounds (one atomic add
+// per round).
+__device__ inline void verify_wave_var(const VerifyArgs &a, uint64_t i0, bool active) {
+    const uint32_t g1 = active ? find_group(a, i0) : 0u;
+    uint32_t it = 0, end = 0;
+    if (g1) {
+        it = a.gstart[g1 - 1];
+        end = a.gstart[g1];
+    }
+    const uint32_t lane = __lane_id();
+    const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(true));
+    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    while (__ballot(it < end)) {
+        uint32_t b = 0, c = 0;
+        if (it < end) {
+            const uint32_t u = it++;
+            if (member_matches(a, i0, u)) {
+                b = a.idstart[u];
+                c = a.idstart[u + 1] - b;
+            }
+        }
+        for (uint32_t t = 0;; ++t) {
+            const bool has = t < c;
+            const uint64_t mask = __ballot(has);
+            if (!mask) break;
+            unsigned long long got = 0;
+            if (lane == first)
+                got = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)__popcll(mask));
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+            if (has) {
+                const uint64_t at = (((uint64_t)hi << 32) | lo) + lanes_below(mask);
+                if (at < a.cap) a.keys[at] = emit | (uint64_t)a.ids[b + t];
+            }
+        }
+    }
+}
+
 // Verifies the start positions of the wave's lanes that have `active` set
 // and emits every (i0, id) occurrence, reserving output room with one atomic
 // add per wave so that outputs with many occurrences do not serialize on the
@@ -94,6 +208,10 @@ __device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
 // prefix sum gives each lane its slots at once; otherwise round t writes the
 // t-th id of each lane's run of equal patterns, from ballots only.
 __device__ inline void verify_wave(const VerifyArgs &a, uint64_t i0, bool active) {
+    if (a.var) {
+        verify_wave_var(a, i0, active);
+        return;
+    }
     const uint32_t u1 = active ? find_pattern(a, i0) : 0u;
     uint32_t b = 0, c = 0;
     if (u1) {

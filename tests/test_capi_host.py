@@ -215,3 +215,49 @@ def test_auto_mode_scans_densely_when_the_filter_cannot_prune():
     assert info["dense"] == 0 and 0 <= info["est_verif"] < 0.1
     assert mag.Plan(sel.patterns, mode="dense").info()["dense"] == 1
     assert mag.Plan(sat.patterns, mode="filter").info()["dense"] == 0
+
+
+def _unequal_set(rng, T, r, lens):
+    pats = []
+    for i in range(r):
+        L = int(rng.choice(lens))
+        u = int(rng.integers(0, T.size - L))
+        pats.append(bytes(T[u:u + L]))
+    return pats
+
+
+def test_unequal_length_plan_filters_the_prefixes():
+    mag = _lib_or_skip()
+    rng = np.random.default_rng(5)
+    T = gen_text(20_000, 20, rng=5)
+    pats = _unequal_set(rng, T, 60, [9, 12, 16, 23, 40])
+    plan = mag.Plan(pats, q=3, k=2, sigma_prime=12)
+    info = plan.info()
+    assert (info["var"], info["m"], info["m_max"], info["r"]) == (1, 9, 40, 60)
+    f = mm.Filter(mm.prefix_set(pats), 3, 2, 12)
+    mu, table = plan.export()
+    assert np.array_equal(mu, f.mu)
+    assert np.array_equal(table.astype(np.uint64), f.table() & np.uint64(0xFF))
+    assert info["n_unique"] == len(set(pats))
+    # the heuristic sees the prefix set
+    h = mag.Plan(pats).info()
+    assert (h["q"], h["k"], h["sigma_prime"]) == mm.heuristic_params(mm.prefix_set(pats))
+    # a list of equal lengths builds an ordinary plan
+    assert mag.Plan([p[:9] for p in pats]).info()["var"] == 0
+
+
+def test_unequal_length_errors():
+    mag = _lib_or_skip()
+    import ctypes
+    from paper_1405_5483_amd._lib import lib
+    with pytest.raises(mag.MagError) as ei:
+        mag.Plan([b"ABC", b"A" * 65])
+    assert ei.value.status == -2
+    with pytest.raises(mag.MagError):
+        mag.Plan([b"ABC", b""])
+    data = np.frombuffer(b"ABCDEF", dtype=np.uint8)
+    h = ctypes.c_void_p()
+    for offs in ([0, 4, 2], [0]):
+        o = np.array(offs, dtype=np.uint64)
+        r = len(offs) - 1
+        assert lib().mag_plan_create_var(data.ctypes.data, o.ctypes.data, r, None, ctypes.byref(h)) == -1

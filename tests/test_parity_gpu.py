@@ -210,6 +210,74 @@ def test_smag_edges(torch_cuda, mag):
     assert mag.encode(_upload(torch_cuda, T[:4]), plan).numel() == 0
 
 
+UNEQUAL = [
+    # sigma, n, r, lengths, q, k, sigma', kind
+    (4, 200_003, 60, (8, 9, 12, 16), 2, 2, 4, "greedy"),
+    (20, 250_001, 300, (12, 16, 20, 32), 3, 1, 12, "greedy"),
+    (64, 220_000, 80, (16, 24, 33, 64), 4, 2, 16, "rank"),
+    (20, 150_000, 100, (5, 6, 7, 64), 1, 2, 20, "greedy"),
+    (20, 180_000, 200, (16, 17, 31), 8, 1, 1 << 14, "qgram"),
+]
+
+
+def _unequal_case(case, seed=0):
+    sigma, n, r, lens, q, k, sp, kind = case
+    rng = np.random.default_rng(n + r + seed)
+    T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
+    pats = []
+    for i in range(r):
+        L = int(rng.choice(lens))
+        if i % 4 == 3:                               # random: mostly absent
+            pats.append(bytes(gen_text(L, sigma, rng=int(rng.integers(1 << 30)))))
+        else:
+            u = int(rng.integers(0, n - L))
+            pats.append(bytes(T[u:u + L]))
+    pats.append(pats[0])                             # a duplicate
+    pats.append(pats[1][: min(lens)])                # a prefix of another pattern
+    tail = bytes(T[n - min(lens):])                  # occurs at the last start; its
+    pats.append(tail + b"\x00" * (max(lens) - len(tail)))   # extension runs past the end
+    pats.append(tail)
+    return T, pats
+
+
+@pytest.mark.parametrize("case", UNEQUAL, ids=[f"s{c[0]}-r{c[2]}-q{c[4]}-{c[7]}" for c in UNEQUAL])
+def test_unequal_lengths_parity(torch_cuda, mag, case):
+    """Patterns of several lengths: the filter over their shortest prefixes,
+    verification over full lengths; filter, dense, deferred and SMAG scans
+    all give the oracle's list, and the filter's counters are the prefix
+    set's."""
+    sigma, n, r, lens, q, k, sp, kind = case
+    T, pats = _unequal_case(case)
+    ref = om.occ_var(T, pats)
+    assert ref[0].size > r // 2
+    want = mm.Filter(mm.prefix_set(pats), q, k, sp, kind).counts(T)
+    for kw in (dict(mode="filter"), dict(mode="dense"), dict(mode="filter", verify="deferred"),
+               dict(mode="filter", encode=True)):
+        plan = mag.Plan(pats, q=q, k=k, sigma_prime=sp, map_kind=kind, **kw)
+        assert plan.info()["var"] == 1
+        pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, offset=3, stats=True)
+        _assert_same(pos, ids, ref)
+        if kw["mode"] == "filter":
+            assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
+
+
+def test_unequal_lengths_nested_closed_form(torch_cuda, mag):
+    # a^n with patterns a^1 .. a^9: a^L occurs at every i <= n - L
+    n = 100_000
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    pats = [b"a" * L for L in (3, 1, 9, 2, 5)]
+    plan = mag.Plan(pats)
+    pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan)
+    assert pos.size == sum(n - len(p) + 1 for p in pats)
+    _assert_same(pos, ids, om.occ_var(T, pats))
+
+
+def test_batch_rejects_unequal_lengths(torch_cuda, mag):
+    plan = mag.Plan([b"ACGTACGT", b"ACGTACGTAC"])
+    with pytest.raises(mag.MagError):
+        mag.Batch([plan])
+
+
 @pytest.mark.parametrize("offset", [0, 1, 3, 7, 13])
 def test_unaligned_text(torch_cuda, mag, offset):
     T = gen_text(100_003, 4, rng=offset)
