@@ -65,6 +65,13 @@ constexpr int kGroup = MAG_SCAN_GROUP;
 #endif
 static_assert(MAG_SCAN_PREFETCH >= 1, "at least one round of loads in flight");
 constexpr int kPrefetch = MAG_SCAN_PREFETCH;   // rounds of loads in flight in phase A
+#ifndef MAG_SCAN_VEC
+#define MAG_SCAN_VEC 1
+#endif
+// Words per sample when consecutive samples sit in consecutive words (stride
+// = 4 * kWordsPerSample bytes, word-aligned): a thread's group of samples is
+// then read with 16-byte loads.
+constexpr int kWordsPerSample = (Q + 3) / 4;
 
 // How phase A turns a gram into its code: Horner with 24-bit multiply-adds,
 // Horner with 32-bit ones, the bit-field map's field extraction, the hash of
@@ -74,25 +81,48 @@ constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2, kCodeHash = 3;
 constexpr int kCodePre16 = 4, kCodePre32 = 5;
 constexpr bool is_pre(int code) { return code == kCodePre16 || code == kCodePre32; }
 
-template <int CODE>
+// ALIGNED: the words come from the 16-byte-load path, gram at w0's first byte.
+template <int CODE, bool ALIGNED = false>
 __device__ __forceinline__ uint32_t code_of(const GramWords &w, const uint8_t *s_mu, uint32_t sp,
                                             uint32_t bshift, uint32_t blen) {
-    if constexpr (CODE == kCodeBits) return gram_code_bits<Q>(w, bshift, blen);
-    else if constexpr (CODE == kCodeHash) return gram_code_hash<Q>(w, blen);
+    if constexpr (CODE == kCodeBits) return gram_code_bits<Q, ALIGNED>(w, bshift, blen);
+    else if constexpr (CODE == kCodeHash) return gram_code_hash<Q, ALIGNED>(w, blen);
     // encoded codes arrive through a resource that may extend into the
     // buffer's unwritten tail (samples past the last one read it before their
     // entry is discarded): clamp to the largest valid code, carried in sp
     else if constexpr (CODE == kCodePre16) return min((w.w0 >> (8u * w.sh)) & 0xFFFFu, sp);
     else if constexpr (CODE == kCodePre32) return min(w.w0, sp);
-    else return gram_code<Q, CODE == kCodeMul24>(w, s_mu, sp);
+    else return gram_code<Q, CODE == kCodeMul24, ALIGNED>(w, s_mu, sp);
 }
 
 // Source words of G consecutive samples, the first at resource offset o and
 // the others `stride` bytes apart: the text words of each q-gram, or the
 // word holding each encoded code.
-template <int CODE, int G>
+template <int CODE, int G, bool VEC>
 __device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rsrc_t rs, uint32_t o,
                                            uint32_t stride) {
+    if constexpr (VEC) {
+        // G samples in G * kWordsPerSample consecutive words starting at the
+        // word-aligned offset o: one 16-byte load per 4 words
+        static_assert(G % 4 == 0, "whole 16-byte loads");
+        uint32_t words[G * kWordsPerSample];
+#pragma unroll
+        for (int v = 0; v < G * kWordsPerSample / 4; ++v) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 16u * v), 0, 0);
+            words[4 * v] = x[0];
+            words[4 * v + 1] = x[1];
+            words[4 * v + 2] = x[2];
+            words[4 * v + 3] = x[3];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            w[u].w0 = words[u * kWordsPerSample];
+            w[u].w1 = kWordsPerSample > 1 ? words[u * kWordsPerSample + 1] : 0u;
+            w[u].w2 = 0u;
+            w[u].sh = 0u;
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
         const uint32_t at = o + (uint32_t)u * stride;
@@ -106,7 +136,7 @@ __device__ __forceinline__ void load_group(GramWords (&w)[G], __amdgpu_buffer_rs
     }
 }
 
-template <bool INTERIOR, int CODE, bool TLDS, int PB, int G, typename ET>
+template <bool INTERIOR, int CODE, bool TLDS, int PB, bool VEC, int G, typename ET>
 __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, int s, int W0,
                                               uint32_t sp, uint32_t bshift, uint32_t blen,
                                               const uint8_t *s_mu, const ET *s_tab, const ET *g_tab,
@@ -114,7 +144,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     const ET none = (ET)~(ET)0;
     uint32_t g[G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) g[u] = code_of<CODE>(w[u], s_mu, sp, bshift, blen);
+    for (int u = 0; u < G; ++u) g[u] = code_of<CODE, VEC>(w[u], s_mu, sp, bshift, blen);
     ET e[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -128,7 +158,7 @@ __device__ __forceinline__ void process_group(const GramWords (&w)[G], ET *s_E, 
     for (int u = 0; u < G; u += 4) store4(s_E + (s + W0 + u), e + u);
 }
 
-template <bool INTERIOR, int CODE, bool TLDS, int PB, typename ET>
+template <bool INTERIOR, int CODE, bool TLDS, int PB, bool VEC, typename ET>
 __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq /* source stride */,
                                         uint32_t sp, uint32_t bshift, uint32_t blen,
                                         const uint8_t *s_mu, const ET *s_tab,
@@ -145,15 +175,15 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
     uint32_t o = (uint32_t)(p0 + s * (int32_t)kq);
     GramWords buf[P][G];
 #pragma unroll
-    for (int r = 0; r < P; ++r) load_group<CODE, G>(buf[r], rs, o + (uint32_t)r * ostep, kq);
+    for (int r = 0; r < P; ++r) load_group<CODE, G, VEC>(buf[r], rs, o + (uint32_t)r * ostep, kq);
     o += (uint32_t)P * ostep;
     for (;;) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             if (s >= (int)TS) return;
-            process_group<INTERIOR, CODE, TLDS, PB, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
+            process_group<INTERIOR, CODE, TLDS, PB, VEC, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
                                                   g_tab, X0, X);
-            load_group<CODE, G>(buf[r], rs, o, kq);
+            load_group<CODE, G, VEC>(buf[r], rs, o, kq);
             o += ostep;
             s += step;
         }
@@ -224,10 +254,17 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
                 const bool interior = X0 - W0 >= 0 && X0 + (int64_t)TS <= (int64_t)a.X;
                 const int32_t p0 = (int32_t)(pbase + X0 * (int64_t)stride);   // resource offset of sample X0
                 ET *E = (it & 1) ? s_E1 : s_E0;
-                if (interior)
-                    phase_a<true, CODE, TLDS, PB>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
-                else
-                    phase_a<false, CODE, TLDS, PB>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                // consecutive samples in consecutive words: 16-byte loads
+                const bool vec = MAG_SCAN_VEC && !is_pre(CODE) &&
+                                 stride == 4u * kWordsPerSample && (p0 & 3) == 0;
+                if (interior) {
+                    if (vec)
+                        phase_a<true, CODE, TLDS, PB, true>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                    else
+                        phase_a<true, CODE, TLDS, PB, false>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                } else {
+                    phase_a<false, CODE, TLDS, PB, false>(E, rs, p0, stride, sp, bshift, blen, s_mu, s_tab, g_tab, W0, TS, X0, a.X, tid);
+                }
             }
         } else if (it >= 1) {
             // Shift-Or over the lane's S samples. The W0 entries before them

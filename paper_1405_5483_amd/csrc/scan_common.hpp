@@ -38,10 +38,11 @@ __device__ __forceinline__ GramWords gram_words(__amdgpu_buffer_rsrc_t rs, uint3
 // Code of a q-gram: Horner over the mapped bytes, last byte first. With MUL24
 // every partial value is below 2^24 (the host checks sigma'^(q-1) < 2^24), so
 // the full-rate 24-bit multiply-add is exact.
-template <int Q, bool MUL24>
+template <int Q, bool MUL24, bool ALIGNED = false>
 __device__ __forceinline__ uint32_t gram_code(const GramWords &gw, const uint8_t *s_mu, uint32_t sp) {
-    const uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
-    const uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    // ALIGNED: the gram starts at w0's first byte (w1 holds bytes 4..7)
+    const uint32_t lo = ALIGNED ? gw.w0 : __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    const uint32_t hi = Q <= 4 ? 0u : ALIGNED ? gw.w1 : __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh);
     uint32_t g = 0;
 #pragma unroll
     for (int t = Q - 1; t >= 0; --t) {
@@ -58,10 +59,10 @@ __device__ __forceinline__ uint32_t gram_code(const GramWords &gw, const uint8_t
 // Code of a q-gram under the bit-field map of Section 3.3: the l bits from
 // bit `shift` of every byte, S[0]'s field lowest. Equal to gram_code with
 // mu(c) = (c >> shift) & (2^l - 1), without the map table.
-template <int Q>
+template <int Q, bool ALIGNED = false>
 __device__ __forceinline__ uint32_t gram_code_bits(const GramWords &gw, uint32_t shift, uint32_t l) {
-    const uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
-    const uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    const uint32_t lo = ALIGNED ? gw.w0 : __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    const uint32_t hi = Q <= 4 ? 0u : ALIGNED ? gw.w1 : __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh);
     uint32_t g = 0;
 #pragma unroll
     for (int t = 0; t < Q; ++t) {
@@ -76,10 +77,10 @@ __device__ __forceinline__ uint32_t gram_code_bits(const GramWords &gw, uint32_t
 // top hbits (<= 28) bits of MurmurHash3's 64-bit finalizer of the gram's raw
 // bytes (S[0] in the low byte). The finalizer's last xor-shift leaves the high
 // word alone, so only the high word of the second product is formed.
-template <int Q>
+template <int Q, bool ALIGNED = false>
 __device__ __forceinline__ uint32_t gram_code_hash(const GramWords &gw, uint32_t hbits) {
-    uint32_t lo = __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
-    uint32_t hi = Q > 4 ? __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh) : 0u;
+    uint32_t lo = ALIGNED ? gw.w0 : __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    uint32_t hi = Q <= 4 ? 0u : ALIGNED ? gw.w1 : __builtin_amdgcn_alignbyte(gw.w2, gw.w1, gw.sh);
     if (Q < 4) lo &= (1u << (8 * Q)) - 1u;
     if (Q > 4 && Q < 8) hi &= (1u << (8 * (Q - 4))) - 1u;
     lo ^= hi >> 1;                                                     // x ^= x >> 33

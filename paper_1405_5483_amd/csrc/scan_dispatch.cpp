@@ -8,7 +8,10 @@ namespace mag {
 namespace {
 
 constexpr uint64_t kTableLdsMax = 64 * 1024;   // mask tables up to this size are staged in LDS
-constexpr uint32_t kEntryBytesPerTile = 16 * 1024;   // one of the two mask-entry buffers
+#ifndef MAG_SCAN_TILE_BYTES
+#define MAG_SCAN_TILE_BYTES (32 * 1024)
+#endif
+constexpr uint32_t kEntryBytesPerTile = MAG_SCAN_TILE_BYTES;   // one of the two mask-entry buffers
 
 int compute_units() {
     static int ncu = 0;
