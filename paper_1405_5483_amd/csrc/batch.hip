@@ -22,6 +22,7 @@
 #include "scan_common.hpp"
 
 namespace mag {
+static_assert(kBatchQueue >= (int)kDenseQueue, "dense tiles fill up to kDenseQueue starts");
 namespace {
 
 using namespace dev;

@@ -14,6 +14,7 @@ using namespace dev;
 
 constexpr int kNT = kDenseThreads;
 constexpr int kQueue = 128;
+static_assert(kQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 
 __global__ __launch_bounds__(kNT) void k_dense(DenseArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -65,8 +66,8 @@ __global__ __launch_bounds__(kNT) void k_dense(DenseArgs a) {
             dense_load<kNT>(rs, nrec, p0n, tid, Wn);
         }
         const int64_t x0 = (int64_t)tile * kDenseTilePositions;
-        dense_test(W, p0 & 3u, x0 + 16 * (int64_t)tid, a.last, s_bloom, a.bshift, hw, mw, lastmask, queue,
-                   qn, vargs, lane, nhit);
+        dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, a.last, s_bloom, a.bshift, hw, mw, lastmask,
+                       queue, qn, vargs, lane, nhit);
 #pragma unroll
         for (int t = 0; t < 10; ++t) W[t] = Wn[t];
         p0 = p0n;

@@ -16,6 +16,7 @@ namespace mag {
 
 constexpr int kDenseThreads = 512;
 constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive positions per thread
+constexpr uint32_t kDenseQueue = 128;   // per-wave queue the callers provide (starts)
 
 struct DenseArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes
@@ -62,7 +63,14 @@ __device__ __forceinline__ void dense_load(__amdgpu_buffer_rsrc_t rs, uint32_t n
 }
 
 // Tests the 16 windows of thread tid (positions xb .. xb + 15, xb = x0 +
-// 16*tid; d = p0 & 3) whose bytes are in W.
+// 16*tid; d = p0 & 3) whose bytes are in W, and queues those that pass.
+// FAST: the hash takes 4 whole words (m >= 16, or m a multiple of 4 from 13
+// up), so no word count or last-word mask is read at run time. The hits of
+// the 16 positions are collected in a mask first; a wave prefix sum then
+// places all of the wave's hits in its queue at once when they fit (the queue
+// holds fewer than 64 starts between calls), and otherwise they are queued
+// position by position with ballots, draining full queues as before.
+template <bool FAST>
 __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, int64_t xb, int64_t last,
                                            const uint32_t *s_bloom, uint32_t bshift, uint32_t hw,
                                            uint32_t mw, uint32_t lastmask, uint64_t *queue, uint32_t &qn,
@@ -70,37 +78,78 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
     uint32_t V[9];                              // bytes from position xb on
 #pragma unroll
     for (int t = 0; t < 9; ++t) V[t] = __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
+    uint32_t hm = 0;                            // bit 4i+s: position xb+4i+s passed the bitmap
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int64_t x = xb + 4 * i + s;
             uint32_t w[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 w[t] = s ? __builtin_amdgcn_alignbyte(V[i + t + 1], V[i + t], s) : V[i + t];
-            if (mw <= 4) {
+            uint32_t h;
+            if constexpr (FAST) {
+                h = prefilter_hash(w, 4);
+            } else {
+                if (mw <= 4) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if ((uint32_t)t == mw - 1) w[t] &= lastmask;
+                    for (int t = 0; t < 4; ++t)
+                        if ((uint32_t)t == mw - 1) w[t] &= lastmask;
+                }
+                h = prefilter_hash(w, (int)hw);
             }
-            const uint32_t h = prefilter_hash(w, (int)hw);
             const uint32_t i1 = h >> bshift, i2 = bloom_second(h) >> bshift;
-            const bool hit = x <= last && ((s_bloom[i1 >> 5] >> (i1 & 31)) & 1u) &&
-                             ((s_bloom[i2 >> 5] >> (i2 & 31)) & 1u);
-            const uint64_t bal = __ballot(hit);
-            if (!bal) continue;
-            if (hit) {
-                queue[qn + lanes_below(bal)] = (uint64_t)x;
-                ++nhit;
-            }
-            qn += (uint32_t)__popcll(bal);
-            if (qn >= 64) {
-                qn -= 64;
-                drain64(vp, queue, qn, lane);
-            }
+            const uint32_t b = (s_bloom[i1 >> 5] >> (i1 & 31)) & (s_bloom[i2 >> 5] >> (i2 & 31)) & 1u;
+            hm |= b << (4 * i + s);
         }
     }
+    // positions past the last start
+    const int64_t room = last - xb + 1;
+    if (room < 16) hm &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
+    if (!__ballot(hm != 0)) return;
+    const uint32_t c = (uint32_t)__popc(hm);
+    uint32_t inc = c;                           // inclusive prefix of c over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    const uint32_t total = __shfl(inc, 63);
+    nhit += c;
+    if (qn + total <= kDenseQueue) {
+        uint32_t at = qn + inc - c;
+        for (uint32_t m = hm; m; m &= m - 1u) queue[at++] = (uint64_t)(xb + __builtin_ctz(m));
+        qn += total;
+        while (qn >= 64) {
+            qn -= 64;
+            drain64(vp, queue, qn, lane);
+        }
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const bool hit = (hm >> u) & 1u;
+        const uint64_t bal = __ballot(hit);
+        if (!bal) continue;
+        if (hit) queue[qn + lanes_below(bal)] = (uint64_t)(xb + u);
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= 64) {
+            qn -= 64;
+            drain64(vp, queue, qn, lane);
+        }
+    }
+}
+
+// dense_test with the hash form chosen from the pattern length.
+__device__ __forceinline__ void dense_test_any(const uint32_t (&W)[10], uint32_t d, int64_t xb,
+                                               int64_t last, const uint32_t *s_bloom, uint32_t bshift,
+                                               uint32_t hw, uint32_t mw, uint32_t lastmask,
+                                               uint64_t *queue, uint32_t &qn, const VerifyArgs *vp,
+                                               int lane, uint64_t &nhit) {
+    if (hw == 4 && (mw > 4 || lastmask == 0xFFFFFFFFu))
+        dense_test<true>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit);
+    else
+        dense_test<false>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit);
 }
 
 // One whole tile: start positions x0 .. x0 + 16*NT - 1 (those up to `last`),
@@ -114,8 +163,8 @@ __device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t n
                                            int lane, uint64_t &nhit) {
     uint32_t W[10];
     dense_load<NT>(rs, nrec, p0, tid, W);
-    dense_test(W, p0 & 3u, x0 + 16 * (int64_t)tid, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp,
-               lane, nhit);
+    dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, last, s_bloom, bshift, hw, mw, lastmask, queue, qn,
+                   vp, lane, nhit);
 }
 
 }  // namespace dev
