@@ -1,8 +1,8 @@
 // Dense mode: every start position is tested against a Bloom bitmap of the
 // patterns' first min(m, 16) bytes; those that pass go to the exact
 // verification of Section 3.2. This is the filter that passes every window
-// (sigma' = 1), done without per-window overhead: one hash and two LDS bit
-// tests per position. Shared by the single-job dense kernel and the batched
+// (sigma' = 1), done without per-window overhead: one hash and kBloomBits LDS
+// bit tests per position. Shared by the single-job dense kernel and the batched
 // kernel.
 #pragma once
 
@@ -98,9 +98,13 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
                 }
                 h = prefilter_hash(w, (int)hw);
             }
-            const uint32_t i1 = h >> bshift, i2 = bloom_second(h) >> bshift;
-            const uint32_t b = (s_bloom[i1 >> 5] >> (i1 & 31)) & (s_bloom[i2 >> 5] >> (i2 & 31)) & 1u;
-            hm |= b << (4 * i + s);
+            uint32_t b = 1u;
+#pragma unroll
+            for (int j = 0; j < kBloomBits; ++j, h = bloom_second(h)) {
+                const uint32_t ix = h >> bshift;
+                b &= s_bloom[ix >> 5] >> (ix & 31);
+            }
+            hm |= (b & 1u) << (4 * i + s);
         }
     }
     // positions past the last start

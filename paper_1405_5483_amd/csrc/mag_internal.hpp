@@ -56,9 +56,14 @@ __host__ __device__ inline uint32_t window_hash(const uint32_t *w, int nwords) {
 }
 
 // Dense mode (every start position tested): a Bloom bitmap of 2^B bits over
-// the same first min(m, 16) bytes, two bits per distinct pattern. B grows with
-// the number of distinct patterns; batched scans use a copy with at most
-// kBloomBatchLog2 bits, built from the same hashes.
+// the same first min(m, 16) bytes, kBloomBits bits per distinct pattern (the
+// hash, then repeated bloom_second remixes of it). B grows with the number of
+// distinct patterns; batched scans use a copy with at most kBloomBatchLog2
+// bits, built from the same hashes.
+#ifndef MAG_BLOOM_BITS
+#define MAG_BLOOM_BITS 3
+#endif
+constexpr int kBloomBits = MAG_BLOOM_BITS;
 constexpr int kBloomMinLog2 = 12;
 constexpr int kBloomMaxLog2 = 20;
 constexpr int kBloomBatchLog2 = 18;

@@ -257,25 +257,26 @@ void build_verifier(mag_plan *p) {
     }
 }
 
-// Bloom bitmaps of the dense mode: bits prefilter_hash >> (32 - B) and
-// bloom_second(hash) >> (32 - B) of every distinct pattern's first min(m, 16)
-// bytes, for B = bloom_log2 and for the batched copy's smaller B.
+// Bloom bitmaps of the dense mode: for every distinct pattern's first
+// min(m, 16) bytes, bits h_j >> (32 - B) for j < kBloomBits, h_0 =
+// prefilter_hash and h_{j+1} = bloom_second(h_j), for B = bloom_log2 and for
+// the batched copy's smaller B.
 void build_bloom(mag_plan *p) {
     int B = kBloomMinLog2;
     while (B < kBloomMaxLog2 && (1ull << B) < 64ull * std::max<uint32_t>(p->n_unique, 1)) ++B;
     p->bloom_log2 = B;
-    // two bits per distinct pattern: a random position passes with the
-    // square of the bitmap's fill
-    const double fill = 1.0 - std::exp(-2.0 * (double)p->n_unique / (double)(1ull << B));
-    p->bloom_fp = fill * fill;
+    // kBloomBits bits per distinct pattern: a random position passes with
+    // the bitmap's fill to that power
+    const double fill =
+        1.0 - std::exp(-(double)kBloomBits * (double)p->n_unique / (double)(1ull << B));
+    p->bloom_fp = std::pow(fill, (double)kBloomBits);
     const int Bb = std::min(B, kBloomBatchLog2);
     p->bloom.assign((1u << B) / 32, 0u);
     p->bloom_batch.assign((1u << Bb) / 32, 0u);
     const int hw = std::min<int>(p->mw, kHashWords);
     for (uint32_t u = 0; u < p->n_unique; ++u) {
-        const uint32_t h = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
-        const uint32_t h2 = bloom_second(h);
-        for (uint32_t x : {h, h2}) {
+        uint32_t x = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
+        for (int j = 0; j < kBloomBits; ++j, x = bloom_second(x)) {
             const uint32_t i = x >> (32 - B), ib = x >> (32 - Bb);
             p->bloom[i >> 5] |= 1u << (i & 31);
             p->bloom_batch[ib >> 5] |= 1u << (ib & 31);
