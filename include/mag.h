@@ -380,6 +380,18 @@ mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launch
 const char *mag_status_string(mag_status s);
 const char *mag_last_error(void);
 
+/* Measurement aid, not part of the method: a plain streaming read of
+ * d[0..n) (device, 16-byte aligned) with 16-byte loads over a
+ * full-occupancy grid, each word folded into an xor written to d_sink
+ * (device, at least mag_stream_read_sink_words() words: word b is block b's
+ * xor of the 32-bit words, the bytes past the last whole 16-byte vector
+ * shifted in by position mod 4), so the read cannot be skipped. Time it on
+ * `stream` to get the read bandwidth a plain stream reaches on the device,
+ * the ceiling the scan is compared with besides the HBM specification.
+ * Enqueued only; no wait. d not 16-byte aligned -> MAG_E_INVALID. */
+mag_status mag_stream_read(const uint8_t *d, uint64_t n, uint32_t *d_sink, void *stream);
+uint32_t mag_stream_read_sink_words(void);
+
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int32_t mag_version(void);
 

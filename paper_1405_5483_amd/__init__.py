@@ -201,6 +201,20 @@ def encode(text, plan: Plan, stream=None):
     return out[:G]
 
 
+def stream_read(buf, sink=None, stream=None):
+    """Measurement aid: one plain streaming read of a uint8 CUDA tensor
+    (``mag_stream_read``); returns the sink tensor of per-block xors."""
+    import torch
+    _check_text(buf)
+    if sink is None:
+        sink = torch.empty(max(int(lib().mag_stream_read_sink_words()), 1), dtype=torch.int32,
+                           device=buf.device)
+    check(lib().mag_stream_read(ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                ctypes.c_void_p(sink.data_ptr()), _stream_ptr(stream)),
+          "mag_stream_read")
+    return sink
+
+
 def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> None:
     """Enqueues a scan without waiting (``mag_scan_async``). ``out`` is an
     int64 [cap, 2] CUDA tensor, ``d_count`` an int64 [1] CUDA tensor that

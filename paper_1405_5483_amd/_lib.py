@@ -82,6 +82,9 @@ SIGNATURES = {
                                        ctypes.c_uint64]),
     "mag_plan_create_var": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "mag_stream_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "mag_stream_read_sink_words": (ctypes.c_uint32, []),
     "mag_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                   ctypes.c_void_p]),

@@ -216,6 +216,14 @@ extern "C" {
 
 int32_t mag_version(void) { return 100; }
 
+mag_status mag_stream_read(const uint8_t *d, uint64_t n, uint32_t *d_sink, void *stream) {
+    if (!d_sink || (n && !d)) return fail(MAG_E_INVALID, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d) & 15) return fail(MAG_E_INVALID, "d must be 16-byte aligned");
+    return launch_stream_read(d, n, d_sink, reinterpret_cast<hipStream_t>(stream));
+}
+
+uint32_t mag_stream_read_sink_words(void) { return stream_read_grid(); }
+
 const char *mag_status_string(mag_status s) {
     switch (s) {
         case MAG_OK: return "ok";

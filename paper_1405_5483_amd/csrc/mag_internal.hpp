@@ -207,6 +207,10 @@ mag_status launch_encode(const mag_plan *p, const uint8_t *text, uint64_t n, voi
                          hipStream_t stream);
 // Bytes per encoded code of a plan: 2 when every code fits 16 bits, else 4.
 int encoded_code_bytes(const mag_plan *p);
+// Streaming-read reference (stream.hip): reads d[0..n) once; sink needs
+// stream_read_grid() words.
+mag_status launch_stream_read(const uint8_t *d, uint64_t n, uint32_t *sink, hipStream_t stream);
+uint32_t stream_read_grid();
 // Verifies the start positions a filter kernel deferred to v.pending
 // (segment counts in v.seg_count) with a full-occupancy grid (verify.hip).
 mag_status launch_verify(const VerifyArgs &v, hipStream_t stream);
