@@ -123,7 +123,8 @@ def profiled_traffic(workload: str, info: dict):
                 rec = json.loads(line[len("traffic-record: "):])
     if rec is None:
         return None, "summary has no traffic record"
-    if [rec["q"], rec["k"], rec["sigma_prime"]] != [info["q"], info["k"], info["sigma_prime"]]:
+    if [rec["q"], rec["k"], rec["sigma_prime"], rec.get("map")] != \
+            [info["q"], info["k"], info["sigma_prime"], _MAP_NAMES[info["map_kind"]]]:
         return None, "counters were taken with other parameters"
     if rec["src_sha256"] != scan_source_hash():
         return None, "scan kernel changed since the counters were taken"
@@ -373,7 +374,8 @@ def main() -> int:
     plan = plan_for(mag, job.patterns, args.select, text, selector)
     plan_ms = (time.perf_counter() - t) * 1e3
     info = plan.info()
-    log(f"plan q={info['q']} k={info['k']} sigma'={info['sigma_prime']} W={info['W']} "
+    log(f"plan q={info['q']} k={info['k']} sigma'={info['sigma_prime']} "
+        f"map={_MAP_NAMES[info['map_kind']]} W={info['W']} "
         f"table={info['table_bytes']} B ({plan_ms:.1f} ms)")
 
     # exact occurrence list once, with counters, and verified against the oracle
@@ -461,7 +463,7 @@ def main() -> int:
         "config": {"workload": args.workload, "text_bytes": n, "sigma": w["sigma"],
                    "dist": w["dist"], "r": job.r, "m": job.m, "select": args.select,
                    "q": info["q"], "k": info["k"], "sigma_prime": info["sigma_prime"],
-                   "parallelism": "single GPU"},
+                   "map": _MAP_NAMES[info["map_kind"]], "parallelism": "single GPU"},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -54,7 +54,11 @@ typedef enum {
                                  lowered until the mask table fits the budget */
     MAG_SELECT_EXPLICIT = 1,  /* q, k, sigma_prime taken from mag_params       */
     MAG_SELECT_LEARNED = 2,   /* a pick of mag_select_learned: q, k, sigma_prime
-                                 as it filled them; all zero = the heuristic   */
+                                 as it filled them; all zero = the heuristic.
+                                 With the greedy map and sigma' = 2^l the plan
+                                 takes the bit-field map instead when its
+                                 expected verifications per byte are at most
+                                 1.25x the greedy map's + 1e-5                */
     MAG_SELECT_AUTOTUNE = 3   /* measured on the device over a small grid      */
 } mag_select;
 

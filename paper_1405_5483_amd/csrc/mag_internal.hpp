@@ -70,6 +70,10 @@ constexpr int kBloomBatchLog2 = 18;
 // MAG_MODE_AUTO scans densely when the filter is expected to verify at least
 // this many start positions per text byte.
 constexpr double kDenseVerifPerByte = 0.1;
+// A learned pick with sigma' = 2^l switches to the bit-field map when that
+// map's expected verifications per byte are at most 1.25x the greedy map's
+// plus this.
+constexpr double kLearnedBitsSlack = 1e-5;
 
 __host__ __device__ inline uint32_t prefilter_hash(const uint32_t *w, int nwords) {
     uint32_t x = w[0];

@@ -469,6 +469,28 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->verify_buffer = (uint64_t)prm.verify_buffer;
     p->encode = prm.encode;
     p->est_verif = estimate_verifications(p);
+    // A learned pick with sigma' = 2^l: the bit-field map's codes need no map
+    // lookups and scan faster; take it when its classes stay about as
+    // selective (the selector's costs were measured with the greedy map).
+    if (prm.select == MAG_SELECT_LEARNED && p->map_kind == MAG_MAP_GREEDY && p->r && sp > 1 &&
+        (sp & (sp - 1)) == 0 && p->est_verif >= 0.0 && p->est_verif < kDenseVerifPerByte) {
+        uint8_t mu_g[256];
+        std::memcpy(mu_g, p->mu, 256);
+        std::vector<uint8_t> table_g = p->table;
+        const double est_g = p->est_verif;
+        p->map_kind = MAG_MAP_BITS;
+        map_bits(p);
+        build_table(p);
+        const double est_b = estimate_verifications(p);
+        if (est_b >= 0.0 && est_b <= 1.25 * est_g + kLearnedBitsSlack) {
+            p->est_verif = est_b;
+        } else {
+            p->map_kind = MAG_MAP_GREEDY;
+            p->bits_shift = 0;
+            std::memcpy(p->mu, mu_g, 256);
+            p->table.swap(table_g);
+        }
+    }
     p->dense = prm.mode == MAG_MODE_DENSE ||
                (prm.mode == MAG_MODE_AUTO && p->est_verif >= kDenseVerifPerByte);
     return MAG_OK;

@@ -261,3 +261,23 @@ def test_unequal_length_errors():
         o = np.array(offs, dtype=np.uint64)
         r = len(offs) - 1
         assert lib().mag_plan_create_var(data.ctypes.data, o.ctypes.data, r, None, ctypes.byref(h)) == -1
+
+
+def test_learned_pick_takes_bit_fields_when_as_selective():
+    mag = _lib_or_skip()
+    from synth import workload
+    job = workload("zipf256m", n=1 << 20)
+    greedy = mag.Plan(job.patterns, q=4, k=1, sigma_prime=16).info()
+    learned = mag.Plan(job.patterns, q=4, k=1, sigma_prime=16, select="learned").info()
+    bits = mag.Plan(job.patterns, q=4, k=1, sigma_prime=16, map_kind="bits").info()
+    assert greedy["map_kind"] == 0 and learned["map_kind"] == 2
+    assert learned["est_verif"] == bits["est_verif"] <= 1.25 * greedy["est_verif"] + 1e-5
+    assert learned["bits_shift"] == mm.bits_shift(job.patterns, 16)
+    # sigma' not a power of two, or a bit-field map that is clearly worse: greedy stays
+    T = gen_text(50_000, 20, rng=3)
+    P = gen_patterns(T, 500, 12, 250, 20, rng=4)
+    assert mag.Plan(P, q=3, k=1, sigma_prime=12, select="learned").info()["map_kind"] == 0
+    g = mag.Plan(P, q=3, k=1, sigma_prime=16).info()["est_verif"]
+    b = mag.Plan(P, q=3, k=1, sigma_prime=16, map_kind="bits").info()["est_verif"]
+    assert b > 1.25 * g + 1e-5
+    assert mag.Plan(P, q=3, k=1, sigma_prime=16, select="learned").info()["map_kind"] == 0
