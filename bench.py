@@ -171,10 +171,17 @@ def cpu_baseline(job, threads: int, max_bytes: int):
         om.occ_hashed(sample, job.patterns, threads=threads)
         runs.append(time.perf_counter() - t)
     sec = statistics.median(runs)
+    # one thread on a quarter of the sample
+    one = job.text[: max_bytes // 4]
+    t = time.perf_counter()
+    om.occ_hashed(one, job.patterns, threads=1)
+    sec1 = time.perf_counter() - t
     return {"value": round(sample.size / sec / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {sample.size} bytes of the same text, all {job.r} patterns, "
-                      f"median of 3 runs of the C hashed matcher ({sec:.2f} s each)"}
+                      f"median of 3 runs of the C hashed matcher ({sec:.2f} s each)",
+            "value_1_thread": round(one.size / sec1 / 1e9, 4),
+            "sample_1_thread": f"first {one.size} bytes, one run on one thread ({sec1:.2f} s)"}
 
 
 def oracle_equal(occ_np, ref):
