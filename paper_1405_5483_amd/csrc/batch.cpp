@@ -24,16 +24,6 @@ int ceil_log2(uint64_t v) {
 // split of the tile sequence among workgroups.
 constexpr uint64_t kTileOverheadBytes = 2048;
 
-int device_compute_units() {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return v;
-}
-
 template <typename T>
 mag_status grow(T **p, size_t *have, size_t want_bytes, const char *what) {
     if (*p && *have >= want_bytes) return MAG_OK;

@@ -4,7 +4,10 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -122,6 +125,26 @@ uint64_t pending_capacity(double expect) {
 }
 
 }  // namespace
+
+int cached_occupancy(const void *fn, int threads, size_t shmem) {
+    static std::mutex mtx;
+    static std::map<std::tuple<const void *, int, size_t>, int> cache;
+    const auto key = std::make_tuple(fn, threads, shmem);
+    {
+        std::lock_guard<std::mutex> lock(mtx);
+        const auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int occ = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, shmem);
+    if (e != hipSuccess) {
+        hip_fail(e, "occupancy query");
+        return 0;
+    }
+    std::lock_guard<std::mutex> lock(mtx);
+    cache[key] = occ;
+    return occ;
+}
 
 mag_status fail(mag_status s, const std::string &msg) {
     g_last_error = msg;
@@ -412,9 +435,18 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
                           : p->dense ? p->bloom_fp * (double)samples
                           : p->est_verif < 0.0 ? -1.0 : p->est_verif * (double)n;
     uint64_t pcap = 0;
+    // a grid of fewer workgroups than half the compute units verifies inline
+    // with few waves: defer when each of them would face many starts
+    const int ncu = device_compute_units();
+    const uint64_t tile = p->dense ? (uint64_t)kDenseTilePositions : kSmallGridTileSamples;
+    const uint64_t tiles = (samples + tile - 1) / tile;
+    const double vwaves = (double)std::max<uint64_t>(tiles, 1) *
+                          (p->dense ? kDenseThreads / 64 : kScanConsumerLanes / 64);
+    const bool small_grid = ncu > 0 && 2 * tiles < (uint64_t)ncu;
     const bool defer = p->verify == MAG_VERIFY_DEFERRED ||
-                       (p->verify == MAG_VERIFY_AUTO && !p->dense &&
-                        (expect < 0.0 || expect >= kDeferMinVerifications));
+                       (p->verify == MAG_VERIFY_AUTO &&
+                        ((!p->dense && (expect < 0.0 || expect >= kDeferMinVerifications)) ||
+                         (small_grid && expect >= kDeferPerWave * vwaves)));
     if (samples && defer)
         pcap = p->verify_buffer ? p->verify_buffer
                                 : pending_capacity(expect < 0.0 ? expect : std::max(expect, (double)(1 << 20)));

@@ -16,7 +16,9 @@ constexpr int kNT = kDenseThreads;
 constexpr int kQueue = 128;
 static_assert(kQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 
-__global__ __launch_bounds__(kNT) void k_dense(DenseArgs a) {
+// At least 4 waves per SIMD: at most 128 VGPRs, so two workgroups share a
+// compute unit whenever the Bloom bitmap leaves room in LDS.
+__global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem);
     uint32_t *s_bloom = reinterpret_cast<uint32_t *>(smem + (kNT / 64) * kQueue * 8);
@@ -94,16 +96,22 @@ mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stre
         (void)hipGetLastError();
         configured = shmem;
     }
-    int dev = 0, ncu = 0, occ = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dense, kNT, shmem);
-    if (e != hipSuccess) return hip_fail(e, "dense scan sizing");
+    static int ncu = 0;
+    if (!ncu) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) {
+            ncu = 0;
+            return hip_fail(e, "dense scan sizing");
+        }
+    }
+    const int occ = cached_occupancy((const void *)k_dense, kNT, shmem);
     if (occ < 1) return fail(MAG_E_UNSUPPORTED, "dense scan does not fit on a compute unit");
     uint64_t grid = (uint64_t)ncu * occ;
     if (grid > a.ntiles) grid = a.ntiles;
     hipLaunchKernelGGL(k_dense, dim3((uint32_t)grid), dim3(kNT), shmem, stream, a);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "dense scan launch");
 }
 

@@ -33,6 +33,11 @@ constexpr int kQgramLoad = 32;
 constexpr double kDeferMinVerifications = 1 << 24;
 constexpr uint64_t kPendingMax = 1ull << 26;
 constexpr uint32_t kPendingSegments = 256;   // deferred-start buffer segments, one counter each
+// A scan whose grid covers less than half the compute units also defers when
+// each of its verifying waves would face at least this many starts: inline,
+// those few waves would verify them one queue after another.
+constexpr double kDeferPerWave = 64;
+constexpr uint64_t kSmallGridTileSamples = 4096;   // filter tile size of short texts
 constexpr int kHashWords = 4;       // the verification hash reads the first 16 bytes
 // Scratch counters: [0] occurrences [1] candidate windows [2] verifications,
 // [4] and [8..11] the count and stats that mag_scan reads back, and
@@ -211,6 +216,14 @@ mag_status launch_encode(const mag_plan *p, const uint8_t *text, uint64_t n, voi
                          hipStream_t stream);
 // Bytes per encoded code of a plan: 2 when every code fits 16 bits, else 4.
 int encoded_code_bytes(const mag_plan *p);
+// Resident workgroups per compute unit of kernel `fn` at `threads` threads
+// and `shmem` bytes of dynamic LDS, queried once per (kernel, threads, size)
+// and then served from a cache (capi.cpp); 0 after an error (detail in the
+// thread's last error).
+int cached_occupancy(const void *fn, int threads, size_t shmem);
+// Compute units of the current device, queried once (scan_dispatch.cpp); 0
+// after an error.
+int device_compute_units();
 // Streaming-read reference (stream.hip): reads d[0..n) once; sink needs
 // stream_read_grid() words.
 mag_status launch_stream_read(const uint8_t *d, uint64_t n, uint32_t *sink, hipStream_t stream);

@@ -368,15 +368,13 @@ mag_status launch_one(const ScanArgs &a, size_t shmem, int ncu, hipStream_t stre
         (void)hipGetLastError();
         configured_bytes = (int)shmem;
     }
-    int occ = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kNT, shmem);
-    if (e != hipSuccess) return hip_fail(e, "occupancy query (scan)");
+    const int occ = cached_occupancy((const void *)fn, kNT, shmem);
     if (occ < 1) return fail(MAG_E_UNSUPPORTED, "scan kernel does not fit on a compute unit");
     uint64_t grid = (uint64_t)ncu * (uint64_t)occ;
     if (grid > a.ntiles) grid = a.ntiles;
     if (grid == 0) return MAG_OK;
     hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kNT), shmem, stream, a);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scan launch");
     return MAG_OK;
 }

@@ -136,8 +136,9 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
         const uint32_t cnt = (uint32_t)__popcll(mask);
         const uint32_t lane = __lane_id();
         const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(true));
-        // one counter per segment keeps the atomics of different workgroups apart
-        const uint32_t seg = blockIdx.x % kPendingSegments;
+        // one counter per (workgroup, wave) segment keeps the atomics apart
+        // and spreads a small grid's starts over many verifying waves
+        const uint32_t seg = (blockIdx.x * 16u + (threadIdx.x >> 6)) % kPendingSegments;
         unsigned long long got = 0;
         if (lane == first) got = atomicAdd((unsigned long long *)&args.seg_count[seg], (unsigned long long)cnt);
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);

@@ -13,7 +13,11 @@ constexpr uint64_t kTableLdsMax = 64 * 1024;   // mask tables up to this size ar
 #endif
 constexpr uint32_t kEntryBytesPerTile = MAG_SCAN_TILE_BYTES;   // one of the two mask-entry buffers
 
-int compute_units() {
+int compute_units() { return device_compute_units(); }
+
+}  // namespace
+
+int device_compute_units() {
     static int ncu = 0;
     if (ncu) return ncu;
     int dev = 0, v = 0;
@@ -25,8 +29,6 @@ int compute_units() {
     ncu = v;
     return ncu;
 }
-
-}  // namespace
 
 VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
     VerifyArgs v{};

@@ -24,7 +24,8 @@ struct VerifyArgs {
     uint64_t key_or;           // batched scans: the job number in the key's top bits
     uint64_t *counters;        // [0] = occurrences found
     uint64_t *pending;         // deferred start positions (NULL: verify inline), kPendingSegments
-                               // segments of seg_cap entries; workgroup g appends to g % segments
+                               // segments of seg_cap entries; wave w of workgroup g appends to
+                               // (16 g + w) % segments
     uint64_t *seg_count;       // starts appended to each segment (may exceed seg_cap)
     uint64_t seg_cap;
     // patterns of unequal lengths (var = 1): slots lead to groups of distinct
@@ -50,17 +51,56 @@ __device__ __forceinline__ uint32_t gword(const VerifyArgs &a, uint64_t off) {
     return *reinterpret_cast<const uint32_t *>(a.tbase + off);
 }
 
+#ifndef MAG_CMP_WORDS
+#define MAG_CMP_WORDS 4
+#endif
+constexpr uint32_t kCmpWords = MAG_CMP_WORDS;   // pattern words compared per round trip
+
+// Whether the words words0 .. words0+nw-1 of the window starting at byte
+// offset `base` + sh equal pw[0 .. nw) (nw <= kCmpWords; the last word masked by
+// lastmask when it is the pattern's last). The chunk's text and pattern words
+// are all loaded before any compare, so they arrive in one round trip.
+__device__ inline bool words_equal(const VerifyArgs &a, uint64_t base, uint32_t sh, uint32_t words0,
+                                   uint32_t nw, const uint32_t *pw, uint32_t lastmask, bool last) {
+    uint32_t tw[kCmpWords + 1], pv[kCmpWords];
+#pragma unroll
+    for (int t = 0; t <= kCmpWords; ++t) tw[t] = (uint32_t)t <= nw ? gword(a, base + 4 * (words0 + t)) : 0u;
+#pragma unroll
+    for (int t = 0; t < kCmpWords; ++t) pv[t] = (uint32_t)t < nw ? pw[t] : 0u;
+    uint32_t diff = 0;
+#pragma unroll
+    for (int t = 0; t < kCmpWords; ++t) {
+        if ((uint32_t)t < nw) {
+            uint32_t x = __builtin_amdgcn_alignbyte(tw[t + 1], tw[t], sh);
+            if (last && (uint32_t)t == nw - 1) x &= lastmask;
+            diff |= x ^ pv[t];
+        }
+    }
+    return diff == 0;
+}
+
+// Whether the window at byte offset base + sh equals the nw-word pattern at
+// pw (last word masked by lastmask), compared kCmpWords words at a time.
+__device__ inline bool window_equal(const VerifyArgs &a, uint64_t base, uint32_t sh, uint32_t nw,
+                                    const uint32_t *pw, uint32_t lastmask) {
+    for (uint32_t c = 0; c < nw; c += kCmpWords) {
+        const uint32_t k = nw - c < kCmpWords ? nw - c : kCmpWords;
+        if (!words_equal(a, base, sh, c, k, pw + c, lastmask, c + k == nw)) return false;
+    }
+    return true;
+}
+
 // Index + 1 of the distinct pattern that equals the window at start position
-// i0, or 0 if none does.
+// i0, or 0 if none does. On a fingerprint hit the window's and the pattern's
+// words are loaded together before they are compared (kCmpWords words per
+// round trip), so a verification waits for a few memory round trips.
 __device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
     const uint64_t p = a.delta + i0;
     const uint64_t base = p & ~3ull;
     const uint32_t sh = (uint32_t)(p & 3);
-    uint32_t w[kMaxM / 4 + 1];
-    w[0] = gword(a, base);
+    uint32_t w[kHashWords + 1];
 #pragma unroll
-    for (int t = 0; t < kHashWords; ++t)
-        if (t < (int)a.hw) w[t + 1] = gword(a, base + 4 * t + 4);
+    for (int t = 0; t <= kHashWords; ++t) w[t] = t <= (int)a.hw ? gword(a, base + 4 * t) : 0u;
     uint32_t hv[kHashWords];
 #pragma unroll
     for (int t = 0; t < kHashWords; ++t) {
@@ -78,17 +118,8 @@ __device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
         if (e == 0) return 0;
         if ((uint32_t)(e >> 32) == h) {
             const uint32_t u = (uint32_t)e - 1u;
-            const uint32_t *pw = a.pwords + (size_t)u * a.mw;
-            bool eq = true;
-            uint32_t lo = w[0];
-            for (uint32_t t = 0; t < a.mw; ++t) {
-                const uint32_t hi = gword(a, base + 4 * t + 4);
-                uint32_t x = __builtin_amdgcn_alignbyte(hi, lo, sh);
-                lo = hi;
-                if (t == a.mw - 1) x &= a.lastmask;
-                if (x != pw[t]) { eq = false; break; }
-            }
-            if (eq) return u + 1;     // distinct patterns: at most one can be equal
+            if (window_equal(a, base, sh, a.mw, a.pwords + (size_t)u * a.mw, a.lastmask))
+                return u + 1;     // distinct patterns: at most one can be equal
         }
         slot = (slot + 1) & a.slot_mask;
     }
@@ -150,15 +181,7 @@ __device__ inline bool member_matches(const VerifyArgs &a, uint64_t i0, uint32_t
     const uint32_t sh = (uint32_t)(p & 3);
     const uint32_t words = (len + 3) / 4;
     const uint32_t lastmask = (len & 3) ? ((1u << (8 * (len & 3))) - 1u) : 0xFFFFFFFFu;
-    uint32_t w0 = gword(a, base);
-    for (uint32_t t = 0; t < words; ++t) {
-        const uint32_t w1 = gword(a, base + 4 * t + 4);
-        uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, sh);
-        w0 = w1;
-        if (t == words - 1) x &= lastmask;
-        if (x != pw[t]) return false;
-    }
-    return true;
+    return window_equal(a, base, sh, words, pw, lastmask);
 }
 
 // Unequal lengths: every member of the window's group that fits before the
