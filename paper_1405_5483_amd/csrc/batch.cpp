@@ -23,6 +23,11 @@ int ceil_log2(uint64_t v) {
 // Fixed cost of a tile (barriers, setup) in text-byte equivalents, for the
 // split of the tile sequence among workgroups.
 constexpr uint64_t kTileOverheadBytes = 2048;
+// Jobs with texts up to this size may defer their verification; the batch's
+// deferred-start buffer holds this many entries (starts past a segment's
+// share are verified inline, so the result never depends on it).
+constexpr uint64_t kBatchDeferMaxText = 1 << 20;
+constexpr uint64_t kBatchPendingEntries = 1 << 23;
 
 template <typename T>
 mag_status grow(T **p, size_t *have, size_t want_bytes, const char *what) {
@@ -57,6 +62,7 @@ struct mag_batch {
     size_t ranges_bytes = 0;
     uint64_t *d_next = nullptr;      // tile claim counters, one per workgroup
     size_t next_bytes = 0;
+    bool defer = false;              // some job defers its verification
     mag::Scratch sc;
 };
 
@@ -108,6 +114,8 @@ void mag_batch_destroy(mag_batch *b) {
         (void)hipFree(b->sc.keys);
         (void)hipFree(b->sc.hist);
         (void)hipFree(b->sc.radix_off);
+        (void)hipFree(b->sc.pending);
+        (void)hipFree(b->sc.seg_count);
         (void)hipSetDevice(cur);
     }
     delete b;
@@ -175,6 +183,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
 
     // jobs and their tiles
     std::vector<JobDesc> jobs(njobs);
+    std::vector<uint8_t> defer(njobs, 0);
     std::vector<uint64_t> tiles_of(njobs), tile_bytes_full(njobs), tail_samples(njobs);
     uint64_t total_tiles = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
@@ -220,6 +229,13 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         sl.idbits = idbits;
         J.v = make_verify_args(p, sl);
         J.v.key_or = (uint64_t)j << (posbits + idbits);
+        // a short text with many patterns keeps one workgroup verifying for
+        // long; its starts go to the batch verification kernel instead
+        const double expect = p->dense ? p->bloom_fp * (double)X : p->est_verif * (double)n[j];
+        const double vwaves = (double)std::max<uint64_t>(J.ntiles, 1) * (kBatchThreads / 64);
+        if (X && n[j] <= kBatchDeferMaxText && posbits <= kBatchJobShift &&
+            ((double)p->r * p->m * 4 >= (double)n[j] || expect >= kDeferPerWave * vwaves))
+            defer[j] = 1;
         tiles_of[j] = J.ntiles;
         tile_bytes_full[j] = (uint64_t)kBatchTileSamples * kq;
         tail_samples[j] = X - (J.ntiles ? (J.ntiles - 1) * kBatchTileSamples : 0);
@@ -264,6 +280,27 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
             ranges[3 * wg + 2] = begin[wg] < total_tiles ? job_of[wg] : 0;
         }
     }
+    // deferred starts: one buffer for the batch, its segment counters zeroed
+    // here once and by the finishing kernel of every run
+    b->defer = false;
+    for (uint32_t j = 0; j < njobs; ++j) b->defer = b->defer || defer[j];
+    if (b->defer) {
+        if (!sc.pending) {
+            e = hipMalloc(&sc.pending, kBatchPendingEntries * sizeof(uint64_t));
+            if (e == hipSuccess) e = hipMalloc(&sc.seg_count, kPendingSegments * sizeof(uint64_t));
+            if (e == hipSuccess) e = hipMemset(sc.seg_count, 0, kPendingSegments * sizeof(uint64_t));
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "deferred-start buffer of the batch");
+            sc.pending_cap = kBatchPendingEntries;
+        }
+        for (uint32_t j = 0; j < njobs; ++j) {
+            if (!defer[j]) continue;
+            jobs[j].v.pending = sc.pending;
+            jobs[j].v.seg_count = sc.seg_count;
+            jobs[j].v.seg_cap = sc.pending_cap / kPendingSegments;
+            jobs[j].v.pending_tag = (uint64_t)j << kBatchJobShift;
+        }
+    }
     mag_status s = grow(&b->d_jobs, &b->jobs_bytes, std::max<size_t>(njobs, 1) * sizeof(JobDesc), "job table");
     if (s != MAG_OK) return s;
     s = grow(&b->d_ranges, &b->ranges_bytes, ranges.size() * sizeof(uint64_t), "tile ranges");
@@ -306,6 +343,9 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     bl.total_tiles = b->total_tiles;
     bl.counters = sc.counters;
     mag_status s = launch_batch(bl, stream);
+    if (s == MAG_OK && b->defer)
+        s = launch_batch_verify(b->d_jobs, sc.pending, sc.seg_count, sc.pending_cap / kPendingSegments,
+                                stream);
     if (s == MAG_OK)
         s = launch_finish(sc, b->cap, 0, d_count, nullptr, d_out, b->idbits, posmask, sorted, stream);
     if (s == MAG_OK && b->cap > small_sort_max()) {

@@ -446,4 +446,56 @@ mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint
     return e == hipSuccess ? MAG_OK : hip_fail(e, "batch offsets launch");
 }
 
+namespace {
+
+constexpr int kBatchVerifyThreads = 256;
+
+// The deferred starts of batched jobs (entry = job << kBatchJobShift |
+// start), spread over the buffer's segments like the single-job
+// verification kernel. Each lane reads its own job's verification
+// arguments; all jobs share the batch's counters, key buffer and capacity,
+// so the wave's collective output reservation still applies.
+__global__ __launch_bounds__(kBatchVerifyThreads) void k_batch_verify(const JobDesc *jobs,
+                                                                      const uint64_t *pending,
+                                                                      const uint64_t *seg_count,
+                                                                      uint64_t seg_cap) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBatchVerifyThreads + threadIdx.x) >> 6;
+    const uint64_t waves = ((uint64_t)gridDim.x * kBatchVerifyThreads) >> 6;
+    const uint64_t per = waves >= kPendingSegments ? waves / kPendingSegments : 1;
+    const uint64_t posmask = (1ull << kBatchJobShift) - 1ull;
+    for (uint64_t w = wave; w < per * kPendingSegments; w += waves) {
+        const uint32_t seg = (uint32_t)(w % kPendingSegments);
+        const uint64_t sub = w / kPendingSegments;
+        const uint64_t count = seg_count[seg];
+        const uint64_t total = count < seg_cap ? count : seg_cap;
+        const uint64_t *src = pending + (uint64_t)seg * seg_cap;
+        for (uint64_t c = sub * 64; c < total; c += per * 64) {
+            const uint64_t i = c + lane;
+            const bool active = i < total;
+            const uint64_t e = active ? src[i] : 0ull;
+            VerifyArgs v;
+            __builtin_memcpy(&v, &jobs[(uint32_t)(e >> kBatchJobShift)].v, sizeof(v));
+            verify_wave(v, e & posmask, active);
+        }
+    }
+}
+
+}  // namespace
+
+mag_status launch_batch_verify(const JobDesc *jobs, const uint64_t *pending, const uint64_t *seg_count,
+                               uint64_t seg_cap, hipStream_t stream) {
+    static uint32_t grid = 0;
+    if (!grid) {
+        const int ncu = device_compute_units();
+        const int occ = cached_occupancy((const void *)k_batch_verify, kBatchVerifyThreads, 0);
+        if (ncu < 1 || occ < 1) return fail(MAG_E_DEVICE, "cannot size the batch verification");
+        grid = (uint32_t)(ncu * occ);
+    }
+    hipLaunchKernelGGL(k_batch_verify, dim3(grid), dim3(kBatchVerifyThreads), 0, stream, jobs, pending,
+                       seg_count, seg_cap);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch verification launch");
+}
+
 }  // namespace mag

@@ -57,6 +57,11 @@ struct BatchLaunch {
 int batch_occupancy();
 mag_status batch_configure();
 mag_status launch_batch(const BatchLaunch &b, hipStream_t stream);
+// Verifies the starts that batched jobs deferred: entry = job << kBatchJobShift
+// | start (batch.hip).
+constexpr int kBatchJobShift = 40;
+mag_status launch_batch_verify(const JobDesc *jobs, const uint64_t *pending, const uint64_t *seg_count,
+                               uint64_t seg_cap, hipStream_t stream);
 // offsets[j] = first record of job j in the sorted keys, offsets[njobs] = count.
 mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
                                 uint64_t *d_offsets, uint32_t njobs, int job_shift,

@@ -136,9 +136,12 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
         const uint32_t cnt = (uint32_t)__popcll(mask);
         const uint32_t lane = __lane_id();
         const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(true));
-        // one counter per (workgroup, wave) segment keeps the atomics apart
-        // and spreads a small grid's starts over many verifying waves
-        const uint32_t seg = (blockIdx.x * 16u + (threadIdx.x >> 6)) % kPendingSegments;
+        // one counter per segment keeps the atomics apart and spreads a small
+        // grid's starts over many verifying waves; a multiplicative hash of
+        // the wave's number (golden-ratio constant, top bits) uses every
+        // segment whichever waves of a workgroup verify
+        static_assert(kPendingSegments == 256, "segment = top 8 bits of the hash");
+        const uint32_t seg = ((blockIdx.x * 16u + (threadIdx.x >> 6)) * 0x9E3779B1u) >> 24;
         unsigned long long got = 0;
         if (lane == first) got = atomicAdd((unsigned long long *)&args.seg_count[seg], (unsigned long long)cnt);
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
@@ -146,7 +149,7 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
         const uint64_t base = ((uint64_t)hi << 32) | lo;
         const uint64_t slot = base + lanes_below(mask);
         const bool stored = active && slot < args.seg_cap;
-        if (stored) args.pending[(uint64_t)seg * args.seg_cap + slot] = i0;
+        if (stored) args.pending[(uint64_t)seg * args.seg_cap + slot] = i0 | args.pending_tag;
         if (base + cnt <= args.seg_cap) return;
         active = active && !stored;
     }

@@ -28,6 +28,7 @@ struct VerifyArgs {
                                // (16 g + w) % segments
     uint64_t *seg_count;       // starts appended to each segment (may exceed seg_cap)
     uint64_t seg_cap;
+    uint64_t pending_tag;      // OR'ed into each deferred start (batches: job << 40)
     // patterns of unequal lengths (var = 1): slots lead to groups of distinct
     // patterns that share their first m bytes (m = the shortest length);
     // group g is distinct patterns gstart[g] .. gstart[g+1]-1, pattern u has
