@@ -41,8 +41,10 @@ constexpr uint64_t kSmallGridTileSamples = 4096;   // filter tile size of short 
 constexpr int kHashWords = 4;       // the verification hash reads the first 16 bytes
 // Scratch counters: [0] occurrences [1] candidate windows [2] verifications,
 // [4] and [8..11] the count and stats that mag_scan reads back, and
-// [kSortCountSlot] the count that the device-wide sort reads.
+// [kSortCountSlot] the count that the device-wide sort reads, and
+// [kFinishDoneSlot] the finishing workgroups that have read the counters.
 constexpr int kSortCountSlot = 12;
+constexpr int kFinishDoneSlot = 13;
 
 // Fingerprint of the first min(m, 16) bytes of a pattern or text window, given
 // as little-endian 32-bit words with bytes past m zeroed. It only has to spread

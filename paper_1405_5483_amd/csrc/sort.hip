@@ -2,15 +2,17 @@
 //
 // The scan emits 64-bit keys (pos << idbits | id, batched scans add the job
 // number above the position) in arbitrary order; keys are unique, since every
-// (pos, id) is reported once. The finishing kernel (one workgroup, launched
-// right after the scan) publishes the occurrence count and the work counters
-// and sorts up to kSmallMax keys in LDS. Larger outputs are sorted by a stable
-// LSD radix sort with 8-bit digits across the whole device: per pass a
-// histogram, a scan of the counts and a scatter kernel. Those kernels read the
-// count from device memory (the finishing kernel leaves it in counters[5]), so
-// they can be enqueued before the host knows it: the grid is sized for an
-// upper bound and workgroups past the real count return at once. No kernel
-// waits on another workgroup.
+// (pos, id) is reported once. The finishing kernel (launched right after the
+// scan) publishes the occurrence count and the work counters and ranks up to
+// kSmallMax keys: each of its workgroups stages the keys in LDS and places
+// kFinishKeys of them, so a small output is sorted by several compute units
+// at once. Larger outputs are sorted by a stable LSD radix sort with 8-bit
+// digits across the whole device: per pass a histogram, a scan of the counts
+// and a scatter kernel. Those kernels read the count from device memory (the
+// finishing kernel leaves it in counters[kSortCountSlot]), so they can be
+// enqueued before the host knows it: the grid is sized for an upper bound and
+// workgroups past the real count return at once. No kernel waits on another
+// workgroup.
 #include <hip/hip_runtime.h>
 
 #include "mag_internal.hpp"
@@ -19,8 +21,10 @@ namespace mag {
 namespace {
 
 constexpr int kFinishThreads = 1024;
+constexpr uint32_t kFinishWaves = kFinishThreads / 64;
 constexpr uint32_t kSmallMax = 8192;
-constexpr uint32_t kRankMax = 2048;           // rank counting below this, bitonic above
+constexpr uint32_t kFinishKeys = 64;              // keys ranked per finishing workgroup
+constexpr uint32_t kFinishGrid = kSmallMax / kFinishKeys;
 constexpr int kRadixThreads = 256;
 constexpr uint32_t kRadixChunk = 4096;        // keys per chunk of the device-wide sort
 constexpr uint32_t kRadixGrid = 1024;         // workgroups per radix kernel (they loop over chunks)
@@ -130,83 +134,83 @@ struct FinishArgs {
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
     __shared__ uint64_t s_keys[kSmallMax];
-    __shared__ uint32_t s_rank[kRankMax];
+    __shared__ uint64_t s_z;
+    __shared__ uint32_t s_rank[kFinishKeys];
     const uint32_t tid = threadIdx.x;
-    const uint64_t z = a.counters[0];
-    const uint64_t cw = a.counters[1], nv = a.counters[2];
-    __syncthreads();      // every thread has read the counters
     if (tid == 0) {
-        *a.d_count = z;
-        if (a.d_stats) {
-            a.d_stats->samples = a.samples;
-            a.d_stats->cand_windows = cw;
-            a.d_stats->verifications = nv;
-            a.d_stats->matches = z;
+        const uint64_t z = a.counters[0], cw = a.counters[1], nv = a.counters[2];
+        s_z = z;
+        if (blockIdx.x == 0) {
+            *a.d_count = z;
+            if (a.d_stats) {
+                a.d_stats->samples = a.samples;
+                a.d_stats->cand_windows = cw;
+                a.d_stats->verifications = nv;
+                a.d_stats->matches = z;
+            }
+            // the count stays for the device-wide sort
+            a.counters[kSortCountSlot] = z;
         }
-        // the count stays for the device-wide sort; the others return to zero
-        // for the next scan
-        a.counters[kSortCountSlot] = z;
-        a.counters[0] = 0;
-        a.counters[1] = 0;
-        a.counters[2] = 0;
-        a.counters[3] = 0;
+        // the last workgroup to have read the counters returns them (and the
+        // arrival count) to zero for the next scan
+        __threadfence();
+        unsigned long long *done = (unsigned long long *)&a.counters[kFinishDoneSlot];
+        if (atomicAdd(done, 1ull) == gridDim.x - 1) {
+            for (int c = 0; c < 4; ++c)
+                __hip_atomic_store(&a.counters[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     // the verification kernel has read the segment counts (it ran before)
-    if (a.seg_count)
+    if (blockIdx.x == 0 && a.seg_count)
         for (uint32_t i = tid; i < kPendingSegments; i += kFinishThreads) a.seg_count[i] = 0;
-    if (z > a.cap || z == 0 || z > kSmallMax) return;
-
-    if (z <= kRankMax) {
-        // keys are unique: a key's output slot is the number of smaller keys.
-        // Each key's count is split over `parts` threads (8 independent sums
-        // each, so LDS reads overlap) and combined with LDS atomics.
-        for (uint32_t i = tid; i < z; i += kFinishThreads) {
-            s_keys[i] = a.keys[i];
-            s_rank[i] = 0;
-        }
-        __syncthreads();
-        const uint32_t parts = z <= kFinishThreads ? kFinishThreads / (uint32_t)z : 1u;
-        const uint32_t span = ((uint32_t)z + parts - 1) / parts;
-        for (uint32_t w = tid; w < (uint32_t)z * parts; w += kFinishThreads) {
-            const uint32_t i = w / parts, part = w % parts;
-            const uint64_t key = s_keys[i];
-            const uint32_t j0 = part * span, j1 = j0 + span < z ? j0 + span : (uint32_t)z;
-            uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            uint32_t j = j0;
-            for (; j + 8 <= j1; j += 8) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc[u] += s_keys[j + u] < key ? 1u : 0u;
-            }
-            for (; j < j1; ++j) acc[0] += s_keys[j] < key ? 1u : 0u;
-            atomicAdd(&s_rank[i], acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5] + acc[6] + acc[7]);
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < z; i += kFinishThreads) {
-            a.out[s_rank[i]] = to_record(s_keys[i], a.idbits, a.posmask);
-            if (a.sorted) a.sorted[s_rank[i]] = s_keys[i];
-        }
-        return;
-    }
-    uint32_t N = 1;
-    while (N < z) N <<= 1;
-    for (uint32_t i = tid; i < N; i += kFinishThreads) s_keys[i] = i < z ? a.keys[i] : ~0ull;
     __syncthreads();
-    for (uint32_t k = 2; k <= N; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < N; i += kFinishThreads) {
-                const uint32_t p = i ^ j;
-                if (p > i) {
-                    const uint64_t x = s_keys[i], y = s_keys[p];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) { s_keys[i] = y; s_keys[p] = x; }
-                }
-            }
-            __syncthreads();
+    const uint64_t z = s_z;
+    if (z > a.cap || z == 0 || z > kSmallMax) return;
+    const uint32_t base = blockIdx.x * kFinishKeys;
+    if (base >= z) return;
+
+    // keys are unique: a key's output slot is the number of smaller keys.
+    // Every workgroup stages all z keys in LDS (eight loads in flight per
+    // thread) and ranks kFinishKeys of them, one per lane; each wave counts
+    // over its share of the keys (8 independent sums, so LDS reads overlap)
+    // and the shares are combined with LDS atomics.
+    const uint32_t zz = (uint32_t)z;
+    for (uint32_t b = 0; b < zz; b += 8 * kFinishThreads) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = b + u * kFinishThreads + tid;
+            v[u] = i < zz ? a.keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = b + u * kFinishThreads + tid;
+            if (i < zz) s_keys[i] = v[u];
         }
     }
-    for (uint32_t i = tid; i < z; i += kFinishThreads) {
-        a.out[i] = to_record(s_keys[i], a.idbits, a.posmask);
-        if (a.sorted) a.sorted[i] = s_keys[i];
+    if (tid < kFinishKeys) s_rank[tid] = 0;
+    __syncthreads();
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    const uint32_t i = base + lane;
+    const uint64_t key = i < zz ? s_keys[i] : 0ull;
+    const uint32_t share = (zz + kFinishWaves - 1) / kFinishWaves;
+    const uint32_t j0 = wave * share < zz ? wave * share : zz;
+    const uint32_t j1 = j0 + share < zz ? j0 + share : zz;
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += s_keys[j + u] < key ? 1u : 0u;
+    }
+    for (; j < j1; ++j) acc[0] += s_keys[j] < key ? 1u : 0u;
+    const uint32_t below = acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5] + acc[6] + acc[7];
+    if (below) atomicAdd(&s_rank[lane], below);
+    __syncthreads();
+    if (i < zz) {
+        const uint32_t r = s_rank[lane];
+        a.out[r] = to_record(key, a.idbits, a.posmask);
+        if (a.sorted) a.sorted[r] = key;
     }
 }
 
@@ -329,7 +333,7 @@ mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *
     a.posmask = posmask;
     a.seg_count = sc.seg_count;
     a.idbits = idbits;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_finish, dim3(kFinishGrid), dim3(kFinishThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "finish launch");
 }
