@@ -20,11 +20,14 @@
 namespace mag {
 namespace {
 
-constexpr int kFinishThreads = 1024;
-constexpr uint32_t kFinishWaves = kFinishThreads / 64;
+constexpr uint32_t kFinishWaves = 8;               // ranking waves per finishing workgroup
+constexpr uint32_t kRankThreads = kFinishWaves * 64;
+constexpr int kFinishThreads = kRankThreads + 64;  // plus the counter wave
 constexpr uint32_t kSmallMax = 8192;
 constexpr uint32_t kFinishKeys = 64;              // keys ranked per finishing workgroup
 constexpr uint32_t kFinishGrid = kSmallMax / kFinishKeys;
+constexpr uint32_t kFinishEager = 1024;           // keys loaded before the count is known
+static_assert(kFinishEager % kRankThreads == 0, "whole eager rounds");
 constexpr int kRadixThreads = 256;
 constexpr uint32_t kRadixChunk = 4096;        // keys per chunk of the device-wide sort
 constexpr uint32_t kRadixGrid = 1024;         // workgroups per radix kernel (they loop over chunks)
@@ -38,6 +41,14 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value) {
 __device__ __forceinline__ uint32_t lanes_below_mask(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// and atomics of the waves stay in flight across it.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ mag_match to_record(uint64_t key, int idbits, uint64_t posmask) {
@@ -137,28 +148,32 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
     __shared__ uint64_t s_z;
     __shared__ uint32_t s_rank[kFinishKeys];
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) {
-        const uint64_t z = a.counters[0], cw = a.counters[1], nv = a.counters[2];
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    // waves 0 .. kFinishWaves-1 rank; the last wave reads the counters and
+    // reports the workgroup's arrival. The first kFinishEager keys are read
+    // alongside the counters (slots past the count hold stale keys and are
+    // never used).
+    const uint32_t eager = a.cap < kFinishEager ? (uint32_t)a.cap : kFinishEager;
+    uint64_t ek[kFinishEager / kRankThreads];
+    if (wave < kFinishWaves) {
+#pragma unroll
+        for (uint32_t u = 0; u < kFinishEager / kRankThreads; ++u) {
+            const uint32_t i = u * kRankThreads + tid;
+            ek[u] = i < eager ? a.keys[i] : 0ull;
+        }
+    } else if (lane == 0) {
+        const uint64_t z = a.counters[0];
         s_z = z;
         if (blockIdx.x == 0) {
             *a.d_count = z;
             if (a.d_stats) {
                 a.d_stats->samples = a.samples;
-                a.d_stats->cand_windows = cw;
-                a.d_stats->verifications = nv;
+                a.d_stats->cand_windows = a.counters[1];
+                a.d_stats->verifications = a.counters[2];
                 a.d_stats->matches = z;
             }
             // the count stays for the device-wide sort
             a.counters[kSortCountSlot] = z;
-        }
-        // the last workgroup to have read the counters returns them (and the
-        // arrival count) to zero for the next scan
-        __threadfence();
-        unsigned long long *done = (unsigned long long *)&a.counters[kFinishDoneSlot];
-        if (atomicAdd(done, 1ull) == gridDim.x - 1) {
-            for (int c = 0; c < 4; ++c)
-                __hip_atomic_store(&a.counters[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     // the verification kernel has read the segment counts (it ran before)
@@ -166,9 +181,36 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
         for (uint32_t i = tid; i < kPendingSegments; i += kFinishThreads) a.seg_count[i] = 0;
     __syncthreads();
     const uint64_t z = s_z;
-    if (z > a.cap || z == 0 || z > kSmallMax) return;
     const uint32_t base = blockIdx.x * kFinishKeys;
-    if (base >= z) return;
+    const bool ranks = z <= a.cap && z != 0 && z <= kSmallMax && base < z;
+
+    if (wave == kFinishWaves) {
+        // every workgroup has read the counters once it arrives here; the
+        // last to arrive returns them (and the arrival count) to zero for the
+        // next scan. This wave loads nothing else, so the ranking waves never
+        // wait for the arrival; it joins their two barriers meanwhile.
+        unsigned long long arrival = 0;
+        if (lane == 0) {
+            // an opaque (per-lane) slot index keeps the compiler from
+            // combining the wave's atomics, which would wait for the result
+            // right away
+            uint32_t slot = kFinishDoneSlot;
+            asm volatile("" : "+v"(slot));
+            arrival = atomicAdd((unsigned long long *)&a.counters[slot], 1ull);
+        }
+        if (ranks) {
+            lds_sync();
+            lds_sync();
+        }
+        if (lane == 0 && arrival == gridDim.x - 1) {
+            for (int c = 0; c < 4; ++c)
+                __hip_atomic_store(&a.counters[c], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.counters[kFinishDoneSlot], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    if (!ranks) return;
 
     // keys are unique: a key's output slot is the number of smaller keys.
     // Every workgroup stages all z keys in LDS (eight loads in flight per
@@ -176,22 +218,26 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
     // over its share of the keys (8 independent sums, so LDS reads overlap)
     // and the shares are combined with LDS atomics.
     const uint32_t zz = (uint32_t)z;
-    for (uint32_t b = 0; b < zz; b += 8 * kFinishThreads) {
+#pragma unroll
+    for (uint32_t u = 0; u < kFinishEager / kRankThreads; ++u) {
+        const uint32_t i = u * kRankThreads + tid;
+        if (i < zz) s_keys[i] = ek[u];
+    }
+    for (uint32_t b = kFinishEager; b < zz; b += 8 * kRankThreads) {
         uint64_t v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const uint32_t i = b + u * kFinishThreads + tid;
+            const uint32_t i = b + u * kRankThreads + tid;
             v[u] = i < zz ? a.keys[i] : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const uint32_t i = b + u * kFinishThreads + tid;
+            const uint32_t i = b + u * kRankThreads + tid;
             if (i < zz) s_keys[i] = v[u];
         }
     }
     if (tid < kFinishKeys) s_rank[tid] = 0;
-    __syncthreads();
-    const uint32_t lane = tid & 63, wave = tid >> 6;
+    lds_sync();
     const uint32_t i = base + lane;
     const uint64_t key = i < zz ? s_keys[i] : 0ull;
     const uint32_t share = (zz + kFinishWaves - 1) / kFinishWaves;
@@ -206,7 +252,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
     for (; j < j1; ++j) acc[0] += s_keys[j] < key ? 1u : 0u;
     const uint32_t below = acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5] + acc[6] + acc[7];
     if (below) atomicAdd(&s_rank[lane], below);
-    __syncthreads();
+    lds_sync();
     if (i < zz) {
         const uint32_t r = s_rank[lane];
         a.out[r] = to_record(key, a.idbits, a.posmask);

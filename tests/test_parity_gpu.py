@@ -342,6 +342,35 @@ def test_many_matches_radix_path(torch_cuda, mag):
     assert st["verifications"] == n - m + 1
 
 
+def test_small_outputs_around_rank_blocks(torch_cuda, mag):
+    # Outputs up to 8192 occurrences are ranked by the finishing kernel in
+    # blocks of 64 keys, with the first 1024 keys loaded before the count is
+    # known; larger ones take the radix sort. Text a^L c^m against
+    # {a^m, a^m} (+ c^m for odd counts) gives exactly z occurrences, with
+    # two ids per position. The same two plans serve every scan in turn, so
+    # counters that were not returned to zero would show in the next count.
+    m = 8
+    plans = {}
+    for odd in (False, True):
+        P = [np.full(m, ord("a"), dtype=np.uint8)] * 2
+        if odd:
+            P.append(np.full(m, ord("c"), dtype=np.uint8))
+        P = np.stack(P)
+        plans[odd] = (P, mag.Plan(P, q=2, k=1, sigma_prime=3))
+    for z in (1, 2, 63, 64, 65, 127, 511, 1023, 1024, 1025, 1537, 4097, 8191, 8192, 8193, 9001):
+        odd = bool(z % 2)
+        P, plan = plans[odd]
+        L = (z - 1) // 2 + m - 1 if odd else z // 2 + m - 1
+        T = np.concatenate([np.full(L, ord("a"), dtype=np.uint8), np.full(m, ord("c"), dtype=np.uint8)])
+        if z == 1:
+            T = np.full(m, ord("c"), dtype=np.uint8)
+        ref = om.occ_hashed(T, P)
+        assert ref[0].size == z, (z, ref[0].size)
+        pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
+        _assert_same(pos, ids, ref)
+        assert st["matches"] == z, (z, st)
+
+
 def test_overflow_reports_exact_count(torch_cuda, mag):
     T = gen_text(100_000, 4, rng=1)
     P = gen_patterns(T, 50, 8, 50, 4, rng=2)
