@@ -79,6 +79,7 @@ constexpr int kWordsPerSample = (Q + 3) / 4;
 // encoding kernel already wrote, 16 or 32 bits wide.
 constexpr int kCodeMul24 = 0, kCodeMul32 = 1, kCodeBits = 2, kCodeHash = 3;
 constexpr int kCodePre16 = 4, kCodePre32 = 5;
+constexpr int kCodeNibbles = 6;   // bit-field map with 4-bit fields, Q <= 4
 constexpr bool is_pre(int code) { return code == kCodePre16 || code == kCodePre32; }
 
 // ALIGNED: the words come from the 16-byte-load path, gram at w0's first byte.
@@ -86,6 +87,7 @@ template <int CODE, bool ALIGNED = false>
 __device__ __forceinline__ uint32_t code_of(const GramWords &w, const uint8_t *s_mu, uint32_t sp,
                                             uint32_t bshift, uint32_t blen) {
     if constexpr (CODE == kCodeBits) return gram_code_bits<Q, ALIGNED>(w, bshift, blen);
+    else if constexpr (CODE == kCodeNibbles) return gram_code_nibbles<(Q <= 4 ? Q : 4), ALIGNED>(w, bshift);
     else if constexpr (CODE == kCodeHash) return gram_code_hash<Q, ALIGNED>(w, blen);
     // encoded codes arrive through a resource that may extend into the
     // buffer's unwritten tail (samples past the last one read it before their
@@ -169,24 +171,39 @@ __device__ __forceinline__ void phase_a(ET *s_E, __amdgpu_buffer_rsrc_t rs, int3
     const int step = G * kProducerThreads;
     int s = G * tid - W0;
     // P rounds of words in flight: round r is processed while rounds r+1 ..
-    // r+P-1 load, and its buffer is refilled with round r+P. Offsets advance
-    // by adds (one multiply per tile).
+    // r+P-1 load, and its buffer is refilled with round r+P at once. The
+    // thread's round count is known up front, so the steady-state loop has
+    // no exit between rounds (an exit there lets the compiler sink a refill
+    // past the next round's wait). Refills past the last round read outside
+    // the tile's resource (zeros) and are never processed. Offsets advance by
+    // adds (one multiply per tile).
+    const int nr = s < (int)TS ? ((int)TS - s + step - 1) / step : 0;
     const uint32_t ostep = (uint32_t)step * kq;
     uint32_t o = (uint32_t)(p0 + s * (int32_t)kq);
     GramWords buf[P][G];
 #pragma unroll
     for (int r = 0; r < P; ++r) load_group<CODE, G, VEC>(buf[r], rs, o + (uint32_t)r * ostep, kq);
     o += (uint32_t)P * ostep;
-    for (;;) {
+    int r0 = 0;
+    for (; r0 + P <= nr; r0 += P) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            if (s >= (int)TS) return;
             process_group<INTERIOR, CODE, TLDS, PB, VEC, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
                                                   g_tab, X0, X);
             load_group<CODE, G, VEC>(buf[r], rs, o, kq);
             o += ostep;
             s += step;
+            // keep the refill here: hoisting the next round's work above it
+            // would wait for every outstanding load before reissuing any
+            __builtin_amdgcn_sched_barrier(0);
         }
+    }
+#pragma unroll
+    for (int r = 0; r < P - 1; ++r) {
+        if (r0 + r >= nr) return;
+        process_group<INTERIOR, CODE, TLDS, PB, VEC, G>(buf[r], s_E, s, W0, sp, bshift, blen, s_mu, s_tab,
+                                              g_tab, X0, X);
+        s += step;
     }
 }
 
@@ -406,6 +423,7 @@ mag_status launch_et(const ScanArgs &a, bool tlds, bool mul24, size_t shmem, int
     if (a.pre == 4) return launch_tables<ET, DT, kCodePre32>(a, tlds, shmem, ncu, stream);
     if (a.qgram) return launch_tables<ET, DT, kCodeHash>(a, tlds, shmem, ncu, stream);
     if (tlds) {   // LDS tables are small: 24-bit Horner steps always suffice
+        if (Q <= 4 && a.blen == 4) return launch_one<ET, DT, true, kCodeNibbles>(a, shmem, ncu, stream);
         return a.blen ? launch_one<ET, DT, true, kCodeBits>(a, shmem, ncu, stream)
                       : launch_one<ET, DT, true, kCodeMul24>(a, shmem, ncu, stream);
     }

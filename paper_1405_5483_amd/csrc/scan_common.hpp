@@ -73,6 +73,20 @@ __device__ __forceinline__ uint32_t gram_code_bits(const GramWords &gw, uint32_t
     return g;
 }
 
+// gram_code_bits for 4-bit fields (sigma' = 16) and Q <= 4: mask the gram's
+// nibbles in place, fold each pair of bytes into one (f0 | f1 << 4 and
+// f2 | f3 << 4; the rotate's wrapped bits land in byte 3, which is not
+// gathered), and gather bytes 0 and 2.
+template <int Q, bool ALIGNED = false>
+__device__ __forceinline__ uint32_t gram_code_nibbles(const GramWords &gw, uint32_t shift) {
+    static_assert(Q >= 1 && Q <= 4, "one word per gram");
+    const uint32_t lo = ALIGNED ? gw.w0 : __builtin_amdgcn_alignbyte(gw.w1, gw.w0, gw.sh);
+    constexpr uint32_t m = Q == 4 ? 0x0F0F0F0Fu : Q == 3 ? 0x000F0F0Fu : Q == 2 ? 0x00000F0Fu : 0x0Fu;
+    const uint32_t x = (lo >> shift) & m;
+    const uint32_t y = x | __builtin_amdgcn_alignbit(x, x, 4);
+    return __builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
+}
+
 // Code of a q-gram under the alphabet mapping on q-grams (Section 3.3): the
 // top hbits (<= 28) bits of MurmurHash3's 64-bit finalizer of the gram's raw
 // bytes (S[0] in the low byte). The finalizer's last xor-shift leaves the high
