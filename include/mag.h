@@ -203,6 +203,15 @@ void mag_plan_destroy(mag_plan *plan);
 /* Resolved parameters and table sizes of a plan. */
 mag_status mag_plan_info(const mag_plan *plan, mag_plan_desc *desc);
 
+/* The plan's resolved choices as creation parameters: select = explicit,
+ * map_kind, q, k and sigma' as chosen (Section 3.2's formulas and Section
+ * 3.3's table fit for the heuristic, the selector's pick for learned plans),
+ * mode = filter or dense as resolved, and the plan's verify, verify_buffer
+ * and encode settings; table_budget 0. mag_plan_create with the same
+ * patterns and these parameters builds the same filter and tables. Errors:
+ * NULL arguments -> MAG_E_INVALID. */
+mag_status mag_plan_get_params(const mag_plan *plan, mag_params *resolved);
+
 /* Host copies of the plan's alphabet map (256 bytes; all zero for
  * MAG_MAP_QGRAM, which has none) and mask table (desc.table_bytes bytes,
  * little-endian entries of desc.entry_bytes; packed tables hold entry c in
@@ -269,6 +278,26 @@ mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const
  * *d_count still hold the exact total and the records are unspecified. */
 mag_status mag_batch_run_async(mag_batch *batch, mag_match *d_out, uint64_t *d_offsets,
                                uint64_t *d_count, void *stream);
+
+/* One job of mag_scan_batch: a plan and its text (device pointer). */
+typedef struct {
+    mag_plan *plan;
+    const uint8_t *d_text;
+    uint64_t n;
+} mag_job;
+
+/* One-shot batched scan: builds a batch over the jobs (a plan may serve
+ * several), binds their texts, runs it on `stream`, waits, and writes the
+ * first record of each job and the total to offsets (host, njobs + 1
+ * uint64). Records land in d_out as for mag_batch_run_async (job by job,
+ * each job's sorted by (pos, id), positions relative to its text). Allocates
+ * and frees its own device scratch, so it is not for graph capture (use the
+ * mag_batch_* calls there). Returns MAG_E_OVERFLOW when the total exceeds
+ * out_cap (offsets[njobs] = the total, the other offsets and the records
+ * unspecified). Errors: NULL arrays, a NULL plan or text (n > 0) ->
+ * MAG_E_INVALID; plans mag_batch_create rejects -> its error. */
+mag_status mag_scan_batch(const mag_job *jobs, uint32_t njobs, mag_match *d_out, uint64_t out_cap,
+                          uint64_t *offsets, void *stream);
 
 /* ---- learned parameter selection ----
  *

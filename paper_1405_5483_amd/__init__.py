@@ -19,7 +19,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, VERIFY, MagError, MagParams, MagPlanDesc,
+from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, VERIFY, MagError, MagJob, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
 __all__ = ["Plan", "Batch", "Selector", "scan", "scan_async", "scan_batch", "autotune",
@@ -107,6 +107,18 @@ class Plan:
         d = MagPlanDesc()
         check(lib().mag_plan_info(self.handle, ctypes.byref(d)), "mag_plan_info")
         return {name: getattr(d, name) for name, _ in MagPlanDesc._fields_}
+
+    def params(self) -> dict:
+        """The resolved choices as Plan keyword arguments
+        (``mag_plan_get_params``): ``Plan(patterns, **plan.params())`` builds
+        the same filter and tables."""
+        prm = MagParams()
+        check(lib().mag_plan_get_params(self.handle, ctypes.byref(prm)), "mag_plan_get_params")
+        inv = lambda d, v: next(name for name, code in d.items() if code == v)
+        return {"select": inv(SELECT, prm.select), "map_kind": inv(MAP_KIND, prm.map_kind),
+                "q": prm.q, "k": prm.k, "sigma_prime": prm.sigma_prime,
+                "mode": inv(MODE, prm.mode), "verify": inv(VERIFY, prm.verify),
+                "verify_buffer": prm.verify_buffer, "encode": bool(prm.encode)}
 
     def export(self, raw: bool = False):
         """(mu [256] uint8, mask table with one entry per code in the entry
@@ -319,15 +331,34 @@ class Batch:
 
 
 def scan_batch(texts, plans, out_cap: int | None = None, stream=None):
-    """One-shot batched scan: job j scans ``texts[j]`` with ``plans[j]``.
-    Returns one int64 [z_j, 2] tensor of sorted (pos, pattern id) per job."""
-    b = Batch(plans)
-    try:
-        cap = out_cap if out_cap is not None else max(1 << 16, sum(t.numel() for t in texts) // 64)
-        b.bind(texts, cap, stream)
-        return b.run(stream)
-    finally:
-        b.close()
+    """One-shot batched scan (``mag_scan_batch``): job j scans ``texts[j]``
+    with ``plans[j]``. Returns one int64 [z_j, 2] tensor of sorted
+    (pos, pattern id) per job; an output above the capacity is rescanned with
+    room for the exact total."""
+    import torch
+    if len(texts) != len(plans):
+        raise ValueError("one plan per text")
+    for t in texts:
+        _check_text(t)
+    njobs = len(texts)
+    jobs = (MagJob * max(njobs, 1))()
+    for j, (t, p) in enumerate(zip(texts, plans)):
+        jobs[j].plan = p.handle.value
+        jobs[j].d_text = t.data_ptr() if t.numel() else None
+        jobs[j].n = t.numel()
+    cap = out_cap if out_cap is not None else max(1 << 16, sum(t.numel() for t in texts) // 64)
+    offsets = (ctypes.c_uint64 * (njobs + 1))()
+    for _ in range(2):
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device="cuda")
+        status = lib().mag_scan_batch(jobs, njobs, ctypes.c_void_p(out.data_ptr()), cap, offsets,
+                                      _stream_ptr(stream))
+        if status == MAG_E_OVERFLOW:
+            cap = int(offsets[njobs])
+            continue
+        check(status, "mag_scan_batch")
+        off = list(offsets)
+        return [out[off[j]:off[j + 1]] for j in range(njobs)]
+    raise MagError(MAG_E_OVERFLOW, "batch output still overflows after resizing")
 
 
 def profile_enable(on: bool = True) -> None:

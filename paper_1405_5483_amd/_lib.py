@@ -59,6 +59,10 @@ class MagPlanDesc(ctypes.Structure):
     ]
 
 
+class MagJob(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_text", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
 class MagTuneOpts(ctypes.Structure):
     _fields_ = [
         ("map_kinds", ctypes.c_int32), ("max_q", ctypes.c_int32), ("max_k", ctypes.c_int32),
@@ -78,6 +82,9 @@ SIGNATURES = {
                                        ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_void_p)]),
     "mag_plan_destroy": (None, [ctypes.c_void_p]),
     "mag_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MagPlanDesc)]),
+    "mag_plan_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MagParams)]),
+    "mag_scan_batch": (ctypes.c_int, [ctypes.POINTER(MagJob), ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
     "mag_plan_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint64]),
     "mag_plan_create_var": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,

@@ -359,4 +359,52 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     return s;
 }
 
+mag_status mag_scan_batch(const mag_job *jobs, uint32_t njobs, mag_match *d_out, uint64_t out_cap,
+                          uint64_t *offsets, void *stream_) {
+    if (!jobs || !offsets) return fail(MAG_E_INVALID, "jobs or offsets is NULL");
+    if (out_cap && !d_out) return fail(MAG_E_INVALID, "d_out is NULL");
+    if (njobs == 0) {
+        offsets[0] = 0;
+        return MAG_OK;
+    }
+    std::vector<mag_plan *> plans(njobs);
+    std::vector<const uint8_t *> texts(njobs);
+    std::vector<uint64_t> n(njobs);
+    for (uint32_t j = 0; j < njobs; ++j) {
+        if (!jobs[j].plan) return fail(MAG_E_INVALID, "a job's plan is NULL");
+        if (jobs[j].n && !jobs[j].d_text) return fail(MAG_E_INVALID, "a job's text is NULL");
+        plans[j] = jobs[j].plan;
+        texts[j] = jobs[j].d_text;
+        n[j] = jobs[j].n;
+    }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+    mag_batch *b = nullptr;
+    mag_status s = mag_batch_create(plans.data(), njobs, &b);
+    if (s != MAG_OK) return s;
+    uint64_t *d_tmp = nullptr;     // the job offsets and the total, then the count
+    s = mag_batch_bind(b, texts.data(), n.data(), out_cap, stream_);
+    if (s == MAG_OK) {
+        const hipError_t e = hipMalloc(&d_tmp, ((size_t)njobs + 2) * sizeof(uint64_t));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            d_tmp = nullptr;
+            s = fail(MAG_E_NOMEM, "device allocation of the batch offsets failed");
+        }
+    }
+    if (s == MAG_OK) s = mag_batch_run_async(b, d_out, d_tmp, d_tmp + njobs + 1, stream_);
+    if (s == MAG_OK) {
+        hipError_t e = hipMemcpyAsync(offsets, d_tmp, ((size_t)njobs + 1) * sizeof(uint64_t),
+                                      hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) s = hip_fail(e, "reading the batch offsets");
+    } else if (d_tmp) {
+        (void)hipStreamSynchronize(stream);    // nothing of ours may still use the buffers
+    }
+    if (d_tmp) (void)hipFree(d_tmp);
+    mag_batch_destroy(b);
+    if (s == MAG_OK && offsets[njobs] > out_cap)
+        s = fail(MAG_E_OVERFLOW, "the jobs have more occurrences than out_cap");
+    return s;
+}
+
 }  // extern "C"

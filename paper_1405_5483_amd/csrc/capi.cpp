@@ -386,6 +386,22 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     return MAG_OK;
 }
 
+mag_status mag_plan_get_params(const mag_plan *p, mag_params *o) {
+    if (!p || !o) return fail(MAG_E_INVALID, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->select = MAG_SELECT_EXPLICIT;
+    o->map_kind = p->map_kind;
+    o->q = p->q;
+    o->k = p->k;
+    o->sigma_prime = p->sigma_prime;
+    o->table_budget = 0;
+    o->mode = p->dense ? MAG_MODE_DENSE : MAG_MODE_FILTER;
+    o->verify = p->verify;
+    o->verify_buffer = (int32_t)p->verify_buffer;
+    o->encode = p->encode;
+    return MAG_OK;
+}
+
 mag_status mag_plan_export(const mag_plan *p, uint8_t *mu_out, void *table_out, uint64_t table_cap) {
     if (!p) return fail(MAG_E_INVALID, "plan is NULL");
     if (mu_out) std::memcpy(mu_out, p->mu, 256);

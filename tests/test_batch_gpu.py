@@ -210,3 +210,24 @@ def test_batch_full_workload(torch_cuda, mag):
         assert np.array_equal(occ[:, 0].astype(np.uint64), rpos), j
         assert np.array_equal(occ[:, 1].astype(np.uint32), rids), j
     b.close()
+
+
+def test_scan_batch_one_shot(torch_cuda, mag):
+    # mag_scan_batch: one call builds, binds, runs and reads the offsets. A
+    # plan serves two jobs, one text is empty, and the first capacity is too
+    # small, so the binding rescans with the exact total it reports.
+    torch = torch_cuda
+    jobs = _small_jobs(6, seed=211)
+    jobs.append(make_job(0, 4, "uniform", 10, 8, 0.5, 212))
+    plans = [mag.Plan(j.patterns) for j in jobs]
+    t2 = gen_text(40_003, jobs[1].recipe["sigma"], rng=213)
+    jobs.append(type(jobs[0])(t2, jobs[1].patterns, {"shared": True}))
+    plans.append(plans[1])
+    texts = _upload(torch, [j.text for j in jobs], [j % 5 for j in range(len(jobs))])
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    assert total > 2
+    res = mag.scan_batch(texts, plans, out_cap=total // 2)
+    _check_jobs(res, jobs)
+    res = mag.scan_batch(texts, plans, out_cap=total)
+    _check_jobs(res, jobs)
+    assert mag.scan_batch([], []) == []

@@ -281,3 +281,27 @@ def test_learned_pick_takes_bit_fields_when_as_selective():
     b = mag.Plan(P, q=3, k=1, sigma_prime=16, map_kind="bits").info()["est_verif"]
     assert b > 1.25 * g + 1e-5
     assert mag.Plan(P, q=3, k=1, sigma_prime=16, select="learned").info()["map_kind"] == 0
+
+
+def test_plan_params_round_trip():
+    # mag_plan_get_params returns the resolved choices as creation
+    # parameters; a plan built from them has the same filter and tables.
+    mag = _lib_or_skip()
+    rng = np.random.default_rng(41)
+    for sigma, r, m, kw in ((4, 50, 16, {}), (20, 200, 12, {"map_kind": "rank"}),
+                            (64, 300, 32, {"q": 4, "k": 1, "sigma_prime": 16, "map_kind": "bits"}),
+                            (20, 100, 16, {"map_kind": "qgram"}), (4, 2000, 8, {"mode": "dense"}),
+                            (20, 40, 16, {"verify": "deferred", "encode": True})):
+        P = rng.integers(0, sigma, size=(r, m), dtype=np.uint8)
+        a = mag.Plan(P, **kw)
+        prm = a.params()
+        assert prm["select"] == "explicit"
+        b = mag.Plan(P, **prm)
+        ia, ib = a.info(), b.info()
+        for key in ("q", "k", "sigma_prime", "map_kind", "dense", "W", "m_prime", "entry_bits",
+                    "n_codes", "table_bytes", "bits_shift", "bloom_log2"):
+            assert ia[key] == ib[key], (kw, key, ia[key], ib[key])
+        mu_a, tab_a = a.export(raw=True)
+        mu_b, tab_b = b.export(raw=True)
+        assert np.array_equal(mu_a, mu_b) and np.array_equal(tab_a, tab_b), kw
+        assert b.params() == prm
