@@ -371,6 +371,33 @@ def test_small_outputs_around_rank_blocks(torch_cuda, mag):
         assert st["matches"] == z, (z, st)
 
 
+def test_capacities_alternating_on_shared_plans(torch_cuda, mag):
+    # Scans on shared plans alternate between a capacity the finishing kernel
+    # sorts in LDS (8192 records) and one that takes the radix sort sized for
+    # the count, so counters one scan left behind would show in the next
+    # one's records or in its work counters, which must equal the oracle
+    # filter's.
+    cases = [(4, 120_000, 40, 16, 3, 1, 4), (20, 90_001, 300, 16, 4, 1, 16), (64, 50_000, 80, 32, 4, 2, 16)]
+    plans = []
+    for sigma, n, r, m, q, k, sp in cases:
+        T = gen_text(n, sigma, rng=n)
+        P = gen_patterns(T, r, m, r // 2, sigma, rng=n + 1)
+        plans.append((T, P, mag.Plan(P, q=q, k=k, sigma_prime=sp, mode="filter")))
+    want = []
+    for (sigma, n, r, m, q, k, sp), (T, P, plan) in zip(cases, plans):
+        ref = om.occ_hashed(T, P)
+        assert 0 < ref[0].size <= 8192
+        want.append((ref, mm.Filter(P, q, k, sp).counts(T)))
+    for rep in range(3):
+        for (T, P, plan), (ref, cnt) in zip(plans, want):
+            for cap in (8192, 1_000_000) if rep % 2 == 0 else (1_000_000, 8192):
+                pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, offset=rep, out_cap=cap, stats=True)
+                _assert_same(pos, ids, ref)
+                assert st["matches"] == ref[0].size
+                for key in ("samples", "cand_windows", "verifications"):
+                    assert st[key] == cnt[key], (cap, key, st[key], cnt[key])
+
+
 def test_overflow_reports_exact_count(torch_cuda, mag):
     T = gen_text(100_000, 4, rng=1)
     P = gen_patterns(T, 50, 8, 50, 4, rng=2)
