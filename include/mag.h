@@ -414,8 +414,9 @@ const char *mag_status_string(mag_status s);
 const char *mag_last_error(void);
 
 /* Measurement aid, not part of the method: a plain streaming read of
- * d[0..n) (device, 16-byte aligned) with 16-byte loads over a
- * full-occupancy grid, each word folded into an xor written to d_sink
+ * d[0..n) (device, 16-byte aligned) with 16-byte loads, one 1024-thread
+ * workgroup per compute unit reading 32 KiB tiles in turn (the fastest plain
+ * read layout measured), each word folded into an xor written to d_sink
  * (device, at least mag_stream_read_sink_words() words: word b is block b's
  * xor of the 32-bit words, the bytes past the last whole 16-byte vector
  * shifted in by position mod 4), so the read cannot be skipped. Time it on

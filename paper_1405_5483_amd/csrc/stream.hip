@@ -10,31 +10,27 @@
 namespace mag {
 namespace {
 
-constexpr int kStreamThreads = 256;
-constexpr int kStreamUnroll = 4;      // 16-byte loads in flight per thread
+constexpr int kStreamThreads = 1024;
+constexpr uint64_t kStreamTileVec = 2048;   // 32 KiB tiles: two 16-byte loads per thread
 
-// Thread t of the grid reads the 16-byte vectors t, t + T, t + 2T, ...
-// (T = threads in the grid), kStreamUnroll at a time; the tail past the last
-// whole vector is read bytewise by thread 0. sink[blockIdx] gets the block's
-// xor.
+// One workgroup per compute unit (the fastest layout measured: faster than a
+// grid-stride sweep of small workgroups). Workgroup g reads tiles g, g + G, ...
+// of kStreamTileVec 16-byte vectors, each thread issuing both of its loads of
+// a tile before using either; the tail past the last whole vector is read
+// bytewise by thread 0. sink[blockIdx] gets the workgroup's xor.
 __global__ __launch_bounds__(kStreamThreads) void k_stream_read(const uint4 *src, uint64_t nvec,
                                                                 const uint8_t *tail, uint32_t ntail,
                                                                 uint32_t *sink) {
     __shared__ uint32_t s_x[kStreamThreads / 64];
-    const uint64_t T = (uint64_t)gridDim.x * kStreamThreads;
-    uint64_t i = (uint64_t)blockIdx.x * kStreamThreads + threadIdx.x;
+    const uint64_t ntiles = (nvec + kStreamTileVec - 1) / kStreamTileVec;
     uint32_t x = 0;
-    for (; i + (kStreamUnroll - 1) * T < nvec; i += kStreamUnroll * T) {
-        uint4 v[kStreamUnroll];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) v[u] = src[i + u * T];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) x ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint64_t i0 = t * kStreamTileVec + threadIdx.x, i1 = i0 + kStreamThreads;
+        const uint4 a = i0 < nvec ? src[i0] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 b = i1 < nvec ? src[i1] : make_uint4(0u, 0u, 0u, 0u);
+        x ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w;
     }
-    for (; i < nvec; i += T) {
-        const uint4 v = src[i];
-        x ^= v.x ^ v.y ^ v.z ^ v.w;
-    }
+    static_assert(kStreamTileVec == 2 * kStreamThreads, "two vectors per thread per tile");
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (uint32_t b = 0; b < ntail; ++b) x ^= (uint32_t)tail[b] << (8 * (b & 3));
     for (int off = 32; off > 0; off >>= 1) x ^= __shfl_xor(x, off);
@@ -52,15 +48,9 @@ __global__ __launch_bounds__(kStreamThreads) void k_stream_read(const uint4 *src
 uint32_t stream_read_grid() {
     static uint32_t grid = 0;
     if (!grid) {
-        int dev = 0, ncu = 0, occ = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_stream_read, kStreamThreads, 0) !=
-                hipSuccess) {
-            (void)hipGetLastError();
-            return 0;
-        }
-        grid = (uint32_t)(ncu * occ);
+        const int ncu = device_compute_units();
+        if (ncu < 1) return 0;
+        grid = (uint32_t)ncu;
     }
     return grid;
 }
