@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
     MAG_OK = 0,
     MAG_E_INVALID = -1,     /* bad argument or parameter combination           */
-    MAG_E_UNSUPPORTED = -2, /* valid but outside this build's limits           */
+    MAG_E_UNSUPPORTED = -2, /* valid but outside the library's limits         */
     MAG_E_NOMEM = -3,       /* host or device allocation failed                */
     MAG_E_DEVICE = -4,      /* a HIP call failed (detail in mag_last_error)    */
     MAG_E_OVERFLOW = -5     /* output capacity too small; count still returned */

@@ -14,7 +14,7 @@
 
 namespace mag {
 
-constexpr int kMaxM = 64;           // longest pattern this build verifies
+constexpr int kMaxM = 64;           // longest pattern the library verifies
 constexpr int kMaxQ = 8;            // longest q-gram
 constexpr int kMaxW = 64;           // automaton bits
 constexpr int kMaxK = 32;           // candidate mask of one window fits 32 bits
