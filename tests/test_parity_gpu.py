@@ -473,6 +473,28 @@ def test_zipf256m_full_size(torch_cuda, mag):
     assert (st["cand_windows"], st["verifications"]) == (want["cand_windows"], want["verifications"])
 
 
+def test_zipf256m_benchmark_configuration(torch_cuda, mag):
+    # The configuration the benchmark times, at full size: the learned
+    # selector's pick (q=4, k=1, sigma'=16, bit-field map, whose 4-bit fields
+    # take the nibble code path), enqueued with scan_async into an output of
+    # 8192 records, the text resident on the device.
+    torch = torch_cuda
+    job = workload("zipf256m")
+    ref = om.occ_hashed(job.text, job.patterns)
+    buf = torch.from_numpy(job.text).cuda()
+    pick = mag.Selector.load().picks([job.patterns])[0]
+    for kw in (pick, dict(q=4, k=1, sigma_prime=16, map_kind="bits", mode="filter")):
+        plan = mag.Plan(job.patterns, **kw)
+        out = torch.empty((8192, 2), dtype=torch.int64, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for _ in range(2):                      # a second scan on the same plan
+            mag.scan_async(buf, plan, out, cnt)
+            torch.cuda.synchronize()
+            z = int(cnt.item())
+            occ = out[:z].cpu().numpy()
+            _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+
+
 def test_prot1g_full_size(torch_cuda, mag):
     job = workload("prot1g")
     ref = om.occ_hashed(job.text, job.patterns)
