@@ -305,3 +305,27 @@ def test_plan_params_round_trip():
         mu_b, tab_b = b.export(raw=True)
         assert np.array_equal(mu_a, mu_b) and np.array_equal(tab_a, tab_b), kw
         assert b.params() == prm
+
+
+def test_scan_batch_and_params_argument_errors():
+    # Host-side argument checks of mag_scan_batch and mag_plan_get_params:
+    # they fail before any device work, so they run without a GPU.
+    mag = _lib_or_skip()
+    from paper_1405_5483_amd import _lib as L
+    lib = L.lib()
+    offsets = (ctypes.c_uint64 * 2)()
+    assert lib.mag_scan_batch(None, 1, None, 0, offsets, None) == L.MAG_E_INVALID
+    jobs = (L.MagJob * 1)()
+    assert lib.mag_scan_batch(jobs, 1, None, 0, None, None) == L.MAG_E_INVALID
+    assert lib.mag_scan_batch(jobs, 1, None, 0, offsets, None) == L.MAG_E_INVALID    # NULL plan
+    plan = mag.Plan(np.frombuffer(b"ACGTACGT", dtype=np.uint8).reshape(1, 8))
+    jobs[0].plan = plan.handle.value
+    jobs[0].d_text = None
+    jobs[0].n = 100
+    assert lib.mag_scan_batch(jobs, 1, None, 0, offsets, None) == L.MAG_E_INVALID    # NULL text, n > 0
+    assert lib.mag_scan_batch(jobs, 1, None, 16, offsets, None) == L.MAG_E_INVALID   # NULL output, cap > 0
+    offsets[0] = 7
+    assert lib.mag_scan_batch(jobs, 0, None, 0, offsets, None) == L.MAG_OK           # no jobs
+    assert offsets[0] == 0
+    assert lib.mag_plan_get_params(None, ctypes.byref(L.MagParams())) == L.MAG_E_INVALID
+    assert lib.mag_plan_get_params(plan.handle, None) == L.MAG_E_INVALID
