@@ -100,8 +100,8 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
             }
             uint32_t b = 1u;
 #pragma unroll
-            for (int j = 0; j < kBloomBits; ++j, h = bloom_second(h)) {
-                const uint32_t ix = h >> bshift;
+            for (int j = 0; j < kBloomBits; ++j) {
+                const uint32_t ix = bloom_probe(h, j) >> bshift;
                 b &= s_bloom[ix >> 5] >> (ix & 31);
             }
             hm |= (b & 1u) << (4 * i + s);

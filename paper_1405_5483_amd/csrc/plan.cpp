@@ -258,8 +258,8 @@ void build_verifier(mag_plan *p) {
 }
 
 // Bloom bitmaps of the dense mode: for every distinct pattern's first
-// min(m, 16) bytes, bits h_j >> (32 - B) for j < kBloomBits, h_0 =
-// prefilter_hash and h_{j+1} = bloom_second(h_j), for B = bloom_log2 and for
+// min(m, 16) bytes, bits h_j >> (32 - B) for j < kBloomBits, h_j =
+// bloom_probe(prefilter_hash, j), for B = bloom_log2 and for
 // the batched copy's smaller B.
 void build_bloom(mag_plan *p) {
     int B = kBloomMinLog2;
@@ -275,8 +275,9 @@ void build_bloom(mag_plan *p) {
     p->bloom_batch.assign((1u << Bb) / 32, 0u);
     const int hw = std::min<int>(p->mw, kHashWords);
     for (uint32_t u = 0; u < p->n_unique; ++u) {
-        uint32_t x = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
-        for (int j = 0; j < kBloomBits; ++j, x = bloom_second(x)) {
+        const uint32_t h = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
+        for (int j = 0; j < kBloomBits; ++j) {
+            const uint32_t x = bloom_probe(h, j);
             const uint32_t i = x >> (32 - B), ib = x >> (32 - Bb);
             p->bloom[i >> 5] |= 1u << (i & 31);
             p->bloom_batch[ib >> 5] |= 1u << (ib & 31);
