@@ -31,6 +31,17 @@ static_assert(kFinishEager % kRankThreads == 0, "whole eager rounds");
 constexpr int kRadixThreads = 256;
 constexpr uint32_t kRadixChunk = 4096;        // keys per chunk of the device-wide sort
 constexpr uint32_t kRadixGrid = 1024;         // workgroups per radix kernel (they loop over chunks)
+constexpr uint32_t kRadixChunkSmall = 1024;   // keys per chunk while that gives at most kRadixGrid chunks
+
+// Keys per chunk for z keys: short sorts take small chunks, so that more
+// workgroups share them and each scatters fewer rounds one after another.
+__host__ __device__ inline uint64_t radix_chunk_keys(uint64_t z) {
+    return z <= (uint64_t)kRadixGrid * kRadixChunkSmall ? kRadixChunkSmall : kRadixChunk;
+}
+__host__ __device__ inline uint64_t radix_chunk_count(uint64_t z) {
+    const uint64_t k = radix_chunk_keys(z);
+    return (z + k - 1) / k;
+}
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -262,7 +273,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
 
 // ---- device-wide LSD radix sort. The count z is read from *zp; every kernel
 // returns at once unless kSmallMax < z <= cap. Keys are cut into chunks of
-// kRadixChunk; cnt and off are digit-major [256][C], C = ceil(z / chunk).
+// radix_chunk_keys(z); cnt and off are digit-major [256][C], C = ceil(z / chunk).
 
 __device__ __forceinline__ bool radix_active(const uint64_t *zp, uint64_t cap, uint64_t *z) {
     *z = *zp;
@@ -274,13 +285,13 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *sr
     __shared__ uint32_t s_hist[256];
     uint64_t z;
     if (!radix_active(zp, cap, &z)) return;
-    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint64_t K = radix_chunk_keys(z), C = (z + K - 1) / K;
     const uint32_t tid = threadIdx.x;
     for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
         s_hist[tid] = 0;
         __syncthreads();
-        const uint64_t beg = c * kRadixChunk;
-        const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
+        const uint64_t beg = c * K;
+        const uint64_t end = beg + K < z ? beg + K : z;
         for (uint64_t i = beg + tid; i < end; i += kRadixThreads)
             atomicAdd(&s_hist[(src[i] >> shift) & 255u], 1u);
         __syncthreads();
@@ -295,7 +306,7 @@ __global__ __launch_bounds__(256) void k_radix_scan(const uint32_t *cnt, uint64_
     __shared__ uint64_t s_tmp[4];
     uint64_t z;
     if (!radix_active(zp, cap, &z)) return;
-    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint64_t K = radix_chunk_keys(z), C = (z + K - 1) / K;
     const uint32_t d = blockIdx.x, tid = threadIdx.x;
     uint64_t carry = 0;
     for (uint64_t base = 0; base < C; base += 256) {
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
     __shared__ uint32_t s_wcnt[kRadixThreads / 64][256];
     uint64_t z;
     if (!radix_active(zp, cap, &z)) return;
-    const uint64_t C = (z + kRadixChunk - 1) / kRadixChunk;
+    const uint64_t K = radix_chunk_keys(z), C = (z + K - 1) / K;
     const uint32_t tid = threadIdx.x;
     uint64_t all;
     s_base[tid] = block_exclusive_scan256(tot[tid], s_tmp, &all);
@@ -327,8 +338,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
     for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
         s_off[tid] = s_base[tid] + off[(size_t)tid * C + c];
         __syncthreads();
-        const uint64_t beg = c * kRadixChunk;
-        const uint64_t end = beg + kRadixChunk < z ? beg + kRadixChunk : z;
+        const uint64_t beg = c * K;
+        const uint64_t end = beg + K < z ? beg + K : z;
         stable_scatter(src, dst, beg, end, shift, s_off, s_wcnt);
     }
 }
@@ -342,7 +353,12 @@ __global__ void k_expand(const uint64_t *keys, const uint64_t *zp, uint64_t cap,
         out[i] = to_record(keys[i], idbits, posmask);
 }
 
-uint64_t radix_chunks(uint64_t bound) { return (bound + kRadixChunk - 1) / kRadixChunk; }
+// Chunks of the largest count a sort of at most `bound` keys can take.
+uint64_t radix_chunks(uint64_t bound) {
+    const uint64_t small = (uint64_t)kRadixGrid * kRadixChunkSmall;
+    const uint64_t a = radix_chunk_count(bound < small ? bound : small), b = radix_chunk_count(bound);
+    return a > b ? a : b;
+}
 
 uint32_t radix_grid(uint64_t bound) {
     const uint64_t C = radix_chunks(bound);

@@ -536,6 +536,33 @@ def test_async_many_matches_device_sort(torch_cuda, mag):
     _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref2)
 
 
+def test_device_sort_chunk_sizes(torch_cuda, mag):
+    # the device-wide sort cuts up to 2^20 keys into 1024-key chunks and more
+    # into 4096-key ones: counts on both sides of that switch, through the
+    # asynchronous entry point (sized for the capacity, so the second and
+    # third scans reuse the first one's buffers) and the synchronous one
+    torch = torch_cuda
+    m = 8
+    P = np.stack([np.full(m, ord("a"), dtype=np.uint8), np.frombuffer(b"aaaaaaab", dtype=np.uint8)])
+    plan = mag.Plan(P, q=2, k=1, sigma_prime=2)
+    T = np.full(1_050_383, ord("a"), dtype=np.uint8)   # 2^20 + 1 occurrences
+    T[1000::4099] = ord("b")
+    buf = torch.from_numpy(T).cuda()
+    out = torch.empty(((1 << 20) + 16, 2), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for n, zref in ((T.size, (1 << 20) + 1), (T.size - 1, 1 << 20), (700_003, None)):
+        ref = om.occ_hashed(T[:n], P)
+        assert zref is None or ref[0].size == zref
+        mag.scan_async(buf[:n], plan, out, cnt)
+        torch.cuda.synchronize()
+        z = int(cnt.item())
+        assert z == ref[0].size
+        occ = out[:z].cpu().numpy()
+        _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
+    occ = mag.scan(buf, plan).cpu().numpy()
+    _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), om.occ_hashed(T, P))
+
+
 def test_autotune_pick_is_exact(torch_cuda, mag):
     job = make_job(3 << 20, 64, "zipf", 300, 32, 0.5, seed=21)
     buf = torch_cuda.from_numpy(job.text).cuda()
