@@ -84,35 +84,45 @@ __device__ __forceinline__ uint64_t same_digit_lanes(bool valid, uint32_t d) {
 // Stable scatter of src[beg, end) by digit (key >> shift) & 255 into dst, the
 // digit d's run for this block starting at s_off[d]. Rounds of blockDim.x
 // consecutive keys; within a round, waves in order and lanes in order, so
-// equal digits keep their input order. s_wcnt is [waves][256] of zeros on
-// entry and on exit.
+// equal digits keep their input order. The keys of kScatterRounds rounds are
+// loaded before the first of them is placed, so their loads overlap. s_wcnt
+// is [waves][256] of zeros on entry and on exit.
+constexpr int kScatterRounds = 4;
 __device__ void stable_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg, uint64_t end,
                                int shift, uint64_t *s_off, uint32_t (*s_wcnt)[256]) {
     const uint32_t tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    for (uint64_t base = beg; base < end; base += blockDim.x) {
-        const uint64_t i = base + tid;
-        const bool valid = i < end;
-        const uint64_t key = valid ? src[i] : 0ull;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        const uint64_t eq = same_digit_lanes(valid, d);
-        const uint32_t rank = lanes_below_mask(eq);
-        if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(eq);
-        __syncthreads();
-        if (valid) {
-            uint64_t off = s_off[d];
-            for (uint32_t v = 0; v < wave; ++v) off += s_wcnt[v][d];
-            dst[off + rank] = key;
+    for (uint64_t base = beg; base < end; base += (uint64_t)kScatterRounds * blockDim.x) {
+        uint64_t keys[kScatterRounds];
+#pragma unroll
+        for (int r = 0; r < kScatterRounds; ++r) {
+            const uint64_t i = base + (uint64_t)r * blockDim.x + tid;
+            keys[r] = i < end ? src[i] : 0ull;
         }
-        __syncthreads();
-        for (uint32_t dd = tid; dd < 256; dd += blockDim.x) {
-            uint32_t add = 0;
-            for (uint32_t v = 0; v < nwaves; ++v) {
-                add += s_wcnt[v][dd];
-                s_wcnt[v][dd] = 0;
+#pragma unroll
+        for (int r = 0; r < kScatterRounds; ++r) {
+            const uint64_t key = keys[r];
+            const bool valid = base + (uint64_t)r * blockDim.x + tid < end;
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            const uint64_t eq = same_digit_lanes(valid, d);
+            const uint32_t rank = lanes_below_mask(eq);
+            if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(eq);
+            __syncthreads();
+            if (valid) {
+                uint64_t off = s_off[d];
+                for (uint32_t v = 0; v < wave; ++v) off += s_wcnt[v][d];
+                dst[off + rank] = key;
             }
-            s_off[dd] += add;
+            __syncthreads();
+            for (uint32_t dd = tid; dd < 256; dd += blockDim.x) {
+                uint32_t add = 0;
+                for (uint32_t v = 0; v < nwaves; ++v) {
+                    add += s_wcnt[v][dd];
+                    s_wcnt[v][dd] = 0;
+                }
+                s_off[dd] += add;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -292,8 +302,18 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *sr
         __syncthreads();
         const uint64_t beg = c * K;
         const uint64_t end = beg + K < z ? beg + K : z;
-        for (uint64_t i = beg + tid; i < end; i += kRadixThreads)
-            atomicAdd(&s_hist[(src[i] >> shift) & 255u], 1u);
+        // four loads in flight before their digits are counted
+        for (uint64_t i = beg + tid; i < end; i += 4 * kRadixThreads) {
+            uint64_t k4[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t j = i + (uint64_t)r * kRadixThreads;
+                k4[r] = j < end ? src[j] : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (i + (uint64_t)r * kRadixThreads < end) atomicAdd(&s_hist[(k4[r] >> shift) & 255u], 1u);
+        }
         __syncthreads();
         cnt[(size_t)tid * C + c] = s_hist[tid];
         __syncthreads();
