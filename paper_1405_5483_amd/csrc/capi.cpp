@@ -454,10 +454,10 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     // a grid of fewer workgroups than half the compute units verifies inline
     // with few waves: defer when each of them would face many starts
     const int ncu = device_compute_units();
-    const uint64_t tile = p->dense ? (uint64_t)kDenseTilePositions : kSmallGridTileSamples;
+    const uint64_t tile = p->dense ? (uint64_t)kDenseScanTile : kSmallGridTileSamples;
     const uint64_t tiles = (samples + tile - 1) / tile;
     const double vwaves = (double)std::max<uint64_t>(tiles, 1) *
-                          (p->dense ? kDenseThreads / 64 : kScanConsumerLanes / 64);
+                          (p->dense ? kDenseScanThreads / 64 : kScanConsumerLanes / 64);
     const bool small_grid = ncu > 0 && 2 * tiles < (uint64_t)ncu;
     const bool defer = p->verify == MAG_VERIFY_DEFERRED ||
                        (p->verify == MAG_VERIFY_AUTO &&
@@ -509,7 +509,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         da.delta = t & 15;
         da.n = n;
         da.last = (int64_t)n - (int64_t)p->m;
-        da.ntiles = samples ? (samples + kDenseTilePositions - 1) / kDenseTilePositions : 0;
+        da.ntiles = samples ? (samples + kDenseScanTile - 1) / kDenseScanTile : 0;
         da.bshift = 32u - (uint32_t)p->bloom_log2;
         da.bloom_vec = (uint32_t)(p->bloom.size() * 4 / 16);
         da.bloom = p->dev.bloom;

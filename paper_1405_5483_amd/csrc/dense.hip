@@ -1,5 +1,5 @@
 // Single-job dense scan: a persistent grid walks tiles of
-// kDenseTilePositions start positions with the Bloom bitmap staged in LDS
+// kDenseScanTile start positions with the Bloom bitmap staged in LDS
 // (see dense.hpp).
 #include <hip/hip_runtime.h>
 
@@ -12,12 +12,12 @@ namespace {
 
 using namespace dev;
 
-constexpr int kNT = kDenseThreads;
+constexpr int kNT = kDenseScanThreads;
 constexpr int kQueue = 128;
 static_assert(kQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 
-// At least 4 waves per SIMD: at most 128 VGPRs, so two workgroups share a
-// compute unit whenever the Bloom bitmap leaves room in LDS.
+// At least 4 waves per SIMD: at most 128 VGPRs, so one workgroup of 16
+// waves fills a compute unit.
 __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem);
@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     const uint32_t hw = a.v.hw, mw = a.v.mw, lastmask = a.v.lastmask;
     // a tile's resource, size and the offset of its first position
     auto tile_at = [&](uint64_t tile, __amdgpu_buffer_rsrc_t &rs, uint32_t &nrec, uint32_t &p0) {
-        const int64_t x0 = (int64_t)tile * kDenseTilePositions;
-        int64_t b1 = x0 + kDenseTilePositions + 40;       // bytes the tile's windows touch
+        const int64_t x0 = (int64_t)tile * kDenseScanTile;
+        int64_t b1 = x0 + kDenseScanTile + 40;            // bytes the tile's windows touch
         if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
         const uint64_t pa0 = (a.delta + (uint64_t)x0) & ~15ull;
         const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
             tile_at(nt, rs, nrec, p0n);
             dense_load<kNT>(rs, nrec, p0n, tid, Wn);
         }
-        const int64_t x0 = (int64_t)tile * kDenseTilePositions;
+        const int64_t x0 = (int64_t)tile * kDenseScanTile;
         dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, a.last, s_bloom, a.bshift, hw, mw, lastmask,
                        queue, qn, vargs, lane, nhit);
 #pragma unroll

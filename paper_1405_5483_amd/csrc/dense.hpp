@@ -14,8 +14,16 @@
 
 namespace mag {
 
-constexpr int kDenseThreads = 512;
+constexpr int kDenseThreads = 512;                        // the batched kernel's dense jobs
 constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive positions per thread
+// The single-job dense kernel: one 1024-thread workgroup holds a compute
+// unit's 16 wave slots (4 per SIMD at up to 128 VGPRs) beside a Bloom bitmap
+// of up to 128 KiB, where two 512-thread ones would not fit.
+#ifndef MAG_DENSE_SCAN_THREADS
+#define MAG_DENSE_SCAN_THREADS 1024
+#endif
+constexpr int kDenseScanThreads = MAG_DENSE_SCAN_THREADS;
+constexpr int kDenseScanTile = 16 * kDenseScanThreads;
 constexpr uint32_t kDenseQueue = 128;   // per-wave queue the callers provide (starts)
 
 struct DenseArgs {
