@@ -145,6 +145,25 @@ def test_deferred_verification_parity(torch_cuda, mag, case):
     _assert_same(pos, ids, ref)
 
 
+def test_dense_tile_edges(torch_cuda, mag):
+    # the single-job dense kernel takes 16,384 start positions per tile, 16
+    # per lane: texts whose last start falls on either side of a tile or lane
+    # boundary, at every text alignment, with patterns copied from the
+    # positions around those boundaries
+    m, tile = 16, 16384
+    T0 = gen_text(3 * tile + 64, 20, rng=91)
+    at = [0, 15, 16, tile - 17, tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile, 2 * tile + 6]
+    P = np.stack([T0[u:u + m] for u in at] + list(gen_patterns(T0, 20, m, 10, 20, rng=92)))
+    plan = mag.Plan(P, mode="dense")
+    assert plan.info()["dense"] == 1
+    for npos in (1, 2, 16, 17, tile - 16, tile - 1, tile, tile + 1, tile + 2, 2 * tile + 7):
+        T = T0[:npos + m - 1]
+        ref = om.occ_hashed(T, P)
+        for off in (0, 1, 2, 3):
+            pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=off)
+            _assert_same(pos, ids, ref)
+
+
 def test_deferred_overflow_and_repeat(torch_cuda, mag):
     """sigma' = 1 verifies every start: 300 000 deferred starts through a
     4096-entry buffer, twice in a row on the same plan (the deferred count
