@@ -16,12 +16,15 @@ constexpr int kNT = kDenseScanThreads;
 constexpr int kQueue = 128;
 static_assert(kQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 
+constexpr uint32_t kBloomWordsMax = 1u << (kBloomMaxLog2 - 5);
+
 // At least 4 waves per SIMD: at most 128 VGPRs, so one workgroup of 16
-// waves fills a compute unit.
+// waves fills a compute unit. The bitmap and the queues are static LDS
+// (144 KiB, the bitmap at address 0): a Bloom word's address is then its
+// index times 4, with no base to add per probe.
 __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem);
-    uint32_t *s_bloom = reinterpret_cast<uint32_t *>(smem + (kNT / 64) * kQueue * 8);
+    __shared__ __align__(16) uint32_t s_bloom[kBloomWordsMax];
+    __shared__ uint64_t s_queue[(kNT / 64) * kQueue];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the kernel's only argument is `a`, at the start of the argument segment
     const VerifyArgs *vargs = (const VerifyArgs *)((const __attribute__((address_space(4))) char *)
@@ -87,15 +90,9 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
 
 mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream) {
     if (!a.ntiles) return MAG_OK;
-    const size_t shmem = (size_t)(kNT / 64) * kQueue * 8 + bloom_bytes;
-    static size_t configured = 0;
-    if (shmem > configured) {
-        // not every runtime needs the opt-in; a real LDS overflow fails the launch below
-        (void)hipFuncSetAttribute((const void *)k_dense, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)shmem);
-        (void)hipGetLastError();
-        configured = shmem;
-    }
+    if (bloom_bytes > (size_t)kBloomWordsMax * 4 || a.bloom_vec * 16ull != bloom_bytes)
+        return fail(MAG_E_INVALID, "Bloom bitmap does not fit the dense kernel's LDS array");
+    const size_t shmem = 0;
     static int ncu = 0;
     if (!ncu) {
         int dev = 0;

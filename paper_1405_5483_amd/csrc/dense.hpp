@@ -109,8 +109,8 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
             uint32_t b = 1u;
 #pragma unroll
             for (int j = 0; j < kBloomBits; ++j) {
-                const uint32_t ix = bloom_probe(h, j) >> bshift;
-                b &= s_bloom[ix >> 5] >> (ix & 31);
+                const uint32_t p = bloom_probe(h, j);
+                b &= s_bloom[p >> (bshift + 5)] >> (p & 31u);
             }
             hm |= (b & 1u) << (4 * i + s);
         }

@@ -63,8 +63,8 @@ __host__ __device__ inline uint32_t window_hash(const uint32_t *w, int nwords) {
 }
 
 // Dense mode (every start position tested): a Bloom bitmap of 2^B bits over
-// the same first min(m, 16) bytes, kBloomBits bits per distinct pattern (the
-// top B bits of bloom_probe of the hash). B grows with the number of
+// the same first min(m, 16) bytes, kBloomBits bits per distinct pattern
+// (bloom_bit of bloom_probe of the hash). B grows with the number of
 // distinct patterns; batched scans use a copy with at most kBloomBatchLog2
 // bits, built from the same hashes.
 #ifndef MAG_BLOOM_BITS
@@ -90,16 +90,19 @@ __host__ __device__ inline uint32_t prefilter_hash(const uint32_t *w, int nwords
     return x * 0x9E3779B1u;
 }
 
-// Bloom bit j of a hash: bit 0 takes the hash's top bits, bit j > 0 the top
-// bits of g = h ^ (h >> 16) rotated left by 11j. g folds the well-mixed high
-// half of the product into its low half, so the rotations stay independent
-// on low-entropy texts (DNA); a few ALU ops replace a multiplicative remix
-// per bit.
+// Bloom probe j of a hash: g = h ^ (h >> 16) rotated left by 11j. g folds
+// the well-mixed high half of the product into its low half, so the
+// rotations stay independent on low-entropy texts (DNA); a few ALU ops
+// replace a multiplicative remix per probe. A probe p of a 2^B-bit bitmap
+// names bit p & 31 of 32-bit word p >> (37 - B) (bloom_bit): the low five
+// bits serve as the shift count as they are.
 __host__ __device__ inline uint32_t bloom_probe(uint32_t h, int j) {
-    if (j == 0) return h;
     const uint32_t g = h ^ (h >> 16);
     const uint32_t r = (uint32_t)(11 * j) & 31u;
     return r ? (g << r) | (g >> (32u - r)) : g;
+}
+__host__ __device__ inline uint32_t bloom_bit(uint32_t p, int B) {
+    return ((p >> (37 - B)) << 5) | (p & 31u);
 }
 
 // Everything a scan needs on the device. Plain pointers into one allocation.

@@ -258,9 +258,8 @@ void build_verifier(mag_plan *p) {
 }
 
 // Bloom bitmaps of the dense mode: for every distinct pattern's first
-// min(m, 16) bytes, bits h_j >> (32 - B) for j < kBloomBits, h_j =
-// bloom_probe(prefilter_hash, j), for B = bloom_log2 and for
-// the batched copy's smaller B.
+// min(m, 16) bytes, bits bloom_bit(bloom_probe(prefilter_hash, j), B) for
+// j < kBloomBits, for B = bloom_log2 and for the batched copy's smaller B.
 void build_bloom(mag_plan *p) {
     int B = kBloomMinLog2;
     while (B < kBloomMaxLog2 && (1ull << B) < 64ull * std::max<uint32_t>(p->n_unique, 1)) ++B;
@@ -278,7 +277,7 @@ void build_bloom(mag_plan *p) {
         const uint32_t h = prefilter_hash(&p->pwords[(size_t)u * p->mw], hw);
         for (int j = 0; j < kBloomBits; ++j) {
             const uint32_t x = bloom_probe(h, j);
-            const uint32_t i = x >> (32 - B), ib = x >> (32 - Bb);
+            const uint32_t i = bloom_bit(x, B), ib = bloom_bit(x, Bb);
             p->bloom[i >> 5] |= 1u << (i & 31);
             p->bloom_batch[ib >> 5] |= 1u << (ib & 31);
         }
