@@ -97,7 +97,7 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
                 w[t] = s ? __builtin_amdgcn_alignbyte(V[i + t + 1], V[i + t], s) : V[i + t];
             uint32_t h;
             if constexpr (FAST) {
-                h = prefilter_hash(w, 4);
+                h = prefilter_hash4(w);
             } else {
                 if (mw <= 4) {
 #pragma unroll

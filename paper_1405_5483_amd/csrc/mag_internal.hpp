@@ -90,6 +90,14 @@ __host__ __device__ inline uint32_t prefilter_hash(const uint32_t *w, int nwords
     return x * 0x9E3779B1u;
 }
 
+// prefilter_hash(w, 4) on the device: the same value, with its first three
+// terms in one 3-input XOR (v_bitop3, truth table 0x96).
+__device__ inline uint32_t prefilter_hash4(const uint32_t *w) {
+    const uint32_t x = __builtin_amdgcn_bitop3_b32(w[0], (w[1] << 7) | (w[1] >> 25),
+                                                   (w[2] << 14) | (w[2] >> 18), 0x96);
+    return (x ^ ((w[3] << 21) | (w[3] >> 11))) * 0x9E3779B1u;
+}
+
 // Bloom probe j of a hash: g = h ^ (h >> 16) rotated left by 11j. g folds
 // the well-mixed high half of the product into its low half, so the
 // rotations stay independent on low-entropy texts (DNA); a few ALU ops
