@@ -149,10 +149,12 @@ __device__ uint64_t steal_tile(uint64_t *next, const uint64_t *ranges, uint32_t 
     }
 }
 
-__global__ __launch_bounds__(kBT) void k_batch(const JobDesc *__restrict__ jobs, uint32_t njobs,
+__global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jobs, uint32_t njobs,
                                                const uint64_t *__restrict__ ranges,
                                                uint64_t *next, uint64_t *counters) {
-    extern __shared__ __align__(16) uint8_t smem[];
+    // static LDS of a fixed size: every carved-out array sits at a known
+    // address, so LDS accesses need no base added at run time
+    __shared__ __align__(16) uint8_t smem[kBatchLdsBytes];
     uint8_t *s_mu = smem;
     uint64_t *s_ctl = reinterpret_cast<uint64_t *>(smem + 256);          // claimed tiles, 2 slots
     uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256 + 16);
@@ -404,21 +406,12 @@ __global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint
 
 }  // namespace
 
-mag_status batch_configure() {
-    static bool done = false;
-    if (done) return MAG_OK;
-    // not every runtime needs the opt-in; a real LDS overflow fails the launch
-    (void)hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kBatchLdsBytes);
-    (void)hipGetLastError();
-    done = true;
-    return MAG_OK;
-}
+mag_status batch_configure() { return MAG_OK; }   // the kernel's LDS is static
 
 int batch_occupancy() {
     batch_configure();
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBT, kBatchLdsBytes) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBT, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -429,7 +422,7 @@ mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
     if (!b.total_tiles || !b.grid) return MAG_OK;
     hipLaunchKernelGGL(k_batch_init, dim3((b.grid + 255) / 256), dim3(256), 0, stream, b.ranges,
                        b.next, b.grid);
-    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), kBatchLdsBytes, stream, b.jobs, b.njobs,
+    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
                        b.ranges, b.next, b.counters);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "batch scan launch");
