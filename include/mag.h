@@ -158,6 +158,13 @@ typedef struct {
     uint32_t var;         /* 1: built by mag_plan_create_var; m is the shortest
                              length and the filter sees every pattern's first
                              m bytes                                           */
+    int32_t q_formula;    /* q by Section 3.2's formula for this pattern set:
+                             log_sigma(r*m), sigma the number of distinct
+                             pattern bytes (at least 2), rounded half up and
+                             clamped to [1, (m+1)/2]; 0 when r == 0. The
+                             heuristic runs min(q_formula, 8): the scan kernels
+                             are built for grams of at most 8 bytes          */
+    int32_t reserved;     /* zero                                               */
 } mag_plan_desc;
 
 /* Work counters of one scan (integers; equal to the oracle's counts). */
@@ -312,8 +319,8 @@ mag_status mag_scan_batch(const mag_job *jobs, uint32_t njobs, mag_match *d_out,
  * Features (host floats): f0 log2(sigma_P)/8, f1 m/32, f2 log10(r)/4, f3 byte
  * entropy/8, f4 largest byte frequency, f5 distinct patterns / r, f5+q for
  * q = 1..8 min(1, -log2(D_q / sigma_P^q)/32) with D_q the distinct q-byte
- * substrings of the patterns (1 if q > m, 0 if sigma_P = 1), f14 heuristic
- * q/8, f15 log2(r*m)/20.
+ * substrings of the patterns (1 if q > m, 0 if sigma_P = 1), f14 the
+ * heuristic's q (at most 8) / 8, f15 log2(r*m)/20.
  *
  * Candidate c < 64: q = c/8 + 1, k = (c/2)%4 + 1; feasible iff 2q-1 <= m,
  * k <= L and W = k*m' <= 32; sigma' = fit (even c) or max(2, fit/2) (odd c,

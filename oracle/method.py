@@ -39,7 +39,7 @@ import math
 import numpy as np
 
 MAX_W = 64          # state bits of the bit-parallel automaton (w = 64 in Section 3.2)
-MAX_Q = 8           # q is a small constant in practice (Section 2 names 2..6)
+MAX_Q = 8           # the q-gram map keys a gram by its raw bytes in one 64-bit word
 DEFAULT_TABLE_BUDGET = 96 * 1024   # bytes of mask table the fixed heuristic allows
 
 
@@ -234,11 +234,12 @@ def entry_bits(W: int, kind: str) -> int:
 def heuristic_q(sigma: int, r: int, m: int) -> int:
     """q = log_sigma(r m) (Section 3.2). Reading: sigma is the number of
     distinct pattern bytes (at least 2), rounded half up, clamped to
-    [1, min((m+1)//2, 8)]: at least one gram position must exist, and q stays
-    the small constant Section 2 describes."""
+    [1, (m+1)//2] so that at least one gram position exists (2q-1 <= m).
+    Nothing else bounds it: Section 3.2's formula may give q above the
+    "small constant" of Section 2 for large r*m over small alphabets."""
     s = max(sigma, 2)
     q = round_half_up(math.log(r * m) / math.log(s))
-    return max(1, min(q, (m + 1) // 2, MAX_Q))
+    return max(1, min(q, (m + 1) // 2))
 
 
 def heuristic_k(sigma: int, r: int, m: int, L: int) -> int:
@@ -256,14 +257,21 @@ def heuristic_k(sigma: int, r: int, m: int, L: int) -> int:
     return max(1, min(k, max(L, 1)))
 
 
-def heuristic_params(patterns: np.ndarray, table_budget: int = DEFAULT_TABLE_BUDGET):
+def heuristic_params(patterns: np.ndarray, table_budget: int = DEFAULT_TABLE_BUDGET,
+                     q_cap: int | None = None):
     """The fixed heuristic: (q, k, sigma'). sigma' starts at sigma_P and is
     lowered until sigma'**q * entry_bytes(W) fits the table budget (the
-    motivation of Section 3.3: table size grows as sigma**q)."""
+    motivation of Section 3.3: table size grows as sigma**q).
+
+    ``q_cap``: an upper limit a caller imposes on q before k and sigma' are
+    derived from it (an implementation that supports grams of at most
+    ``q_cap`` bytes); None keeps Section 3.2's q."""
     p = np.asarray(patterns, dtype=np.uint8)
     r, m = p.shape
     sp = sigma_p(p)
     q = heuristic_q(sp, r, m)
+    if q_cap is not None:
+        q = min(q, q_cap)
     L = gram_positions(m, q)
     k = heuristic_k(sp, r, m, L)
     mprime = sub_pattern_length(L, k)

@@ -21,7 +21,7 @@ bytes):
   f6+q-1 for q = 1..8: D_q = number of distinct q-byte substrings over all
       patterns and offsets; coverage D_q / sigma_P^q of the q-gram space;
       f = min(1, -log2(coverage) / 32) (0 when sigma_P = 1), and 1 when q > m
-  f14 q of the fixed heuristic / 8
+  f14 min(q of Section 3.2's formula, 8) / 8 (the feature saturates at 8)
   f15 log2(N) / 20
 
 Candidate c (0..63): q = c // 8 + 1, k = (c // 2) % 4 + 1, level = c % 2.
@@ -81,7 +81,7 @@ def features(patterns: np.ndarray) -> np.ndarray:
         else:
             lg_cov = math.log2(distinct_substrings(p, q)) - q * math.log2(sp)
             f[5 + q] = min(1.0, -lg_cov / 32.0)
-    f[14] = method.heuristic_q(sp, r, m) / 8.0
+    f[14] = min(method.heuristic_q(sp, r, m), 8) / 8.0
     f[15] = math.log2(N) / 20.0
     return f
 

@@ -56,6 +56,7 @@ class MagPlanDesc(ctypes.Structure):
         ("bits_shift", ctypes.c_int32), ("entry_bits", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("est_verif", ctypes.c_double), ("m_max", ctypes.c_uint32), ("var", ctypes.c_uint32),
+        ("q_formula", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

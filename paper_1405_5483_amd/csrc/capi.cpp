@@ -383,6 +383,7 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->est_verif = p->est_verif;
     d->m_max = p->m_max;
     d->var = (uint32_t)p->var;
+    d->q_formula = p->q_formula;
     return MAG_OK;
 }
 

@@ -153,6 +153,7 @@ struct mag_plan {
 
     // filter parameters
     int q = 1, k = 1, sigma_prime = 1, L = 0, mprime = 0, W = 0, esz = 1;
+    int q_formula = 0;               // Section 3.2's q for this pattern set, before kMaxQ
     int map_kind = MAG_MAP_GREEDY, select = MAG_SELECT_HEURISTIC;
     int bits_shift = 0;              // s of the bit-field map
     int qbits = 0;                   // log2 sigma' of the q-gram map
@@ -199,8 +200,11 @@ mag_status hip_fail(hipError_t e, const char *what);
 // first use; fails if the plan lives on another device (capi.cpp).
 mag_status ensure_device(mag_plan *p);
 
-// q of the fixed heuristic: log base max(sigma, 2) of r*m, rounded half up,
-// clamped to [1, min((m+1)/2, kMaxQ)] (plan.cpp).
+// q by Section 3.2's formula: log base max(sigma, 2) of r*m, rounded half
+// up, clamped to [1, (m+1)/2] (at least one gram position).
+int heuristic_q_formula(int sigma, uint32_t r, uint32_t m);
+// q of the fixed heuristic as the library runs it: the formula's q, at most
+// kMaxQ (the longest gram the scan kernels are built for).
 int heuristic_q(int sigma, uint32_t r, uint32_t m);
 
 // Verifications per text byte the filter of a built plan is expected to make,

@@ -359,10 +359,15 @@ double estimate_verifications(const mag_plan *p) {
     return cand * q / ((double)k * q);
 }
 
-int heuristic_q(int sigma, uint32_t r, uint32_t m) {
+int heuristic_q_formula(int sigma, uint32_t r, uint32_t m) {
+    if (r == 0 || m == 0) return 0;
     const double s = std::max(sigma, 2);
     const double lg = std::log((double)r * m) / std::log(s);   // log_sigma(rm)
-    return std::max(1, std::min({round_half_up(lg), (int)(m + 1) / 2, kMaxQ}));
+    return std::max(1, std::min(round_half_up(lg), (int)(m + 1) / 2));
+}
+
+int heuristic_q(int sigma, uint32_t r, uint32_t m) {
+    return std::min(heuristic_q_formula(sigma, r, m), kMaxQ);
 }
 
 mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t m,
@@ -391,6 +396,12 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     p->map_kind = prm.map_kind;
     p->select = prm.select;
 
+    {
+        uint64_t hist[256];
+        std::vector<int> order;
+        frequency_order(p, hist, order);
+        p->q_formula = heuristic_q_formula((int)order.size(), r, m);
+    }
     int q, k, sp;
     const int budget = prm.table_budget > 0 ? prm.table_budget
                                             : (qgram ? kQgramTableBudget : kDefaultTableBudget);

@@ -40,6 +40,10 @@ def test_every_declared_symbol_is_exported():
     assert sorted(SIGNATURES) == names
 
 
+LIBRARY_MAX_Q = 8   # longest gram the scan kernels are built for (mag_plan_desc.q_formula)
+# jobs of the 512-job batched workload whose Section 3.2 q is 9
+OVER_Q8_JOBS = [4, 18, 25, 69, 126, 137, 142, 236, 309, 326, 343, 345, 444, 448]
+
 CASES = [
     # sigma, r, m, q, k, sigma', kind
     (4, 20, 8, 2, 1, 4, "greedy"),
@@ -109,11 +113,42 @@ def test_heuristic_equals_oracle(seed):
     m = int(rng.choice([4, 8, 16, 32, 64]))
     T = gen_text(8192, sigma, rng=seed)
     P = gen_patterns(T, r, m, r // 2, sigma, rng=seed + 1)
+    q_paper = mm.heuristic_q(mm.sigma_p(P), r, m)
     for budget in (0, 8 * 1024, 1 << 20):
         plan = mag.Plan(P, table_budget=budget)
         info = plan.info()
-        want = mm.heuristic_params(P, budget or mm.DEFAULT_TABLE_BUDGET)
+        # the library runs Section 3.2's q up to its longest gram, 8 bytes
+        assert info["q_formula"] == q_paper
+        assert info["q"] == min(q_paper, LIBRARY_MAX_Q)
+        want = mm.heuristic_params(P, budget or mm.DEFAULT_TABLE_BUDGET, q_cap=LIBRARY_MAX_Q)
         assert (info["q"], info["k"], info["sigma_prime"]) == want
+        if q_paper <= LIBRARY_MAX_Q:
+            assert want == mm.heuristic_params(P, budget or mm.DEFAULT_TABLE_BUDGET)
+
+
+def test_heuristic_q_above_the_library_limit_in_the_batched_workload():
+    """Section 3.2's q = round(log_sigma(r m)) exceeds the library's 8-byte
+    grams only for DNA jobs with m = 32 and r >= 4096 (log_4(4096 * 32) =
+    8.5 rounds to 9). In the 512-job workload these are the 14 jobs listed
+    below; each runs q = 8 with k and sigma' derived from it."""
+    mag = _lib_or_skip()
+    from synth import batch_recipes, make_job
+    over = []
+    for j, (rec, ss) in enumerate(batch_recipes(512)):
+        if rec["sigma"] != 4 or rec["m"] != 32:
+            continue          # q <= log_4(10^4 * 32) < 8.5 needs sigma_P <= 4 and m = 32
+        job = make_job(min(rec["n"], 1 << 16), rec["sigma"], rec["dist"], rec["r"], rec["m"],
+                       rec["frac"], ss)
+        q_paper = mm.heuristic_q(mm.sigma_p(job.patterns), rec["r"], rec["m"])
+        info = mag.Plan(job.patterns).info()
+        assert info["q_formula"] == q_paper
+        assert info["q"] == min(q_paper, LIBRARY_MAX_Q)
+        assert (info["q"], info["k"], info["sigma_prime"]) == \
+            mm.heuristic_params(job.patterns, q_cap=LIBRARY_MAX_Q)
+        if q_paper > LIBRARY_MAX_Q:
+            assert q_paper == 9 and rec["r"] >= 4096
+            over.append(j)
+    assert over == OVER_Q8_JOBS, over
 
 
 @pytest.mark.parametrize("seed", range(12))

@@ -382,6 +382,54 @@ def test_qgram_candidate_rate():
     assert abs(rate - expect) < 5 * math.sqrt(expect / cnt["samples"]) + 1e-3, (rate, expect)
 
 
+def test_qgram_heuristic_hand_counted():
+    """heuristic_params_qgram on sets whose classes are counted by hand.
+
+    * {abcabcab, abcdabcd}, m = 8: q = min(8, (8+1)//2) = 4, L = (8-4+1)//4 = 1,
+      k = 1, m' = 1, W = 1 (1-bit entries). Class 0 holds the grams at
+      offsets s = 0..3: abca, bcab, cabc, abca from the first pattern (3
+      distinct) and abcd, bcda, cdab, dabc from the second (4), so D = 7.
+      sigma' = the smallest power of two >= 32 * 7 = 224, i.e. 256: a
+      256-bit table. A 16-byte budget (128 bits) halves it once to 128; an
+      8-byte budget twice, to 64.
+    * {a^24}, m = 24: q = 8, L = (24-8+1)//8 = 2, W = 2 (2-bit entries). Every
+      gram is aaaaaaaa, so D = 1 and sigma' = 32 (64 bits); a 4-byte budget
+      (32 bits) halves it to 16.
+    * {(ab)^12}, m = 24: q = 8, W = 2. Class b holds, over s = 0..7, the
+      grams at offsets s + 8b: abababab for even s and babababa for odd s,
+      so D = 2 and sigma' = 64.
+    """
+    two = np.frombuffer(b"abcabcababcdabcd", dtype=np.uint8).reshape(2, 8)
+    assert mm.heuristic_params_qgram(two) == (4, 1, 256)
+    assert mm.heuristic_params_qgram(two, table_budget=16) == (4, 1, 128)
+    assert mm.heuristic_params_qgram(two, table_budget=8) == (4, 1, 64)
+    a24 = np.frombuffer(b"a" * 24, dtype=np.uint8).reshape(1, 24)
+    assert mm.heuristic_params_qgram(a24) == (8, 1, 32)
+    assert mm.heuristic_params_qgram(a24, table_budget=4) == (8, 1, 16)
+    ab = np.frombuffer(b"ab" * 12, dtype=np.uint8).reshape(1, 24)
+    assert mm.heuristic_params_qgram(ab) == (8, 1, 64)
+
+
+def test_heuristic_q_formula_hand_computed():
+    """Section 3.2's q = round(log_sigma(r m)), clamped to [1, (m+1)//2] only:
+    sigma = 4, r = 4096, m = 32 gives log_4(131072) = 8.5 -> 9 (above the
+    "2..6 in practice" of Section 2, and allowed); sigma = 4, r = 100,
+    m = 16: log_4(1600) = 5.32 -> 5; sigma = 2, r = 1000, m = 8:
+    log_2(8000) = 12.97 -> 13, clamped to (8+1)//2 = 4; sigma = 20,
+    r = 10^5, m = 16: log_20(1.6e6) = 4.76 -> 5."""
+    assert mm.heuristic_q(4, 4096, 32) == 9
+    assert mm.heuristic_q(4, 100, 16) == 5
+    assert mm.heuristic_q(2, 1000, 8) == 4
+    assert mm.heuristic_q(20, 100_000, 16) == 5
+    # the cap is only applied on request
+    P = np.frombuffer(b"ACGT" * 8, dtype=np.uint8).reshape(1, 32).repeat(4096, axis=0)
+    P = P.copy()
+    P[:, 0] = np.frombuffer(b"ACGT", dtype=np.uint8)[np.arange(4096) % 4]
+    q, k, sp = mm.heuristic_params(P)
+    assert q == 9
+    assert mm.heuristic_params(P, q_cap=8)[0] == 8
+
+
 def test_qgram_heuristic_invariants():
     for sigma, r, m in ((4, 100, 16), (64, 1000, 32), (20, 3000, 16), (20, 50, 8), (2, 20, 5)):
         T = gen_text(30_000, sigma, rng=r)
