@@ -105,6 +105,23 @@ typedef enum {
                            Not accepted by mag_batch_create unless dense.      */
 } mag_map_kind;
 
+/* How the dense mode tests a start position before exact verification. */
+typedef enum {
+    MAG_DENSE_PROBE_AUTO = 0,   /* slices when the patterns have m >= 6 and their
+                                   bytes carry enough entropy (6 H >= B + 4 bits,
+                                   H the pattern bytes' entropy, 2^B the bitmap's
+                                   bits), else the Bloom bitmap                 */
+    MAG_DENSE_PROBE_SLICES = 1, /* one bitmap word per position: every distinct
+                                   pattern sets the bits of its 6-byte slices at
+                                   offsets 0, 2, .., 2(k-1) (k <= 8, the Bloom
+                                   optimum for the pattern count), and a position
+                                   passes when its own slices' bits are all set;
+                                   neighbouring positions share the probes.
+                                   Needs m >= 6                                  */
+    MAG_DENSE_PROBE_BLOOM = 2   /* three probes per position into a Bloom bitmap
+                                   of the first min(m, 16) bytes                */
+} mag_dense_probe;
+
 typedef struct {
     int32_t select;       /* mag_select                                         */
     int32_t map_kind;     /* mag_map_kind                                       */
@@ -124,7 +141,10 @@ typedef struct {
                              (Section 3.2, "Implementation"). Same results;
                              the dense mode and batches always compute on the
                              fly                                               */
-    int32_t reserved[2];  /* must be zero                                       */
+    int32_t chunk_bytes;  /* reserved for the tile size; must be 0 (auto)       */
+    int32_t words_per_lane; /* reserved for the lane run length; must be 0      */
+    int32_t dense_probe;  /* mag_dense_probe                                    */
+    int32_t reserved[3];  /* must be zero                                       */
 } mag_params;
 
 typedef struct {
@@ -164,7 +184,11 @@ typedef struct {
                              clamped to [1, (m+1)/2]; 0 when r == 0. The
                              heuristic runs min(q_formula, 8): the scan kernels
                              are built for grams of at most 8 bytes          */
-    int32_t reserved;     /* zero                                               */
+    int32_t dense_slices; /* one-probe dense bitmap: slices per pattern (k of
+                             MAG_DENSE_PROBE_SLICES); 0 when dense scans use the
+                             Bloom bitmap                                      */
+    double dense_pass;    /* estimated share of start positions the dense
+                             mode's bitmap passes to exact verification        */
 } mag_plan_desc;
 
 /* Work counters of one scan (integers; equal to the oracle's counts). */

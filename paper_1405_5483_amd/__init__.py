@@ -19,7 +19,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, VERIFY, MagError, MagJob, MagParams, MagPlanDesc,
+from ._lib import (DENSE_PROBE, MAG_E_OVERFLOW, MAP_KIND, MODE, SELECT, VERIFY, MagError, MagJob, MagParams, MagPlanDesc,
                    MagStats, MagTuneOpts, check, lib)
 
 __all__ = ["Plan", "Batch", "Selector", "scan", "scan_async", "scan_batch", "autotune",
@@ -63,7 +63,7 @@ class Plan:
                  k: int | None = None, sigma_prime: int | None = None,
                  map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
                  verify: str = "auto", verify_buffer: int = 0, encode: bool = False,
-                 candidate: int | None = None):
+                 dense_probe: str = "auto", candidate: int | None = None):
         var = _unequal(patterns)
         if var is None:
             p = _as_patterns(patterns)
@@ -86,6 +86,7 @@ class Plan:
         prm.verify = VERIFY[verify]
         prm.verify_buffer = int(verify_buffer)
         prm.encode = 1 if encode else 0
+        prm.dense_probe = DENSE_PROBE[dense_probe]
         handle = ctypes.c_void_p()
         self._h = None
         if var is None:
@@ -118,7 +119,8 @@ class Plan:
         return {"select": inv(SELECT, prm.select), "map_kind": inv(MAP_KIND, prm.map_kind),
                 "q": prm.q, "k": prm.k, "sigma_prime": prm.sigma_prime,
                 "mode": inv(MODE, prm.mode), "verify": inv(VERIFY, prm.verify),
-                "verify_buffer": prm.verify_buffer, "encode": bool(prm.encode)}
+                "verify_buffer": prm.verify_buffer, "encode": bool(prm.encode),
+                "dense_probe": inv(DENSE_PROBE, prm.dense_probe)}
 
     def export(self, raw: bool = False):
         """(mu [256] uint8, mask table with one entry per code in the entry

@@ -23,6 +23,7 @@ SELECT = {"heuristic": 0, "explicit": 1, "learned": 2, "autotune": 3}
 MAP_KIND = {"greedy": 0, "rank": 1, "bits": 2, "qgram": 3}
 VERIFY = {"auto": 0, "inline": 1, "deferred": 2}
 MODE = {"auto": 0, "filter": 1, "dense": 2}
+DENSE_PROBE = {"auto": 0, "slices": 1, "bloom": 2}
 
 
 class MagParams(ctypes.Structure):
@@ -37,7 +38,10 @@ class MagParams(ctypes.Structure):
         ("verify", ctypes.c_int32),
         ("verify_buffer", ctypes.c_int32),
         ("encode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("chunk_bytes", ctypes.c_int32),
+        ("words_per_lane", ctypes.c_int32),
+        ("dense_probe", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -56,7 +60,8 @@ class MagPlanDesc(ctypes.Structure):
         ("bits_shift", ctypes.c_int32), ("entry_bits", ctypes.c_int32),
         ("n_codes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("est_verif", ctypes.c_double), ("m_max", ctypes.c_uint32), ("var", ctypes.c_uint32),
-        ("q_formula", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("q_formula", ctypes.c_int32), ("dense_slices", ctypes.c_int32),
+        ("dense_pass", ctypes.c_double),
     ]
 
 

@@ -174,7 +174,9 @@ mag_status ensure_device(mag_plan *p) {
     const uint64_t o_ids = round16(o_ids0 + p->idstart.size() * 4);
     const uint64_t o_bloom = round16(o_ids + p->ids.size() * 4 + 16);
     const uint64_t o_bloomb = round16(o_bloom + p->bloom.size() * 4);
-    const uint64_t o_pwoff = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
+    const uint64_t o_sl = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
+    const uint64_t o_wf = round16(o_sl + p->slices.size() * 4 + 16);
+    const uint64_t o_pwoff = round16(o_wf + p->wfilter.size() * 8 + 16);
     const uint64_t o_plen = round16(o_pwoff + p->pwoff.size() * 4);
     const uint64_t o_gstart = round16(o_plen + p->plen.size() * 4);
     const uint64_t total = round16(o_gstart + p->gstart.size() * 4 + 16);
@@ -194,6 +196,8 @@ mag_status ensure_device(mag_plan *p) {
     if (!p->bloom.empty()) std::memcpy(&host[o_bloom], p->bloom.data(), p->bloom.size() * 4);
     if (!p->bloom_batch.empty())
         std::memcpy(&host[o_bloomb], p->bloom_batch.data(), p->bloom_batch.size() * 4);
+    if (!p->slices.empty()) std::memcpy(&host[o_sl], p->slices.data(), p->slices.size() * 4);
+    if (!p->wfilter.empty()) std::memcpy(&host[o_wf], p->wfilter.data(), p->wfilter.size() * 8);
     if (!p->pwoff.empty()) std::memcpy(&host[o_pwoff], p->pwoff.data(), p->pwoff.size() * 4);
     if (!p->plen.empty()) std::memcpy(&host[o_plen], p->plen.data(), p->plen.size() * 4);
     if (!p->gstart.empty()) std::memcpy(&host[o_gstart], p->gstart.data(), p->gstart.size() * 4);
@@ -211,6 +215,8 @@ mag_status ensure_device(mag_plan *p) {
     p->dev.ids = reinterpret_cast<const uint32_t *>(base + o_ids);
     p->dev.bloom = reinterpret_cast<const uint32_t *>(base + o_bloom);
     p->dev.bloom_batch = reinterpret_cast<const uint32_t *>(base + o_bloomb);
+    p->dev.slices = reinterpret_cast<const uint32_t *>(base + o_sl);
+    p->dev.wfilter = p->wfilter.empty() ? nullptr : reinterpret_cast<const uint64_t *>(base + o_wf);
     p->dev.pwoff = reinterpret_cast<const uint32_t *>(base + o_pwoff);
     p->dev.plen = reinterpret_cast<const uint32_t *>(base + o_plen);
     p->dev.gstart = reinterpret_cast<const uint32_t *>(base + o_gstart);
@@ -384,6 +390,8 @@ mag_status mag_plan_info(const mag_plan *p, mag_plan_desc *d) {
     d->m_max = p->m_max;
     d->var = (uint32_t)p->var;
     d->q_formula = p->q_formula;
+    d->dense_slices = p->slice_k;
+    d->dense_pass = p->slice_k ? p->slice_fp : p->bloom_fp;
     return MAG_OK;
 }
 
@@ -400,6 +408,7 @@ mag_status mag_plan_get_params(const mag_plan *p, mag_params *o) {
     o->verify = p->verify;
     o->verify_buffer = (int32_t)p->verify_buffer;
     o->encode = p->encode;
+    o->dense_probe = p->dense_probe;
     return MAG_OK;
 }
 
@@ -448,14 +457,16 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
                                       : (n >= (uint64_t)p->q ? (n - p->q) / kq + 1 : 0);
 
     // many expected verifications: the filter kernels defer them
+    const bool slices = p->dense && p->slice_k > 0;
     const double expect = p->r == 0 ? 0.0
-                          : p->dense ? p->bloom_fp * (double)samples
+                          : p->dense ? (slices ? p->slice_fp : p->bloom_fp) * (double)samples
                           : p->est_verif < 0.0 ? -1.0 : p->est_verif * (double)n;
     uint64_t pcap = 0;
     // a grid of fewer workgroups than half the compute units verifies inline
     // with few waves: defer when each of them would face many starts
     const int ncu = device_compute_units();
-    const uint64_t tile = p->dense ? (uint64_t)kDenseScanTile : kSmallGridTileSamples;
+    const uint64_t tile = slices ? (uint64_t)kSliceScanTile
+                          : p->dense ? (uint64_t)kDenseScanTile : kSmallGridTileSamples;
     const uint64_t tiles = (samples + tile - 1) / tile;
     const double vwaves = (double)std::max<uint64_t>(tiles, 1) *
                           (p->dense ? kDenseScanThreads / 64 : kScanConsumerLanes / 64);
@@ -510,13 +521,20 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         da.delta = t & 15;
         da.n = n;
         da.last = (int64_t)n - (int64_t)p->m;
-        da.ntiles = samples ? (samples + kDenseScanTile - 1) / kDenseScanTile : 0;
         da.bshift = 32u - (uint32_t)p->bloom_log2;
-        da.bloom_vec = (uint32_t)(p->bloom.size() * 4 / 16);
-        da.bloom = p->dev.bloom;
         da.counters = p->scratch.counters;
         da.v = make_verify_args(p, sl);
-        s = launch_dense(da, p->bloom.size() * 4, stream);
+        if (slices) {
+            da.ntiles = samples ? (samples + kSliceScanTile - 1) / kSliceScanTile : 0;
+            da.bloom_vec = (uint32_t)(p->slices.size() * 4 / 16);
+            da.bloom = p->dev.slices;
+            s = launch_dense_slices(da, p->slices.size() * 4, p->slice_k, stream);
+        } else {
+            da.ntiles = samples ? (samples + kDenseScanTile - 1) / kDenseScanTile : 0;
+            da.bloom_vec = (uint32_t)(p->bloom.size() * 4 / 16);
+            da.bloom = p->dev.bloom;
+            s = launch_dense(da, p->bloom.size() * 4, stream);
+        }
     } else {
         if (smag) s = launch_encode(p, d_text, n, p->scratch.codes, sl.csz, stream);
         if (s == MAG_OK) s = launch_scan(p, sl, stream);

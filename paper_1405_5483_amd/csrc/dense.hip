@@ -86,7 +86,160 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     }
 }
 
+// The one-probe dense scan (slice_test): the same grid and bitmap staging as
+// k_dense; tiles of kSliceScanTile positions, wave w covering positions
+// 1008 w .. 1008 w + 1007 of its tile, each lane loading the 32 bytes from
+// the word that holds its first position. Each wave keeps the loads of its
+// next two tiles in flight while it tests the current one (three register
+// sets, used in turn). AL: the text starts on a 4-byte boundary, so no byte
+// realignment is needed (tiles are a multiple of 4 positions long).
+template <int K, bool AL>
+__global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
+    __shared__ __align__(16) uint32_t s_bits[kBloomWordsMax];
+    __shared__ uint64_t s_queue[(kNT / 64) * kQueue];
+    __shared__ uint64_t s_found[(kNT / 64) * kFoundBuf];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const VerifyArgs *vargs = (const VerifyArgs *)((const __attribute__((address_space(4))) char *)
+                                                       __builtin_amdgcn_kernarg_segment_ptr() +
+                                                   offsetof(DenseArgs, v));
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.bloom);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
+        for (uint32_t v = tid; v < a.bloom_vec; v += kNT) dst[v] = src[v];
+    }
+    __syncthreads();
+    uint64_t *queue = s_queue + wave * kQueue;
+    uint64_t *fbuf = s_found + wave * kFoundBuf;
+    uint32_t qn = 0, nhit = 0, fbn = 0;
+    // byte offset of this lane's first position in its tile
+    const uint32_t lane_off = (uint32_t)(kSliceWaveSpan * wave + 16 * lane);
+    // Tiles whose lanes' 32 bytes all lie inside the text take two whole
+    // loads per lane (the pipelined loop below), the last ones (at most two)
+    // single range-checked dwords. Resource offsets are taken from the
+    // 16-byte-aligned text base, which the text's first tile byte follows by
+    // d = delta & 3 within its word.
+    const uint64_t pa_end = (a.delta + a.n) & ~3ull;  // whole words of text from tbase
+    uint64_t nfull = 0;
+    {
+        const uint64_t need = kSliceScanTile + 4u * kSliceLoadWords + 16;   // a tile's bytes from its word
+        nfull = pa_end >= need ? (pa_end - need) / kSliceScanTile + 1 : 0;
+        if (nfull > a.ntiles) nfull = a.ntiles;
+    }
+    const uint32_t d = (uint32_t)(a.delta & 3u);
+    auto load = [&](uint64_t tile, uint32_t (&W)[kSliceLoadWords]) {
+        // the word holding the tile's first position, and a resource from the
+        // 16-byte boundary below it over the tile's lanes' bytes
+        const uint64_t w0 = (a.delta & ~3ull) + tile * (uint64_t)kSliceScanTile;
+        const uint64_t pa0 = w0 & ~15ull;
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, kSliceScanTile + 64u);
+        const int at = (int)(w0 - pa0 + lane_off);
+        const uint4 v0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at, 0, 0));
+        const uint4 v1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at + 16, 0, 0));
+        W[0] = v0.x; W[1] = v0.y; W[2] = v0.z; W[3] = v0.w;
+        W[4] = v1.x; W[5] = v1.y; W[6] = v1.z; W[7] = v1.w;
+    };
+    auto run = [&](uint64_t tile, const uint32_t (&W)[kSliceLoadWords]) {
+        const int64_t xb = (int64_t)tile * kSliceScanTile + lane_off;
+        slice_test<K, AL>(W, d, xb, a.last - xb + 1, s_bits, a.bshift, queue, qn, vargs, lane, nhit, fbuf,
+                          fbn);
+    };
+    const uint64_t G = gridDim.x;
+    uint64_t tile = blockIdx.x;
+    uint32_t Wa[kSliceLoadWords], Wb[kSliceLoadWords], Wc[kSliceLoadWords];
+    // every step issues the same loads (past the last full tile they reload
+    // it), so the wait before a tile's use counts the same loads after it on
+    // every path and the two tiles ahead stay in flight
+    const uint64_t lastfull = nfull ? nfull - 1 : 0;
+    auto ahead = [&](uint64_t t) { return t < lastfull ? t : lastfull; };
+    if (tile < nfull) {
+        load(tile, Wa);
+        load(ahead(tile + G), Wb);
+    }
+    while (tile < nfull) {
+        load(ahead(tile + 2 * G), Wc);
+        run(tile, Wa);
+        if ((tile += G) >= nfull) break;
+        load(ahead(tile + 2 * G), Wa);
+        run(tile, Wb);
+        if ((tile += G) >= nfull) break;
+        load(ahead(tile + 2 * G), Wb);
+        run(tile, Wc);
+        tile += G;
+    }
+    // the tail tiles, dword by dword within the text's resource
+    for (tile = nfull + ((blockIdx.x + G - nfull % G) % G); tile < a.ntiles; tile += G) {
+        const int64_t x0 = (int64_t)tile * kSliceScanTile;
+        int64_t b1 = x0 + kSliceScanTile + 48;
+        if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
+        const uint64_t pa0 = (a.delta + (uint64_t)x0) & ~15ull;
+        const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
+        const uint32_t p0 = (uint32_t)(a.delta + (uint64_t)x0 - pa0);
+        const uint32_t at = (p0 & ~3u) + lane_off;
+        uint32_t W[kSliceLoadWords];
+#pragma unroll
+        for (int t = 0; t < kSliceLoadWords; ++t) W[t] = ld32(rs, at + 4u * t);
+        run(tile, W);
+    }
+    if (qn) fbn = drain_partial_found(vargs, queue, qn, lane, fbuf, fbn);
+    if (fbn) flush_found_args(vargs, fbuf, fbn);
+    unsigned long long nh = nhit;
+    for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
+    if (lane == 0 && nh) {
+        atomicAdd((unsigned long long *)&a.counters[1], nh);
+        atomicAdd((unsigned long long *)&a.counters[2], nh);
+    }
+}
+
+int compute_units(int &ncu) {
+    if (ncu) return 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        ncu = 0;
+        hip_fail(e, "dense scan sizing");
+        return -1;
+    }
+    return 0;
+}
+
+template <int K>
+mag_status launch_slices_k(const DenseArgs &a, hipStream_t stream) {
+    static int ncu = 0;
+    if (compute_units(ncu)) return MAG_E_DEVICE;
+    const bool al = (a.delta & 3) == 0;
+    const void *fn = al ? (const void *)k_dense_slices<K, true> : (const void *)k_dense_slices<K, false>;
+    const int occ = cached_occupancy(fn, kNT, 0);
+    if (occ < 1) return fail(MAG_E_UNSUPPORTED, "dense scan does not fit on a compute unit");
+    uint64_t grid = (uint64_t)ncu * occ;
+    if (grid > a.ntiles) grid = a.ntiles;
+    if (al)
+        hipLaunchKernelGGL((k_dense_slices<K, true>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_dense_slices<K, false>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "dense scan launch");
+}
+
 }  // namespace
+
+mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, hipStream_t stream) {
+    if (!a.ntiles) return MAG_OK;
+    if (bitmap_bytes > (size_t)kBloomWordsMax * 4 || a.bloom_vec * 16ull != bitmap_bytes)
+        return fail(MAG_E_INVALID, "slice bitmap does not fit the dense kernel's LDS array");
+    switch (k) {
+        case 1: return launch_slices_k<1>(a, stream);
+        case 2: return launch_slices_k<2>(a, stream);
+        case 3: return launch_slices_k<3>(a, stream);
+        case 4: return launch_slices_k<4>(a, stream);
+        case 5: return launch_slices_k<5>(a, stream);
+        case 6: return launch_slices_k<6>(a, stream);
+        case 7: return launch_slices_k<7>(a, stream);
+        case 8: return launch_slices_k<8>(a, stream);
+    }
+    return fail(MAG_E_INVALID, "slices per pattern outside [1, 8]");
+}
 
 mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream) {
     if (!a.ntiles) return MAG_OK;

@@ -25,6 +25,8 @@ constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive posi
 constexpr int kDenseScanThreads = MAG_DENSE_SCAN_THREADS;
 constexpr int kDenseScanTile = 16 * kDenseScanThreads;
 constexpr uint32_t kDenseQueue = 128;   // per-wave queue the callers provide (starts)
+// one-probe dense kernel: 63 owning lanes of 16 positions per wave
+constexpr int kSliceScanTile = 16 * 63 * (kDenseScanThreads / 64);
 
 struct DenseArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes
@@ -40,6 +42,9 @@ struct DenseArgs {
 };
 
 mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream);
+// The one-probe dense kernel: a.bloom is the slice bitmap, k its slices per
+// pattern, a.ntiles counts tiles of kSliceScanTile positions.
+mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, hipStream_t stream);
 
 namespace dev {
 
@@ -69,6 +74,9 @@ __device__ __forceinline__ void dense_load(__amdgpu_buffer_rsrc_t rs, uint32_t n
         for (int t = 0; t < 10; ++t) W[t] = ld32(rs, a + 4u * t);
     }
 }
+
+__device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
+                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit);
 
 // Tests the 16 windows of thread tid (positions xb .. xb + 15, xb = x0 +
 // 16*tid; d = p0 & 3) whose bytes are in W, and queues those that pass.
@@ -115,6 +123,14 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
             hm |= (b & 1u) << (4 * i + s);
         }
     }
+    queue_hits(hm, xb, last, queue, qn, vp, lane, nhit);
+}
+
+// Queues the positions xb + u of this lane whose bit u (u < 16) is set in hm
+// and that do not pass `last`; verifies full queues. Every lane of the wave
+// calls it.
+__device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
+                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit) {
     // positions past the last start
     const int64_t room = last - xb + 1;
     if (room < 16) hm &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
@@ -148,6 +164,100 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
         if (qn >= 64) {
             qn -= 64;
             drain64(vp, queue, qn, lane);
+        }
+    }
+}
+
+// One-probe dense mode (slice_hash). A wave covers 63 * 16 consecutive start
+// positions: lane L < 63 owns the 16 from xb = its wave's first + 16 L, and
+// lane 63 probes the 16 that follow the wave's last (the next wave's first),
+// so that every owner finds the probes of the positions up to 15 past its
+// own in the next lane. W holds the 32 bytes from the word that contains xb
+// (d = xb's byte offset in it; AL: d = 0). Bit u of a lane's probe mask is
+// the bitmap bit of the slice at xb + u; position xb + u passes when bits u,
+// u + 2, .., u + 2(K-1) of the mask extended by the next lane's are all set.
+constexpr int kSliceOwners = 63;
+constexpr int kSliceWaveSpan = 16 * kSliceOwners;
+constexpr int kSliceLoadWords = 8;
+
+template <bool AL>
+__device__ __forceinline__ void slice_words(const uint32_t (&W)[kSliceLoadWords], uint32_t d,
+                                            uint32_t (&V)[6]) {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) V[t] = AL ? W[t] : __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
+}
+
+__device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[6], const uint32_t *s_bits,
+                                                 uint32_t bshift) {
+    uint32_t A[19];                             // A[i]: the word of bytes xb+i .. xb+i+3
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        A[i] = (i & 3) ? __builtin_amdgcn_alignbyte(V[i / 4 + 1], V[i / 4], i & 3) : V[i / 4];
+    uint32_t hm = 0;
+    const uint32_t ashift = bshift + 3;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const uint32_t h = __umul24(A[u + 3], kSliceK2) + __umul24(A[u], kSliceK1);
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(
+            reinterpret_cast<const char *>(s_bits) + ((h >> ashift) & ~3u));
+        hm |= __builtin_amdgcn_ubfe(w, h >> bshift, 1u) << u;
+    }
+    return hm;
+}
+
+// drain64 / drain_partial with the wave's found-key buffer.
+__device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
+                                                  int lane, uint64_t *fbuf, uint32_t fbn) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint64_t e = queue[from + lane];
+    __builtin_amdgcn_wave_barrier();
+    return verify_one_buffered(v, e, true, fbuf, fbn);
+}
+
+__device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, const uint64_t *queue,
+                                                        uint32_t qn, int lane, uint64_t *fbuf, uint32_t fbn) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const bool active = (uint32_t)lane < qn;
+    const uint64_t e = active ? queue[lane] : 0ull;
+    __builtin_amdgcn_wave_barrier();
+    return verify_one_buffered(v, e, active, fbuf, fbn);
+}
+
+// One lane-run of the one-probe dense mode: probes, the K-slice test, and the
+// queueing of the passing positions (room: starts left from xb, <= 0 when
+// none), one per lane and round with a ballot; found keys collect in the
+// wave's buffer fbuf (fbn keys). Every lane of the wave calls it.
+template <int K, bool AL>
+__device__ __forceinline__ void slice_test(const uint32_t (&W)[kSliceLoadWords], uint32_t d, int64_t xb,
+                                           int64_t room, const uint32_t *s_bits, uint32_t bshift,
+                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int lane,
+                                           uint32_t &nhit, uint64_t *fbuf, uint32_t &fbn) {
+    uint32_t V[6];
+    slice_words<AL>(W, d, V);
+    const uint32_t hm = slice_probes(V, s_bits, bshift);
+    uint32_t pass = hm;
+    if constexpr (K > 1) {
+        const uint32_t ext = hm | (__shfl_down(hm, 1) << 16);
+#pragma unroll
+        for (int j = 1; j < K; ++j) pass &= ext >> (kSliceStride * j);
+    }
+    pass &= lane < kSliceOwners ? 0xFFFFu : 0u;
+    if (room < 16) pass &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
+    nhit += (uint32_t)__popc(pass);
+    while (__ballot(pass != 0)) {
+        const bool act = pass != 0;
+        const uint32_t u = (uint32_t)__builtin_ctz(pass | 0x10000u);
+        pass &= pass - 1u;
+        const uint64_t bal = __ballot(act);
+        if (act) queue[qn + lanes_below(bal)] = (uint64_t)(xb + u);
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= 64) {
+            qn -= 64;
+            fbn = drain64_found(vp, queue, qn, lane, fbuf, fbn);
         }
     }
 }

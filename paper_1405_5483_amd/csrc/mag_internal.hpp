@@ -113,6 +113,41 @@ __host__ __device__ inline uint32_t bloom_bit(uint32_t p, int B) {
     return ((p >> (37 - B)) << 5) | (p & 31u);
 }
 
+// Dense mode with one bitmap probe per start position (the "sliced" bitmap):
+// each distinct pattern sets one bit for each of its first k 6-byte slices at
+// offsets 0, 2, .., 2(k-1), and a start position passes when the bits of its
+// own slices at those offsets are all set. Consecutive positions share their
+// probes (position x's slice at offset 2j is position x+2j's slice at offset
+// 0), so a scan reads one bitmap word per position whatever k is. The slice
+// hash sums two 24-bit products, one per half of the slice (bytes o..o+2 and
+// o+3..o+5, little-endian), so it maps to full-rate 24-bit multiplies on the
+// device; the multipliers are the top 24 bits of the 32-bit golden-ratio
+// constant 0x9E3779B9 (Knuth's multiplicative hashing) and of MurmurHash3's
+// finalizer multiplier 0x85EBCA6B, made odd. A slice hash h names bit
+// (h >> (32 - B)) & 31 of 32-bit word h >> (37 - B) of a 2^B-bit bitmap.
+constexpr uint32_t kSliceK1 = 0x9E3779u;
+constexpr uint32_t kSliceK2 = 0x85EBCBu;
+constexpr int kSliceBytes = 6;
+constexpr int kSliceStride = 2;
+constexpr int kSliceMaxK = 8;
+__host__ __device__ inline uint32_t slice_hash(uint32_t lo, uint32_t hi) {
+    return (hi & 0xFFFFFFu) * kSliceK2 + (lo & 0xFFFFFFu) * kSliceK1;
+}
+
+// Word filter in front of the probe slots of the one-probe dense mode: a
+// blocked Bloom filter of 2^F 64-bit words over the distinct patterns' window
+// hashes h (window_hash). Pattern h sets, in word h >> (32 - F), the bits
+// word_filter_mask(h): kWordFilterBits 6-bit fields of h times the 32-bit
+// golden-ratio constant. A start whose hash fails it matches no pattern, so
+// its verification costs one 8-byte load instead of a walk over the slots.
+constexpr int kWordFilterBits = 5;
+__host__ __device__ inline uint64_t word_filter_mask(uint32_t h) {
+    const uint32_t x = h * 0x9E3779B1u;
+    uint64_t m = 0;
+    for (int j = 0; j < kWordFilterBits; ++j) m |= 1ull << ((x >> (6 * j)) & 63u);
+    return m;
+}
+
 // Everything a scan needs on the device. Plain pointers into one allocation.
 struct DeviceTables {
     uint8_t *base = nullptr;        // the single allocation
@@ -124,6 +159,8 @@ struct DeviceTables {
     const uint32_t *ids = nullptr;     // r
     const uint32_t *bloom = nullptr;   // 2^bloom_log2 bits
     const uint32_t *bloom_batch = nullptr;  // 2^min(bloom_log2, kBloomBatchLog2) bits
+    const uint32_t *slices = nullptr;  // 2^bloom_log2 bits of the one-probe dense mode
+    const uint64_t *wfilter = nullptr; // 2^wf_bits words: the word filter (one-probe dense mode)
     const uint32_t *pwoff = nullptr;   // unequal lengths: word offset of each distinct pattern
     const uint32_t *plen = nullptr;    //   its length
     const uint32_t *gstart = nullptr;  //   first distinct pattern of each prefix group (+ end)
@@ -182,6 +219,14 @@ struct mag_plan {
     std::vector<uint32_t> pwoff, plen, gstart;
     uint64_t verify_buffer = 0;      // deferred-start buffer entries (0: sized per scan)
     std::vector<uint32_t> bloom, bloom_batch;
+    // one-probe dense mode: slice_k slices per distinct pattern in a bitmap of
+    // 2^bloom_log2 bits (slice_k = 0: the dense mode uses the Bloom bitmap)
+    int dense_probe = MAG_DENSE_PROBE_AUTO;
+    int slice_k = 0;
+    double slice_fp = 0.0;           // estimated share of start positions it passes
+    std::vector<uint32_t> slices;
+    int wf_bits = 0;                 // log2 words of the word filter (0: none)
+    std::vector<uint64_t> wfilter;
 
     // device side
     std::mutex mtx;

@@ -284,6 +284,63 @@ void build_bloom(mag_plan *p) {
     }
 }
 
+// One-probe dense bitmap (slice_hash): built when the patterns are at least
+// kSliceBytes long and their bytes carry enough entropy that a 6-byte slice
+// spreads over the bitmap (6 H >= B + 4 bits, H the byte entropy of the
+// pattern set). k = ln 2 * 2^B / (distinct patterns) slices, the Bloom
+// optimum, within [1, kSliceMaxK] and the slices that fit in m bytes.
+void build_slices(mag_plan *p, int dense_probe) {
+    p->slice_k = 0;
+    p->slice_fp = 0.0;
+    p->slices.clear();
+    p->wf_bits = 0;
+    p->wfilter.clear();
+    if (dense_probe == MAG_DENSE_PROBE_BLOOM || p->m < (uint32_t)kSliceBytes || p->n_unique == 0)
+        return;
+    const int B = p->bloom_log2;
+    if (dense_probe != MAG_DENSE_PROBE_SLICES) {
+        double hist[256] = {0};
+        for (uint8_t c : p->patterns) hist[c] += 1.0;
+        double H = 0.0;
+        for (double c : hist)
+            if (c > 0) {
+                const double f = c / (double)p->patterns.size();
+                H -= f * std::log2(f);
+            }
+        if (kSliceBytes * H < B + 4.0) return;
+    }
+    const int kmax = std::min<int>(kSliceMaxK, ((int)p->m - kSliceBytes) / kSliceStride + 1);
+    int k = (int)std::lround(std::log(2.0) * (double)(1ull << B) / (double)p->n_unique);
+    k = std::max(1, std::min(k, kmax));
+    p->slice_k = k;
+    p->slices.assign((1u << B) / 32, 0u);
+    uint8_t buf[kMaxM + 8];
+    for (uint32_t u = 0; u < p->n_unique; ++u) {
+        std::memset(buf, 0, sizeof(buf));
+        std::memcpy(buf, &p->pwords[(size_t)u * p->mw], p->m);
+        for (int j = 0; j < k; ++j) {
+            const uint8_t *s = buf + kSliceStride * j;
+            const uint32_t lo = s[0] | (uint32_t)s[1] << 8 | (uint32_t)s[2] << 16;
+            const uint32_t hi = s[3] | (uint32_t)s[4] << 8 | (uint32_t)s[5] << 16;
+            const uint32_t h = slice_hash(lo, hi);
+            p->slices[h >> (37 - B)] |= 1u << ((h >> (32 - B)) & 31u);
+        }
+    }
+    uint64_t set = 0;
+    for (uint32_t w : p->slices) set += (uint64_t)__builtin_popcount(w);
+    p->slice_fp = std::pow((double)set / (double)(1ull << B), (double)k);
+    // the word filter over the window hashes: about one pattern per word
+    int F = 6;
+    while (F < 30 && (1ull << F) < p->n_unique) ++F;
+    p->wf_bits = F;
+    p->wfilter.assign(1ull << F, 0ull);
+    const int hw = std::min<int>(p->mw, kHashWords);
+    for (uint32_t u = 0; u < p->n_unique; ++u) {
+        const uint32_t h = window_hash(&p->pwords[(size_t)u * p->mw], hw);
+        p->wfilter[h >> (32 - F)] |= word_filter_mask(h);
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -386,6 +443,12 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
         return fail(MAG_E_INVALID, "unknown verify");
     if (prm.verify_buffer < 0) return fail(MAG_E_INVALID, "verify_buffer must be >= 0");
     if (prm.encode != 0 && prm.encode != 1) return fail(MAG_E_INVALID, "encode must be 0 or 1");
+    if (prm.dense_probe < MAG_DENSE_PROBE_AUTO || prm.dense_probe > MAG_DENSE_PROBE_BLOOM)
+        return fail(MAG_E_INVALID, "unknown dense_probe");
+    if (prm.dense_probe == MAG_DENSE_PROBE_SLICES && m < (uint32_t)kSliceBytes)
+        return fail(MAG_E_INVALID, "the one-probe dense bitmap needs m >= 6");
+    if (prm.chunk_bytes != 0 || prm.words_per_lane != 0)
+        return fail(MAG_E_UNSUPPORTED, "chunk_bytes and words_per_lane must be 0");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
 
     p->r = r;
@@ -475,6 +538,8 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     build_table(p);
     build_verifier(p);
     build_bloom(p);
+    build_slices(p, prm.dense_probe);
+    p->dense_probe = prm.dense_probe;
     p->mode = prm.mode;
     p->verify = prm.verify;
     p->verify_buffer = (uint64_t)prm.verify_buffer;

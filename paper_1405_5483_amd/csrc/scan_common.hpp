@@ -170,6 +170,28 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
     verify_wave(args, i0, active);
 }
 
+// verify_one with the keys of inline verification collected in the wave's
+// LDS buffer fbuf (holding fbn keys; see emit_found_buffered); returns the
+// new count. Deferred and unequal-length scans take verify_one's path.
+__device__ static __attribute__((noinline)) uint32_t verify_one_buffered(const VerifyArgs *v, uint64_t i0,
+                                                                         bool active, uint64_t *fbuf,
+                                                                         uint32_t fbn) {
+    VerifyArgs args;
+    __builtin_memcpy(&args, v, sizeof(args));
+    if (args.pending || args.var) {
+        verify_one(v, i0, active);
+        return fbn;
+    }
+    return emit_found_buffered(args, i0, active ? find_pattern(args, i0) : 0u, fbuf, fbn);
+}
+
+__device__ static __attribute__((noinline)) void flush_found_args(const VerifyArgs *v, const uint64_t *fbuf,
+                                                                  uint32_t fbn) {
+    VerifyArgs args;
+    __builtin_memcpy(&args, v, sizeof(args));
+    flush_found(args, fbuf, fbn);
+}
+
 // Verifies the 64 start positions queue[from .. from+64) of this wave, one per
 // lane. The queue is written by other lanes of the same wave.
 __device__ __forceinline__ void drain64(const VerifyArgs *v, const uint64_t *queue, uint32_t from,

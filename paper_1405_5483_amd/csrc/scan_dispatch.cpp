@@ -58,6 +58,8 @@ VerifyArgs make_verify_args(const mag_plan *p, const ScanLaunch &s) {
     v.pwoff = p->dev.pwoff;
     v.plen = p->dev.plen;
     v.gstart = p->dev.gstart;
+    v.wfilter = p->dev.wfilter;
+    v.wf_shift = p->wf_bits ? 32u - (uint32_t)p->wf_bits : 0u;
     return v;
 }
 

@@ -36,6 +36,9 @@ struct VerifyArgs {
     uint64_t n;                // text bytes
     const uint32_t *pwoff, *plen, *gstart;
     uint32_t var, pad2_;
+    // word filter in front of the probe slots (NULL: none): words wfilter[h >> wf_shift]
+    const uint64_t *wfilter;
+    uint32_t wf_shift, pad3_;
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
@@ -113,6 +116,11 @@ __device__ inline uint32_t find_pattern(const VerifyArgs &a, uint64_t i0) {
         hv[t] = x;
     }
     const uint32_t h = window_hash(hv, (int)a.hw);
+    if (a.wfilter) {
+        // a hash that fails the word filter is no pattern's: one load decides
+        const uint64_t mask = word_filter_mask(h);
+        if ((a.wfilter[h >> a.wf_shift] & mask) != mask) return 0;
+    }
     uint32_t slot = h >> a.slot_shift;
     for (;;) {
         const uint64_t e = a.slots[slot];
@@ -231,12 +239,19 @@ __device__ inline void verify_wave_var(const VerifyArgs &a, uint64_t i0, bool ac
 // counter. With all 64 lanes executing (the scan kernels call it so) a wave
 // prefix sum gives each lane its slots at once; otherwise round t writes the
 // t-th id of each lane's run of equal patterns, from ballots only.
+__device__ inline void emit_found(const VerifyArgs &a, uint64_t i0, uint32_t u1);
+
 __device__ inline void verify_wave(const VerifyArgs &a, uint64_t i0, bool active) {
     if (a.var) {
         verify_wave_var(a, i0, active);
         return;
     }
-    const uint32_t u1 = active ? find_pattern(a, i0) : 0u;
+    emit_found(a, i0, active ? find_pattern(a, i0) : 0u);
+}
+
+// Emits every id of distinct pattern u1 - 1 (none for u1 = 0) at start i0,
+// reserving output room with one atomic add per wave.
+__device__ inline void emit_found(const VerifyArgs &a, uint64_t i0, uint32_t u1) {
     uint32_t b = 0, c = 0;
     if (u1) {
         b = a.idstart[u1 - 1];
@@ -277,6 +292,63 @@ __device__ inline void verify_wave(const VerifyArgs &a, uint64_t i0, bool active
             if (at < a.cap) a.keys[at] = emit | (uint64_t)a.ids[b + t];
         }
     }
+}
+
+// Per-wave buffering of output keys (the one-probe dense mode, whose waves
+// find matches in most of their verification rounds): a wave collects its
+// keys in an LDS buffer of kFoundBuf keys and writes them to the output with
+// one atomic add per buffer, instead of one contended atomic add on the
+// output counter per round. All 64 lanes call these.
+constexpr uint32_t kFoundBuf = 32;
+
+// Writes buf[0 .. n) (n wave-uniform) to the output.
+__device__ inline void flush_found(const VerifyArgs &a, const uint64_t *buf, uint32_t n) {
+    if (!n) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t lane = __lane_id();
+    unsigned long long got = 0;
+    if (lane == 0) got = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)n);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+    const uint64_t base = ((uint64_t)hi << 32) | lo;
+    for (uint32_t i = lane; i < n; i += 64)
+        if (base + i < a.cap) a.keys[base + i] = buf[i];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// emit_found into buf (holding fbn keys); returns the new count. Keys that do
+// not fit flush the buffer first; a round with more keys than the buffer
+// holds goes to the output directly.
+__device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0, uint32_t u1, uint64_t *buf,
+                                               uint32_t fbn) {
+    uint32_t b = 0, c = 0;
+    if (u1) {
+        b = a.idstart[u1 - 1];
+        c = a.idstart[u1] - b;
+    }
+    const uint32_t lane = __lane_id();
+    uint32_t inc = c;                         // inclusive prefix of c over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane >= (uint32_t)off) inc += o;
+    }
+    const uint32_t total = __shfl(inc, 63);
+    if (total == 0) return fbn;
+    if (fbn + total > kFoundBuf) {
+        flush_found(a, buf, fbn);
+        fbn = 0;
+    }
+    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    if (total > kFoundBuf) {
+        emit_found(a, i0, u1);
+        return 0;
+    }
+    const uint32_t at = fbn + inc - c;
+    for (uint32_t t = 0; t < c; ++t) buf[at + t] = emit | (uint64_t)a.ids[b + t];
+    return fbn + total;
 }
 
 }  // namespace mag

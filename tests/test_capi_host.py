@@ -326,6 +326,9 @@ def test_plan_params_round_trip():
     for sigma, r, m, kw in ((4, 50, 16, {}), (20, 200, 12, {"map_kind": "rank"}),
                             (64, 300, 32, {"q": 4, "k": 1, "sigma_prime": 16, "map_kind": "bits"}),
                             (20, 100, 16, {"map_kind": "qgram"}), (4, 2000, 8, {"mode": "dense"}),
+                            (20, 5000, 16, {"mode": "dense"}),
+                            (20, 5000, 16, {"mode": "dense", "dense_probe": "bloom"}),
+                            (4, 3000, 12, {"mode": "dense", "dense_probe": "slices"}),
                             (20, 40, 16, {"verify": "deferred", "encode": True})):
         P = rng.integers(0, sigma, size=(r, m), dtype=np.uint8)
         a = mag.Plan(P, **kw)
@@ -334,12 +337,37 @@ def test_plan_params_round_trip():
         b = mag.Plan(P, **prm)
         ia, ib = a.info(), b.info()
         for key in ("q", "k", "sigma_prime", "map_kind", "dense", "W", "m_prime", "entry_bits",
-                    "n_codes", "table_bytes", "bits_shift", "bloom_log2"):
+                    "n_codes", "table_bytes", "bits_shift", "bloom_log2", "dense_slices",
+                    "dense_pass"):
             assert ia[key] == ib[key], (kw, key, ia[key], ib[key])
         mu_a, tab_a = a.export(raw=True)
         mu_b, tab_b = b.export(raw=True)
         assert np.array_equal(mu_a, mu_b) and np.array_equal(tab_a, tab_b), kw
         assert b.params() == prm
+
+
+def test_dense_probe_choice():
+    """The dense mode's probe: slices for protein-like pattern bytes (6 H >= B
+    + 4 bits), the Bloom bitmap for DNA, k = round(ln 2 * 2^B / distinct
+    patterns) within [1, min(8, (m - 6) / 2 + 1)], and the estimated pass
+    share the slice bitmap's fill to the power k."""
+    import math
+    mag = _lib_or_skip()
+    rng = np.random.default_rng(7)
+    prot = rng.integers(0, 20, size=(100_000, 16), dtype=np.uint8) + 65
+    info = mag.Plan(prot, mode="dense").info()
+    n = len({bytes(r) for r in prot})
+    assert info["bloom_log2"] == 20
+    assert info["dense_slices"] == min(6, round(math.log(2) * 2 ** 20 / n)) == 6
+    assert 0.003 < info["dense_pass"] < 0.01          # fill about 0.43, to the 6th power
+    dna = rng.integers(0, 4, size=(5000, 16), dtype=np.uint8)
+    assert mag.Plan(dna, mode="dense").info()["dense_slices"] == 0
+    assert mag.Plan(dna, mode="dense", dense_probe="slices").info()["dense_slices"] >= 1
+    assert mag.Plan(prot, mode="dense", dense_probe="bloom").info()["dense_slices"] == 0
+    # m = 7: one slice fits at offset 0 only
+    assert mag.Plan(prot[:50, :7], mode="dense").info()["dense_slices"] == 1
+    with pytest.raises(mag.MagError):
+        mag.Plan(prot[:50, :5], mode="dense", dense_probe="slices")
 
 
 def test_scan_batch_and_params_argument_errors():

@@ -106,15 +106,19 @@ def test_parity_and_counts(torch_cuda, mag, case):
     assert st["matches"] == ref[0].size
 
 
+@pytest.mark.parametrize("probe", ["bloom", "slices"])
 @pytest.mark.parametrize("case", CASES, ids=[f"s{c[0]}-n{c[1]}-r{c[2]}-m{c[3]}" for c in CASES])
-def test_dense_mode_parity(torch_cuda, mag, case):
-    """Every start position through the Bloom bitmap: the same occurrence
-    list; every occurring position passes the bitmap."""
+def test_dense_mode_parity(torch_cuda, mag, case, probe):
+    """Every start position through the dense bitmap (three-probe Bloom, or
+    one probe per position into the slice bitmap): the same occurrence list;
+    every occurring position passes the bitmap."""
     sigma, n, r, m, q, k, sp, kind = case
     T = gen_text(n, sigma, dist="zipf" if sigma == 64 else "uniform", rng=n + r)
     P = gen_patterns(T, r, m, (3 * r) // 4, sigma, rng=r * 31 + m)
-    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="dense")
-    assert plan.info()["dense"] == 1
+    plan = mag.Plan(P, q=q, k=k, sigma_prime=sp, map_kind=kind, mode="dense", dense_probe=probe)
+    info = plan.info()
+    assert info["dense"] == 1
+    assert (info["dense_slices"] > 0) == (probe == "slices")
     pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
     ref = om.occ_hashed(T, P)
     _assert_same(pos, ids, ref)
@@ -162,6 +166,50 @@ def test_dense_tile_edges(torch_cuda, mag):
         for off in (0, 1, 2, 3):
             pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=off)
             _assert_same(pos, ids, ref)
+
+
+def test_dense_slice_tile_edges(torch_cuda, mag):
+    # the one-probe dense kernel takes 16,128 start positions per tile: 16
+    # waves of 63 owning lanes with 16 positions each (1,008 per wave), the
+    # 64th lane of a wave probing the next wave's first 16. Texts whose last
+    # start falls around lane, wave and tile boundaries, at every alignment,
+    # with patterns copied from around those boundaries, for every number of
+    # slices per pattern (k = 1 .. 6 for m = 16, forced by the pattern count)
+    m, tile, span = 16, 16128, 1008
+    T0 = gen_text(3 * tile + 64, 20, rng=93)
+    at = [0, 1, 15, 16, span - 17, span - 16, span - 1, span, span + 1, 2 * span - 1,
+          tile - 17, tile - 16, tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile, 2 * tile + 6]
+    base = np.stack([T0[u:u + m] for u in at])
+    seen = set()
+    # uniform extra patterns (all distinct): k = round(ln 2 * 2^20 / count)
+    for extra in (0, 140_000, 180_000, 250_000, 400_000, 800_000):
+        P = np.concatenate([base, gen_patterns(T0, extra, m, 0, 20, rng=94)]) if extra else base
+        plan = mag.Plan(P, mode="dense", dense_probe="slices")
+        k = plan.info()["dense_slices"]
+        seen.add(k)
+        for npos in (1, 17, span - 1, span, span + 1, tile - 1, tile, 2 * tile + 7):
+            T = T0[:npos + m - 1]
+            ref = om.occ_hashed(T, P)
+            for off in (0, 1, 2, 3):
+                pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=off)
+                _assert_same(pos, ids, ref)
+    assert seen == {1, 2, 3, 4, 5, 6}
+
+
+@pytest.mark.parametrize("m", [6, 7, 8, 9, 10, 13, 20, 32, 64])
+def test_dense_slice_lengths(torch_cuda, mag, m):
+    """Slices at offsets 0, 2, .. within m bytes: every length from the
+    shortest the slices allow, with occurrences planted near both ends."""
+    T = gen_text(70_001, 20, rng=95 + m)
+    P = gen_patterns(T, 400, m, 300, 20, rng=96 + m)
+    plan = mag.Plan(P, mode="dense", dense_probe="slices")
+    info = plan.info()
+    assert 1 <= info["dense_slices"] <= min(8, (m - 6) // 2 + 1)
+    Tm = np.concatenate([P[0], T, P[1]])
+    pos, ids, st = _gpu_occ(torch_cuda, mag, Tm, plan, stats=True)
+    ref = om.occ_hashed(Tm, P)
+    _assert_same(pos, ids, ref)
+    assert st["cand_windows"] >= np.unique(ref[0]).size
 
 
 def test_deferred_overflow_and_repeat(torch_cuda, mag):
