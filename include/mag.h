@@ -276,6 +276,24 @@ mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
                           mag_match *d_out, uint64_t out_cap, uint64_t *d_count,
                           mag_stats *d_stats, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * scan as mag_scan_async, with every scratch buffer (counters, sort keys,
+ * radix-sort counts, deferred-start buffer) in one static device array of
+ * 28 MiB per GPU instead of the plan's own scratch. It calls no hipMalloc,
+ * hipFree or other allocating routine. Limits: out_cap <= 2^20 records
+ * (else MAG_E_INVALID); at most 2^20 deferred starts are buffered (the rest
+ * are verified inline, so results never depend on it); SMAG plans compute
+ * their codes on the fly (same results). The plan's tables must already be
+ * on the current device: a plan is uploaded by its first mag_scan or
+ * mag_scan_async there (MAG_E_INVALID otherwise). The first call on a device
+ * looks up that device's copy of the array. Every call on a GPU shares that
+ * GPU's array and clears its counters first: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialized by the caller.
+ * Enqueued on `stream` without waiting; outputs as for mag_scan_async. */
+mag_status mag_scan_noalloc(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                            uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream);
+
 /* As mag_scan_async, then waits for the stream and returns the count in
  * *n_matches (host) and the counters in *stats (host, may be NULL). Returns
  * MAG_E_OVERFLOW when z > out_cap (with *n_matches = z). */

@@ -242,6 +242,18 @@ def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> Non
                                _stream_ptr(stream)), "mag_scan_async")
 
 
+def scan_noalloc(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> None:
+    """``scan_async`` through ``mag_scan_noalloc``: no device allocation, the
+    scratch in the library's static per-GPU array (out_cap at most 2^20; the
+    plan must have been scanned once on this device)."""
+    _check_text(text)
+    check(lib().mag_scan_noalloc(plan.handle, ctypes.c_void_p(text.data_ptr()), text.numel(),
+                                 ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                 ctypes.c_void_p(d_count.data_ptr()),
+                                 ctypes.c_void_p(d_stats.data_ptr()) if d_stats is not None else None,
+                                 _stream_ptr(stream)), "mag_scan_noalloc")
+
+
 class Batch:
     """Many (text, plan) jobs scanned in one persistent launch (``mag_batch_*``).
 

@@ -427,26 +427,44 @@ mag_status mag_plan_export(const mag_plan *p, uint8_t *mu_out, void *table_out, 
 namespace mag {
 namespace {
 // Enqueues counter reset, scan and finishing kernel; returns the key layout.
+// fixed: scratch laid out in advance (the allocation-free entry point): the
+// plan must already be resident on the current device, nothing is
+// allocated, deferred starts beyond fixed->pending_cap are verified inline,
+// SMAG plans compute their codes on the fly, and no profiling events are
+// recorded.
 mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                         uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream_,
-                        bool device_sort, int *idbits_out, int *nbits_out) {
+                        bool device_sort, int *idbits_out, int *nbits_out, Scratch *fixed = nullptr) {
     if (!p) return fail(MAG_E_INVALID, "plan is NULL");
     if (!d_count) return fail(MAG_E_INVALID, "d_count is NULL");
     if (n && !d_text) return fail(MAG_E_INVALID, "d_text is NULL");
     if (out_cap && !d_out) return fail(MAG_E_INVALID, "d_out is NULL");
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
     std::lock_guard<std::mutex> lock(p->mtx);
-    mag_status s = ensure_device(p);
-    if (s != MAG_OK) return s;
-    s = ensure_keys(p, out_cap, stream);
-    if (s != MAG_OK) return s;
+    mag_status s = MAG_OK;
     // without the host reading the count, large outputs are sorted by
     // kernels sized for the capacity
     const bool sort_on_device = device_sort && out_cap > small_sort_max();
-    if (sort_on_device) {
-        s = ensure_radix_scratch(p->scratch, out_cap, stream);
+    if (fixed) {
+        int dev = 0;
+        const hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (p->device != dev)
+            return fail(MAG_E_INVALID, "plan tables are not on this device (scan the plan once with "
+                                       "mag_scan_async first)");
+        if (out_cap > fixed->keys_cap)
+            return fail(MAG_E_INVALID, "out_cap above the allocation-free scan's limit");
+    } else {
+        s = ensure_device(p);
         if (s != MAG_OK) return s;
+        s = ensure_keys(p, out_cap, stream);
+        if (s != MAG_OK) return s;
+        if (sort_on_device) {
+            s = ensure_radix_scratch(p->scratch, out_cap, stream);
+            if (s != MAG_OK) return s;
+        }
     }
+    Scratch &sc = fixed ? *fixed : p->scratch;
 
     const int idbits = ceil_log2(p->r > 1 ? p->r : 2);
     const int posbits = ceil_log2(n + 1 > 2 ? n + 1 : 2);
@@ -478,7 +496,9 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     if (samples && defer)
         pcap = p->verify_buffer ? p->verify_buffer
                                 : pending_capacity(expect < 0.0 ? expect : std::max(expect, (double)(1 << 20)));
-    if (pcap) {
+    if (pcap && fixed) {
+        pcap = std::min(pcap, fixed->pending_cap);
+    } else if (pcap) {
         s = ensure_pending(p, pcap, stream);
         if (s != MAG_OK) return s;
     }
@@ -486,14 +506,14 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     ScanLaunch sl;
     sl.text = d_text;
     sl.n = n;
-    sl.keys = p->scratch.keys;
+    sl.keys = sc.keys;
     sl.cap = out_cap;
-    sl.counters = p->scratch.counters;
+    sl.counters = sc.counters;
     sl.idbits = idbits;
-    sl.pending = pcap ? p->scratch.pending : nullptr;
-    sl.pending_cap = pcap ? p->scratch.pending_cap : 0;
-    sl.seg_count = pcap ? p->scratch.seg_count : nullptr;
-    const bool smag = p->encode && !p->dense && p->r && n >= (uint64_t)p->q;
+    sl.pending = pcap ? sc.pending : nullptr;
+    sl.pending_cap = pcap ? (fixed ? pcap : sc.pending_cap) : 0;
+    sl.seg_count = pcap ? sc.seg_count : nullptr;
+    const bool smag = !fixed && p->encode && !p->dense && p->r && n >= (uint64_t)p->q;
     if (smag) {
         sl.csz = encoded_code_bytes(p);
         // 16 bytes of slack: phase A reads the 32-bit word holding each code
@@ -502,8 +522,8 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         sl.codes = p->scratch.codes;
     }
     ProfileRecord rec{{nullptr, nullptr, nullptr}};
-    bool prof;
-    {
+    bool prof = false;
+    if (!fixed) {
         std::lock_guard<std::mutex> pl(g_prof_mtx);
         prof = g_prof_on;
     }
@@ -522,7 +542,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         da.n = n;
         da.last = (int64_t)n - (int64_t)p->m;
         da.bshift = 32u - (uint32_t)p->bloom_log2;
-        da.counters = p->scratch.counters;
+        da.counters = sc.counters;
         da.v = make_verify_args(p, sl);
         if (slices) {
             da.ntiles = samples ? (samples + kSliceScanTile - 1) / kSliceScanTile : 0;
@@ -544,13 +564,12 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     if (prof) (void)hipEventRecord(rec.ev[1], stream);
     if (idbits_out) *idbits_out = idbits;
     if (nbits_out) *nbits_out = idbits + posbits;
-    s = launch_finish(p->scratch, out_cap, samples, d_count, d_stats, d_out, idbits, ~0ull, nullptr,
-                      stream);
+    s = launch_finish(sc, out_cap, samples, d_count, d_stats, d_out, idbits, ~0ull, nullptr, stream);
     if (s != MAG_OK) return s;
     if (sort_on_device) {
-        s = launch_radix_sort(p->scratch, out_cap, out_cap, idbits + posbits, stream);
+        s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, stream);
         if (s == MAG_OK)
-            s = launch_expand(p->scratch, out_cap, out_cap, idbits + posbits, d_out, idbits, ~0ull, stream);
+            s = launch_expand(sc, out_cap, out_cap, idbits + posbits, d_out, idbits, ~0ull, stream);
         if (s != MAG_OK) return s;
     }
     if (prof) {
@@ -562,9 +581,92 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
 }
 
 }  // namespace
+
+// ---- the allocation-free scan (mag_scan_noalloc) ----
+// Its scratch is one static device array per GPU; `scratch` below is only a
+// host-side stand-in for it, so host code uses the per-device address from
+// hipGetSymbolAddress instead (noalloc_base).
+constexpr uint64_t kNoAllocCap = 1ull << 20;       // largest out_cap
+constexpr uint64_t kNoAllocPending = 1ull << 20;   // deferred starts it holds (more: inline)
+constexpr uint64_t kNoAllocBytes = 28ull << 20;
+
+}  // namespace mag
+
+static __device__ __align__(256) uint8_t scratch[mag::kNoAllocBytes];
+
+namespace mag {
+namespace {
+
+std::mutex g_noalloc_mtx;
+std::map<int, uint8_t *> g_noalloc_base;
+
+// The current device's copy of `scratch`, looked up once per device.
+mag_status noalloc_base(int dev, uint8_t **out) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mtx);
+    const auto it = g_noalloc_base.find(dev);
+    if (it != g_noalloc_base.end()) {
+        *out = it->second;
+        return MAG_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress of the allocation-free scratch");
+    g_noalloc_base[dev] = static_cast<uint8_t *>(ptr);
+    *out = static_cast<uint8_t *>(ptr);
+    return MAG_OK;
+}
+
+uint64_t round256(uint64_t v) { return (v + 255) & ~255ull; }
+
+// Lays the scan's scratch out in the static array at `base`: counters and
+// segment counters, the two key buffers, the radix sort's counts and
+// offsets, and the deferred-start buffer.
+mag_status noalloc_layout(uint8_t *base, int dev, Scratch &sc) {
+    const uint64_t C = radix_scratch_chunks(kNoAllocCap);
+    const uint64_t o_cnt = 0;
+    const uint64_t o_keys = round256((16 + kPendingSegments) * sizeof(uint64_t));
+    const uint64_t o_hist = round256(o_keys + 2 * kNoAllocCap * sizeof(uint64_t));
+    const uint64_t o_off = round256(o_hist + 256 * C * sizeof(uint32_t));
+    const uint64_t o_pend = round256(o_off + (256 * C + 256) * sizeof(uint64_t));
+    const uint64_t end = o_pend + kNoAllocPending * sizeof(uint64_t);
+    if (end > kNoAllocBytes) return fail(MAG_E_UNSUPPORTED, "allocation-free scratch layout too large");
+    sc.device = dev;
+    sc.counters = reinterpret_cast<uint64_t *>(base + o_cnt);
+    sc.seg_count = sc.counters + 16;
+    sc.keys = reinterpret_cast<uint64_t *>(base + o_keys);
+    sc.keys_cap = kNoAllocCap;
+    sc.hist = reinterpret_cast<uint32_t *>(base + o_hist);
+    sc.radix_off = reinterpret_cast<uint64_t *>(base + o_off);
+    sc.radix_chunks = C;
+    sc.pending = reinterpret_cast<uint64_t *>(base + o_pend);
+    sc.pending_cap = kNoAllocPending;
+    return MAG_OK;
+}
+
+}  // namespace
 }  // namespace mag
 
 extern "C" {
+
+mag_status mag_scan_noalloc(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d_out,
+                            uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream) {
+    if (!p) return fail(MAG_E_INVALID, "plan is NULL");
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (out_cap > kNoAllocCap) return fail(MAG_E_INVALID, "out_cap above the allocation-free scan's limit (2^20)");
+    uint8_t *base = nullptr;
+    mag_status s = noalloc_base(dev, &base);
+    if (s != MAG_OK) return s;
+    Scratch sc;
+    s = noalloc_layout(base, dev, sc);
+    if (s != MAG_OK) return s;
+    // the counters and segment counters start at zero, whatever an earlier
+    // call left (a fill kernel, so that the call can be captured in a graph)
+    s = launch_fill_u64(sc.counters, 16 + kPendingSegments, 0, reinterpret_cast<hipStream_t>(stream));
+    if (s != MAG_OK) return s;
+    return scan_enqueue(p, d_text, n, d_out, out_cap, d_count, d_stats, stream, true, nullptr, nullptr, &sc);
+}
 
 mag_status mag_encode(mag_plan *p, const uint8_t *d_text, uint64_t n, uint32_t *d_codes,
                       uint64_t cap, uint64_t *n_codes, void *stream) {

@@ -317,6 +317,9 @@ mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *
 // with grids sized for counts up to `bound`: the scratch for `bound`, the
 // passes over the nbits low key bits, and the records.
 mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream);
+// Chunks of the device-wide radix sort's counts for outputs of up to `bound`
+// keys (its scratch: 256 * chunks u32 counts, 256 * chunks + 256 u64 offsets).
+uint64_t radix_scratch_chunks(uint64_t bound);
 mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, hipStream_t stream);
 mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, mag_match *out,
                          int idbits, uint64_t posmask, hipStream_t stream);

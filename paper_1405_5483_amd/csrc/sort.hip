@@ -387,6 +387,8 @@ uint32_t radix_grid(uint64_t bound) {
 
 }  // namespace
 
+uint64_t radix_scratch_chunks(uint64_t bound) { return radix_chunks(bound); }
+
 mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStream_t stream) {
     if (!count) return MAG_OK;
     uint64_t blocks = (count + 255) / 256;
