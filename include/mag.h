@@ -317,6 +317,14 @@ void mag_batch_destroy(mag_batch *batch);
 mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const uint64_t *n,
                           uint64_t out_cap, void *stream);
 
+/* The batched kernel's tile shape (the batch autotuner's knob): each lane's
+ * Shift-Or run takes words_per_lane samples (8, 16 or 32), so filter jobs are
+ * cut into tiles of 512 * words_per_lane samples (a tile is one workgroup's
+ * unit of work in the persistent launch); dense jobs always take tiles of
+ * 8192 start positions. Default 16. Takes effect at the next mag_batch_bind.
+ * Errors: other values -> MAG_E_INVALID. */
+mag_status mag_batch_set_words_per_lane(mag_batch *batch, int32_t words_per_lane);
+
 /* Scans every bound job in one persistent launch and sorts the output, all
  * enqueued on `stream` without host synchronization or allocation (so the
  * sequence can be captured in a hipGraph and replayed). Occurrences land in
@@ -431,31 +439,62 @@ typedef struct {
     int32_t max_k;        /* largest k tried; 0 = 8                                  */
     int64_t table_budget; /* largest mask table in bytes; 0 = 64 KiB (LDS-resident)  */
     int32_t repeats;      /* timed scans per candidate (median); 0 = 3               */
-    int32_t max_candidates; /* cap on candidates timed, best predicted first; 0 = 64 */
-    int32_t reserved[4];  /* must be zero                                            */
+    int32_t max_candidates; /* cap on filter candidates timed, best predicted
+                               first; 0 = 64                                        */
+    int32_t modes;        /* bit 0: filter, bit 1: dense (timed beside the filter
+                             candidates); 0 = both                                  */
+    int32_t fixed_tiles;  /* 1: keep the default tile shape (no words-per-lane
+                             timing)                                                */
+    int32_t batch_only;   /* 1: only parameters batches accept (W = k*m' <= 32)      */
+    int32_t reserved;     /* must be zero                                            */
 } mag_tune_opts;
 
-/* Autotuner: picks (q, k, sigma', map) for a pattern set by timing the scan on
- * a device-resident text sample d_sample[0..n_sample). Candidates are every q
- * with 2q-1 <= m, k <= L, reduced alphabet sizes from 2 to sigma_P and both
- * maps whose mask table fits the budget; they are ranked by a density
- * estimate (superimposed classes of Section 2: expected verifications per
- * sample) plus the sampling cost, and the best-ranked ones are timed. Any
- * choice returns exactly the same occurrences (the filter only prunes); the
- * pick only changes the time. *best receives explicit parameters
- * (select = MAG_SELECT_EXPLICIT) and *best_ms the median scan time of the
- * sample (either may be NULL). Uses the device and stream like mag_scan. */
+/* Autotuner: picks the mode, (q, k, sigma', map) and the tile shape for a
+ * pattern set by timing the scan on a device-resident text sample
+ * d_sample[0..n_sample) (the choice of q and k is Section 3.2's trade-off,
+ * settled by measurement instead of its formulas). Filter candidates are
+ * every q with 2q-1 <= m, k <= L, reduced alphabet sizes from 2 to sigma_P
+ * and both maps whose mask table fits the budget; they are ranked by a
+ * density estimate (superimposed classes of Section 2: expected
+ * verifications per sample) plus the sampling cost, and the best-ranked ones
+ * are timed with mode = MAG_MODE_FILTER, beside the dense mode. The winner's
+ * words_per_lane is then timed at half and 1.5 times its default (filter)
+ * or at 32 (dense) and kept on a gain of 3% or more. Any choice returns
+ * exactly the same occurrences (the filter only prunes); the pick only
+ * changes the time. *best receives explicit parameters (select =
+ * MAG_SELECT_EXPLICIT, mode filter or dense) and *best_ms the median scan
+ * time of the sample (either may be NULL). Uses the device and stream like
+ * mag_scan. */
 mag_status mag_autotune(const uint8_t *patterns, uint32_t r, uint32_t m,
                         const mag_tune_opts *opts, const uint8_t *d_sample, uint64_t n_sample,
                         mag_params *best, float *best_ms, void *stream);
 
-/* Kernel timing for benchmarks. While enabled (process-wide), every scan
- * records HIP events on its own stream around each of its two kernels: the
- * scan kernel (filter with fused exact verification) and the finishing kernel
- * (count, counters and sorted output). mag_profile_read waits for the recorded
- * events, stores their summed elapsed times in milliseconds, sets *launches to
- * the number of scans measured, and clears the record. Enabling adds three
- * event records per scan; disabled by default. */
+/* Batch autotuner (the batched scans' "chunk size, q and k"): jobs are
+ * grouped into classes by pattern length, distinct pattern bytes and
+ * log2(r), and mag_autotune (with opts) times candidates for each class on a
+ * sample of its largest job's text (at most sample_bytes, 0 = 4 MiB);
+ * params[j] (host, njobs entries) receives the pick for job j's class. Then
+ * the whole batch, planned with those parameters, is timed with 8, 16 and 32
+ * words per lane (tiles of 512 times that many samples) and the fastest goes
+ * to *words_per_lane. jobs[j].plan is ignored (may be NULL); the patterns
+ * come from pat[j] (host, r[j] * m[j] bytes). Allocates and waits; not for
+ * graph capture. Errors: NULL arrays -> MAG_E_INVALID; errors of
+ * mag_autotune or the batch calls. */
+mag_status mag_autotune_batch(const mag_job *jobs, const uint8_t *const *pat, const uint32_t *r,
+                              const uint32_t *m, uint32_t njobs, const mag_tune_opts *opts,
+                              uint64_t sample_bytes, mag_params *params, int32_t *words_per_lane,
+                              void *stream);
+
+/* Kernel timing for benchmarks. While enabled (process-wide), every scan and
+ * every mag_batch_run_async records HIP events on its own stream: before its
+ * scan kernel (the filter or dense kernel with fused exact verification; the
+ * batched kernel), after it, and after the scan's last kernel (deferred
+ * verification, finishing kernel, sort, batch offsets). mag_profile_read
+ * waits for the recorded events, stores their summed elapsed times in
+ * milliseconds (scan kernel; the rest), sets *launches to the number of scans
+ * measured, and clears the record. Nothing is recorded on a stream that is
+ * being captured. Enabling adds three event records per scan; disabled by
+ * default. */
 mag_status mag_profile_enable(int enable);
 mag_status mag_profile_read(double *scan_ms, double *finish_ms, uint64_t *launches);
 

@@ -63,7 +63,8 @@ class Plan:
                  k: int | None = None, sigma_prime: int | None = None,
                  map_kind: str = "greedy", table_budget: int = 0, mode: str = "auto",
                  verify: str = "auto", verify_buffer: int = 0, encode: bool = False,
-                 dense_probe: str = "auto", candidate: int | None = None):
+                 dense_probe: str = "auto", chunk_bytes: int = 0, words_per_lane: int = 0,
+                 candidate: int | None = None):
         var = _unequal(patterns)
         if var is None:
             p = _as_patterns(patterns)
@@ -87,6 +88,8 @@ class Plan:
         prm.verify_buffer = int(verify_buffer)
         prm.encode = 1 if encode else 0
         prm.dense_probe = DENSE_PROBE[dense_probe]
+        prm.chunk_bytes = int(chunk_bytes)
+        prm.words_per_lane = int(words_per_lane)
         handle = ctypes.c_void_p()
         self._h = None
         if var is None:
@@ -120,7 +123,8 @@ class Plan:
                 "q": prm.q, "k": prm.k, "sigma_prime": prm.sigma_prime,
                 "mode": inv(MODE, prm.mode), "verify": inv(VERIFY, prm.verify),
                 "verify_buffer": prm.verify_buffer, "encode": bool(prm.encode),
-                "dense_probe": inv(DENSE_PROBE, prm.dense_probe)}
+                "dense_probe": inv(DENSE_PROBE, prm.dense_probe), "chunk_bytes": prm.chunk_bytes,
+                "words_per_lane": prm.words_per_lane}
 
     def export(self, raw: bool = False):
         """(mu [256] uint8, mask table with one entry per code in the entry
@@ -263,7 +267,7 @@ class Batch:
     no host synchronization or allocation, so it can be captured in a graph.
     """
 
-    def __init__(self, plans):
+    def __init__(self, plans, words_per_lane: int = 0):
         self.plans = list(plans)          # the library keeps raw pointers to them
         arr = (ctypes.c_void_p * max(len(self.plans), 1))(
             *[p.handle.value for p in self.plans])
@@ -274,6 +278,14 @@ class Batch:
         self._h = handle
         self.texts = []
         self.out_cap = 0
+        if words_per_lane:
+            self.set_words_per_lane(words_per_lane)
+
+    def set_words_per_lane(self, words_per_lane: int) -> None:
+        """Filter tiles of 512 * words_per_lane samples (8, 16 or 32); takes
+        effect at the next bind."""
+        check(lib().mag_batch_set_words_per_lane(self.handle, int(words_per_lane)),
+              "mag_batch_set_words_per_lane")
 
     @property
     def njobs(self) -> int:
@@ -391,24 +403,66 @@ def profile_read() -> dict:
 _MAP_NAME = {v: k for k, v in MAP_KIND.items()}
 
 
-def autotune(patterns, sample, *, map_kinds: int = 0, max_q: int = 0, max_k: int = 0,
-             table_budget: int = 0, repeats: int = 0, max_candidates: int = 0, stream=None) -> dict:
-    """Parameters picked by ``mag_autotune`` from scans of ``sample`` (a uint8
-    CUDA tensor): dict with q, k, sigma_prime, map_kind and the sample's median
-    scan time in ms. Pass the dict's parameters to :class:`Plan`."""
-    p = _as_patterns(patterns)
-    _check_text(sample)
+def _tune_opts(map_kinds=0, max_q=0, max_k=0, table_budget=0, repeats=0, max_candidates=0,
+               modes=0, fixed_tiles=False):
     o = MagTuneOpts()
     o.map_kinds, o.max_q, o.max_k = map_kinds, max_q, max_k
     o.table_budget, o.repeats, o.max_candidates = table_budget, repeats, max_candidates
+    o.modes, o.fixed_tiles = modes, int(bool(fixed_tiles))
+    return o
+
+
+def _plan_kwargs(prm: MagParams) -> dict:
+    """Plan keyword arguments of explicit parameters returned by the library."""
+    inv = lambda d, v: next(name for name, code in d.items() if code == v)
+    return {"q": prm.q, "k": prm.k, "sigma_prime": prm.sigma_prime, "map_kind": _MAP_NAME[prm.map_kind],
+            "mode": inv(MODE, prm.mode), "words_per_lane": prm.words_per_lane}
+
+
+def autotune(patterns, sample, *, stream=None, **opts) -> dict:
+    """Parameters picked by ``mag_autotune`` from scans of ``sample`` (a uint8
+    CUDA tensor): dict of :class:`Plan` keyword arguments (q, k, sigma_prime,
+    map_kind, mode, words_per_lane) plus the sample's median scan time in ms
+    (``sample_ms``, not a Plan argument). Options: map_kinds, max_q, max_k,
+    table_budget, repeats, max_candidates, modes, fixed_tiles."""
+    p = _as_patterns(patterns)
+    _check_text(sample)
+    o = _tune_opts(**opts)
     best = MagParams()
     ms = ctypes.c_float(0.0)
     check(lib().mag_autotune(p.ctypes.data if p.size else None, p.shape[0], p.shape[1],
                              ctypes.byref(o), ctypes.c_void_p(sample.data_ptr()), sample.numel(),
                              ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)),
           "mag_autotune")
-    return {"q": best.q, "k": best.k, "sigma_prime": best.sigma_prime,
-            "map_kind": _MAP_NAME[best.map_kind], "sample_ms": ms.value}
+    return {**_plan_kwargs(best), "sample_ms": ms.value}
+
+
+def autotune_batch(patterns, texts, *, sample_bytes: int = 0, stream=None, **opts):
+    """``mag_autotune_batch``: per-job Plan keyword arguments (one tuned pick
+    per job class) and the batched kernel's words per lane, for jobs given as
+    pattern arrays and uint8 CUDA text tensors. Returns (list of dicts,
+    words_per_lane)."""
+    pats = [_as_patterns(p) for p in patterns]
+    texts = list(texts)
+    if len(pats) != len(texts):
+        raise ValueError("one text per pattern set")
+    for t in texts:
+        _check_text(t)
+    nj = len(pats)
+    jobs = (MagJob * max(nj, 1))()
+    for j, t in enumerate(texts):
+        jobs[j].plan = None
+        jobs[j].d_text = t.data_ptr() or None
+        jobs[j].n = t.numel()
+    pp = (ctypes.c_void_p * max(nj, 1))(*[p.ctypes.data if p.size else None for p in pats])
+    rr = (ctypes.c_uint32 * max(nj, 1))(*[p.shape[0] for p in pats])
+    mm = (ctypes.c_uint32 * max(nj, 1))(*[p.shape[1] for p in pats])
+    out = (MagParams * max(nj, 1))()
+    wpl = ctypes.c_int32(0)
+    o = _tune_opts(**opts)
+    check(lib().mag_autotune_batch(jobs, pp, rr, mm, nj, ctypes.byref(o), int(sample_bytes), out,
+                                   ctypes.byref(wpl), _stream_ptr(stream)), "mag_autotune_batch")
+    return [_plan_kwargs(out[j]) for j in range(nj)], wpl.value
 
 
 # ------------------------------------------------------------------ learned selection

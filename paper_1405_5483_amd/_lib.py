@@ -73,7 +73,9 @@ class MagTuneOpts(ctypes.Structure):
     _fields_ = [
         ("map_kinds", ctypes.c_int32), ("max_q", ctypes.c_int32), ("max_k", ctypes.c_int32),
         ("table_budget", ctypes.c_int64), ("repeats", ctypes.c_int32),
-        ("max_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+        ("max_candidates", ctypes.c_int32), ("modes", ctypes.c_int32),
+        ("fixed_tiles", ctypes.c_int32), ("batch_only", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -110,6 +112,7 @@ SIGNATURES = {
     "mag_scan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                 ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(MagStats), ctypes.c_void_p]),
+    "mag_batch_set_words_per_lane": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mag_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "mag_batch_destroy": (None, [ctypes.c_void_p]),
@@ -145,6 +148,10 @@ SIGNATURES = {
                                     ctypes.POINTER(MagTuneOpts), ctypes.c_void_p, ctypes.c_uint64,
                                     ctypes.POINTER(MagParams), ctypes.POINTER(ctypes.c_float),
                                     ctypes.c_void_p]),
+    "mag_autotune_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(MagTuneOpts),
+                                          ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "mag_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "mag_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64)]),

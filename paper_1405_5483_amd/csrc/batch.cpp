@@ -63,6 +63,8 @@ struct mag_batch {
     uint64_t *d_next = nullptr;      // tile claim counters, one per workgroup
     size_t next_bytes = 0;
     bool defer = false;              // some job defers its verification
+    int words_per_lane = mag::kBatchWordsDefault;   // filter tiles of 512 * words samples
+    int bound_words = mag::kBatchWordsDefault;      // the value the bound tile layout uses
     mag::Scratch sc;
 };
 
@@ -184,7 +186,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     // jobs and their tiles
     std::vector<JobDesc> jobs(njobs);
     std::vector<uint8_t> defer(njobs, 0);
-    std::vector<uint64_t> tiles_of(njobs), tile_bytes_full(njobs), tail_samples(njobs);
+    std::vector<uint64_t> tiles_of(njobs), tile_bytes_full(njobs), tail_samples(njobs), tile_samples(njobs);
+    const int wpl = b->words_per_lane;
     uint64_t total_tiles = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
         const mag_plan *p = b->plans[j];
@@ -200,7 +203,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.n = n[j];
         J.X = X;
         J.tile_first = total_tiles;
-        J.ntiles = (X + kBatchTileSamples - 1) / kBatchTileSamples;
+        const uint64_t TS = p->dense ? (uint64_t)kDenseTilePositions : (uint64_t)kBatchThreads * wpl;
+        J.ntiles = (X + TS - 1) / TS;
         J.mu = p->dev.mu;
         J.table = p->dev.table;
         J.q = p->q;
@@ -237,21 +241,22 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
             ((double)p->r * p->m * 4 >= (double)n[j] || expect >= kDeferPerWave * vwaves))
             defer[j] = 1;
         tiles_of[j] = J.ntiles;
-        tile_bytes_full[j] = (uint64_t)kBatchTileSamples * kq;
-        tail_samples[j] = X - (J.ntiles ? (J.ntiles - 1) * kBatchTileSamples : 0);
+        tile_bytes_full[j] = TS * kq;
+        tile_samples[j] = TS;
+        tail_samples[j] = X - (J.ntiles ? (J.ntiles - 1) * TS : 0);
         total_tiles += J.ntiles;
     }
 
     // contiguous tile ranges of about equal weight, one per workgroup
     const int ncu = device_compute_units();
-    const int occ = batch_occupancy();
+    const int occ = batch_occupancy(wpl);
     if (ncu < 1 || occ < 1) return fail(MAG_E_DEVICE, "cannot size the batch launch");
     uint64_t grid = (uint64_t)ncu * occ;
     if (grid > total_tiles) grid = total_tiles;
     std::vector<uint64_t> ranges(3 * std::max<uint64_t>(grid, 1), 0);
     if (grid) {
         auto tile_weight = [&](uint32_t j, uint64_t t) {
-            const uint64_t samples = t + 1 < tiles_of[j] ? (uint64_t)kBatchTileSamples : tail_samples[j];
+            const uint64_t samples = t + 1 < tiles_of[j] ? tile_samples[j] : tail_samples[j];
             // a dense tile reads one byte per position but hashes every one of them
             return samples * (jobs[j].dense ? 4 : jobs[j].kq) + kTileOverheadBytes;
         };
@@ -317,7 +322,17 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     b->nbits = idbits + posbits + jobbits;
     b->total_tiles = total_tiles;
     b->grid = (uint32_t)grid;
+    b->bound_words = wpl;
     b->bound = true;
+    return MAG_OK;
+}
+
+mag_status mag_batch_set_words_per_lane(mag_batch *b, int32_t words_per_lane) {
+    if (!b) return fail(MAG_E_INVALID, "batch is NULL");
+    if (words_per_lane != 8 && words_per_lane != 16 && words_per_lane != 32)
+        return fail(MAG_E_INVALID, "words_per_lane must be 8, 16 or 32");
+    std::lock_guard<std::mutex> lock(b->mtx);
+    b->words_per_lane = words_per_lane;
     return MAG_OK;
 }
 
@@ -342,7 +357,11 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     bl.grid = b->grid;
     bl.total_tiles = b->total_tiles;
     bl.counters = sc.counters;
-    mag_status s = launch_batch(bl, stream);
+    bl.words_per_lane = (uint32_t)b->bound_words;
+    ProfileMarks prof;
+    mag_status s = profile_start(prof, stream);
+    if (s == MAG_OK) s = launch_batch(bl, stream);
+    profile_mark(prof, stream);
     if (s == MAG_OK && b->defer)
         s = launch_batch_verify(b->d_jobs, sc.pending, sc.seg_count, sc.pending_cap / kPendingSegments,
                                 stream);
@@ -356,6 +375,7 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     if (s == MAG_OK)
         s = launch_batch_offsets(sorted, sc.counters + kSortCountSlot, b->cap, d_offsets, njobs,
                                  b->posbits + b->idbits, stream);
+    profile_commit(prof, stream);
     return s;
 }
 

@@ -1,7 +1,8 @@
 // Batched MAG scans: many independent (text, pattern set) jobs in one
 // persistent launch.
 //
-// Every job is cut into tiles of kBatchTileSamples samples; the tiles of all
+// Every job is cut into tiles (512 * words-per-lane samples; dense jobs
+// kDenseTilePositions start positions); the tiles of all
 // jobs form one global sequence (job after job) that the host splits into
 // contiguous ranges of about equal text bytes, one per workgroup, so a
 // workgroup restages a job's alphabet map and mask table in LDS only when its
@@ -29,10 +30,7 @@ using namespace dev;
 
 constexpr int kBT = kBatchThreads;
 constexpr int kWaves = kBT / 64;
-constexpr int kTS = kBatchTileSamples;
-constexpr int kS = kTS / kBT;                 // samples per lane in the Shift-Or phase
-constexpr int kLaneVecs = kS / 4;             // 16-byte vectors of u32 entries per lane
-static_assert(kS % 4 == 0 && kBatchMaxWarm % 4 == 0, "lane runs are whole vectors");
+static_assert(kBatchMaxWarm % 4 == 0, "lane runs are whole vectors");
 
 __device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 // readfirstlane returns int: each half goes through uint32_t so that the low
@@ -68,15 +66,15 @@ __device__ __forceinline__ uint32_t l2_entry(__amdgpu_buffer_rsrc_t trs, uint32_
     else return __builtin_amdgcn_raw_buffer_load_b32(trs, (int)(4 * g), 0, 0);
 }
 
-// Mask entries (as u32) of samples X0-w0 .. X0+kTS-1 of one job: entry of
+// Mask entries (as u32) of samples X0-w0 .. X0+TS-1 of one job: entry of
 // sample X0+s goes to E index s + w0. Thread tid computes vectors tid,
 // tid + kBT, ... two at a time (both loads issued before the lookups).
-template <int Q, int ESZ>
+template <int TS, int Q, int ESZ>
 __device__ void phase_a(uint4 *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint32_t kq, uint32_t sp,
                         const uint8_t *s_mu, const uint8_t *s_tab, __amdgpu_buffer_rsrc_t trs,
                         bool tlds, int w0, int64_t X0, int64_t X, int tid) {
     const uint32_t none = ESZ == 1 ? 0xFFu : ESZ == 2 ? 0xFFFFu : 0xFFFFFFFFu;
-    const int nvec = (kTS + w0) / 4;
+    const int nvec = (TS + w0) / 4;
     for (int V = tid; V < nvec; V += 2 * kBT) {
         GramWords w[2][4];
 #pragma unroll
@@ -104,14 +102,14 @@ __device__ void phase_a(uint4 *s_E, __amdgpu_buffer_rsrc_t rs, int32_t p0, uint3
     }
 }
 
-template <int Q>
+template <int TS, int Q>
 __device__ __forceinline__ void phase_a_q(uint32_t esz, uint4 *s_E, __amdgpu_buffer_rsrc_t rs,
                                           int32_t p0, uint32_t kq, uint32_t sp, const uint8_t *s_mu,
                                           const uint8_t *s_tab, __amdgpu_buffer_rsrc_t trs, bool tlds,
                                           int w0, int64_t X0, int64_t X, int tid) {
-    if (esz == 1) phase_a<Q, 1>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
-    else if (esz == 2) phase_a<Q, 2>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
-    else phase_a<Q, 4>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+    if (esz == 1) phase_a<TS, Q, 1>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+    else if (esz == 2) phase_a<TS, Q, 2>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
+    else phase_a<TS, Q, 4>(s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, w0, X0, X, tid);
 }
 
 constexpr uint64_t kNoTile = ~0ull;
@@ -149,17 +147,22 @@ __device__ uint64_t steal_tile(uint64_t *next, const uint64_t *ranges, uint32_t 
     }
 }
 
+// TS: samples per filter tile (512 * words per lane).
+template <int TS>
 __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jobs, uint32_t njobs,
                                                const uint64_t *__restrict__ ranges,
                                                uint64_t *next, uint64_t *counters) {
+    constexpr int kS = TS / kBT;                 // samples per lane in the Shift-Or phase
+    constexpr int kLaneVecs = kS / 4;            // 16-byte vectors of u32 entries per lane
+    static_assert(kS % 4 == 0, "lane runs are whole vectors");
     // static LDS of a fixed size: every carved-out array sits at a known
     // address, so LDS accesses need no base added at run time
-    __shared__ __align__(16) uint8_t smem[kBatchLdsBytes];
+    __shared__ __align__(16) uint8_t smem[batch_lds_bytes(TS)];
     uint8_t *s_mu = smem;
     uint64_t *s_ctl = reinterpret_cast<uint64_t *>(smem + 256);          // claimed tiles, 2 slots
     uint64_t *s_queue = reinterpret_cast<uint64_t *>(smem + 256 + 16);
     uint4 *s_E = reinterpret_cast<uint4 *>(smem + 256 + 16 + kWaves * kBatchQueue * 8);
-    uint8_t *s_tab = smem + 256 + 16 + kWaves * kBatchQueue * 8 + kBatchEntryBytes;
+    uint8_t *s_tab = smem + 256 + 16 + kWaves * kBatchQueue * 8 + batch_entry_bytes(TS);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *queue = s_queue + wave * kBatchQueue;
@@ -249,10 +252,10 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
                 for (uint32_t v = tid; v < tvec; v += kBT) dst[v] = src[v];
             }
         }
-        const int64_t X0 = (int64_t)(g - tfirst) * kTS;
+        const int64_t X0 = (int64_t)(g - tfirst) * (dense ? kDenseTilePositions : TS);
         if (dense) {
-            // start positions X0 .. X0 + kTS - 1 against the Bloom bitmap in s_tab
-            int64_t e1 = X0 + kTS + 40;
+            // start positions X0 .. X0 + kDenseTilePositions - 1 against the Bloom bitmap in s_tab
+            int64_t e1 = X0 + kDenseTilePositions + 40;
             if (e1 > (int64_t)n) e1 = (int64_t)n;
             const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
             const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         // text bytes the tile's samples touch, warm-up included
         int64_t b0 = (X0 - (int64_t)w0) * kq;
         if (b0 < 0) b0 = 0;
-        int64_t b1 = (X0 + kTS) * (int64_t)kq + kMaxQ;
+        int64_t b1 = (X0 + TS) * (int64_t)kq + kMaxQ;
         if (b1 > (int64_t)n) b1 = (int64_t)n;
         if (b1 < b0) b1 = b0;
         const uint64_t pa0 = (delta + (uint64_t)b0) & ~15ull;
@@ -287,14 +290,14 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         const int32_t p0 = (int32_t)((int64_t)delta - (int64_t)pa0 + X0 * (int64_t)kq);
         __syncthreads();                    // tables staged; the previous tile's entries consumed
         switch (q) {
-            case 1: phase_a_q<1>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 2: phase_a_q<2>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 3: phase_a_q<3>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 4: phase_a_q<4>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 5: phase_a_q<5>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 6: phase_a_q<6>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            case 7: phase_a_q<7>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
-            default: phase_a_q<8>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 1: phase_a_q<TS, 1>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 2: phase_a_q<TS, 2>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 3: phase_a_q<TS, 3>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 4: phase_a_q<TS, 4>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 5: phase_a_q<TS, 5>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 6: phase_a_q<TS, 6>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            case 7: phase_a_q<TS, 7>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
+            default: phase_a_q<TS, 8>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
         }
         if (wave == 0) {
             uint64_t t = kNoTile;
@@ -408,10 +411,20 @@ __global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint
 
 mag_status batch_configure() { return MAG_OK; }   // the kernel's LDS is static
 
-int batch_occupancy() {
+namespace {
+const void *batch_kernel(int words_per_lane) {
+    switch (words_per_lane) {
+        case 8: return (const void *)k_batch<8 * kBT>;
+        case 32: return (const void *)k_batch<32 * kBT>;
+        default: return (const void *)k_batch<16 * kBT>;
+    }
+}
+}  // namespace
+
+int batch_occupancy(int words_per_lane) {
     batch_configure();
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch, kBT, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel(words_per_lane), kBT, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -422,8 +435,20 @@ mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
     if (!b.total_tiles || !b.grid) return MAG_OK;
     hipLaunchKernelGGL(k_batch_init, dim3((b.grid + 255) / 256), dim3(256), 0, stream, b.ranges,
                        b.next, b.grid);
-    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
-                       b.ranges, b.next, b.counters);
+    switch (b.words_per_lane) {
+        case 8:
+            hipLaunchKernelGGL(k_batch<8 * kBT>, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
+                               b.ranges, b.next, b.counters);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_batch<32 * kBT>, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
+                               b.ranges, b.next, b.counters);
+            break;
+        default:
+            hipLaunchKernelGGL(k_batch<16 * kBT>, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
+                               b.ranges, b.next, b.counters);
+            break;
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "batch scan launch");
 }

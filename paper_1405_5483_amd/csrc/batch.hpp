@@ -12,19 +12,22 @@
 namespace mag {
 
 constexpr int kBatchThreads = 512;               // threads per workgroup
-constexpr int kBatchTileSamples = 8192;          // samples (dense jobs: start positions) per tile
+// Filter tiles hold 512 * words-per-lane samples, words per lane (the Shift-Or
+// run of one lane) 8, 16 (default) or 32, chosen per batch; dense jobs always
+// take tiles of kDenseTilePositions start positions (16 per lane).
+constexpr int kBatchWordsDefault = 16;
 constexpr int kBatchMaxWarm = 32;                // warm-up entries before a tile (>= m' - 1)
 constexpr int kBatchQueue = 128;                 // per-wave queue of start positions
-// mask entries of one tile as u32, in whole groups of eight 16-byte vectors
-constexpr uint32_t kBatchEntryBytes =
-    ((kBatchTileSamples + kBatchMaxWarm) * 4 + 127) / 128 * 128;
+// mask entries of one tile of TS samples as u32, in whole groups of eight
+// 16-byte vectors
+constexpr uint32_t batch_entry_bytes(int TS) { return ((TS + kBatchMaxWarm) * 4 + 127) / 128 * 128; }
 constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
-static_assert(kBatchTileSamples == kDenseTilePositions && kBatchThreads == kDenseThreads,
-              "dense tiles of the batch kernel are the dense kernel's tiles");
+static_assert(kBatchThreads == kDenseThreads, "dense tiles of the batch kernel are the dense kernel's tiles");
 static_assert((1u << kBloomBatchLog2) / 8 <= kBatchTableLds, "batched Bloom bitmaps fit in LDS");
 // alphabet map, two claimed-tile slots, queues, entries, table
-constexpr uint32_t kBatchLdsBytes =
-    256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + kBatchEntryBytes + kBatchTableLds;
+constexpr uint32_t batch_lds_bytes(int TS) {
+    return 256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + batch_entry_bytes(TS) + kBatchTableLds;
+}
 
 // One job as the kernel sees it. Written by the host at bind time.
 struct JobDesc {
@@ -51,10 +54,12 @@ struct BatchLaunch {
     uint32_t grid;
     uint64_t total_tiles;
     uint64_t *counters;
+    uint32_t words_per_lane;   // 8, 16 or 32: filter tiles of 512 * words samples
 };
 
-// Workgroups of the batch kernel that fit on one compute unit (0 on error).
-int batch_occupancy();
+// Workgroups of the batch kernel with `words_per_lane` that fit on one
+// compute unit (0 on error).
+int batch_occupancy(int words_per_lane);
 mag_status batch_configure();
 mag_status launch_batch(const BatchLaunch &b, hipStream_t stream);
 // Verifies the starts that batched jobs deferred: entry = job << kBatchJobShift

@@ -39,6 +39,43 @@ hipEvent_t make_event() {
 
 uint64_t round16(uint64_t v) { return (v + 15) & ~15ull; }
 
+}  // namespace
+
+mag_status profile_start(ProfileMarks &pm, hipStream_t stream) {
+    pm = ProfileMarks{};
+    {
+        std::lock_guard<std::mutex> pl(g_prof_mtx);
+        if (!g_prof_on) return MAG_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return MAG_OK;
+    }
+    if (cs != hipStreamCaptureStatusNone) return MAG_OK;
+    for (auto &ev : pm.ev) {
+        ev = make_event();
+        if (!ev) return fail(MAG_E_DEVICE, "hipEventCreate");
+    }
+    pm.on = true;
+    (void)hipEventRecord(pm.ev[0], stream);
+    return MAG_OK;
+}
+
+void profile_mark(ProfileMarks &pm, hipStream_t stream) {
+    if (pm.on) (void)hipEventRecord(pm.ev[1], stream);
+}
+
+void profile_commit(ProfileMarks &pm, hipStream_t stream) {
+    if (!pm.on) return;
+    (void)hipEventRecord(pm.ev[2], stream);
+    std::lock_guard<std::mutex> pl(g_prof_mtx);
+    g_prof.push_back(ProfileRecord{{pm.ev[0], pm.ev[1], pm.ev[2]}});
+    pm.on = false;
+}
+
+namespace {
+
 int ceil_log2(uint64_t v) {
     int b = 0;
     while (b < 64 && (1ull << b) < v) ++b;
@@ -409,6 +446,8 @@ mag_status mag_plan_get_params(const mag_plan *p, mag_params *o) {
     o->verify_buffer = (int32_t)p->verify_buffer;
     o->encode = p->encode;
     o->dense_probe = p->dense_probe;
+    o->chunk_bytes = p->chunk_bytes;
+    o->words_per_lane = p->words_per_lane;
     return MAG_OK;
 }
 
@@ -483,7 +522,8 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     // a grid of fewer workgroups than half the compute units verifies inline
     // with few waves: defer when each of them would face many starts
     const int ncu = device_compute_units();
-    const uint64_t tile = slices ? (uint64_t)kSliceScanTile
+    const int lane_pos = dense_lane_positions(p);
+    const uint64_t tile = slices ? (uint64_t)slice_scan_tile(lane_pos)
                           : p->dense ? (uint64_t)kDenseScanTile : kSmallGridTileSamples;
     const uint64_t tiles = (samples + tile - 1) / tile;
     const double vwaves = (double)std::max<uint64_t>(tiles, 1) *
@@ -521,18 +561,10 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         if (s != MAG_OK) return s;
         sl.codes = p->scratch.codes;
     }
-    ProfileRecord rec{{nullptr, nullptr, nullptr}};
-    bool prof = false;
+    ProfileMarks prof;
     if (!fixed) {
-        std::lock_guard<std::mutex> pl(g_prof_mtx);
-        prof = g_prof_on;
-    }
-    if (prof) {
-        for (auto &ev : rec.ev) {
-            ev = make_event();
-            if (!ev) return fail(MAG_E_DEVICE, "hipEventCreate");
-        }
-        (void)hipEventRecord(rec.ev[0], stream);
+        s = profile_start(prof, stream);
+        if (s != MAG_OK) return s;
     }
     if (p->dense) {
         DenseArgs da{};
@@ -545,10 +577,11 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
         da.counters = sc.counters;
         da.v = make_verify_args(p, sl);
         if (slices) {
-            da.ntiles = samples ? (samples + kSliceScanTile - 1) / kSliceScanTile : 0;
+            const uint64_t st = (uint64_t)slice_scan_tile(lane_pos);
+            da.ntiles = samples ? (samples + st - 1) / st : 0;
             da.bloom_vec = (uint32_t)(p->slices.size() * 4 / 16);
             da.bloom = p->dev.slices;
-            s = launch_dense_slices(da, p->slices.size() * 4, p->slice_k, stream);
+            s = launch_dense_slices(da, p->slices.size() * 4, p->slice_k, lane_pos, stream);
         } else {
             da.ntiles = samples ? (samples + kDenseScanTile - 1) / kDenseScanTile : 0;
             da.bloom_vec = (uint32_t)(p->bloom.size() * 4 / 16);
@@ -561,7 +594,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     }
     if (s == MAG_OK && sl.pending) s = launch_verify(make_verify_args(p, sl), stream);
     if (s != MAG_OK) return s;
-    if (prof) (void)hipEventRecord(rec.ev[1], stream);
+    profile_mark(prof, stream);
     if (idbits_out) *idbits_out = idbits;
     if (nbits_out) *nbits_out = idbits + posbits;
     s = launch_finish(sc, out_cap, samples, d_count, d_stats, d_out, idbits, ~0ull, nullptr, stream);
@@ -572,11 +605,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
             s = launch_expand(sc, out_cap, out_cap, idbits + posbits, d_out, idbits, ~0ull, stream);
         if (s != MAG_OK) return s;
     }
-    if (prof) {
-        (void)hipEventRecord(rec.ev[2], stream);
-        std::lock_guard<std::mutex> pl(g_prof_mtx);
-        g_prof.push_back(rec);
-    }
+    profile_commit(prof, stream);
     return MAG_OK;
 }
 

@@ -87,14 +87,16 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
 }
 
 // The one-probe dense scan (slice_test): the same grid and bitmap staging as
-// k_dense; tiles of kSliceScanTile positions, wave w covering positions
-// 1008 w .. 1008 w + 1007 of its tile, each lane loading the 32 bytes from
-// the word that holds its first position. Each wave keeps the loads of its
-// next two tiles in flight while it tests the current one (three register
-// sets, used in turn). AL: the text starts on a 4-byte boundary, so no byte
-// realignment is needed (tiles are a multiple of 4 positions long).
-template <int K, bool AL>
+// k_dense; tiles of slice_scan_tile(P) positions, wave w covering positions
+// 63 P w .. 63 P (w + 1) - 1 of its tile, each lane loading the 2P bytes
+// from the word that holds its first position. Each wave keeps the loads of
+// its next two tiles in flight while it tests the current one (three
+// register sets, used in turn). AL: the text starts on a 4-byte boundary, so
+// no byte realignment is needed (tiles are a multiple of 4 positions long).
+template <int K, int P, bool AL>
 __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
+    constexpr int kTile = slice_scan_tile(P);
+    constexpr int kLW = SliceLane<P>::kLoadWords;
     __shared__ __align__(16) uint32_t s_bits[kBloomWordsMax];
     __shared__ uint64_t s_queue[(kNT / 64) * kQueue];
     __shared__ uint64_t s_found[(kNT / 64) * kFoundBuf];
@@ -112,40 +114,41 @@ __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
     uint64_t *fbuf = s_found + wave * kFoundBuf;
     uint32_t qn = 0, nhit = 0, fbn = 0;
     // byte offset of this lane's first position in its tile
-    const uint32_t lane_off = (uint32_t)(kSliceWaveSpan * wave + 16 * lane);
-    // Tiles whose lanes' 32 bytes all lie inside the text take two whole
-    // loads per lane (the pipelined loop below), the last ones (at most two)
-    // single range-checked dwords. Resource offsets are taken from the
-    // 16-byte-aligned text base, which the text's first tile byte follows by
-    // d = delta & 3 within its word.
+    const uint32_t lane_off = (uint32_t)(P * (kSliceOwners * wave + lane));
+    // Tiles whose lanes' 2P bytes all lie inside the text take whole 16-byte
+    // loads (the pipelined loop below), the last ones (at most two) single
+    // range-checked dwords. Resource offsets are taken from the 16-byte-aligned
+    // text base, which the text's first tile byte follows by d = delta & 3
+    // within its word.
     const uint64_t pa_end = (a.delta + a.n) & ~3ull;  // whole words of text from tbase
     uint64_t nfull = 0;
     {
-        const uint64_t need = kSliceScanTile + 4u * kSliceLoadWords + 16;   // a tile's bytes from its word
-        nfull = pa_end >= need ? (pa_end - need) / kSliceScanTile + 1 : 0;
+        const uint64_t need = kTile + 4u * kLW + 16;   // a tile's bytes from its word
+        nfull = pa_end >= need ? (pa_end - need) / kTile + 1 : 0;
         if (nfull > a.ntiles) nfull = a.ntiles;
     }
     const uint32_t d = (uint32_t)(a.delta & 3u);
-    auto load = [&](uint64_t tile, uint32_t (&W)[kSliceLoadWords]) {
+    auto load = [&](uint64_t tile, uint32_t (&W)[kLW]) {
         // the word holding the tile's first position, and a resource from the
         // 16-byte boundary below it over the tile's lanes' bytes
-        const uint64_t w0 = (a.delta & ~3ull) + tile * (uint64_t)kSliceScanTile;
+        const uint64_t w0 = (a.delta & ~3ull) + tile * (uint64_t)kTile;
         const uint64_t pa0 = w0 & ~15ull;
-        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, kSliceScanTile + 64u);
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, kTile + 4u * kLW + 32u);
         const int at = (int)(w0 - pa0 + lane_off);
-        const uint4 v0 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at, 0, 0));
-        const uint4 v1 = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at + 16, 0, 0));
-        W[0] = v0.x; W[1] = v0.y; W[2] = v0.z; W[3] = v0.w;
-        W[4] = v1.x; W[5] = v1.y; W[6] = v1.z; W[7] = v1.w;
+#pragma unroll
+        for (int v = 0; v < kLW / 4; ++v) {
+            const uint4 x = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at + 16 * v, 0, 0));
+            W[4 * v] = x.x; W[4 * v + 1] = x.y; W[4 * v + 2] = x.z; W[4 * v + 3] = x.w;
+        }
     };
-    auto run = [&](uint64_t tile, const uint32_t (&W)[kSliceLoadWords]) {
-        const int64_t xb = (int64_t)tile * kSliceScanTile + lane_off;
-        slice_test<K, AL>(W, d, xb, a.last - xb + 1, s_bits, a.bshift, queue, qn, vargs, lane, nhit, fbuf,
-                          fbn);
+    auto run = [&](uint64_t tile, const uint32_t (&W)[kLW]) {
+        const int64_t xb = (int64_t)tile * kTile + lane_off;
+        slice_test<K, P, AL>(W, d, xb, a.last - xb + 1, s_bits, a.bshift, queue, qn, vargs, lane, nhit, fbuf,
+                             fbn);
     };
     const uint64_t G = gridDim.x;
     uint64_t tile = blockIdx.x;
-    uint32_t Wa[kSliceLoadWords], Wb[kSliceLoadWords], Wc[kSliceLoadWords];
+    uint32_t Wa[kLW], Wb[kLW], Wc[kLW];
     // every step issues the same loads (past the last full tile they reload
     // it), so the wait before a tile's use counts the same loads after it on
     // every path and the two tiles ahead stay in flight
@@ -168,17 +171,17 @@ __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
     }
     // the tail tiles, dword by dword within the text's resource
     for (tile = nfull + ((blockIdx.x + G - nfull % G) % G); tile < a.ntiles; tile += G) {
-        const int64_t x0 = (int64_t)tile * kSliceScanTile;
-        int64_t b1 = x0 + kSliceScanTile + 48;
+        const int64_t x0 = (int64_t)tile * kTile;
+        int64_t b1 = x0 + kTile + 4 * kLW + 16;
         if (b1 > (int64_t)a.n) b1 = (int64_t)a.n;
         const uint64_t pa0 = (a.delta + (uint64_t)x0) & ~15ull;
         const uint64_t pa1 = (a.delta + (uint64_t)b1 + 15) & ~15ull;
         const __amdgpu_buffer_rsrc_t rs = tile_rsrc(a.tbase + pa0, (uint32_t)(pa1 - pa0));
         const uint32_t p0 = (uint32_t)(a.delta + (uint64_t)x0 - pa0);
         const uint32_t at = (p0 & ~3u) + lane_off;
-        uint32_t W[kSliceLoadWords];
+        uint32_t W[kLW];
 #pragma unroll
-        for (int t = 0; t < kSliceLoadWords; ++t) W[t] = ld32(rs, at + 4u * t);
+        for (int t = 0; t < kLW; ++t) W[t] = ld32(rs, at + 4u * t);
         run(tile, W);
     }
     if (qn) fbn = drain_partial_found(vargs, queue, qn, lane, fbuf, fbn);
@@ -204,39 +207,45 @@ int compute_units(int &ncu) {
     return 0;
 }
 
-template <int K>
-mag_status launch_slices_k(const DenseArgs &a, hipStream_t stream) {
+template <int K, int P>
+mag_status launch_slices_kp(const DenseArgs &a, hipStream_t stream) {
     static int ncu = 0;
     if (compute_units(ncu)) return MAG_E_DEVICE;
     const bool al = (a.delta & 3) == 0;
-    const void *fn = al ? (const void *)k_dense_slices<K, true> : (const void *)k_dense_slices<K, false>;
+    const void *fn = al ? (const void *)k_dense_slices<K, P, true> : (const void *)k_dense_slices<K, P, false>;
     const int occ = cached_occupancy(fn, kNT, 0);
     if (occ < 1) return fail(MAG_E_UNSUPPORTED, "dense scan does not fit on a compute unit");
     uint64_t grid = (uint64_t)ncu * occ;
     if (grid > a.ntiles) grid = a.ntiles;
     if (al)
-        hipLaunchKernelGGL((k_dense_slices<K, true>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
+        hipLaunchKernelGGL((k_dense_slices<K, P, true>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_dense_slices<K, false>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
+        hipLaunchKernelGGL((k_dense_slices<K, P, false>), dim3((uint32_t)grid), dim3(kNT), 0, stream, a);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "dense scan launch");
 }
 
+template <int K>
+mag_status launch_slices_k(const DenseArgs &a, int P, hipStream_t stream) {
+    return P == 32 ? launch_slices_kp<K, 32>(a, stream) : launch_slices_kp<K, 16>(a, stream);
+}
+
 }  // namespace
 
-mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, hipStream_t stream) {
+mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, int P, hipStream_t stream) {
     if (!a.ntiles) return MAG_OK;
     if (bitmap_bytes > (size_t)kBloomWordsMax * 4 || a.bloom_vec * 16ull != bitmap_bytes)
         return fail(MAG_E_INVALID, "slice bitmap does not fit the dense kernel's LDS array");
+    if (P != 16 && P != 32) return fail(MAG_E_INVALID, "positions per lane must be 16 or 32");
     switch (k) {
-        case 1: return launch_slices_k<1>(a, stream);
-        case 2: return launch_slices_k<2>(a, stream);
-        case 3: return launch_slices_k<3>(a, stream);
-        case 4: return launch_slices_k<4>(a, stream);
-        case 5: return launch_slices_k<5>(a, stream);
-        case 6: return launch_slices_k<6>(a, stream);
-        case 7: return launch_slices_k<7>(a, stream);
-        case 8: return launch_slices_k<8>(a, stream);
+        case 1: return launch_slices_k<1>(a, P, stream);
+        case 2: return launch_slices_k<2>(a, P, stream);
+        case 3: return launch_slices_k<3>(a, P, stream);
+        case 4: return launch_slices_k<4>(a, P, stream);
+        case 5: return launch_slices_k<5>(a, P, stream);
+        case 6: return launch_slices_k<6>(a, P, stream);
+        case 7: return launch_slices_k<7>(a, P, stream);
+        case 8: return launch_slices_k<8>(a, P, stream);
     }
     return fail(MAG_E_INVALID, "slices per pattern outside [1, 8]");
 }

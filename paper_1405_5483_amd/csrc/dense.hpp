@@ -25,8 +25,9 @@ constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive posi
 constexpr int kDenseScanThreads = MAG_DENSE_SCAN_THREADS;
 constexpr int kDenseScanTile = 16 * kDenseScanThreads;
 constexpr uint32_t kDenseQueue = 128;   // per-wave queue the callers provide (starts)
-// one-probe dense kernel: 63 owning lanes of 16 positions per wave
-constexpr int kSliceScanTile = 16 * 63 * (kDenseScanThreads / 64);
+// one-probe dense kernel: 63 owning lanes of P (16 or 32, the words per
+// lane) positions per wave; a tile is the workgroup's 16 waves
+constexpr int slice_scan_tile(int P) { return P * 63 * (kDenseScanThreads / 64); }
 
 struct DenseArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes
@@ -43,8 +44,9 @@ struct DenseArgs {
 
 mag_status launch_dense(const DenseArgs &a, size_t bloom_bytes, hipStream_t stream);
 // The one-probe dense kernel: a.bloom is the slice bitmap, k its slices per
-// pattern, a.ntiles counts tiles of kSliceScanTile positions.
-mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, hipStream_t stream);
+// pattern, P the positions per lane (16 or 32), a.ntiles counts tiles of
+// slice_scan_tile(P) positions.
+mag_status launch_dense_slices(const DenseArgs &a, size_t bitmap_bytes, int k, int P, hipStream_t stream);
 
 namespace dev {
 
@@ -168,35 +170,40 @@ __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last
     }
 }
 
-// One-probe dense mode (slice_hash). A wave covers 63 * 16 consecutive start
-// positions: lane L < 63 owns the 16 from xb = its wave's first + 16 L, and
-// lane 63 probes the 16 that follow the wave's last (the next wave's first),
-// so that every owner finds the probes of the positions up to 15 past its
-// own in the next lane. W holds the 32 bytes from the word that contains xb
-// (d = xb's byte offset in it; AL: d = 0). Bit u of a lane's probe mask is
-// the bitmap bit of the slice at xb + u; position xb + u passes when bits u,
-// u + 2, .., u + 2(K-1) of the mask extended by the next lane's are all set.
+// One-probe dense mode (slice_hash). A wave covers 63 * P consecutive start
+// positions (P = 16 or 32): lane L < 63 owns the P from xb = its wave's first
+// + P L, and lane 63 probes the P that follow the wave's last (the next
+// wave's first), so that every owner finds the probes of the positions up to
+// P - 1 past its own in the next lane. W holds the 2P bytes from the word
+// that contains xb (d = xb's byte offset in it; AL: d = 0). Bit u of a lane's
+// probe mask is the bitmap bit of the slice at xb + u; position xb + u passes
+// when bits u, u + 2, .., u + 2(K-1) of the mask extended by the next lane's
+// are all set.
 constexpr int kSliceOwners = 63;
-constexpr int kSliceWaveSpan = 16 * kSliceOwners;
-constexpr int kSliceLoadWords = 8;
+template <int P> struct SliceLane {
+    static constexpr int kLoadWords = P / 2;         // 2P bytes
+    static constexpr int kWords = P / 4 + 2;         // realigned words: bytes xb .. xb + P + 7
+};
 
-template <bool AL>
-__device__ __forceinline__ void slice_words(const uint32_t (&W)[kSliceLoadWords], uint32_t d,
-                                            uint32_t (&V)[6]) {
+template <int P, bool AL>
+__device__ __forceinline__ void slice_words(const uint32_t (&W)[SliceLane<P>::kLoadWords], uint32_t d,
+                                            uint32_t (&V)[SliceLane<P>::kWords]) {
 #pragma unroll
-    for (int t = 0; t < 6; ++t) V[t] = AL ? W[t] : __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
+    for (int t = 0; t < SliceLane<P>::kWords; ++t)
+        V[t] = AL ? W[t] : __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
 }
 
-__device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[6], const uint32_t *s_bits,
-                                                 uint32_t bshift) {
-    uint32_t A[19];                             // A[i]: the word of bytes xb+i .. xb+i+3
+template <int P>
+__device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[SliceLane<P>::kWords],
+                                                 const uint32_t *s_bits, uint32_t bshift) {
+    uint32_t A[P + 3];                          // A[i]: the word of bytes xb+i .. xb+i+3
 #pragma unroll
-    for (int i = 0; i < 19; ++i)
+    for (int i = 0; i < P + 3; ++i)
         A[i] = (i & 3) ? __builtin_amdgcn_alignbyte(V[i / 4 + 1], V[i / 4], i & 3) : V[i / 4];
     uint32_t hm = 0;
     const uint32_t ashift = bshift + 3;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < P; ++u) {
         const uint32_t h = __umul24(A[u + 3], kSliceK2) + __umul24(A[u], kSliceK1);
         const uint32_t w = *reinterpret_cast<const uint32_t *>(
             reinterpret_cast<const char *>(s_bits) + ((h >> ashift) & ~3u));
@@ -231,26 +238,38 @@ __device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, con
 // queueing of the passing positions (room: starts left from xb, <= 0 when
 // none), one per lane and round with a ballot; found keys collect in the
 // wave's buffer fbuf (fbn keys). Every lane of the wave calls it.
-template <int K, bool AL>
-__device__ __forceinline__ void slice_test(const uint32_t (&W)[kSliceLoadWords], uint32_t d, int64_t xb,
-                                           int64_t room, const uint32_t *s_bits, uint32_t bshift,
-                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int lane,
-                                           uint32_t &nhit, uint64_t *fbuf, uint32_t &fbn) {
-    uint32_t V[6];
-    slice_words<AL>(W, d, V);
-    const uint32_t hm = slice_probes(V, s_bits, bshift);
+template <int K, int P, bool AL>
+__device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::kLoadWords], uint32_t d,
+                                           int64_t xb, int64_t room, const uint32_t *s_bits,
+                                           uint32_t bshift, uint64_t *queue, uint32_t &qn,
+                                           const VerifyArgs *vp, int lane, uint32_t &nhit, uint64_t *fbuf,
+                                           uint32_t &fbn) {
+    uint32_t V[SliceLane<P>::kWords];
+    slice_words<P, AL>(W, d, V);
+    const uint32_t hm = slice_probes<P>(V, s_bits, bshift);
     uint32_t pass = hm;
     if constexpr (K > 1) {
-        const uint32_t ext = hm | (__shfl_down(hm, 1) << 16);
+        // the next lane's probes of the positions after this lane's
+        const uint32_t nx = __shfl_down(hm, 1);
+        if constexpr (P == 32) {
+            const uint64_t ext = (uint64_t)hm | ((uint64_t)nx << 32);
+            uint64_t pw = ext;
 #pragma unroll
-        for (int j = 1; j < K; ++j) pass &= ext >> (kSliceStride * j);
+            for (int j = 1; j < K; ++j) pw &= ext >> (kSliceStride * j);
+            pass = (uint32_t)pw;
+        } else {
+            const uint32_t ext = hm | (nx << 16);
+#pragma unroll
+            for (int j = 1; j < K; ++j) pass &= ext >> (kSliceStride * j);
+            pass &= 0xFFFFu;
+        }
     }
-    pass &= lane < kSliceOwners ? 0xFFFFu : 0u;
-    if (room < 16) pass &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
+    if (lane >= kSliceOwners) pass = 0u;
+    if (room < P) pass &= room <= 0 ? 0u : (uint32_t)((1ull << (uint32_t)room) - 1u);
     nhit += (uint32_t)__popc(pass);
     while (__ballot(pass != 0)) {
         const bool act = pass != 0;
-        const uint32_t u = (uint32_t)__builtin_ctz(pass | 0x10000u);
+        const uint32_t u = act ? (uint32_t)__builtin_ctz(pass) : 0u;
         pass &= pass - 1u;
         const uint64_t bal = __ballot(act);
         if (act) queue[qn + lanes_below(bal)] = (uint64_t)(xb + u);

@@ -222,6 +222,10 @@ struct mag_plan {
     // one-probe dense mode: slice_k slices per distinct pattern in a bitmap of
     // 2^bloom_log2 bits (slice_k = 0: the dense mode uses the Bloom bitmap)
     int dense_probe = MAG_DENSE_PROBE_AUTO;
+    // tile shape asked for at creation (0 = auto): text bytes per tile, or
+    // entries (samples, start positions) per lane (filter_lane_entries and
+    // dense_lane_positions resolve them)
+    int chunk_bytes = 0, words_per_lane = 0;
     int slice_k = 0;
     double slice_fp = 0.0;           // estimated share of start positions it passes
     std::vector<uint32_t> slices;
@@ -236,6 +240,22 @@ struct mag_plan {
 };
 
 namespace mag {
+
+// Benchmark timing (capi.cpp): while mag_profile_enable is on and `stream` is
+// not being captured, profile_start records an event before a scan's first
+// kernel, profile_mark(1) one after its scan kernel and profile_commit one
+// after its last kernel and keeps the record for mag_profile_read.
+struct ProfileMarks {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool on = false;
+};
+mag_status profile_start(ProfileMarks &pm, hipStream_t stream);
+void profile_mark(ProfileMarks &pm, hipStream_t stream);
+void profile_commit(ProfileMarks &pm, hipStream_t stream);
+
+// Positions per lane of the one-probe dense kernel (16 or 32) for a plan's
+// chunk_bytes / words_per_lane (scan_dispatch.cpp).
+int dense_lane_positions(const mag_plan *p);
 
 // Thread-local error text (capi.cpp).
 mag_status fail(mag_status s, const std::string &msg);

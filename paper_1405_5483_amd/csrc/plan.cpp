@@ -447,8 +447,12 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
         return fail(MAG_E_INVALID, "unknown dense_probe");
     if (prm.dense_probe == MAG_DENSE_PROBE_SLICES && m < (uint32_t)kSliceBytes)
         return fail(MAG_E_INVALID, "the one-probe dense bitmap needs m >= 6");
-    if (prm.chunk_bytes != 0 || prm.words_per_lane != 0)
-        return fail(MAG_E_UNSUPPORTED, "chunk_bytes and words_per_lane must be 0");
+    if (prm.chunk_bytes < 0 || prm.words_per_lane < 0)
+        return fail(MAG_E_INVALID, "chunk_bytes and words_per_lane must be >= 0");
+    if (prm.chunk_bytes && prm.words_per_lane)
+        return fail(MAG_E_INVALID, "give chunk_bytes or words_per_lane, not both");
+    if (prm.words_per_lane > 256 || (prm.chunk_bytes && prm.chunk_bytes < 1024))
+        return fail(MAG_E_INVALID, "words_per_lane above 256 or chunk_bytes below 1024");
     if (r >= (1u << 31)) return fail(MAG_E_UNSUPPORTED, "too many patterns");
 
     p->r = r;
@@ -540,6 +544,8 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     build_bloom(p);
     build_slices(p, prm.dense_probe);
     p->dense_probe = prm.dense_probe;
+    p->chunk_bytes = prm.chunk_bytes;
+    p->words_per_lane = prm.words_per_lane;
     p->mode = prm.mode;
     p->verify = prm.verify;
     p->verify_buffer = (uint64_t)prm.verify_buffer;

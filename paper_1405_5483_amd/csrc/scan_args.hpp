@@ -18,6 +18,7 @@ namespace mag {
 constexpr int kScanThreads = MAG_SCAN_THREADS;        // threads per scan workgroup
 constexpr int kScanProducerWaves = MAG_SCAN_PRODUCERS; // waves that compute mask entries
 constexpr int kScanConsumerLanes = kScanThreads - 64 * kScanProducerWaves;  // Shift-Or lanes
+constexpr uint64_t kScanLdsMax = 160 * 1024;   // LDS of one workgroup on gfx950
 
 struct ScanArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes

@@ -1,5 +1,6 @@
 // Host side of the scan launch: tile sizing and the choice among the per-q
 // kernel objects (scan.hip compiled once per q).
+#include "dense.hpp"
 #include "mag_internal.hpp"
 #include "scan_args.hpp"
 
@@ -109,6 +110,12 @@ mag_status launch_encode(const mag_plan *p, const uint8_t *text, uint64_t n, voi
     }
 }
 
+int dense_lane_positions(const mag_plan *p) {
+    if (p->words_per_lane > 0) return p->words_per_lane >= 24 ? 32 : 16;
+    if (p->chunk_bytes > 0) return p->chunk_bytes >= slice_scan_tile(24) ? 32 : 16;
+    return 16;
+}
+
 mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t stream) {
     if (s.n < (uint64_t)p->q || p->r == 0) return MAG_OK;
     const int ncu = compute_units();
@@ -141,11 +148,25 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
     const uint32_t epv = 16 / esz;                      // entries per 16-byte LDS read
     // lane runs start on 16-byte vector boundaries: S is a multiple of epv
     uint32_t S = kEntryBytesPerTile / (kScanConsumerLanes * esz) / epv * epv;
-    if (S < epv) S = epv;
-    // small texts: shorter lane runs so that every compute unit gets tiles
-    while (S > epv && (a.X + (uint64_t)kScanConsumerLanes * S - 1) /
-                              ((uint64_t)kScanConsumerLanes * S) < 2ull * (uint64_t)ncu)
-        S -= epv;
+    if (p->words_per_lane > 0 || p->chunk_bytes > 0) {
+        // the plan's tile shape: entries per lane, or text bytes per tile
+        // (256 lanes of kq bytes per entry), within the LDS left beside the
+        // mask table (two entry buffers)
+        S = p->words_per_lane > 0 ? (uint32_t)p->words_per_lane
+                                  : (uint32_t)((uint64_t)p->chunk_bytes / ((uint64_t)kScanConsumerLanes * a.kq));
+        const uint64_t tab = p->table.size() <= kTableLdsMax ? p->table.size() : 0;
+        const uint64_t room = (kScanLdsMax - 256 - (kScanConsumerLanes / 64) * 128 * 8 - tab) / 2;
+        const uint64_t cap = (room - 128 * esz) / esz / kScanConsumerLanes;   // w0 + 16 <= 80 entries
+        if (S > cap) S = (uint32_t)cap;
+        S = S / epv * epv;
+        if (S < epv) S = epv;
+    } else {
+        if (S < epv) S = epv;
+        // small texts: shorter lane runs so that every compute unit gets tiles
+        while (S > epv && (a.X + (uint64_t)kScanConsumerLanes * S - 1) /
+                                  ((uint64_t)kScanConsumerLanes * S) < 2ull * (uint64_t)ncu)
+            S -= epv;
+    }
     a.S = S;
     a.tile_samples = kScanConsumerLanes * S;
     a.ntiles = (a.X + a.tile_samples - 1) / a.tile_samples;

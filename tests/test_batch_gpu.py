@@ -231,3 +231,33 @@ def test_scan_batch_one_shot(torch_cuda, mag):
     res = mag.scan_batch(texts, plans, out_cap=total)
     _check_jobs(res, jobs)
     assert mag.scan_batch([], []) == []
+
+
+@pytest.mark.parametrize("words", [8, 16, 32])
+def test_batch_words_per_lane(torch_cuda, mag, words):
+    """Filter tiles of 512 * words samples (dense jobs keep 8192 positions):
+    the same lists for every tile shape, jobs of a few tiles each."""
+    jobs = _small_jobs(20, seed=303, n_log2=(12.0, 19.0))
+    plans = [mag.Plan(j.patterns, mode="dense" if i % 4 == 3 else "filter") for i, j in enumerate(jobs)]
+    texts = _upload(torch_cuda, [j.text for j in jobs], [(5 * j) % 16 for j in range(len(jobs))])
+    b = mag.Batch(plans, words_per_lane=words)
+    b.bind(texts, 1 << 17)
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
+def test_autotuned_batch(torch_cuda, mag):
+    """The batch autotuner's picks (one per job class, filter or dense, with
+    their tile shapes) and its words per lane: every job's list equals the
+    oracle's."""
+    jobs = _small_jobs(32, seed=404, n_log2=(12.0, 18.0), r_log10=(1.0, 3.5))
+    texts = _upload(torch_cuda, [j.text for j in jobs])
+    kws, words = mag.autotune_batch([j.patterns for j in jobs], texts, sample_bytes=1 << 16,
+                                    max_candidates=4, repeats=1)
+    assert words in (8, 16, 32) and len(kws) == len(jobs)
+    assert all(kw["mode"] in ("filter", "dense") for kw in kws)
+    plans = [mag.Plan(j.patterns, **kw) for j, kw in zip(jobs, kws)]
+    b = mag.Batch(plans, words_per_lane=words)
+    b.bind(texts, 1 << 18)
+    _check_jobs(b.run(), jobs)
+    b.close()

@@ -346,6 +346,19 @@ def test_plan_params_round_trip():
         assert b.params() == prm
 
 
+def test_tile_shape_parameters():
+    """chunk_bytes and words_per_lane: at most one of them, within range, and
+    returned by mag_plan_get_params."""
+    mag = _lib_or_skip()
+    P = np.frombuffer(b"ABCDEFGHIJKLMNOP" * 4, dtype=np.uint8).reshape(4, 16)
+    assert mag.Plan(P, words_per_lane=32).params()["words_per_lane"] == 32
+    assert mag.Plan(P, chunk_bytes=65536).params()["chunk_bytes"] == 65536
+    for bad in (dict(words_per_lane=16, chunk_bytes=4096), dict(words_per_lane=257),
+                dict(chunk_bytes=512), dict(words_per_lane=-1)):
+        with pytest.raises(mag.MagError):
+            mag.Plan(P, **bad)
+
+
 def test_dense_probe_choice():
     """The dense mode's probe: slices for protein-like pattern bytes (6 H >= B
     + 4 bits), the Bloom bitmap for DNA, k = round(ln 2 * 2^B / distinct

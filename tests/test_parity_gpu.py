@@ -635,8 +635,51 @@ def test_autotune_pick_is_exact(torch_cuda, mag):
     buf = torch_cuda.from_numpy(job.text).cuda()
     best = mag.autotune(job.patterns, buf[: 1 << 20], max_candidates=12)
     assert 2 * best["q"] - 1 <= 32 and best["sample_ms"] > 0
-    plan = mag.Plan(job.patterns, q=best["q"], k=best["k"], sigma_prime=best["sigma_prime"],
-                    map_kind=best["map_kind"])
+    assert best["mode"] in ("filter", "dense")
+    plan = mag.Plan(job.patterns, **{k: v for k, v in best.items() if k != "sample_ms"})
     occ = mag.scan(buf, plan).cpu().numpy()
     _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32),
                  om.occ_hashed(job.text, job.patterns))
+
+
+@pytest.mark.parametrize("case", [
+    # sigma, r, m, plan keywords (a filter plan's entries per lane or chunk, a
+    # dense plan's positions per lane)
+    (64, 300, 32, dict(q=4, k=1, sigma_prime=16, map_kind="bits", mode="filter", words_per_lane=16)),
+    (64, 300, 32, dict(q=4, k=1, sigma_prime=16, map_kind="bits", mode="filter", words_per_lane=200)),
+    (20, 200, 16, dict(q=3, k=2, sigma_prime=8, mode="filter", chunk_bytes=4096)),
+    (4, 100, 16, dict(q=5, k=1, sigma_prime=4, mode="filter", words_per_lane=64)),
+    (20, 5000, 16, dict(mode="dense", dense_probe="slices", words_per_lane=32)),
+    (20, 5000, 12, dict(mode="dense", dense_probe="slices", chunk_bytes=40000)),
+], ids=["filter-wpl16", "filter-wpl200", "filter-chunk4k", "dna-wpl64", "dense-wpl32", "dense-chunk"])
+def test_tile_shapes(torch_cuda, mag, case):
+    """Tile shapes other than the default (entries per lane of the filter
+    kernel, positions per lane of the one-probe dense kernel): the same lists,
+    at several text lengths and alignments."""
+    sigma, r, m, kw = case
+    T0 = gen_text(300_013, sigma, dist="zipf" if sigma == 64 else "uniform", rng=r + m)
+    P = gen_patterns(T0, r, m, (3 * r) // 4, sigma, rng=r + 7)
+    plan = mag.Plan(P, **kw)
+    assert plan.params()["words_per_lane"] == kw.get("words_per_lane", 0)
+    for npos in (1, 40_000, 64_513, 300_013 - m + 1):
+        T = T0[:npos + m - 1]
+        ref = om.occ_hashed(T, P)
+        for off in (0, 3):
+            pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=off)
+            _assert_same(pos, ids, ref)
+
+
+def test_dense_slice_tile_edges_32(torch_cuda, mag):
+    # 32 positions per lane: tiles of 32,256 positions (16 waves of 63 owning
+    # lanes); last starts around lane, wave and tile boundaries
+    m, span, tile = 16, 32 * 63, 32 * 63 * 16
+    T0 = gen_text(2 * tile + 128, 20, rng=97)
+    at = [0, 31, 32, span - 33, span - 1, span, tile - 1, tile, tile + 1]
+    P = np.concatenate([np.stack([T0[u:u + m] for u in at]), gen_patterns(T0, 3000, m, 0, 20, rng=98)])
+    plan = mag.Plan(P, mode="dense", dense_probe="slices", words_per_lane=32)
+    for npos in (1, 33, span - 1, span, span + 1, tile - 1, tile, tile + 1, 2 * tile + 64):
+        T = T0[:npos + m - 1]
+        ref = om.occ_hashed(T, P)
+        for off in (0, 1, 2, 3):
+            pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan, offset=off)
+            _assert_same(pos, ids, ref)
