@@ -191,18 +191,29 @@ typedef struct {
                              mode's bitmap passes to exact verification        */
 } mag_plan_desc;
 
-/* Work counters of one scan (integers; equal to the oracle's counts). */
+/* Work counters of one scan (integers; equal to the oracle's counts) and
+ * the plan's resolved parameters. mag_scan fills every field; the device
+ * copy that mag_scan_async and mag_scan_noalloc write holds all of them but
+ * scan_ms (0: only mag_scan, which waits, times the scan). */
 typedef struct {
-    uint64_t samples;        /* text q-grams read by the filter                 */
-    uint64_t cand_windows;   /* (x, j) windows that passed the filter           */
+    uint64_t samples;        /* text q-grams read by the filter (dense mode:
+                                start positions tested)                        */
+    uint64_t cand_windows;   /* (x, j) windows that passed the filter (dense
+                                mode: positions that passed its bitmap)        */
     uint64_t verifications;  /* start positions verified exactly                */
     uint64_t matches;        /* occurrences found                               */
+    int32_t q, k, sigma_prime, m_prime;   /* the plan's filter parameters       */
+    float plan_ms;           /* host time mag_plan_create took for the plan     */
+    float scan_ms;           /* device time of the scan and finishing kernels
+                                (mag_scan only, else 0)                         */
 } mag_stats;
 
 typedef struct mag_plan mag_plan;
 
-/* Builds a plan for r patterns of length m (host array, row-major r*m bytes;
- * copied, so the caller may free it on return). params may be NULL (heuristic,
+/* Builds a plan for the pattern set of Section 1's problem: r patterns of
+ * length m (host array, row-major r*m bytes; copied, so the caller may free
+ * it on return), preprocessed by Sections 2-3 (alphabet map, superimposed
+ * q-gram classes, Shift-Or masks, verification set). params may be NULL (heuristic,
  * greedy map). Host-only work: device tables are uploaded on first use.
  * Errors: m == 0 or m > 64, explicit q with 2q-1 > m, k outside [1, L],
  * sigma' outside [1, 256] (for MAG_MAP_QGRAM: not a power of two in
@@ -262,7 +273,8 @@ mag_status mag_plan_export(const mag_plan *plan, uint8_t *mu_out, void *table_ou
 mag_status mag_encode(mag_plan *plan, const uint8_t *d_text, uint64_t n, uint32_t *d_codes,
                       uint64_t cap, uint64_t *n_codes, void *stream);
 
-/* Scans d_text[0..n) and enqueues everything on `stream` without waiting:
+/* Section 1's problem for one text: every occurrence (i, id) of the plan's
+ * patterns in d_text[0..n). Enqueues everything on `stream` without waiting:
  * filter, verification and the final sort. Writes min(z, out_cap) sorted
  * records to d_out and z, the exact number of occurrences, to *d_count (a
  * device uint64). If z > out_cap the records are unspecified (never written
@@ -294,7 +306,8 @@ mag_status mag_scan_async(mag_plan *plan, const uint8_t *d_text, uint64_t n,
 mag_status mag_scan_noalloc(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
                             uint64_t out_cap, uint64_t *d_count, mag_stats *d_stats, void *stream);
 
-/* As mag_scan_async, then waits for the stream and returns the count in
+/* Section 1's problem for one text, as mag_scan_async, then waits for the
+ * stream and returns the count in
  * *n_matches (host) and the counters in *stats (host, may be NULL). Returns
  * MAG_E_OVERFLOW when z > out_cap (with *n_matches = z). */
 mag_status mag_scan(mag_plan *plan, const uint8_t *d_text, uint64_t n, mag_match *d_out,
@@ -343,7 +356,8 @@ typedef struct {
     uint64_t n;
 } mag_job;
 
-/* One-shot batched scan: builds a batch over the jobs (a plan may serve
+/* One-shot batched scan (Section 1's problem for many independent (text,
+ * pattern set) instances): builds a batch over the jobs (a plan may serve
  * several), binds their texts, runs it on `stream`, waits, and writes the
  * first record of each job and the total to offsets (host, njobs + 1
  * uint64). Records land in d_out as for mag_batch_run_async (job by job,

@@ -197,7 +197,7 @@ def scan(text, plan: Plan, out_cap: int | None = None, stats: bool = False, stre
     z = int(count.value)
     res = out[:z]
     if stats:
-        return res, {name: int(getattr(st, name)) for name, _ in MagStats._fields_}
+        return res, {name: getattr(st, name) for name, _ in MagStats._fields_}
     return res
 
 
@@ -236,8 +236,9 @@ def stream_read(buf, sink=None, stream=None):
 def scan_async(text, plan: Plan, out, d_count, d_stats=None, stream=None) -> None:
     """Enqueues a scan without waiting (``mag_scan_async``). ``out`` is an
     int64 [cap, 2] CUDA tensor, ``d_count`` an int64 [1] CUDA tensor that
-    receives the exact occurrence count, ``d_stats`` an optional int64 [4]
-    CUDA tensor for the counters."""
+    receives the exact occurrence count, ``d_stats`` an optional CUDA tensor
+    of at least 56 bytes (e.g. int64 [7]) for ``mag_stats``: the four counters
+    as int64 [0:4], then q, k, sigma', m' as int32 and plan_ms as float32."""
     _check_text(text)
     check(lib().mag_scan_async(plan.handle, ctypes.c_void_p(text.data_ptr()), text.numel(),
                                ctypes.c_void_p(out.data_ptr()), out.shape[0],

@@ -81,7 +81,9 @@ class MagTuneOpts(ctypes.Structure):
 
 class MagStats(ctypes.Structure):
     _fields_ = [("samples", ctypes.c_uint64), ("cand_windows", ctypes.c_uint64),
-                ("verifications", ctypes.c_uint64), ("matches", ctypes.c_uint64)]
+                ("verifications", ctypes.c_uint64), ("matches", ctypes.c_uint64),
+                ("q", ctypes.c_int32), ("k", ctypes.c_int32), ("sigma_prime", ctypes.c_int32),
+                ("m_prime", ctypes.c_int32), ("plan_ms", ctypes.c_float), ("scan_ms", ctypes.c_float)]
 
 
 # name -> (restype, argtypes); every function declared in include/mag.h

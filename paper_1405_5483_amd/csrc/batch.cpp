@@ -161,10 +161,10 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     Scratch &sc = b->sc;
     if (!sc.counters) {
         size_t have = 0;
-        mag_status s = grow(&sc.counters, &have, 16 * sizeof(uint64_t), "batch counters");
+        mag_status s = grow(&sc.counters, &have, kCounterWords * sizeof(uint64_t), "batch counters");
         if (s != MAG_OK) return s;
         // the finishing kernel of every run returns the counters to zero
-        e = hipMemset(sc.counters, 0, 16 * sizeof(uint64_t));
+        e = hipMemset(sc.counters, 0, kCounterWords * sizeof(uint64_t));
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "clearing batch counters");
     }
@@ -366,7 +366,8 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
         s = launch_batch_verify(b->d_jobs, sc.pending, sc.seg_count, sc.pending_cap / kPendingSegments,
                                 stream);
     if (s == MAG_OK)
-        s = launch_finish(sc, b->cap, 0, d_count, nullptr, d_out, b->idbits, posmask, sorted, stream);
+        s = launch_finish(sc, b->cap, 0, d_count, nullptr, StatsInfo{}, d_out, b->idbits, posmask, sorted,
+                          stream);
     if (s == MAG_OK && b->cap > small_sort_max()) {
         s = launch_radix_sort(sc, b->cap, b->cap, b->nbits, stream);
         if (s == MAG_OK)

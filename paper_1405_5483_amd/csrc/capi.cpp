@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -261,13 +262,13 @@ mag_status ensure_device(mag_plan *p) {
     // fixed scratch: counters[4], the count and the stats of mag_scan
     Scratch &sc = p->scratch;
     sc.device = dev;
-    e = hipMalloc(&sc.counters, 16 * sizeof(uint64_t));
+    e = hipMalloc(&sc.counters, kCounterWords * sizeof(uint64_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(MAG_E_NOMEM, "device allocation of scan scratch failed");
     }
     // the finishing kernel of every scan returns the counters to zero
-    e = hipMemset(sc.counters, 0, 16 * sizeof(uint64_t));
+    e = hipMemset(sc.counters, 0, kCounterWords * sizeof(uint64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "clearing scan counters");
     p->device = dev;
@@ -347,7 +348,9 @@ mag_status mag_plan_create(const uint8_t *patterns, uint32_t r, uint32_t m,
     if (!p) return fail(MAG_E_NOMEM, "host allocation failed");
     mag_status s;
     try {
+        const auto t0 = std::chrono::steady_clock::now();
         s = build_plan(p, patterns, r, m, params);
+        p->plan_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } catch (const std::bad_alloc &) {
         s = fail(MAG_E_NOMEM, "host allocation failed while building the plan");
     }
@@ -371,7 +374,9 @@ mag_status mag_plan_create_var(const uint8_t *bytes, const uint64_t *offsets, ui
     if (!p) return fail(MAG_E_NOMEM, "host allocation failed");
     mag_status s;
     try {
+        const auto t0 = std::chrono::steady_clock::now();
         s = build_plan_var(p, bytes, offsets, r, params);
+        p->plan_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } catch (const std::bad_alloc &) {
         s = fail(MAG_E_NOMEM, "host allocation failed while building the plan");
     }
@@ -597,7 +602,13 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     profile_mark(prof, stream);
     if (idbits_out) *idbits_out = idbits;
     if (nbits_out) *nbits_out = idbits + posbits;
-    s = launch_finish(sc, out_cap, samples, d_count, d_stats, d_out, idbits, ~0ull, nullptr, stream);
+    StatsInfo info;
+    info.q = p->q;
+    info.k = p->k;
+    info.sigma_prime = p->sigma_prime;
+    info.m_prime = p->mprime;
+    info.plan_ms = p->plan_ms;
+    s = launch_finish(sc, out_cap, samples, d_count, d_stats, info, d_out, idbits, ~0ull, nullptr, stream);
     if (s != MAG_OK) return s;
     if (sort_on_device) {
         s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, stream);
@@ -653,7 +664,7 @@ uint64_t round256(uint64_t v) { return (v + 255) & ~255ull; }
 mag_status noalloc_layout(uint8_t *base, int dev, Scratch &sc) {
     const uint64_t C = radix_scratch_chunks(kNoAllocCap);
     const uint64_t o_cnt = 0;
-    const uint64_t o_keys = round256((16 + kPendingSegments) * sizeof(uint64_t));
+    const uint64_t o_keys = round256((kCounterWords + kPendingSegments) * sizeof(uint64_t));
     const uint64_t o_hist = round256(o_keys + 2 * kNoAllocCap * sizeof(uint64_t));
     const uint64_t o_off = round256(o_hist + 256 * C * sizeof(uint32_t));
     const uint64_t o_pend = round256(o_off + (256 * C + 256) * sizeof(uint64_t));
@@ -661,7 +672,7 @@ mag_status noalloc_layout(uint8_t *base, int dev, Scratch &sc) {
     if (end > kNoAllocBytes) return fail(MAG_E_UNSUPPORTED, "allocation-free scratch layout too large");
     sc.device = dev;
     sc.counters = reinterpret_cast<uint64_t *>(base + o_cnt);
-    sc.seg_count = sc.counters + 16;
+    sc.seg_count = sc.counters + kCounterWords;
     sc.keys = reinterpret_cast<uint64_t *>(base + o_keys);
     sc.keys_cap = kNoAllocCap;
     sc.hist = reinterpret_cast<uint32_t *>(base + o_hist);
@@ -692,7 +703,7 @@ mag_status mag_scan_noalloc(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_
     if (s != MAG_OK) return s;
     // the counters and segment counters start at zero, whatever an earlier
     // call left (a fill kernel, so that the call can be captured in a graph)
-    s = launch_fill_u64(sc.counters, 16 + kPendingSegments, 0, reinterpret_cast<hipStream_t>(stream));
+    s = launch_fill_u64(sc.counters, kCounterWords + kPendingSegments, 0, reinterpret_cast<hipStream_t>(stream));
     if (s != MAG_OK) return s;
     return scan_enqueue(p, d_text, n, d_out, out_cap, d_count, d_stats, stream, true, nullptr, nullptr, &sc);
 }
@@ -729,25 +740,45 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
     }
     // the count and the counters land in the plan's own scratch words
     uint64_t *d_cnt = p->scratch.counters + 4;
-    mag_stats *d_st = reinterpret_cast<mag_stats *>(p->scratch.counters + 8);
+    mag_stats *d_st = reinterpret_cast<mag_stats *>(p->scratch.counters + kStatsSlot);
+    static_assert(kStatsSlot * 8 + sizeof(mag_stats) <= kCounterWords * 8, "stats fit the counter words");
     int idbits = 0, nbits = 0;
+    // with stats, events around the scan's kernels give scan_ms
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (stats) {
+        ev[0] = make_event();
+        ev[1] = make_event();
+        if (ev[0] && ev[1]) (void)hipEventRecord(ev[0], stream);
+    }
     mag_status s = scan_enqueue(p, d_text, n, d_out, out_cap, d_cnt, d_st, stream_, false, &idbits,
                                 &nbits);
+    if (ev[0] && ev[1] && s == MAG_OK) (void)hipEventRecord(ev[1], stream);
+    uint64_t host[kCounterWords];
+    hipError_t e = hipSuccess;
+    if (s == MAG_OK) {
+        e = hipMemcpyAsync(host, p->scratch.counters, kCounterWords * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    float scan_ms = 0.0f;
+    if (s == MAG_OK && e == hipSuccess && ev[0] && ev[1])
+        (void)hipEventElapsedTime(&scan_ms, ev[0], ev[1]);
+    for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
     if (s != MAG_OK) return s;
-    uint64_t host[12];
-    hipError_t e = hipMemcpyAsync(host, p->scratch.counters + 4, 8 * sizeof(uint64_t),
-                                  hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "reading the match count");
-    *n_matches = host[0];
-    if (stats) std::memcpy(stats, &host[4], sizeof(mag_stats));
-    if (host[0] > out_cap)
+    *n_matches = host[4];
+    if (stats) {
+        std::memcpy(stats, &host[kStatsSlot], sizeof(mag_stats));
+        stats->scan_ms = scan_ms;
+    }
+    if (host[4] > out_cap)
         return fail(MAG_E_OVERFLOW, "output capacity smaller than the match count");
-    if (host[0] > small_sort_max()) {
+    if (host[4] > small_sort_max()) {
         std::lock_guard<std::mutex> lock(p->mtx);
-        s = ensure_radix_scratch(p->scratch, host[0], stream);
-        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[0], out_cap, nbits, stream);
-        if (s == MAG_OK) s = launch_expand(p->scratch, host[0], out_cap, nbits, d_out, idbits, ~0ull, stream);
+        s = ensure_radix_scratch(p->scratch, host[4], stream);
+        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[4], out_cap, nbits, stream);
+        if (s == MAG_OK) s = launch_expand(p->scratch, host[4], out_cap, nbits, d_out, idbits, ~0ull, stream);
     }
     return s;
 }

@@ -45,10 +45,22 @@ constexpr int kHashWords = 4;       // the verification hash reads the first 16 
 // [kFinishDoneSlot] the finishing workgroups that have read the counters.
 constexpr int kSortCountSlot = 12;
 constexpr int kFinishDoneSlot = 13;
+constexpr int kStatsSlot = 16;          // mag_scan's mag_stats (7 words)
+constexpr int kCounterWords = 32;       // counter words of a scan's scratch
+
+// The plan fields a scan's finishing kernel writes into mag_stats.
+struct StatsInfo {
+    int32_t q = 0, k = 0, sigma_prime = 0, m_prime = 0;
+    float plan_ms = 0.0f;
+};
 
 // Fingerprint of the first min(m, 16) bytes of a pattern or text window, given
 // as little-endian 32-bit words with bytes past m zeroed. It only has to spread
-// keys over the probe table; equality is decided by a full compare.
+// keys over the probe table; equality is decided by a full compare. It is a
+// multiply / xor-shift mix in the style of MurmurHash3's 32-bit finalizer
+// (fmix32) and uses that finalizer's two multipliers, 0x85EBCA6B and
+// 0xC2B2AE35: one multiply and xor-shift per word, then fmix32's last three
+// steps.
 __host__ __device__ inline uint32_t window_hash(const uint32_t *w, int nwords) {
     uint32_t h = 0x9E3779B9u;
     for (int t = 0; t < nwords; ++t) {
@@ -222,6 +234,7 @@ struct mag_plan {
     // one-probe dense mode: slice_k slices per distinct pattern in a bitmap of
     // 2^bloom_log2 bits (slice_k = 0: the dense mode uses the Bloom bitmap)
     int dense_probe = MAG_DENSE_PROBE_AUTO;
+    float plan_ms = 0.0f;            // host time of mag_plan_create
     // tile shape asked for at creation (0 = auto): text bytes per tile, or
     // entries (samples, start positions) per lane (filter_lane_entries and
     // dense_lane_positions resolve them)
@@ -331,8 +344,8 @@ uint32_t small_sort_max();
 // into `sorted` if not null). Records hold ((key >> idbits) & posmask, key's
 // low idbits).
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
-                         mag_stats *d_stats, mag_match *out, int idbits, uint64_t posmask,
-                         uint64_t *sorted, hipStream_t stream);
+                         mag_stats *d_stats, const StatsInfo &info, mag_match *out, int idbits,
+                         uint64_t posmask, uint64_t *sorted, hipStream_t stream);
 // Device-wide radix sort of the keys for counts in (small_sort_max(), cap],
 // with grids sized for counts up to `bound`: the scratch for `bound`, the
 // passes over the nbits low key bits, and the records.

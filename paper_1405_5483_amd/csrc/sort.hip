@@ -156,6 +156,7 @@ struct FinishArgs {
     uint64_t *counters;    // read, published, then returned to zero
     uint64_t *d_count;
     mag_stats *d_stats;
+    StatsInfo info;
     uint64_t samples;
     mag_match *out;
     uint64_t *sorted;      // optional: the sorted keys of small outputs too
@@ -192,6 +193,12 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs a) {
                 a.d_stats->cand_windows = a.counters[1];
                 a.d_stats->verifications = a.counters[2];
                 a.d_stats->matches = z;
+                a.d_stats->q = a.info.q;
+                a.d_stats->k = a.info.k;
+                a.d_stats->sigma_prime = a.info.sigma_prime;
+                a.d_stats->m_prime = a.info.m_prime;
+                a.d_stats->plan_ms = a.info.plan_ms;
+                a.d_stats->scan_ms = 0.0f;
             }
             // the count stays for the device-wide sort
             a.counters[kSortCountSlot] = z;
@@ -403,14 +410,15 @@ uint32_t small_sort_max() { return kSmallMax; }
 int radix_passes(int nbits) { return (nbits + 7) / 8; }
 
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
-                         mag_stats *d_stats, mag_match *out, int idbits, uint64_t posmask,
-                         uint64_t *sorted, hipStream_t stream) {
+                         mag_stats *d_stats, const StatsInfo &info, mag_match *out, int idbits,
+                         uint64_t posmask, uint64_t *sorted, hipStream_t stream) {
     FinishArgs a;
     a.keys = sc.keys;
     a.cap = cap;
     a.counters = sc.counters;
     a.d_count = d_count;
     a.d_stats = d_stats;
+    a.info = info;
     a.samples = samples;
     a.out = out;
     a.sorted = sorted;

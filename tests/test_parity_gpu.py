@@ -497,7 +497,7 @@ def test_async_entry_point(torch_cuda, mag):
     buf = torch.from_numpy(T).cuda()
     out = torch.empty((4096, 2), dtype=torch.int64, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    st = torch.zeros(7, dtype=torch.int64, device="cuda")
     for _ in range(3):                 # repeated calls reuse the plan's scratch
         mag.scan_async(buf, plan, out, cnt, st)
     torch.cuda.synchronize()
@@ -506,6 +506,18 @@ def test_async_entry_point(torch_cuda, mag):
     occ = out[:z].cpu().numpy()
     _assert_same(occ[:, 0].astype(np.uint64), occ[:, 1].astype(np.uint32), ref)
     assert int(st[3].item()) == z
+    # mag_stats after the four counters: q, k, sigma', m' (int32), plan_ms,
+    # scan_ms (float32; 0 from the asynchronous entry point)
+    info = plan.info()
+    words = st.cpu().numpy().view(np.int32)
+    assert list(words[8:12]) == [info["q"], info["k"], info["sigma_prime"], info["m_prime"]]
+    floats = st.cpu().numpy().view(np.float32)
+    assert floats[12] > 0 and floats[13] == 0
+    # the synchronous entry point also times the scan
+    _, sync = mag.scan(buf, plan, stats=True)
+    assert (sync["q"], sync["k"], sync["sigma_prime"], sync["m_prime"]) == \
+        (info["q"], info["k"], info["sigma_prime"], info["m_prime"])
+    assert sync["matches"] == z and sync["scan_ms"] > 0 and sync["plan_ms"] == floats[12]
 
 
 @pytest.mark.parametrize("sel", ["heuristic", "explicit-best"])

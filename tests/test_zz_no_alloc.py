@@ -34,7 +34,7 @@ def mag():
 def _records(torch, mag, fn, text, plan, cap):
     out = torch.full((cap, 2), -1, dtype=torch.int64, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    st = torch.zeros(7, dtype=torch.int64, device="cuda")
     fn(text, plan, out, cnt, st)
     torch.cuda.synchronize()
     z = int(cnt.item())
