@@ -289,7 +289,7 @@ def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
     z = sum(r[0].size for r in refs)
     fixed = [mag.Plan(j.patterns) for j in jobs]
     t = time.perf_counter()
-    picks = selector.picks([j.patterns for j in jobs], threads=CPU_SHARE)
+    picks = selector.picks([j.patterns for j in jobs], threads=CPU_SHARE, batch=True)
     learned = [mag.Plan(j.patterns, **pk) for j, pk in zip(jobs, picks)]
     select_ms = (time.perf_counter() - t) * 1e3
 

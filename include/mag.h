@@ -374,11 +374,13 @@ mag_status mag_scan_batch(const mag_job *jobs, uint32_t njobs, mag_match *d_out,
  *
  * The paper fixes q and k by formulas (Section 3.2) and lowers sigma' until
  * the sigma'^q table fits (Section 3.3). The selector predicts instead, from
- * 16 statistics of the pattern set, the scan cost per text byte of each
- * triple of a fixed grid of 64 (q, k, sigma') candidates, with a small
- * network (16 -> 64 ReLU -> 64 ReLU -> 64, FP32) whose forward, gradient,
- * Adam and selection kernels run on the device; it takes the cheapest
- * feasible candidate and falls back to the heuristic.
+ * 16 statistics of the pattern set, the scan cost per text byte (outputs
+ * 0..31) and the verifications per text byte (outputs 32..63) of each of 32
+ * choices, with a small network (16 -> 64 ReLU -> 64 ReLU -> 64, FP32) whose
+ * forward, gradient, Adam and selection kernels run on the device; it takes
+ * the choice of lowest predicted cost among the feasible ones and falls back
+ * to the heuristic. Both output groups are trained on what the scans
+ * themselves measure: their kernel time and their verification count.
  *
  * Features (host floats): f0 log2(sigma_P)/8, f1 m/32, f2 log10(r)/4, f3 byte
  * entropy/8, f4 largest byte frequency, f5 distinct patterns / r, f5+q for
@@ -386,16 +388,24 @@ mag_status mag_scan_batch(const mag_job *jobs, uint32_t njobs, mag_match *d_out,
  * substrings of the patterns (1 if q > m, 0 if sigma_P = 1), f14 the
  * heuristic's q (at most 8) / 8, f15 log2(r*m)/20.
  *
- * Candidate c < 64: q = c/8 + 1, k = (c/2)%4 + 1; feasible iff 2q-1 <= m,
- * k <= L and W = k*m' <= 32; sigma' = fit (even c) or max(2, fit/2) (odd c,
- * infeasible when equal to fit), fit = the largest s <= sigma_P with
- * s^q * entry_bytes(W) <= 64 KiB; greedy map. Feasible picks also run in
- * batches (W <= 32). */
+ * Choices: 0 = the dense mode (mode MAG_MODE_DENSE; q, k, sigma' from the
+ * heuristic), 1 = the alphabet mapping on q-grams (MAG_MAP_QGRAM with its
+ * heuristic; feasible when r > 0; batches reject it), 2..31 = filter triples
+ * (mode MAG_MODE_FILTER, greedy map): c = 2..25 take q = (2, 3, 4, 5, 6, 8)[i/4],
+ * k = (i/2)%2 + 1, level i%2 for i = c - 2; 26..29 take (q, k) = (2, 3),
+ * (3, 3), (4, 3), (2, 4) at level 0; 30 and 31 take q = 7, k = 1 at levels 0
+ * and 1. A triple is feasible iff 2q-1 <= m, k <= L and W = k*m' <= 32;
+ * sigma' = fit (level 0) or max(2, fit/2) (level 1, infeasible when equal to
+ * fit), fit = the largest s <= sigma_P with s^q * entry_bytes(W) <= 64 KiB.
+ * Feasible filter picks also run in batches (W <= 32). Slots 32..63 are never
+ * feasible (they are the verification outputs). */
 
 /* out: 16 floats. Errors: r == 0 or m == 0 -> MAG_E_INVALID. */
 mag_status mag_select_features(const uint8_t *patterns, uint32_t r, uint32_t m, float *out);
 
-/* out[64] parameters (select = explicit) and feasible[64] (1 or 0). */
+/* out[64] parameters of the choices (filter triples: select = explicit; the
+ * dense and q-gram choices: select = learned with q, k, sigma' left to the
+ * plan's heuristics) and feasible[64] (1 or 0; slots 32..63 always 0). */
 mag_status mag_select_candidates(const uint8_t *patterns, uint32_t r, uint32_t m,
                                  mag_params *out, uint8_t *feasible);
 

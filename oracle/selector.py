@@ -24,12 +24,20 @@ bytes):
   f14 min(q of Section 3.2's formula, 8) / 8 (the feature saturates at 8)
   f15 log2(N) / 20
 
-Candidate c (0..63): q = c // 8 + 1, k = (c // 2) % 4 + 1, level = c % 2.
+Choices c (0..31), each returned as (kind, q, k, sigma'):
+  0   ("dense", 0, 0, 0): every start position tested (always feasible);
+  1   ("qgram", 0, 0, 0): the alphabet mapping on q-grams with its own
+      heuristic (feasible when r > 0);
+  2.. filter triples ("filter", q, k, sigma') with the greedy map:
+      c = 2..25: i = c - 2, q = (2, 3, 4, 5, 6, 8)[i // 4], k = (i // 2) % 2 + 1,
+      level = i % 2; 26..29: (q, k) = (2, 3), (3, 3), (4, 3), (2, 4), level 0;
+      30, 31: q = 7, k = 1, levels 0 and 1.
 Feasible iff 2q - 1 <= m, k <= L = (m - q + 1) // q and W = k m' <= 32 with
 m' = min(L // k, 64 // k) >= 1. Entry bytes e(W) in {1, 2, 4}; "fit" is the
 largest s <= sigma_P with s^q e(W) <= 64 KiB; level 0 takes sigma' = fit,
-level 1 sigma' = max(2, fit // 2), infeasible when that equals fit. The map
-is the greedy one.
+level 1 sigma' = max(2, fit // 2), infeasible when that equals fit.
+The network has 64 outputs: 0..31 predict each choice's cost, 32..63 its
+verifications per byte; slots 32..63 are never choices (None).
 """
 
 from __future__ import annotations
@@ -41,7 +49,10 @@ import numpy as np
 from . import method
 
 N_FEATURES = 16
-N_CANDIDATES = 64
+N_CANDIDATES = 64       # network outputs
+N_CHOICES = 32          # outputs that are choices (the rest predict verifications)
+_QS = (2, 3, 4, 5, 6, 8)
+_EXTRA = {26: (2, 3, 0), 27: (3, 3, 0), 28: (4, 3, 0), 29: (2, 4, 0), 30: (7, 1, 0), 31: (7, 1, 1)}
 TABLE_BUDGET = 64 * 1024
 MAX_W_BATCH = 32
 
@@ -86,12 +97,26 @@ def features(patterns: np.ndarray) -> np.ndarray:
     return f
 
 
+def grid_entry(c: int):
+    """(q, k, level) of filter choice c (2 <= c < 32)."""
+    if c < 26:
+        i = c - 2
+        return _QS[i // 4], (i // 2) % 2 + 1, i % 2
+    return _EXTRA[c]
+
+
 def candidate(patterns: np.ndarray, c: int):
-    """(q, k, sigma') of candidate c for this set, or None if infeasible."""
+    """(kind, q, k, sigma') of choice c for this set, or None if infeasible."""
     p = np.asarray(patterns, dtype=np.uint8)
     r, m = p.shape
+    if c >= N_CHOICES:
+        return None
+    if c == 0:
+        return ("dense", 0, 0, 0)
+    if c == 1:
+        return ("qgram", 0, 0, 0) if r > 0 else None
     sp = max(method.sigma_p(p), 1)
-    q, k, level = c // 8 + 1, (c // 2) % 4 + 1, c % 2
+    q, k, level = grid_entry(c)
     if 2 * q - 1 > m:
         return None
     L = (m - q + 1) // q
@@ -107,11 +132,11 @@ def candidate(patterns: np.ndarray, c: int):
         if s ** q * e <= TABLE_BUDGET:
             fit = s
     if level == 0:
-        return (q, k, fit)
+        return ("filter", q, k, fit)
     half = max(2, fit // 2)
     if half >= fit:
         return None
-    return (q, k, half)
+    return ("filter", q, k, half)
 
 
 def candidates(patterns: np.ndarray):

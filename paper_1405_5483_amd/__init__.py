@@ -469,7 +469,8 @@ def autotune_batch(patterns, texts, *, sample_bytes: int = 0, stream=None, **opt
 # ------------------------------------------------------------------ learned selection
 
 SEL_FEATURES = 16
-SEL_CANDIDATES = 64
+SEL_CANDIDATES = 64      # network outputs
+SEL_CHOICES = 32         # outputs 0..31: the choices' costs; 32..63: their verifications
 
 
 def select_features(patterns) -> np.ndarray:
@@ -481,16 +482,36 @@ def select_features(patterns) -> np.ndarray:
     return out
 
 
+def _choice(prm: MagParams):
+    if prm.mode == MODE["dense"]:
+        return ("dense", 0, 0, 0)
+    if prm.map_kind == MAP_KIND["qgram"]:
+        return ("qgram", 0, 0, 0)
+    return ("filter", prm.q, prm.k, prm.sigma_prime)
+
+
+def choice_kwargs(choice) -> dict:
+    """Plan keyword arguments of a selector choice (kind, q, k, sigma')."""
+    kind, q, k, sp = choice
+    if kind == "dense":
+        return {"select": "learned", "mode": "dense"}
+    if kind == "qgram":
+        return {"select": "learned", "map_kind": "qgram", "mode": "filter"}
+    return {"select": "learned", "q": q, "k": k, "sigma_prime": sp, "map_kind": "greedy",
+            "mode": "filter"}
+
+
 def select_candidates(patterns):
-    """The 64 candidate triples of a set: list of (q, k, sigma') or None."""
+    """The selector's 64 output slots for a set: (kind, q, k, sigma') for
+    the feasible choices among slots 0..31 (kind "dense", "qgram" or
+    "filter"), None elsewhere."""
     p = _as_patterns(patterns)
     prm = (MagParams * SEL_CANDIDATES)()
     feas = np.zeros(SEL_CANDIDATES, dtype=np.uint8)
     check(lib().mag_select_candidates(p.ctypes.data if p.size else None, p.shape[0], p.shape[1],
                                       ctypes.cast(prm, ctypes.c_void_p), feas.ctypes.data),
           "mag_select_candidates")
-    return [(prm[c].q, prm[c].k, prm[c].sigma_prime) if feas[c] else None
-            for c in range(SEL_CANDIDATES)]
+    return [_choice(prm[c]) if feas[c] else None for c in range(SEL_CANDIDATES)]
 
 
 class Selector:
@@ -581,13 +602,13 @@ class Selector:
                                        p.shape[1], ctypes.byref(out), _stream_ptr(stream)),
               "mag_select_learned")
         if out.select == SELECT["learned"]:
-            return {"q": out.q, "k": out.k, "sigma_prime": out.sigma_prime, "map_kind": "greedy",
-                    "select": "learned"}
+            return choice_kwargs(_choice(out))
         return {"select": "heuristic"}
 
-    def picks(self, pattern_sets, threads: int = 16, stream=None) -> list[dict]:
+    def picks(self, pattern_sets, threads: int = 16, stream=None, batch: bool = False) -> list[dict]:
         """Parameters for many sets: features on host threads, one selection
-        launch for all of them."""
+        launch for all of them. batch=True leaves out the q-gram map, which
+        batches do not take."""
         import concurrent.futures as cf
         import torch
         sets = [_as_patterns(p) for p in pattern_sets]
@@ -599,7 +620,8 @@ class Selector:
         with cf.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
             prepped = list(ex.map(prep, sets))
         X = np.stack([f for f, _ in prepped]).astype(np.float32)
-        F = np.array([[c is not None for c in cand] for _, cand in prepped], dtype=np.uint8)
+        F = np.array([[c is not None and not (batch and c[0] == "qgram") for c in cand]
+                      for _, cand in prepped], dtype=np.uint8)
         xd = torch.from_numpy(X).cuda()
         fd = torch.from_numpy(F).cuda()
         pk = self.select(xd, fd, stream).cpu().numpy()
@@ -608,9 +630,7 @@ class Selector:
             if c < 0:
                 out.append({"select": "heuristic"})
             else:
-                q, k, sp = cand[c]
-                out.append({"q": q, "k": k, "sigma_prime": sp, "map_kind": "greedy",
-                            "select": "learned", "candidate": int(c)})
+                out.append({**choice_kwargs(cand[c]), "candidate": int(c)})
         return out
 
     def close(self):

@@ -14,6 +14,7 @@ namespace mag {
 constexpr int kSelIn = 16;
 constexpr int kSelHid = 64;
 constexpr int kSelOut = 64;
+constexpr int kSelChoices = 32;   // outputs 0..31 predict cost, 32..63 verifications
 constexpr int kSelW1 = 0;
 constexpr int kSelB1 = kSelW1 + kSelHid * kSelIn;
 constexpr int kSelW2 = kSelB1 + kSelHid;

@@ -4,9 +4,10 @@
 //
 // The paper fixes q and k by formulas (Section 3.2) and lowers sigma' to keep
 // sigma'^q tables small (Section 3.3). The selector instead predicts, for
-// every triple of a fixed grid, the scan cost per text byte from statistics
-// of the pattern set, and takes the cheapest feasible triple; the fixed
-// formulas remain the fallback.
+// each of 32 choices (the dense mode, the alphabet mapping on q-grams, and 30
+// (q, k, sigma') filter triples), the scan cost per text byte and the
+// verifications per text byte from statistics of the pattern set, and takes
+// the cheapest feasible choice; the fixed formulas remain the fallback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +23,27 @@ namespace {
 
 constexpr uint64_t kSelTableBudget = 64 * 1024;
 constexpr int kSelMaxW = 32;      // batch-compatible state width
+
+// Filter triples of choices 2..31: (q, k, level); level 0 takes sigma' = fit,
+// level 1 sigma' = max(2, fit / 2).
+struct GridEntry {
+    int q, k, level;
+};
+GridEntry filter_entry(int c) {
+    static const int qs[6] = {2, 3, 4, 5, 6, 8};
+    if (c < 26) {
+        const int i = c - 2;
+        return {qs[i / 4], (i / 2) % 2 + 1, i % 2};
+    }
+    switch (c) {
+        case 26: return {2, 3, 0};
+        case 27: return {3, 3, 0};
+        case 28: return {4, 3, 0};
+        case 29: return {2, 4, 0};
+        case 30: return {7, 1, 0};
+        default: return {7, 1, 1};
+    }
+}
 
 // D[q-1] = number of distinct q-byte substrings (q = 1..8) over every
 // pattern and offset. Every window (pattern, offset) gets the key of its next
@@ -151,10 +173,23 @@ mag_status mag_select_candidates(const uint8_t *patterns, uint32_t r, uint32_t m
     for (bool b : present) sp += b ? 1 : 0;
     sp = std::max(sp, 1);
     for (int c = 0; c < kSelOut; ++c) {
-        mag_params &o = out[c];
-        std::memset(&o, 0, sizeof(o));
+        std::memset(&out[c], 0, sizeof(out[c]));
         feasible[c] = 0;
-        const int q = c / 8 + 1, k = (c / 2) % 4 + 1, level = c % 2;
+    }
+    // choice 0: every start position tested (the plan's heuristic q, k, sigma'
+    // only shape the unused filter); choice 1: the alphabet mapping on
+    // q-grams with its own heuristic
+    out[0].select = MAG_SELECT_LEARNED;
+    out[0].mode = MAG_MODE_DENSE;
+    feasible[0] = 1;
+    out[1].select = MAG_SELECT_LEARNED;
+    out[1].mode = MAG_MODE_FILTER;
+    out[1].map_kind = MAG_MAP_QGRAM;
+    feasible[1] = r > 0 ? 1 : 0;
+    for (int c = 2; c < kSelChoices; ++c) {
+        mag_params &o = out[c];
+        const GridEntry g = filter_entry(c);
+        const int q = g.q, k = g.k;
         if (2 * q - 1 > (int)m) continue;
         const int L = ((int)m - q + 1) / q;
         if (k > L) continue;
@@ -168,11 +203,12 @@ mag_status mag_select_candidates(const uint8_t *patterns, uint32_t r, uint32_t m
             if (codes * e <= (double)kSelTableBudget) fit = s;
         }
         int sig = fit;
-        if (level == 1) {
+        if (g.level == 1) {
             sig = std::max(2, fit / 2);
             if (sig >= fit) continue;
         }
         o.select = MAG_SELECT_EXPLICIT;
+        o.mode = MAG_MODE_FILTER;
         o.map_kind = MAG_MAP_GREEDY;
         o.q = q;
         o.k = k;
@@ -299,7 +335,7 @@ mag_status mag_select_learned(mag_mlp *h, const uint8_t *patterns, uint32_t r, u
     e = hipMemcpyAsync(&pick, h->pick1, sizeof(pick), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "selector pick download");
-    if (pick >= 0 && pick < kSelOut && feas[pick]) {
+    if (pick >= 0 && pick < kSelChoices && feas[pick]) {
         *out = cand[pick];
         out->select = MAG_SELECT_LEARNED;
     }

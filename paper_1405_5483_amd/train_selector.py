@@ -5,17 +5,23 @@
     python -m paper_1405_5483_amd.train_selector evaluate --model selector_model.npz --sets 2000
 
 collect: pattern sets drawn like the batched workload's (sigma in {4, 20, 64},
-uniform or Zipf(1.0) text, r log-uniform over 10..10^4, m in {8, 16, 32},
-half of the set sampled from its text), against six 16 MiB training texts
-(one per sigma and distribution). For each set, ``--per-set`` random
-feasible candidates of the grid are timed: the scan kernel's device time
-(HIP events around it), the smaller of two runs, as log2 nanoseconds per
-text byte. Set seeds come from SeedSequence(5) and text seeds from
-SeedSequence(5) too (a separate spawn).
+uniform or Zipf(1.0) text, r log-uniform over 10^a..10^b with (a, b) = --r-exp,
+1..4 by default, m in {8, 16, 32}, half of the set sampled from its text),
+against six 16 MiB training texts
+(one per sigma and distribution). For each set, the dense choice and
+``--per-set`` - 1 other random feasible choices of the grid are scanned: the
+scan kernel's device time (HIP events around it), the smaller of two runs,
+as log2 nanoseconds per text byte (outputs 0..31), and the scan's
+verification count, as log2 of verifications per text byte plus 2^-24
+(outputs 32..63). Set seeds come from SeedSequence(--seed, 5 by default) and
+text seeds from SeedSequence(5) (a separate spawn). The shipped model is
+trained on 20,000 sets with r over 10..10^4 (seed 5) and 5,000 with r over
+10^4..10^5 (seed 7), which reaches the 100,000-pattern protein workload.
 
 train: the network (16 -> 64 -> 64 -> 64) is trained on the device by the
-library's own gradient and Adam kernels, on targets standardized over the
-training labels, with the masked squared error over the timed candidates.
+library's own gradient and Adam kernels, on targets standardized per output
+group (costs, verifications) over the training labels, with the masked
+squared error over the scanned choices.
 
 evaluate: held-out sets (SeedSequence(6)) over six 64 MiB texts: each set is
 scanned with the fixed heuristic's parameters and with the network's pick;
@@ -53,14 +59,15 @@ def make_texts(synth, n: int, seed: int):
             for (s, d), k in zip(TEXT_KINDS, kids)]
 
 
-def set_recipes(count: int, seed: int):
-    """(text index, r, m, generator seed) per pattern set."""
+def set_recipes(count: int, seed: int, r_exp=(1.0, 4.0)):
+    """(text index, r, m, generator seed) per pattern set; r log-uniform
+    over 10^r_exp[0]..10^r_exp[1]."""
     ss = np.random.SeedSequence([seed, 1])
     out = []
     for child in ss.spawn(count):
         rng = np.random.Generator(np.random.PCG64(child))
         t = int(rng.integers(0, len(TEXT_KINDS)))
-        r = int(round(10.0 ** rng.uniform(1.0, 4.0)))
+        r = int(round(10.0 ** rng.uniform(r_exp[0], r_exp[1])))
         m = int(rng.choice([8, 16, 32]))
         out.append((t, r, m, child.spawn(1)[0]))
     return out
@@ -73,30 +80,35 @@ def make_set(synth, texts, recipe):
     return synth.gen_patterns(texts[t], r, m, r // 2, sigma, rng)
 
 
-def _scan_ms(torch, mag, text, plan, out, cnt, repeats=2):
+def _scan_ms(torch, mag, text, plan, out, cnt, repeats=2, stats=None):
     """Device time of the scan kernel alone (the library's profiling
-    events), the smaller of `repeats` runs."""
+    events), the smaller of `repeats` runs; with stats (an int64 [7] CUDA
+    tensor) also the scan's verification count."""
     best = math.inf
     for _ in range(repeats):
         mag.profile_read()
-        mag.scan_async(text, plan, out, cnt)
+        mag.scan_async(text, plan, out, cnt, stats)
         t = mag.profile_read()["scan_ms"]
         best = min(best, t)
-    return best
+    if stats is None:
+        return best
+    return best, int(stats[2].item())
 
 
 def collect(args):
     torch, synth, mag = _import()
     texts = make_texts(synth, args.text_bytes, 5)
     dtexts = [torch.from_numpy(t).cuda() for t in texts]
-    recipes = set_recipes(args.start + args.sets, 5)[args.start:]
+    recipes = set_recipes(args.start + args.sets, args.seed, tuple(args.r_exp))[args.start:]
     rng = np.random.default_rng(args.start + 12345)
     out = torch.empty((8192, 2), dtype=torch.int64, device="cuda")
     cnt = torch.empty(1, dtype=torch.int64, device="cuda")
     mag.profile_enable(True)
+    st = torch.zeros(7, dtype=torch.int64, device="cuda")
     X = np.zeros((len(recipes), mag.SEL_FEATURES), np.float32)
     T = np.zeros((len(recipes), mag.SEL_CANDIDATES), np.float32)
     M = np.zeros((len(recipes), mag.SEL_CANDIDATES), np.uint8)
+    V = np.zeros((len(recipes), mag.SEL_CHOICES), np.float64)   # verifications per byte, as measured
     H = np.zeros(len(recipes), np.float32)     # the heuristic's own cost, for reference
     ex = cf.ThreadPoolExecutor(max_workers=args.threads)
     t0 = time.time()
@@ -104,23 +116,26 @@ def collect(args):
         P = make_set(synth, texts, rec)
         X[i] = mag.select_features(P)
         cand = mag.select_candidates(P)
-        feas = [c for c in range(mag.SEL_CANDIDATES) if cand[c] is not None]
-        pick = rng.choice(feas, size=min(args.per_set, len(feas)), replace=False)
-        specs = [dict(q=cand[c][0], k=cand[c][1], sigma_prime=cand[c][2]) for c in pick] + [{}]
+        feas = [c for c in range(1, mag.SEL_CHOICES) if cand[c] is not None]
+        pick = [0] + list(rng.choice(feas, size=min(args.per_set - 1, len(feas)), replace=False))
+        specs = [mag.choice_kwargs(cand[c]) for c in pick] + [{}]
         plans = list(ex.map(lambda kw: mag.Plan(P, **kw), specs))
         n = texts[rec[0]].size
-        for c, plan in zip(list(pick) + [-1], plans):
-            ms = _scan_ms(torch, mag, dtexts[rec[0]], plan, out, cnt)
+        for c, plan in zip(pick + [-1], plans):
+            ms, ver = _scan_ms(torch, mag, dtexts[rec[0]], plan, out, cnt, stats=st)
             lab = math.log2(ms * 1e6 / n)
             if c >= 0:
                 T[i, c] = lab
                 M[i, c] = 1
+                V[i, c] = ver / n
+                T[i, mag.SEL_CHOICES + c] = math.log2(ver / n + 2.0 ** -24)
+                M[i, mag.SEL_CHOICES + c] = 1
             else:
                 H[i] = lab
             plan.close()
         if (i + 1) % 200 == 0:
             print(f"collect: {i + 1}/{len(recipes)} sets, {time.time() - t0:.0f} s", flush=True)
-    np.savez(args.out, X=X, T=T, M=M, H=H, start=args.start, text_bytes=args.text_bytes)
+    np.savez(args.out, X=X, T=T, M=M, V=V, H=H, start=args.start, text_bytes=args.text_bytes)
     print(f"collect: wrote {args.out}", flush=True)
 
 
@@ -130,8 +145,12 @@ def train(args):
     X = np.concatenate([p["X"] for p in parts]).astype(np.float32)
     T = np.concatenate([p["T"] for p in parts]).astype(np.float64)
     M = np.concatenate([p["M"] for p in parts]).astype(np.uint8)
-    lab = T[M == 1]
-    mu, sd = float(lab.mean()), float(lab.std() + 1e-9)
+    # standardized per output group: the choices' costs, their verifications
+    C = mag.SEL_CHOICES
+    mu, sd = np.zeros(T.shape[1]), np.ones(T.shape[1])
+    for g in (slice(0, C), slice(C, T.shape[1])):
+        lab = T[:, g][M[:, g] == 1]
+        mu[g], sd[g] = float(lab.mean()), float(lab.std() + 1e-9)
     Tn = np.where(M == 1, (T - mu) / sd, 0.0).astype(np.float32)
     n = X.shape[0]
     rng = np.random.default_rng(args.seed)
@@ -167,7 +186,7 @@ def train(args):
                              md[torch.from_numpy(tr).cuda()])
             print(f"train: epoch {ep} lr {lr:.2e} train {float(tl.item()):.4f} val {v:.4f}", flush=True)
     np.savez(args.model, params=best_p, target_mean=mu, target_std=sd, val_loss=best,
-             n_sets=n, n_labels=int(M.sum()))
+             n_sets=n, n_labels=int(M.sum()), n_cost_labels=int(M[:, :C].sum()))
     print(f"train: best val {best:.4f}, wrote {args.model}", flush=True)
 
 
@@ -222,6 +241,8 @@ def main(argv=None):
     c.add_argument("--text-bytes", type=int, default=16 << 20)
     c.add_argument("--threads", type=int, default=16)
     c.add_argument("--out", required=True)
+    c.add_argument("--seed", type=int, default=5)
+    c.add_argument("--r-exp", type=float, nargs=2, default=[1.0, 4.0])
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--model", default=DEFAULT_MODEL)

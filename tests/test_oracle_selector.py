@@ -63,25 +63,35 @@ def test_distinct_substrings_brute_force():
 def test_candidates_dna_m8():
     P = _pats([b"ACGTACGT", b"TTGACCAG"])     # sigma_P = 4, m = 8
     c = selector.candidates(P)
-    assert c[0] == (1, 1, 4) and c[1] == (1, 1, 2)           # q=1, k=1
-    assert c[2] == (1, 2, 4)                                 # k=2: m'=4, W=8
-    assert c[8 * 3 + 0] == (4, 1, 4) and c[8 * 3 + 1] == (4, 1, 2)
-    assert c[8 * 3 + 2] is None                              # q=4: L=1 < k=2
-    assert all(x is None for x in c[8 * 4:])                 # q >= 5: 2q-1 > 8
+    assert c[0] == ("dense", 0, 0, 0) and c[1] == ("qgram", 0, 0, 0)
+    # choices 2..5: q = 2 with (k, level) = (1, 0), (1, 1), (2, 0), (2, 1)
+    assert c[2] == ("filter", 2, 1, 4) and c[3] == ("filter", 2, 1, 2)   # 4^2 tiny
+    assert c[4] == ("filter", 2, 2, 4)                       # L = 3, m' = 1, W = 2
+    # choices 14..17: q = 5 (2q-1 = 9 > 8): infeasible; so is q = 8
+    assert all(x is None for x in c[14:26])
+    assert c[10] == ("filter", 4, 1, 4)                      # q = 4: L = 1
+    assert c[12] is None                                     # q = 4, k = 2 > L
+    assert c[26] == ("filter", 2, 3, 4)                      # k = 3 <= L = 3
+    assert c[29] is None                                     # q = 2, k = 4 > L
+    assert c[30] is None and c[31] is None                   # q = 7: 2q-1 = 13 > 8
+    assert all(x is None for x in c[32:])                    # verification outputs
 
 
 def test_candidates_protein_m16():
     rng = np.random.default_rng(1)
     P = rng.choice(np.frombuffer(b"ACDEFGHIKLMNPQRSTVWY", dtype=np.uint8), size=(200, 16))
     c = selector.candidates(P)
-    assert c[8 * 3 + 0] == (4, 1, 16)       # 16^4 = 65536 fits 64 KiB, 17^4 does not
-    assert c[8 * 3 + 1] == (4, 1, 8)
-    assert c[8 * 3 + 4] == (4, 3, 16)       # k=3: m'=1, W=3
-    assert c[8 * 3 + 6] is None             # k=4 > L=3
-    assert c[8 * 7 + 0] == (8, 1, 4)        # 4^8 = 65536
-    assert c[8 * 7 + 1] == (8, 1, 2)
-    assert c[0] == (1, 1, 20)               # q=1: the whole alphabet
-    assert c[6] == (1, 4, 20) and c[7] == (1, 4, 10)
+    assert c[10] == ("filter", 4, 1, 16)    # 16^4 = 65536 fits 64 KiB, 17^4 does not
+    assert c[11] == ("filter", 4, 1, 8)
+    assert c[28] == ("filter", 4, 3, 16)    # k = 3: m' = 1, W = 3
+    assert c[22] == ("filter", 8, 1, 4)     # 4^8 = 65536
+    assert c[23] == ("filter", 8, 1, 2)
+    assert c[24] is None                    # q = 8, k = 2 > L = 1
+    assert c[2] == ("filter", 2, 1, 20)     # 20^2 fits: the whole alphabet
+    assert c[29] == ("filter", 2, 4, 20) and c[30] == ("filter", 7, 1, 4)
+    assert c[0] == ("dense", 0, 0, 0) and c[1] == ("qgram", 0, 0, 0)
+    # no patterns: the q-gram map has nothing to map
+    assert selector.candidates(np.zeros((0, 16), np.uint8))[1] is None
 
 
 def test_candidates_respect_budget_and_width():
@@ -90,15 +100,16 @@ def test_candidates_respect_budget_and_width():
         for sig in (2, 4, 20, 64):
             P = rng.integers(0, sig, size=(50, m)).astype(np.uint8)
             for c, t in enumerate(selector.candidates(P)):
-                if t is None:
+                if t is None or t[0] != "filter":
                     continue
-                q, k, sp = t
+                _, q, k, sp = t
                 L = (m - q + 1) // q
                 W = k * min(L // k, 64 // k)
                 e = 1 if W <= 8 else 2 if W <= 16 else 4
+                assert 2 <= c < 32
                 assert 2 * q - 1 <= m and 1 <= k <= L and 1 <= W <= 32
                 assert sp ** q * e <= 64 * 1024 and sp <= max(len(np.unique(P)), 1)
-                assert (q, k) == (c // 8 + 1, (c // 2) % 4 + 1)
+                assert (q, k) == selector.grid_entry(c)[:2]
 
 
 # -------------------------------------------------------------------- MLP
