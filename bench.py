@@ -15,6 +15,9 @@ library on the scan's own stream, in a second pass over the same steps so
 that the events stay out of the per-step time), the CPU oracle timed on the
 host's cores, and further measurements, each checked against the oracle:
 
+* filter_mode: the same 1 GiB scan through the paper's filter kernel (the
+  dense mode switched off), with the heuristic's parameters and with
+  q = 5, k = 1, sigma' = 20, and each one's verifications per text byte;
 * workloads.zipf256m: the 256 MiB Zipf scan (filter kernel) with its own
   roofline block, the fixed heuristic beside it, and MAG against SMAG (the
   text encoded first) with the same plan;
@@ -278,8 +281,11 @@ def learned_vs_fixed(torch, mag, selector, sets: int, text_bytes: int, oracle_ev
                       f"with at most {cap} occurrences) whose two sorted occurrence lists are identical"}
 
 
-def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
-    import numpy as np
+def batch_section(torch, mag, selector, steps: int, stream_gbps: float, plans: str = "all"):
+    """The 512-job workload: per-job scans with fixed parameters, and the
+    batched kernel with fixed, learned and autotuned plans, every job's list
+    checked against the oracle. plans="learned" runs only the batch of learned
+    plans."""
     from oracle import match as om
     from synth import batch_jobs
     jobs = batch_jobs(512, workers=CPU_SHARE)
@@ -287,22 +293,10 @@ def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
     texts = [torch.from_numpy(j.text).cuda() for j in jobs]
     refs = [om.occ_hashed(j.text, j.patterns, threads=CPU_SHARE) for j in jobs]
     z = sum(r[0].size for r in refs)
-    fixed = [mag.Plan(j.patterns) for j in jobs]
     t = time.perf_counter()
     picks = selector.picks([j.patterns for j in jobs], threads=CPU_SHARE, batch=True)
     learned = [mag.Plan(j.patterns, **pk) for j, pk in zip(jobs, picks)]
     select_ms = (time.perf_counter() - t) * 1e3
-
-    # per-job scans with fixed parameters, one after another
-    torch.cuda.synchronize()
-    per_job = []
-    for rep in range(2):
-        t = time.perf_counter()
-        for tx, p in zip(texts, fixed):
-            mag.scan(tx, p)
-        torch.cuda.synchronize()
-        per_job.append((time.perf_counter() - t) * 1e3)
-    per_job_ms = min(per_job)
 
     def batched(plans, words_per_lane=0):
         b = mag.Batch(plans, words_per_lane=words_per_lane)
@@ -345,8 +339,27 @@ def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
         b.close()
         return ms, exact, prof["scan_ms"] / max(prof["launches"], 1)
 
-    bf_ms, bf_exact, bf_k = batched(fixed)
     bl_ms, bl_exact, bl_k = batched(learned)
+    traffic, src = profiled_traffic("batch512", None, "k_batch")
+    roof = roofline_block("k_batch", total, bl_k, stream_gbps, traffic, src)
+    if plans == "learned":
+        return {"jobs": 512, "text_bytes": total, "occurrences": z,
+                "batched_learned_ms": round(bl_ms, 3), "k_batch_learned_ms": round(bl_k, 4),
+                "batched_learned_GBps": round(total / (bl_ms * 1e-3) / 1e9, 2),
+                "roofline": roof, "bit_exact": bool(bl_exact)}
+
+    # per-job scans with fixed parameters, one after another
+    fixed = [mag.Plan(j.patterns) for j in jobs]
+    torch.cuda.synchronize()
+    per_job = []
+    for rep in range(2):
+        t = time.perf_counter()
+        for tx, p in zip(texts, fixed):
+            mag.scan(tx, p)
+        torch.cuda.synchronize()
+        per_job.append((time.perf_counter() - t) * 1e3)
+    per_job_ms = min(per_job)
+    bf_ms, bf_exact, bf_k = batched(fixed)
     # autotuned: one tuned pick per job class, then the batched kernel's words
     # per lane, timed on the batch itself (host work before the timed region)
     t = time.perf_counter()
@@ -355,7 +368,6 @@ def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
     tuned = [mag.Plan(j.patterns, **kw) for j, kw in zip(jobs, tuned_kw)]
     tune_s = time.perf_counter() - t
     ba_ms, ba_exact, ba_k = batched(tuned, tuned_wpl)
-    traffic, src = profiled_traffic("batch512", None, "k_batch")
     return {"jobs": 512, "text_bytes": total, "occurrences": z,
             "per_job_fixed_ms": round(per_job_ms, 3),
             "batched_fixed_ms": round(bf_ms, 3), "batched_learned_ms": round(bl_ms, 3),
@@ -369,11 +381,50 @@ def batch_section(torch, mag, selector, steps: int, stream_gbps: float):
             "speedup_learned_vs_fixed_batched": round(bf_ms / bl_ms, 3),
             "k_batch_fixed_ms": round(bf_k, 4), "k_batch_learned_ms": round(bl_k, 4),
             "k_batch_autotuned_ms": round(ba_k, 4),
-            "roofline": roofline_block("k_batch", total, bl_k, stream_gbps, traffic, src),
+            "roofline": roof,
             "selector_ms": round(select_ms, 1),
             "bit_exact": bool(bf_exact and bl_exact and ba_exact),
             "timing": "graph replays of bind-time launches; k_batch from library events on eager runs; "
                       "per-job scans wall clock"}
+
+
+def compare_section(torch, mag, job, text, ref, z, out, cnt, steps: int, warmup: int):
+    """The headline workload with the fixed heuristic's parameters, and
+    through the paper's filter kernel (the dense mode switched off) with the
+    heuristic's parameters and with q = 5, k = 1, sigma' = 20; each checked
+    against the oracle."""
+    n = job.n
+    # the same workload with the fixed heuristic's parameters
+    fixed_plan = mag.Plan(job.patterns)
+    finfo = fixed_plan.info()
+    fixed_ms, fprof = time_scans(torch, mag, text, fixed_plan, out, cnt, steps, warmup)
+    fz = int(cnt.item())
+    fixed_exact = fz == z and (ref is None or oracle_equal(out[:fz].cpu().numpy(), ref))
+    fixed = {"GBps": round(n / (fixed_ms * 1e-3) / 1e9, 3), "ms_per_step": round(fixed_ms, 5),
+             "scan_kernel_ms": round(fprof["scan_ms"] / max(fprof["launches"], 1), 5),
+             "q": finfo["q"], "k": finfo["k"], "sigma_prime": finfo["sigma_prime"],
+             "kernel": scan_kernel_name(finfo), "bit_exact": fixed_exact}
+    fixed_plan.close()
+
+    # the paper's own filter on the same scan (no dense mode): the
+    # heuristic's parameters, and sigma' = sigma = 20 with q = 5
+    filter_mode = {}
+    for label, kw in (("heuristic", {}), ("q5_k1_sigma20", dict(q=5, k=1, sigma_prime=20))):
+        fp = mag.Plan(job.patterns, mode="filter", **kw)
+        fi = fp.info()
+        _, fst = mag.scan(text, fp, stats=True)
+        f_ms, f_prof = time_scans(torch, mag, text, fp, out, cnt, max(3, steps // 4), 1)
+        f_z = int(cnt.item())
+        filter_mode[label] = {
+            "GBps": round(n / (f_ms * 1e-3) / 1e9, 3), "ms_per_step": round(f_ms, 5),
+            "scan_kernel_ms": round(f_prof["scan_ms"] / max(f_prof["launches"], 1), 5),
+            "q": fi["q"], "k": fi["k"], "sigma_prime": fi["sigma_prime"],
+            "table_bytes": fi["table_bytes"], "kernel": scan_kernel_name(fi),
+            "verifications_per_byte": round(fst["verifications"] / n, 5),
+            "bit_exact": f_z == z and (ref is None or oracle_equal(out[:f_z].cpu().numpy(), ref))}
+        log(f"filter mode {label}: {filter_mode[label]}")
+        fp.close()
+    return fixed, filter_mode
 
 
 def workload_section(torch, mag, selector, name: str, steps: int, warmup: int, stream_gbps,
@@ -439,10 +490,16 @@ def main() -> int:
                     help="skip the headline timing; run the batch section only (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 256 MiB device copies (counter calibration)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the fixed-parameter and filter-mode runs of the headline workload "
+                         "(profiling: only the selected plan's kernels run)")
+    ap.add_argument("--batch-plans", choices=("all", "learned"), default="all",
+                    help="with --only-batch: 'learned' runs only the batch of learned plans "
+                         "(profiling: every batched launch is the one the roofline reports)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the scan shards by text range with no exchange; see the design notes)",
+              "(a multi-GPU scan would shard the text by range, each shard overlapping the next by m - 1 bytes)",
               file=sys.stderr)
         return 2
 
@@ -460,7 +517,10 @@ def main() -> int:
         probe = torch.zeros(1 << 28, dtype=torch.uint8, device="cuda")
         sgb = stream_read_gbps(torch, mag, probe)
         del probe
-        b = batch_section(torch, mag, selector, args.steps, sgb)
+        if args.copy_calibration:
+            log("copy calibration: 3 x 256 MiB")
+            copy_calibration(torch)
+        b = batch_section(torch, mag, selector, args.steps, sgb, plans=args.batch_plans)
         print(json.dumps({"batch": b}), flush=True)
         return 0
     log(f"generating workload {args.workload}")
@@ -508,17 +568,10 @@ def main() -> int:
         log("copy calibration: 3 x 256 MiB")
         copy_calibration(torch)
 
-    # the same workload with the fixed heuristic's parameters
-    fixed_plan = mag.Plan(job.patterns)
-    finfo = fixed_plan.info()
-    fixed_ms, fprof = time_scans(torch, mag, text, fixed_plan, out, cnt, args.steps, args.warmup)
-    fz = int(cnt.item())
-    fixed_exact = fz == z and (ref is None or oracle_equal(out[:fz].cpu().numpy(), ref))
-    fixed = {"GBps": round(n / (fixed_ms * 1e-3) / 1e9, 3), "ms_per_step": round(fixed_ms, 5),
-             "scan_kernel_ms": round(fprof["scan_ms"] / max(fprof["launches"], 1), 5),
-             "q": finfo["q"], "k": finfo["k"], "sigma_prime": finfo["sigma_prime"],
-             "kernel": scan_kernel_name(finfo), "bit_exact": fixed_exact}
-    fixed_plan.close()
+    fixed, filter_mode = None, None
+    if not args.no_compare:
+        fixed, filter_mode = compare_section(torch, mag, job, text, ref, z, out, cnt, args.steps,
+                                             args.warmup)
 
     extras = {}
     if not args.no_extras:
@@ -563,6 +616,7 @@ def main() -> int:
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
         "roofline": roofline_block(kernel, n, scan_ms, stream_gbps, traffic, traffic_src),
         "fixed_params": fixed,
+        "filter_mode": filter_mode,
         "finish_ms": round(finish_ms, 5),
         "plan_ms": round(plan_ms, 3),
         "occurrences": z,

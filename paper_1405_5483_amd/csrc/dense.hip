@@ -88,15 +88,15 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
 
 // The one-probe dense scan (slice_test): the same grid and bitmap staging as
 // k_dense; tiles of slice_scan_tile(P) positions, wave w covering positions
-// 63 P w .. 63 P (w + 1) - 1 of its tile, each lane loading the 2P bytes
-// from the word that holds its first position. Each wave keeps the loads of
+// 63 P w .. 63 P (w + 1) - 1 of its tile, each lane loading the words its
+// probes read, from the word that holds its first position. Each wave keeps the loads of
 // its next two tiles in flight while it tests the current one (three
 // register sets, used in turn). AL: the text starts on a 4-byte boundary, so
 // no byte realignment is needed (tiles are a multiple of 4 positions long).
 template <int K, int P, bool AL>
 __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
     constexpr int kTile = slice_scan_tile(P);
-    constexpr int kLW = SliceLane<P>::kLoadWords;
+    constexpr int kLW = SliceLane<P>::load_words(AL);
     __shared__ __align__(16) uint32_t s_bits[kBloomWordsMax];
     __shared__ uint64_t s_queue[(kNT / 64) * kQueue];
     __shared__ uint64_t s_found[(kNT / 64) * kFoundBuf];
@@ -139,6 +139,16 @@ __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
         for (int v = 0; v < kLW / 4; ++v) {
             const uint4 x = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at + 16 * v, 0, 0));
             W[4 * v] = x.x; W[4 * v + 1] = x.y; W[4 * v + 2] = x.z; W[4 * v + 3] = x.w;
+        }
+        constexpr int r0 = kLW & ~3;
+        if constexpr (kLW % 4 == 1) {
+            W[r0] = __builtin_amdgcn_raw_buffer_load_b32(rs, at + 4 * r0, 0, 0);
+        } else if constexpr (kLW % 4 == 2) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, at + 4 * r0, 0, 0);
+            W[r0] = x[0]; W[r0 + 1] = x[1];
+        } else if constexpr (kLW % 4 == 3) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b96(rs, at + 4 * r0, 0, 0);
+            W[r0] = x[0]; W[r0 + 1] = x[1]; W[r0 + 2] = x[2];
         }
     };
     auto run = [&](uint64_t tile, const uint32_t (&W)[kLW]) {

@@ -174,19 +174,23 @@ __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last
 // positions (P = 16 or 32): lane L < 63 owns the P from xb = its wave's first
 // + P L, and lane 63 probes the P that follow the wave's last (the next
 // wave's first), so that every owner finds the probes of the positions up to
-// P - 1 past its own in the next lane. W holds the 2P bytes from the word
-// that contains xb (d = xb's byte offset in it; AL: d = 0). Bit u of a lane's
+// P - 1 past its own in the next lane. W holds load_words(AL) words from the
+// word that contains xb (d = xb's byte offset in it; AL: d = 0): exactly the
+// words the probes read, so that no loaded register is left dead (a dead
+// load's register, reused, makes the wave wait for that load before the
+// prefetched tiles behind it arrive). Bit u of a lane's
 // probe mask is the bitmap bit of the slice at xb + u; position xb + u passes
 // when bits u, u + 2, .., u + 2(K-1) of the mask extended by the next lane's
 // are all set.
 constexpr int kSliceOwners = 63;
 template <int P> struct SliceLane {
-    static constexpr int kLoadWords = P / 2;         // 2P bytes
     static constexpr int kWords = P / 4 + 2;         // realigned words: bytes xb .. xb + P + 7
+    // words loaded per lane: one more when xb is not word-aligned
+    static constexpr int load_words(bool al) { return kWords + (al ? 0 : 1); }
 };
 
 template <int P, bool AL>
-__device__ __forceinline__ void slice_words(const uint32_t (&W)[SliceLane<P>::kLoadWords], uint32_t d,
+__device__ __forceinline__ void slice_words(const uint32_t (&W)[SliceLane<P>::load_words(AL)], uint32_t d,
                                             uint32_t (&V)[SliceLane<P>::kWords]) {
 #pragma unroll
     for (int t = 0; t < SliceLane<P>::kWords; ++t)
@@ -239,7 +243,7 @@ __device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, con
 // none), one per lane and round with a ballot; found keys collect in the
 // wave's buffer fbuf (fbn keys). Every lane of the wave calls it.
 template <int K, int P, bool AL>
-__device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::kLoadWords], uint32_t d,
+__device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::load_words(AL)], uint32_t d,
                                            int64_t xb, int64_t room, const uint32_t *s_bits,
                                            uint32_t bshift, uint64_t *queue, uint32_t &qn,
                                            const VerifyArgs *vp, int lane, uint32_t &nhit, uint64_t *fbuf,
