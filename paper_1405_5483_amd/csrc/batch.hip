@@ -167,6 +167,13 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *queue = s_queue + wave * kBatchQueue;
     uint32_t qn = 0;
+    // While the workgroup runs dense tiles, the entry buffer (used only by
+    // filter tiles) holds each wave's found keys, written to the output with
+    // one atomic add per buffer instead of one per verification round; the
+    // buffers are flushed before a filter tile's mask entries overwrite them.
+    constexpr uint32_t kFoundCap = batch_entry_bytes(TS) / 8 / kWaves;
+    uint64_t *fbuf = reinterpret_cast<uint64_t *>(s_E) + wave * kFoundCap;
+    uint32_t fbn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t me = blockIdx.x, G = gridDim.x;
     const uint64_t own_end = uni64(ranges[3 * me + 1]);
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
             dense_tile<kBT>(drs, (uint32_t)(da1 - da0), (uint32_t)(delta + (uint64_t)X0 - da0), X0,
                             (int64_t)n - (int64_t)m,
                             reinterpret_cast<const uint32_t *>(s_tab), bshift, hw, mw, lastmask, queue,
-                            qn, vp, tid, lane, nver);
+                            qn, vp, tid, lane, nver, FoundBuf{fbuf, &fbn, kFoundCap});
             __syncthreads();                // s_ctl for the next tile
             continue;
         }
@@ -288,6 +295,10 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         const uint64_t pa1 = (delta + (uint64_t)b1 + 15) & ~15ull;
         const __amdgpu_buffer_rsrc_t rs = tile_rsrc(tbase + pa0, (uint32_t)(pa1 - pa0));
         const int32_t p0 = (int32_t)((int64_t)delta - (int64_t)pa0 + X0 * (int64_t)kq);
+        if (fbn) {                          // found keys of earlier dense tiles
+            flush_found_args(vp, fbuf, fbn);
+            fbn = 0;
+        }
         __syncthreads();                    // tables staged; the previous tile's entries consumed
         switch (q) {
             case 1: phase_a_q<TS, 1>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
@@ -373,6 +384,7 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         }
     }
     if (cur >= 0 && qn) drain_partial(vp, queue, qn, lane);
+    if (fbn) flush_found_args(vp, fbuf, fbn);
     if (lane == 0 && ncand) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)ncand);
     unsigned long long nv = nver;
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);

@@ -77,8 +77,20 @@ __device__ __forceinline__ void dense_load(__amdgpu_buffer_rsrc_t rs, uint32_t n
     }
 }
 
+// Found-key buffer of a wave (see emit_found_buffered): buf holds *n of at
+// most cap keys; buf == nullptr emits every verification round directly.
+struct FoundBuf {
+    uint64_t *buf = nullptr;
+    uint32_t *n = nullptr;
+    uint32_t cap = 0;
+};
+
 __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
-                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit);
+                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit,
+                                           FoundBuf fb);
+__device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
+                                                  int lane, uint64_t *fbuf, uint32_t fbn,
+                                                  uint32_t cap = kFoundBuf);
 
 // Tests the 16 windows of thread tid (positions xb .. xb + 15, xb = x0 +
 // 16*tid; d = p0 & 3) whose bytes are in W, and queues those that pass.
@@ -92,7 +104,7 @@ template <bool FAST>
 __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, int64_t xb, int64_t last,
                                            const uint32_t *s_bloom, uint32_t bshift, uint32_t hw,
                                            uint32_t mw, uint32_t lastmask, uint64_t *queue, uint32_t &qn,
-                                           const VerifyArgs *vp, int lane, uint64_t &nhit) {
+                                           const VerifyArgs *vp, int lane, uint64_t &nhit, FoundBuf fb) {
     uint32_t V[9];                              // bytes from position xb on
 #pragma unroll
     for (int t = 0; t < 9; ++t) V[t] = __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
@@ -125,14 +137,19 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
             hm |= (b & 1u) << (4 * i + s);
         }
     }
-    queue_hits(hm, xb, last, queue, qn, vp, lane, nhit);
+    queue_hits(hm, xb, last, queue, qn, vp, lane, nhit, fb);
 }
 
 // Queues the positions xb + u of this lane whose bit u (u < 16) is set in hm
-// and that do not pass `last`; verifies full queues. Every lane of the wave
-// calls it.
+// and that do not pass `last`; verifies full queues, their keys going to the
+// found-key buffer fb when it has one. Every lane of the wave calls it.
 __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
-                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit) {
+                                           uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit,
+                                           FoundBuf fb) {
+    auto drain = [&](uint32_t from) {
+        if (fb.buf) *fb.n = drain64_found(vp, queue, from, lane, fb.buf, *fb.n, fb.cap);
+        else drain64(vp, queue, from, lane);
+    };
     // positions past the last start
     const int64_t room = last - xb + 1;
     if (room < 16) hm &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
@@ -152,7 +169,7 @@ __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last
         qn += total;
         while (qn >= 64) {
             qn -= 64;
-            drain64(vp, queue, qn, lane);
+            drain(qn);
         }
         return;
     }
@@ -165,7 +182,7 @@ __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last
         qn += (uint32_t)__popcll(bal);
         if (qn >= 64) {
             qn -= 64;
-            drain64(vp, queue, qn, lane);
+            drain(qn);
         }
     }
 }
@@ -218,24 +235,25 @@ __device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[SliceLane<P
 
 // drain64 / drain_partial with the wave's found-key buffer.
 __device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
-                                                  int lane, uint64_t *fbuf, uint32_t fbn) {
+                                                  int lane, uint64_t *fbuf, uint32_t fbn, uint32_t cap) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const uint64_t e = queue[from + lane];
     __builtin_amdgcn_wave_barrier();
-    return verify_one_buffered(v, e, true, fbuf, fbn);
+    return verify_one_buffered(v, e, true, fbuf, fbn, cap);
 }
 
 __device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, const uint64_t *queue,
-                                                        uint32_t qn, int lane, uint64_t *fbuf, uint32_t fbn) {
+                                                        uint32_t qn, int lane, uint64_t *fbuf, uint32_t fbn,
+                                                        uint32_t cap = kFoundBuf) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const bool active = (uint32_t)lane < qn;
     const uint64_t e = active ? queue[lane] : 0ull;
     __builtin_amdgcn_wave_barrier();
-    return verify_one_buffered(v, e, active, fbuf, fbn);
+    return verify_one_buffered(v, e, active, fbuf, fbn, cap);
 }
 
 // One lane-run of the one-probe dense mode: probes, the K-slice test, and the
@@ -290,11 +308,11 @@ __device__ __forceinline__ void dense_test_any(const uint32_t (&W)[10], uint32_t
                                                int64_t last, const uint32_t *s_bloom, uint32_t bshift,
                                                uint32_t hw, uint32_t mw, uint32_t lastmask,
                                                uint64_t *queue, uint32_t &qn, const VerifyArgs *vp,
-                                               int lane, uint64_t &nhit) {
+                                               int lane, uint64_t &nhit, FoundBuf fb = {}) {
     if (hw == 4 && (mw > 4 || lastmask == 0xFFFFFFFFu))
-        dense_test<true>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit);
+        dense_test<true>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit, fb);
     else
-        dense_test<false>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit);
+        dense_test<false>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit, fb);
 }
 
 // One whole tile: start positions x0 .. x0 + 16*NT - 1 (those up to `last`),
@@ -305,11 +323,11 @@ __device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t n
                                            int64_t x0, int64_t last, const uint32_t *s_bloom,
                                            uint32_t bshift, uint32_t hw, uint32_t mw, uint32_t lastmask,
                                            uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int tid,
-                                           int lane, uint64_t &nhit) {
+                                           int lane, uint64_t &nhit, FoundBuf fb = {}) {
     uint32_t W[10];
     dense_load<NT>(rs, nrec, p0, tid, W);
     dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, last, s_bloom, bshift, hw, mw, lastmask, queue, qn,
-                   vp, lane, nhit);
+                   vp, lane, nhit, fb);
 }
 
 }  // namespace dev

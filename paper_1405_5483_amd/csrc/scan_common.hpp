@@ -175,14 +175,14 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
 // new count. Deferred and unequal-length scans take verify_one's path.
 __device__ static __attribute__((noinline)) uint32_t verify_one_buffered(const VerifyArgs *v, uint64_t i0,
                                                                          bool active, uint64_t *fbuf,
-                                                                         uint32_t fbn) {
+                                                                         uint32_t fbn, uint32_t cap) {
     VerifyArgs args;
     __builtin_memcpy(&args, v, sizeof(args));
     if (args.pending || args.var) {
         verify_one(v, i0, active);
         return fbn;
     }
-    return emit_found_buffered(args, i0, active ? find_pattern(args, i0) : 0u, fbuf, fbn);
+    return emit_found_buffered(args, i0, active ? find_pattern(args, i0) : 0u, fbuf, fbn, cap);
 }
 
 __device__ static __attribute__((noinline)) void flush_found_args(const VerifyArgs *v, const uint64_t *fbuf,

@@ -318,11 +318,11 @@ __device__ inline void flush_found(const VerifyArgs &a, const uint64_t *buf, uin
     __builtin_amdgcn_wave_barrier();
 }
 
-// emit_found into buf (holding fbn keys); returns the new count. Keys that do
-// not fit flush the buffer first; a round with more keys than the buffer
-// holds goes to the output directly.
+// emit_found into buf (holding fbn of at most cap keys); returns the new
+// count. Keys that do not fit flush the buffer first; a round with more keys
+// than the buffer holds goes to the output directly.
 __device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0, uint32_t u1, uint64_t *buf,
-                                               uint32_t fbn) {
+                                               uint32_t fbn, uint32_t cap = kFoundBuf) {
     uint32_t b = 0, c = 0;
     if (u1) {
         b = a.idstart[u1 - 1];
@@ -337,12 +337,12 @@ __device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0,
     }
     const uint32_t total = __shfl(inc, 63);
     if (total == 0) return fbn;
-    if (fbn + total > kFoundBuf) {
+    if (fbn + total > cap) {
         flush_found(a, buf, fbn);
         fbn = 0;
     }
     const uint64_t emit = a.key_or | (i0 << a.idbits);
-    if (total > kFoundBuf) {
+    if (total > cap) {
         emit_found(a, i0, u1);
         return 0;
     }
