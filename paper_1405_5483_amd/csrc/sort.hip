@@ -81,49 +81,82 @@ __device__ __forceinline__ uint64_t same_digit_lanes(bool valid, uint32_t d) {
     return eq;
 }
 
-// Stable scatter of src[beg, end) by digit (key >> shift) & 255 into dst, the
-// digit d's run for this block starting at s_off[d]. Rounds of blockDim.x
-// consecutive keys; within a round, waves in order and lanes in order, so
-// equal digits keep their input order. The keys of kScatterRounds rounds are
-// loaded before the first of them is placed, so their loads overlap. s_wcnt
-// is [waves][256] of zeros on entry and on exit.
-constexpr int kScatterRounds = 4;
-__device__ void stable_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg, uint64_t end,
-                               int shift, uint64_t *s_off, uint32_t (*s_wcnt)[256]) {
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    for (uint64_t base = beg; base < end; base += (uint64_t)kScatterRounds * blockDim.x) {
-        uint64_t keys[kScatterRounds];
+// Stable scatter of one chunk src[beg, end) (K keys, the last chunk fewer)
+// by digit d = (key >> shift) & 255 into dst, digit d's run for this chunk
+// starting at s_off[d]. The chunk is ordered by digit in LDS first: wave w
+// takes keys [w K/4, (w+1) K/4) of the chunk, in input order, and ranks each
+// among equal digits with ballots. The ordered chunk is then written out by
+// consecutive threads to consecutive addresses of each digit's run, so the
+// global writes come in runs of whole cache lines rather than one key per
+// digit and round. s_run[wave][256] is zero on entry and on exit.
+__device__ uint64_t block_exclusive_scan256(uint64_t v, uint64_t *s_tmp, uint64_t *total);
+constexpr int kScatterWaves = kRadixThreads / 64;
+static_assert(kRadixChunk % kRadixThreads == 0 && kRadixChunkSmall % kRadixThreads == 0,
+              "chunks are whole rounds of every wave");
+constexpr int kScatterMaxRounds = kRadixChunk / kRadixThreads;   // keys per lane
+__device__ void chunk_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg, uint64_t end, uint64_t K,
+                              int shift, const uint64_t *s_off, uint64_t *s_keys,
+                              uint32_t (*s_run)[256], uint32_t *s_start, uint64_t *s_tmp) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t n = (uint32_t)(end - beg);
+    const uint32_t per = (uint32_t)(K / kScatterWaves);          // keys per wave, a multiple of 64
+    const uint32_t rounds = per / 64;
+    const uint32_t w0 = wave * per;
+    uint64_t key[kScatterMaxRounds];
+    uint32_t at[kScatterMaxRounds];                            // place among the wave's equal digits
 #pragma unroll
-        for (int r = 0; r < kScatterRounds; ++r) {
-            const uint64_t i = base + (uint64_t)r * blockDim.x + tid;
-            keys[r] = i < end ? src[i] : 0ull;
+    for (int r = 0; r < kScatterMaxRounds; ++r) {
+        const uint32_t i = w0 + 64u * r + lane;
+        key[r] = (r < (int)rounds && i < n) ? src[beg + i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kScatterMaxRounds; ++r) {
+        if (r >= (int)rounds) continue;      // wave-uniform
+        const bool valid = w0 + 64u * r + lane < n;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        const uint64_t eq = same_digit_lanes(valid, d);
+        const uint32_t rank = lanes_below_mask(eq);
+        const uint32_t before = valid ? s_run[wave][d] : 0u;
+        at[r] = before + rank;
+        // the lanes of one digit read the count before its first lane adds to it
+        if (valid && rank == 0) s_run[wave][d] = before + (uint32_t)__popcll(eq);
+    }
+    __syncthreads();
+    {
+        // digit tid: its start in the ordered chunk, and each wave's start within it
+        uint32_t c[kScatterWaves], tot = 0;
+#pragma unroll
+        for (int v = 0; v < kScatterWaves; ++v) {
+            c[v] = s_run[v][tid];
+            tot += c[v];
         }
+        uint64_t all;
+        const uint32_t st = (uint32_t)block_exclusive_scan256(tot, s_tmp, &all);
+        s_start[tid] = st;
+        uint32_t acc = st;
 #pragma unroll
-        for (int r = 0; r < kScatterRounds; ++r) {
-            const uint64_t key = keys[r];
-            const bool valid = base + (uint64_t)r * blockDim.x + tid < end;
-            const uint32_t d = (uint32_t)(key >> shift) & 255u;
-            const uint64_t eq = same_digit_lanes(valid, d);
-            const uint32_t rank = lanes_below_mask(eq);
-            if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(eq);
-            __syncthreads();
-            if (valid) {
-                uint64_t off = s_off[d];
-                for (uint32_t v = 0; v < wave; ++v) off += s_wcnt[v][d];
-                dst[off + rank] = key;
-            }
-            __syncthreads();
-            for (uint32_t dd = tid; dd < 256; dd += blockDim.x) {
-                uint32_t add = 0;
-                for (uint32_t v = 0; v < nwaves; ++v) {
-                    add += s_wcnt[v][dd];
-                    s_wcnt[v][dd] = 0;
-                }
-                s_off[dd] += add;
-            }
-            __syncthreads();
+        for (int v = 0; v < kScatterWaves; ++v) {
+            s_run[v][tid] = acc;
+            acc += c[v];
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScatterMaxRounds; ++r) {
+        if (r < (int)rounds && w0 + 64u * r + lane < n) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            s_keys[s_run[wave][d] + at[r]] = key[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kRadixThreads) {
+        const uint64_t k = s_keys[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        dst[s_off[d] + (i - s_start[d])] = k;
+    }
+#pragma unroll
+    for (int v = 0; v < kScatterWaves; ++v) s_run[v][tid] = 0;
+    __syncthreads();
 }
 
 // Exclusive prefix sum over a 256-thread block (one value per thread); the
@@ -354,20 +387,22 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
     __shared__ uint64_t s_base[256];
     __shared__ uint64_t s_off[256];
     __shared__ uint64_t s_tmp[4];
-    __shared__ uint32_t s_wcnt[kRadixThreads / 64][256];
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_run[kScatterWaves][256];
+    __shared__ uint64_t s_keys[kRadixChunk];
     uint64_t z;
     if (!radix_active(zp, cap, &z)) return;
     const uint64_t K = radix_chunk_keys(z), C = (z + K - 1) / K;
     const uint32_t tid = threadIdx.x;
     uint64_t all;
     s_base[tid] = block_exclusive_scan256(tot[tid], s_tmp, &all);
-    for (int v = 0; v < kRadixThreads / 64; ++v) s_wcnt[v][tid] = 0;
+    for (int v = 0; v < kScatterWaves; ++v) s_run[v][tid] = 0;
     for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
         s_off[tid] = s_base[tid] + off[(size_t)tid * C + c];
         __syncthreads();
         const uint64_t beg = c * K;
         const uint64_t end = beg + K < z ? beg + K : z;
-        stable_scatter(src, dst, beg, end, shift, s_off, s_wcnt);
+        chunk_scatter(src, dst, beg, end, K, shift, s_off, s_keys, s_run, s_start, s_tmp);
     }
 }
 
