@@ -347,7 +347,9 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     const uint32_t njobs = (uint32_t)b->plans.size();
     Scratch &sc = b->sc;
     const uint64_t posmask = (1ull << b->posbits) - 1ull;
-    uint64_t *sorted = sorted_keys(sc, b->cap, b->nbits);
+    // batched plans have equal-length patterns: no pass over the id bits
+    const int lo = sort_low_bit(false, b->idbits);
+    uint64_t *sorted = sorted_keys(sc, b->cap, b->nbits, lo);
 
     BatchLaunch bl;
     bl.jobs = b->d_jobs;
@@ -369,9 +371,9 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
         s = launch_finish(sc, b->cap, 0, d_count, nullptr, StatsInfo{}, d_out, b->idbits, posmask, sorted,
                           stream);
     if (s == MAG_OK && b->cap > small_sort_max()) {
-        s = launch_radix_sort(sc, b->cap, b->cap, b->nbits, stream);
+        s = launch_radix_sort(sc, b->cap, b->cap, b->nbits, lo, stream);
         if (s == MAG_OK)
-            s = launch_expand(sc, b->cap, b->cap, b->nbits, d_out, b->idbits, posmask, stream);
+            s = launch_expand(sc, b->cap, b->cap, b->nbits, lo, d_out, b->idbits, posmask, stream);
     }
     if (s == MAG_OK)
         s = launch_batch_offsets(sorted, sc.counters + kSortCountSlot, b->cap, d_offsets, njobs,

@@ -611,9 +611,10 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     s = launch_finish(sc, out_cap, samples, d_count, d_stats, info, d_out, idbits, ~0ull, nullptr, stream);
     if (s != MAG_OK) return s;
     if (sort_on_device) {
-        s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, stream);
+        const int lo = sort_low_bit(p->var, idbits);
+        s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, lo, stream);
         if (s == MAG_OK)
-            s = launch_expand(sc, out_cap, out_cap, idbits + posbits, d_out, idbits, ~0ull, stream);
+            s = launch_expand(sc, out_cap, out_cap, idbits + posbits, lo, d_out, idbits, ~0ull, stream);
         if (s != MAG_OK) return s;
     }
     profile_commit(prof, stream);
@@ -777,8 +778,10 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
     if (host[4] > small_sort_max()) {
         std::lock_guard<std::mutex> lock(p->mtx);
         s = ensure_radix_scratch(p->scratch, host[4], stream);
-        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[4], out_cap, nbits, stream);
-        if (s == MAG_OK) s = launch_expand(p->scratch, host[4], out_cap, nbits, d_out, idbits, ~0ull, stream);
+        const int lo = sort_low_bit(p->var, idbits);
+        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[4], out_cap, nbits, lo, stream);
+        if (s == MAG_OK)
+            s = launch_expand(p->scratch, host[4], out_cap, nbits, lo, d_out, idbits, ~0ull, stream);
     }
     return s;
 }

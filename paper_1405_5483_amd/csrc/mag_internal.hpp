@@ -348,15 +348,22 @@ mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *
                          uint64_t posmask, uint64_t *sorted, hipStream_t stream);
 // Device-wide radix sort of the keys for counts in (small_sort_max(), cap],
 // with grids sized for counts up to `bound`: the scratch for `bound`, the
-// passes over the nbits low key bits, and the records.
+// passes over key bits lo .. nbits - 1, and the records. The passes are
+// stable, so bits below lo keep the order in which the keys were written.
 mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream);
 // Chunks of the device-wide radix sort's counts for outputs of up to `bound`
 // keys (its scratch: 256 * chunks u32 counts, 256 * chunks + 256 u64 offsets).
 uint64_t radix_scratch_chunks(uint64_t bound);
-mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, hipStream_t stream);
-mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, mag_match *out,
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream);
+mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, mag_match *out,
                          int idbits, uint64_t posmask, hipStream_t stream);
 // The key buffer that holds the sorted keys after the radix passes.
-uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits);
+uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits, int lo);
+// Lowest key bit the radix passes sort on. With equal-length patterns every
+// start matches one distinct pattern, whose ids are written one after another
+// in ascending order (id runs, emit_found), so the id bits need no pass; with
+// unequal lengths several members of a prefix group can match one start, in
+// member order, and the ids are sorted too.
+inline int sort_low_bit(bool var, int idbits) { return var ? 0 : idbits; }
 
 }  // namespace mag

@@ -442,7 +442,7 @@ mag_status launch_fill_u64(uint64_t *ptr, uint64_t count, uint64_t value, hipStr
 
 uint32_t small_sort_max() { return kSmallMax; }
 
-int radix_passes(int nbits) { return (nbits + 7) / 8; }
+int radix_passes(int nbits, int lo) { return nbits > lo ? (nbits - lo + 7) / 8 : 0; }
 
 mag_status launch_finish(Scratch &sc, uint64_t cap, uint64_t samples, uint64_t *d_count,
                          mag_stats *d_stats, const StatsInfo &info, mag_match *out, int idbits,
@@ -486,7 +486,7 @@ mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream)
     return MAG_OK;
 }
 
-mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, hipStream_t stream) {
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream) {
     if (bound <= kSmallMax) return MAG_OK;
     if (sc.radix_chunks < radix_chunks(bound) || !sc.hist)
         return fail(MAG_E_INVALID, "radix scratch smaller than the bound");
@@ -495,8 +495,8 @@ mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbit
     const uint64_t *zp = sc.counters + kSortCountSlot;
     uint64_t *src = sc.keys, *dst = sc.keys + cap;
     uint64_t *tot = sc.radix_off + (size_t)256 * sc.radix_chunks;
-    for (int p = 0; p < radix_passes(nbits); ++p) {
-        const int shift = 8 * p;
+    for (int p = 0; p < radix_passes(nbits, lo); ++p) {
+        const int shift = lo + 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kRadixThreads), 0, stream,
                            (const uint64_t *)src, zp, cap, shift, sc.hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, stream, (const uint32_t *)sc.hist,
@@ -512,18 +512,18 @@ mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbit
     return e == hipSuccess ? MAG_OK : hip_fail(e, "radix sort launch");
 }
 
-uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits) {
-    return (radix_passes(nbits) & 1) ? sc.keys + cap : sc.keys;
+uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits, int lo) {
+    return (radix_passes(nbits, lo) & 1) ? sc.keys + cap : sc.keys;
 }
 
-mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, mag_match *out,
+mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, mag_match *out,
                          int idbits, uint64_t posmask, hipStream_t stream) {
     if (bound <= kSmallMax) return MAG_OK;
     if (bound > cap) bound = cap;
     uint64_t blocks = (bound + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_expand, dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint64_t *)sorted_keys(sc, cap, nbits),
+                       (const uint64_t *)sorted_keys(sc, cap, nbits, lo),
                        (const uint64_t *)(sc.counters + kSortCountSlot), cap, out, idbits, posmask);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "expand launch");

@@ -396,17 +396,37 @@ def test_extreme_bytes(torch_cuda, mag):
         _assert_same(pos, ids, om.occ_hashed(T, P))
 
 
-def test_many_matches_radix_path(torch_cuda, mag):
-    # a^n against {a^m} x 3 ids: 3(n-m+1) occurrences, far beyond the LDS sort
+@pytest.mark.parametrize("kw", [dict(q=2, k=2, sigma_prime=2), dict(mode="dense")],
+                         ids=["filter", "dense"])
+def test_many_matches_radix_path(torch_cuda, mag, kw):
+    # a^n against {a^m} x 3 ids: 3(n-m+1) occurrences, far beyond the LDS sort.
+    # The device sort passes over the position bits only; the three ids of a
+    # start leave the verification as one ascending run, which the stable
+    # passes keep in order.
     n, m = 200_000, 8
     T = np.full(n, ord("a"), dtype=np.uint8)
     P = np.full((3, m), ord("a"), dtype=np.uint8)
-    plan = mag.Plan(P, q=2, k=2, sigma_prime=2)
+    plan = mag.Plan(P, **kw)
     pos, ids, st = _gpu_occ(torch_cuda, mag, T, plan, stats=True)
     assert pos.size == 3 * (n - m + 1)
     assert np.array_equal(pos, np.repeat(np.arange(n - m + 1, dtype=np.uint64), 3))
     assert np.array_equal(ids, np.tile(np.arange(3, dtype=np.uint32), n - m + 1))
     assert st["verifications"] == n - m + 1
+
+
+def test_many_matches_unequal_lengths_radix_path(torch_cuda, mag):
+    # a^n against {a^10, a^8, a^9, a^8}: every pattern that fits matches at
+    # every start, found through one prefix group in member order (not id
+    # order), so the device sort also passes over the id bits here
+    n = 30_000
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    pats = [b"a" * 10, b"a" * 8, b"a" * 9, b"a" * 8]
+    plan = mag.Plan(pats)
+    assert plan.info()["var"] == 1
+    pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan)
+    ref = om.occ_var(T, pats)
+    assert ref[0].size > 8192
+    _assert_same(pos, ids, ref)
 
 
 def test_small_outputs_around_rank_blocks(torch_cuda, mag):
