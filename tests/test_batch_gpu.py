@@ -128,6 +128,38 @@ def test_batch_device_wide_sort(torch_cuda, mag):
     b.close()
 
 
+def test_batch_dense_jobs_between_filter_jobs(torch_cuda, mag):
+    """Dense jobs (protein-like and Zipf alphabets, m = 8, 16, 32), many of
+    whose patterns occur, with DNA dense jobs and filter jobs between them:
+    the waves' found-key buffers of dense tiles must be flushed before a
+    filter tile reuses their memory. Text lengths fall on and around multiples
+    of 8064 and 8192 start positions, at unaligned addresses."""
+    torch = torch_cuda
+    tile = 16 * 63 * 8
+    jobs, plans = [], []
+    cases = [(20, 8, 3 * tile + 7), (20, 16, tile), (20, 32, tile - 1), (64, 8, 2 * tile + 33),
+             (64, 16, 5000), (64, 32, 4 * tile + 1), (20, 16, 17), (20, 8, 200_003)]
+    for i, (sigma, m, n) in enumerate(cases):
+        job = make_job(n, sigma, "uniform" if i % 2 else "zipf", 300 if m == 8 else 3000, m, 1.0, 500 + i)
+        jobs.append(job)
+        plans.append(mag.Plan(job.patterns, mode="dense"))
+        if i % 3 == 1:                      # a DNA dense job, then a filter job
+            dna = make_job(60_000, 4, "uniform", 500, 8, 0.5, 600 + i)
+            jobs.append(dna)
+            plans.append(mag.Plan(dna.patterns, mode="dense"))
+            flt = make_job(90_000, 20, "uniform", 100, 16, 0.5, 700 + i)
+            jobs.append(flt)
+            plans.append(mag.Plan(flt.patterns, mode="filter"))
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    assert total > 8192
+    texts = _upload(torch, [j.text for j in jobs], [(5 * j) % 16 for j in range(len(jobs))])
+    b = mag.Batch(plans)
+    b.bind(texts, total + 64)
+    _check_jobs(b.run(), jobs)
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
 def test_batch_graph_replay(torch_cuda, mag):
     torch = torch_cuda
     jobs = _small_jobs(12, seed=404)
