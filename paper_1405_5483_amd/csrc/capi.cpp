@@ -527,7 +527,7 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     // a grid of fewer workgroups than half the compute units verifies inline
     // with few waves: defer when each of them would face many starts
     const int ncu = device_compute_units();
-    const int lane_pos = dense_lane_positions(p);
+    const int lane_pos = dense_lane_positions(p, samples, ncu);
     const uint64_t tile = slices ? (uint64_t)slice_scan_tile(lane_pos)
                           : p->dense ? (uint64_t)kDenseScanTile : kSmallGridTileSamples;
     const uint64_t tiles = (samples + tile - 1) / tile;

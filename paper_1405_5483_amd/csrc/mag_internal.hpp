@@ -267,8 +267,9 @@ void profile_mark(ProfileMarks &pm, hipStream_t stream);
 void profile_commit(ProfileMarks &pm, hipStream_t stream);
 
 // Positions per lane of the one-probe dense kernel (16 or 32) for a plan's
-// chunk_bytes / words_per_lane (scan_dispatch.cpp).
-int dense_lane_positions(const mag_plan *p);
+// chunk_bytes / words_per_lane, or by default for a scan of `positions`
+// start positions on `ncu` compute units (scan_dispatch.cpp).
+int dense_lane_positions(const mag_plan *p, uint64_t positions, int ncu);
 
 // Thread-local error text (capi.cpp).
 mag_status fail(mag_status s, const std::string &msg);
