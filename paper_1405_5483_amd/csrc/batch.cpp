@@ -29,6 +29,43 @@ constexpr uint64_t kTileOverheadBytes = 2048;
 constexpr uint64_t kBatchDeferMaxText = 1 << 20;
 constexpr uint64_t kBatchPendingEntries = 1 << 23;
 
+// Contiguous tile ranges of about equal weight, one per workgroup, over a
+// tile sequence laid out job after job (tiles_of[j] tiles of job j, weight(j,
+// t) of its tile t): ranges[3w] = first tile, [3w+1] = end, [3w+2] = the job
+// of the first tile.
+template <typename Weight>
+std::vector<uint64_t> split_ranges(uint64_t grid, const std::vector<uint64_t> &tiles_of, uint64_t total_tiles,
+                                   Weight weight) {
+    std::vector<uint64_t> ranges(3 * std::max<uint64_t>(grid, 1), 0);
+    if (!grid) return ranges;
+    const uint32_t njobs = (uint32_t)tiles_of.size();
+    long double total = 0;
+    for (uint32_t j = 0; j < njobs; ++j)
+        for (uint64_t t = 0; t < tiles_of[j]; ++t) total += (long double)weight(j, t);
+    std::vector<uint64_t> begin(grid + 1, total_tiles);
+    std::vector<uint32_t> job_of(grid, 0);
+    uint64_t next_wg = 0, g = 0;
+    long double run = 0;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        for (uint64_t t = 0; t < tiles_of[j]; ++t, ++g) {
+            uint64_t w = (uint64_t)(run * (long double)grid / total);
+            if (w >= grid) w = grid - 1;
+            while (next_wg <= w) {
+                begin[next_wg] = g;
+                job_of[next_wg] = j;
+                ++next_wg;
+            }
+            run += (long double)weight(j, t);
+        }
+    }
+    for (uint64_t wg = 0; wg < grid; ++wg) {
+        ranges[3 * wg] = begin[wg];
+        ranges[3 * wg + 1] = begin[wg + 1] > begin[wg] ? begin[wg + 1] : begin[wg];
+        ranges[3 * wg + 2] = begin[wg] < total_tiles ? job_of[wg] : 0;
+    }
+    return ranges;
+}
+
 template <typename T>
 mag_status grow(T **p, size_t *have, size_t want_bytes, const char *what) {
     if (*p && *have >= want_bytes) return MAG_OK;
@@ -62,6 +99,16 @@ struct mag_batch {
     size_t ranges_bytes = 0;
     uint64_t *d_next = nullptr;      // tile claim counters, one per workgroup
     size_t next_bytes = 0;
+    // the dense jobs' launch: its job table, tile ranges and claims
+    uint32_t ndense = 0;
+    uint64_t dense_tiles = 0;
+    uint32_t dense_grid = 0;
+    mag::JobDesc *d_djobs = nullptr;
+    size_t djobs_bytes = 0;
+    uint64_t *d_dranges = nullptr;
+    size_t dranges_bytes = 0;
+    uint64_t *d_dnext = nullptr;
+    size_t dnext_bytes = 0;
     bool defer = false;              // some job defers its verification
     int words_per_lane = mag::kBatchWordsDefault;   // filter tiles of 512 * words samples
     int bound_words = mag::kBatchWordsDefault;      // the value the bound tile layout uses
@@ -112,6 +159,9 @@ void mag_batch_destroy(mag_batch *b) {
         (void)hipFree(b->d_jobs);
         (void)hipFree(b->d_ranges);
         (void)hipFree(b->d_next);
+        (void)hipFree(b->d_djobs);
+        (void)hipFree(b->d_dranges);
+        (void)hipFree(b->d_dnext);
         (void)hipFree(b->sc.counters);
         (void)hipFree(b->sc.keys);
         (void)hipFree(b->sc.hist);
@@ -189,6 +239,10 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     std::vector<uint64_t> tiles_of(njobs), tile_bytes_full(njobs), tail_samples(njobs), tile_samples(njobs);
     const int wpl = b->words_per_lane;
     uint64_t total_tiles = 0;
+    // dense jobs: their own tile sequence (tiles of the single-job dense kernels)
+    std::vector<JobDesc> djobs;
+    std::vector<uint64_t> dtiles_of, dtile_pos, dtail_pos, dstage_bytes;
+    uint64_t dense_tiles = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
         const mag_plan *p = b->plans[j];
         JobDesc &J = jobs[j];
@@ -203,7 +257,9 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.n = n[j];
         J.X = X;
         J.tile_first = total_tiles;
-        const uint64_t TS = p->dense ? (uint64_t)kDenseTilePositions : (uint64_t)kBatchThreads * wpl;
+        const bool slices = p->dense && p->slice_k > 0;
+        const uint64_t TS = slices ? (uint64_t)kBatchSliceTile
+                            : p->dense ? (uint64_t)kDenseScanTile : (uint64_t)kBatchThreads * wpl;
         J.ntiles = (X + TS - 1) / TS;
         J.mu = p->dev.mu;
         J.table = p->dev.table;
@@ -218,11 +274,25 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.tlds = p->table.size() <= kBatchTableLds ? 1 : 0;
         J.table_vec = (uint32_t)((p->table.size() + 15) / 16);
         J.dense = p->dense ? 1u : 0u;
-        if (p->dense) {
-            J.table = p->dev.bloom_batch;
+        const bool codes = p->dense && p->code_shift >= 0;
+        if (codes) {
+            // exact window codes: the code bitmap (at most 8 KiB) in LDS
+            J.table = p->dev.code_bits;
             J.tlds = 1;
-            J.table_vec = (uint32_t)(p->bloom_batch.size() * 4 / 16);
-            J.bshift = 32u - (uint32_t)std::min(p->bloom_log2, kBloomBatchLog2);
+            J.table_vec = (uint32_t)(p->code_bits.size() * 4 / 16);
+            J.code_shift = (uint32_t)p->code_shift;
+            J.code_rep = p->code_rep;
+            J.code_mask = (uint32_t)((1ull << (2 * p->m)) - 1);
+            J.code_ids = p->dev.code_ids;
+        } else if (p->dense) {
+            // the slice bitmap of the one-probe mode at full size, else the
+            // Bloom bitmap's batched copy (at most 32 KiB, which leaves the
+            // rest of the LDS array to the found-key buffers)
+            J.table = slices ? p->dev.slices : p->dev.bloom_batch;
+            J.tlds = 1;
+            J.table_vec = (uint32_t)((slices ? p->slices.size() : p->bloom_batch.size()) * 4 / 16);
+            J.bshift = 32u - (uint32_t)(slices ? p->bloom_log2 : std::min(p->bloom_log2, kBloomBatchLog2));
+            J.slice_k = slices ? (uint32_t)p->slice_k : 0u;
         }
         ScanLaunch sl;
         sl.text = d_texts[j];
@@ -235,11 +305,25 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.v.key_or = (uint64_t)j << (posbits + idbits);
         // a short text with many patterns keeps one workgroup verifying for
         // long; its starts go to the batch verification kernel instead
-        const double expect = p->dense ? p->bloom_fp * (double)X : p->est_verif * (double)n[j];
-        const double vwaves = (double)std::max<uint64_t>(J.ntiles, 1) * (kBatchThreads / 64);
+        const double expect = slices ? p->slice_fp * (double)X
+                              : p->dense ? p->bloom_fp * (double)X : p->est_verif * (double)n[j];
+        const double vwaves = (double)std::max<uint64_t>(J.ntiles, 1) *
+                              ((p->dense ? kDenseScanThreads : kBatchThreads) / 64);
         if (X && n[j] <= kBatchDeferMaxText && posbits <= kBatchJobShift &&
             ((double)p->r * p->m * 4 >= (double)n[j] || expect >= kDeferPerWave * vwaves))
             defer[j] = 1;
+        if (p->dense) {
+            // the job leaves the filter launch's sequence (no tiles there)
+            JobDesc D = J;
+            D.tile_first = dense_tiles;
+            djobs.push_back(D);
+            dtiles_of.push_back(J.ntiles);
+            dtile_pos.push_back(TS);
+            dtail_pos.push_back(X - (J.ntiles ? (J.ntiles - 1) * TS : 0));
+            dstage_bytes.push_back((uint64_t)J.table_vec * 16);
+            dense_tiles += J.ntiles;
+            J.ntiles = 0;
+        }
         tiles_of[j] = J.ntiles;
         tile_bytes_full[j] = TS * kq;
         tile_samples[j] = TS;
@@ -247,44 +331,26 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         total_tiles += J.ntiles;
     }
 
-    // contiguous tile ranges of about equal weight, one per workgroup
+    // contiguous tile ranges of about equal weight, one per workgroup, for
+    // each of the two launches
     const int ncu = device_compute_units();
     const int occ = batch_occupancy(wpl);
-    if (ncu < 1 || occ < 1) return fail(MAG_E_DEVICE, "cannot size the batch launch");
+    const int docc = batch_dense_occupancy();
+    if (ncu < 1 || occ < 1 || docc < 1) return fail(MAG_E_DEVICE, "cannot size the batch launch");
     uint64_t grid = (uint64_t)ncu * occ;
     if (grid > total_tiles) grid = total_tiles;
-    std::vector<uint64_t> ranges(3 * std::max<uint64_t>(grid, 1), 0);
-    if (grid) {
-        auto tile_weight = [&](uint32_t j, uint64_t t) {
-            const uint64_t samples = t + 1 < tiles_of[j] ? tile_samples[j] : tail_samples[j];
-            // a dense tile reads one byte per position but hashes every one of them
-            return samples * (jobs[j].dense ? 4 : jobs[j].kq) + kTileOverheadBytes;
-        };
-        long double total = 0;
-        for (uint32_t j = 0; j < njobs; ++j)
-            for (uint64_t t = 0; t < tiles_of[j]; ++t) total += (long double)tile_weight(j, t);
-        std::vector<uint64_t> begin(grid + 1, total_tiles);
-        std::vector<uint32_t> job_of(grid, 0);
-        uint64_t next_wg = 0, g = 0;
-        long double run = 0;
-        for (uint32_t j = 0; j < njobs; ++j) {
-            for (uint64_t t = 0; t < tiles_of[j]; ++t, ++g) {
-                uint64_t w = (uint64_t)(run * (long double)grid / total);
-                if (w >= grid) w = grid - 1;
-                while (next_wg <= w) {
-                    begin[next_wg] = g;
-                    job_of[next_wg] = j;
-                    ++next_wg;
-                }
-                run += (long double)tile_weight(j, t);
-            }
-        }
-        for (uint64_t wg = 0; wg < grid; ++wg) {
-            ranges[3 * wg] = begin[wg];
-            ranges[3 * wg + 1] = begin[wg + 1] > begin[wg] ? begin[wg + 1] : begin[wg];
-            ranges[3 * wg + 2] = begin[wg] < total_tiles ? job_of[wg] : 0;
-        }
-    }
+    const std::vector<uint64_t> ranges = split_ranges(grid, tiles_of, total_tiles, [&](uint32_t j, uint64_t t) {
+        const uint64_t samples = t + 1 < tiles_of[j] ? tile_samples[j] : tail_samples[j];
+        return samples * jobs[j].kq + kTileOverheadBytes;
+    });
+    uint64_t dgrid = (uint64_t)ncu * docc;
+    if (dgrid > dense_tiles) dgrid = dense_tiles;
+    const std::vector<uint64_t> dranges = split_ranges(dgrid, dtiles_of, dense_tiles, [&](uint32_t d, uint64_t t) {
+        // a dense tile reads one byte per position but hashes every one of
+        // them; a job's first tile also stages its bitmap
+        const uint64_t pos = t + 1 < dtiles_of[d] ? dtile_pos[d] : dtail_pos[d];
+        return pos * 4 + kTileOverheadBytes + (t == 0 ? dstage_bytes[d] : 0);
+    });
     // deferred starts: one buffer for the batch, its segment counters zeroed
     // here once and by the finishing kernel of every run
     b->defer = false;
@@ -312,10 +378,28 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     if (s != MAG_OK) return s;
     s = grow(&b->d_next, &b->next_bytes, std::max<size_t>(grid, 1) * sizeof(uint64_t), "tile claims");
     if (s != MAG_OK) return s;
+    // the dense jobs carry the deferred-start fields set above
+    for (JobDesc &D : djobs) {
+        const uint32_t j = (uint32_t)(D.v.key_or >> (posbits + idbits));
+        D.v = jobs[j].v;
+    }
+    s = grow(&b->d_djobs, &b->djobs_bytes, std::max<size_t>(djobs.size(), 1) * sizeof(JobDesc), "dense job table");
+    if (s != MAG_OK) return s;
+    s = grow(&b->d_dranges, &b->dranges_bytes, dranges.size() * sizeof(uint64_t), "dense tile ranges");
+    if (s != MAG_OK) return s;
+    s = grow(&b->d_dnext, &b->dnext_bytes, std::max<size_t>(dgrid, 1) * sizeof(uint64_t), "dense tile claims");
+    if (s != MAG_OK) return s;
     if (njobs) e = hipMemcpy(b->d_jobs, jobs.data(), njobs * sizeof(JobDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !djobs.empty())
+        e = hipMemcpy(b->d_djobs, djobs.data(), djobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_dranges, dranges.data(), dranges.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload of the job table");
+    b->ndense = (uint32_t)djobs.size();
+    b->dense_tiles = dense_tiles;
+    b->dense_grid = (uint32_t)dgrid;
     b->cap = out_cap;
     b->idbits = idbits;
     b->posbits = posbits;
@@ -360,9 +444,17 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     bl.total_tiles = b->total_tiles;
     bl.counters = sc.counters;
     bl.words_per_lane = (uint32_t)b->bound_words;
+    BatchLaunch dl = bl;
+    dl.jobs = b->d_djobs;
+    dl.njobs = b->ndense;
+    dl.ranges = b->d_dranges;
+    dl.next = b->d_dnext;
+    dl.grid = b->dense_grid;
+    dl.total_tiles = b->dense_tiles;
     ProfileMarks prof;
     mag_status s = profile_start(prof, stream);
     if (s == MAG_OK) s = launch_batch(bl, stream);
+    if (s == MAG_OK) s = launch_batch_dense(dl, stream);
     profile_mark(prof, stream);
     if (s == MAG_OK && b->defer)
         s = launch_batch_verify(b->d_jobs, sc.pending, sc.seg_count, sc.pending_cap / kPendingSegments,

@@ -1,12 +1,13 @@
 // Batched MAG scans: many independent (text, pattern set) jobs in one
 // persistent launch.
 //
-// Every job is cut into tiles (512 * words-per-lane samples; dense jobs
-// kDenseTilePositions start positions); the tiles of all
-// jobs form one global sequence (job after job) that the host splits into
-// contiguous ranges of about equal text bytes, one per workgroup, so a
-// workgroup restages a job's alphabet map and mask table in LDS only when its
-// range crosses into the next job. Per tile the kernel runs the two phases of
+// Every filter job is cut into tiles of 512 * words-per-lane samples; the
+// tiles of all filter jobs form one global sequence (job after job) that the
+// host splits into contiguous ranges of about equal text bytes, one per
+// workgroup, so a workgroup restages a job's alphabet map and mask table in
+// LDS only when its range crosses into the next job. Dense jobs run in their
+// own persistent launch (k_batch_dense, below) with the single-job dense
+// kernels' tiles and bitmaps. Per tile the kernel runs the two phases of
 // the single-job scan with all of its threads: the mask entries of the
 // tile's samples (with the job's q, k, sigma' and table; q selects one of
 // eight compile-time variants per tile), then the Shift-Or recurrence over
@@ -23,7 +24,6 @@
 #include "scan_common.hpp"
 
 namespace mag {
-static_assert(kBatchQueue >= (int)kDenseQueue, "dense tiles fill up to kDenseQueue starts");
 namespace {
 
 using namespace dev;
@@ -167,13 +167,6 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *queue = s_queue + wave * kBatchQueue;
     uint32_t qn = 0;
-    // While the workgroup runs dense tiles, the entry buffer (used only by
-    // filter tiles) holds each wave's found keys, written to the output with
-    // one atomic add per buffer instead of one per verification round; the
-    // buffers are flushed before a filter tile's mask entries overwrite them.
-    constexpr uint32_t kFoundCap = batch_entry_bytes(TS) / 8 / kWaves;
-    uint64_t *fbuf = reinterpret_cast<uint64_t *>(s_E) + wave * kFoundCap;
-    uint32_t fbn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t me = blockIdx.x, G = gridDim.x;
     const uint64_t own_end = uni64(ranges[3 * me + 1]);
@@ -200,7 +193,6 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
     __amdgpu_buffer_rsrc_t trs = tile_rsrc(nullptr, 0);
     uint64_t delta = 0, n = 0, X = 0, tfirst = 0, tend = 0;
     uint32_t q = 1, k = 1, kq = 1, mprime = 1, W = 1, sp = 1, esz = 1, w0 = 0, tlds = 0, m = 1;
-    uint32_t dense = 0, bshift = 32, hw = 1, mw = 1, lastmask = 0;
 
     for (uint32_t slot = 0;; slot ^= 1) {
         const uint64_t g = uni64(s_ctl[slot]);
@@ -242,11 +234,6 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
             w0 = uni32(J.w0);
             tlds = uni32(J.tlds);
             m = uni32(J.v.m);
-            dense = uni32(J.dense);
-            bshift = uni32(J.bshift);
-            hw = uni32(J.v.hw);
-            mw = uni32(J.v.mw);
-            lastmask = uni32(J.v.lastmask);
             const uint32_t tvec = uni32(J.table_vec);
             const uint8_t *mu = uniptr(J.mu);
             const uint8_t *table = uniptr(reinterpret_cast<const uint8_t *>(J.table));
@@ -259,32 +246,7 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
                 for (uint32_t v = tid; v < tvec; v += kBT) dst[v] = src[v];
             }
         }
-        const int64_t X0 = (int64_t)(g - tfirst) * (dense ? kDenseTilePositions : TS);
-        if (dense) {
-            // start positions X0 .. X0 + kDenseTilePositions - 1 against the Bloom bitmap in s_tab
-            int64_t e1 = X0 + kDenseTilePositions + 40;
-            if (e1 > (int64_t)n) e1 = (int64_t)n;
-            const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
-            const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;
-            const __amdgpu_buffer_rsrc_t drs = tile_rsrc(tbase + da0, (uint32_t)(da1 - da0));
-            __syncthreads();                // the bitmap is staged
-            if (wave == 0) {
-                uint64_t t = kNoTile;
-                if (!own_done) {
-                    const uint64_t c = __shfl(pending, 0);
-                    if (c < own_end) t = c;
-                    else own_done = true;
-                }
-                if (t == kNoTile) t = steal_tile(next, ranges, G, me, lane);
-                if (lane == 0) s_ctl[slot ^ 1] = t;
-            }
-            dense_tile<kBT>(drs, (uint32_t)(da1 - da0), (uint32_t)(delta + (uint64_t)X0 - da0), X0,
-                            (int64_t)n - (int64_t)m,
-                            reinterpret_cast<const uint32_t *>(s_tab), bshift, hw, mw, lastmask, queue,
-                            qn, vp, tid, lane, nver, FoundBuf{fbuf, &fbn, kFoundCap});
-            __syncthreads();                // s_ctl for the next tile
-            continue;
-        }
+        const int64_t X0 = (int64_t)(g - tfirst) * TS;
         // text bytes the tile's samples touch, warm-up included
         int64_t b0 = (X0 - (int64_t)w0) * kq;
         if (b0 < 0) b0 = 0;
@@ -295,10 +257,6 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         const uint64_t pa1 = (delta + (uint64_t)b1 + 15) & ~15ull;
         const __amdgpu_buffer_rsrc_t rs = tile_rsrc(tbase + pa0, (uint32_t)(pa1 - pa0));
         const int32_t p0 = (int32_t)((int64_t)delta - (int64_t)pa0 + X0 * (int64_t)kq);
-        if (fbn) {                          // found keys of earlier dense tiles
-            flush_found_args(vp, fbuf, fbn);
-            fbn = 0;
-        }
         __syncthreads();                    // tables staged; the previous tile's entries consumed
         switch (q) {
             case 1: phase_a_q<TS, 1>(esz, s_E, rs, p0, kq, sp, s_mu, s_tab, trs, tlds, (int)w0, X0, (int64_t)X, tid); break;
@@ -384,11 +342,290 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
         }
     }
     if (cur >= 0 && qn) drain_partial(vp, queue, qn, lane);
-    if (fbn) flush_found_args(vp, fbuf, fbn);
     if (lane == 0 && ncand) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)ncand);
     unsigned long long nv = nver;
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
     if (lane == 0 && nv) atomicAdd((unsigned long long *)&counters[2], nv);
+}
+
+// ---- dense jobs ----
+//
+// One 1024-thread workgroup per compute unit, as in the single-job dense
+// kernels: the job's bitmap (the slice bitmap of the one-probe mode, or the
+// Bloom bitmap, up to 128 KiB) in a static LDS array at address 0, per-wave
+// queues and found-key buffers after it. Tiles are those of the single-job
+// kernels (kBatchSliceTile or kDenseScanTile start positions); workgroups
+// claim them from contiguous ranges of the dense tile sequence and steal as
+// the filter launch does, and restage the bitmap when the job changes. When
+// a job's bitmap leaves at least half of its array free, the free part holds
+// the waves' found-key buffers (up to 1,024 keys each instead of 32): jobs
+// with short DNA patterns find a match at several percent of their start
+// positions, and one output reservation per 32 keys would serialize them on
+// the output counter.
+constexpr int kDT = kDenseScanThreads;
+constexpr int kDQueue = 128;
+static_assert(kDQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
+constexpr uint32_t kDBitsWords = 1u << (kBloomMaxLog2 - 5);
+
+// One slice tile: start positions x0 .. x0 + kBatchSliceTile - 1 (those up to
+// `last`), lane L < 63 of wave w owning the 16 from x0 + 16 (63 w + L). rs
+// covers the tile's bytes from a 16-byte boundary and p0 is the resource
+// offset of x0; loads past the resource read zeros, which only positions past
+// `last` see.
+template <int K>
+__device__ __forceinline__ void slice_tile(__amdgpu_buffer_rsrc_t rs, uint32_t p0, int64_t x0, int64_t last,
+                                           const uint32_t *s_bits, uint32_t bshift, uint64_t *queue,
+                                           uint32_t &qn, const VerifyArgs *vp, int lane, int wave,
+                                           uint32_t &nhit, uint64_t *fbuf, uint32_t &fbn, uint32_t fbcap) {
+    constexpr int P = kBatchSliceLane;
+    constexpr int kLW = SliceLane<P>::load_words(false);
+    static_assert(kLW == 7, "one 16-byte and one 12-byte load per lane");
+    const uint32_t lane_off = (uint32_t)(P * (kSliceOwners * wave + lane));
+    const int at = (int)((p0 & ~3u) + lane_off);
+    uint32_t W[kLW];
+    const uint4 x = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at, 0, 0));
+    const auto y = __builtin_amdgcn_raw_buffer_load_b96(rs, at + 16, 0, 0);
+    W[0] = x.x; W[1] = x.y; W[2] = x.z; W[3] = x.w;
+    W[4] = y[0]; W[5] = y[1]; W[6] = y[2];
+    const int64_t xb = x0 + lane_off;
+    slice_test<K, P, false>(W, p0 & 3u, xb, last - xb + 1, s_bits, bshift, queue, qn, vp, lane, nhit, fbuf,
+                            fbn, fbcap);
+}
+
+// Emits the occurrences of the queued starts of a job with exact codes:
+// entry = start | code << 48, code_ids[code] the distinct pattern's index + 1.
+// All 64 lanes call it; lanes at or past `count` hold no entry.
+constexpr int kCodeShift = 48;
+__device__ static __attribute__((noinline)) uint32_t drain_codes(const VerifyArgs *v, const uint64_t *queue,
+                                                                uint32_t from, uint32_t count,
+                                                                const uint32_t *code_ids, uint64_t *fbuf,
+                                                                uint32_t fbn, uint32_t fcap) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t lane = __lane_id();
+    const bool active = lane < count;
+    const uint64_t e = active ? queue[from + lane] : 0ull;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t u1 = active ? code_ids[e >> kCodeShift] : 0u;
+    VerifyArgs args;
+    __builtin_memcpy(&args, v, sizeof(args));
+    return emit_found_buffered(args, e & ((1ull << kCodeShift) - 1), u1, fbuf, fbn, fcap);
+}
+
+// The 16 start positions xb .. xb + 15 of one lane in a job with exact codes
+// (W: the 40 bytes from the word holding xb, d = xb's byte offset in it).
+// Each byte's code is (b >> shift) & 3; four bytes' codes are packed into one
+// byte and the lane's 24 bytes into 48 bits, so a window's code is one funnel
+// shift and a mask, and one LDS bit test decides it. A byte is a pattern byte
+// iff the code's byte (a byte permute of rep) equals it; a window holding
+// another byte is dropped (the lanes of a wave check this only when one of
+// them holds such a byte). Passing starts are queued with their codes and
+// emitted 64 at a time.
+__device__ __forceinline__ void code_test(const uint32_t (&W)[10], uint32_t d, int64_t xb, int64_t last,
+                                          const uint32_t *s_bits, uint32_t shift, uint32_t rep,
+                                          uint32_t cmask, uint32_t m, uint64_t *queue, uint32_t &qn,
+                                          const VerifyArgs *vp, const uint32_t *code_ids, int lane,
+                                          uint64_t &nhit, uint64_t *fbuf, uint32_t &fbn, uint32_t fcap) {
+    uint32_t V[6], x[6], q[6];
+    uint32_t bad = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        V[t] = __builtin_amdgcn_alignbyte(W[t + 1], W[t], d);
+        const uint32_t T = (V[t] >> shift) & 0x03030303u;
+        x[t] = __builtin_amdgcn_perm(rep, rep, T) ^ V[t];    // nonzero bytes: not pattern bytes
+        bad |= x[t];
+        const uint32_t pp = T | (T >> 6);
+        q[t] = pp | (pp >> 12);                             // the 4 codes in bits 0..7
+    }
+    const uint32_t lo16 = __builtin_amdgcn_perm(q[1], q[0], 0x0C0C0400u);
+    const uint32_t hi16 = __builtin_amdgcn_perm(q[3], q[2], 0x0C0C0400u);
+    const uint32_t Slo = __builtin_amdgcn_perm(hi16, lo16, 0x05040100u);   // codes of bytes 0..15
+    const uint32_t Shi = __builtin_amdgcn_perm(q[5], q[4], 0x0C0C0400u);   // bytes 16..23
+    uint32_t hm = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const uint32_t code = (u ? __builtin_amdgcn_alignbit(Shi, Slo, 2u * u) : Slo) & cmask;
+        hm |= __builtin_amdgcn_ubfe(s_bits[code >> 5], code, 1u) << u;
+    }
+    if (__ballot(bad != 0) && bad) {
+        // byte k of the lane is not a pattern byte: drop the windows holding it
+        uint32_t badk = 0;
+#pragma unroll
+        for (int k = 0; k < 23; ++k)
+            badk |= (((x[k >> 2] >> (8 * (k & 3))) & 0xFFu) != 0u ? 1u : 0u) << k;
+        const uint32_t wmask = (1u << m) - 1u;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if ((badk >> u) & wmask) hm &= ~(1u << u);
+    }
+    const int64_t room = last - xb + 1;
+    if (room < 16) hm &= room <= 0 ? 0u : ((1u << (uint32_t)room) - 1u);
+    nhit += (uint32_t)__popc(hm);
+    while (__ballot(hm != 0)) {
+        const bool act = hm != 0;
+        const uint32_t u = act ? (uint32_t)__builtin_ctz(hm) : 0u;
+        hm &= hm - 1u;
+        const uint64_t bal = __ballot(act);
+        if (act) {
+            const uint32_t code = __builtin_amdgcn_alignbit(Shi, Slo, 2u * u) & cmask;
+            queue[qn + lanes_below(bal)] = (uint64_t)(xb + u) | ((uint64_t)code << kCodeShift);
+        }
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= 64) {
+            qn -= 64;
+            fbn = drain_codes(vp, queue, qn, 64, code_ids, fbuf, fbn, fcap);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restrict__ jobs, uint32_t njobs,
+                                                     const uint64_t *__restrict__ ranges, uint64_t *next,
+                                                     uint64_t *counters) {
+    __shared__ __align__(16) uint32_t s_bits[kDBitsWords];
+    __shared__ uint64_t s_queue[(kDT / 64) * kDQueue];
+    __shared__ uint64_t s_found[(kDT / 64) * kFoundBuf];
+    __shared__ uint64_t s_ctl[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *queue = s_queue + wave * kDQueue;
+    uint64_t *fbuf = s_found + wave * kFoundBuf;
+    uint32_t fcap = kFoundBuf;
+    uint32_t qn = 0, fbn = 0, nslice = 0;
+    uint64_t nbloom = 0;
+    const uint32_t me = blockIdx.x, G = gridDim.x;
+    const uint64_t own_end = uni64(ranges[3 * me + 1]);
+    bool own_done = false;
+    if (wave == 0) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd((unsigned long long *)&next[me], 1ull);
+        c = __shfl(c, 0);
+        uint64_t t = c;
+        if (c >= own_end) {
+            own_done = true;
+            t = steal_tile(next, ranges, G, me, lane);
+        }
+        if (lane == 0) s_ctl[0] = t;
+    }
+    __syncthreads();
+
+    int cur = -1;
+    const VerifyArgs *vp = nullptr;
+    const uint8_t *tbase = nullptr;
+    uint64_t delta = 0, n = 0, tfirst = 0, tend = 0;
+    uint32_t m = 1, slice_k = 0, bshift = 32, hw = 1, mw = 1, lastmask = 0, tile = kDenseScanTile;
+    uint32_t code_shift = 0, code_rep = 0, code_mask = 0;
+    const uint32_t *code_ids = nullptr;
+    for (uint32_t slot = 0;; slot ^= 1) {
+        const uint64_t g = uni64(s_ctl[slot]);
+        if (g == kNoTile) break;
+        unsigned long long pending = 0;
+        if (wave == 0 && !own_done && lane == 0)
+            pending = atomicAdd((unsigned long long *)&next[me], 1ull);
+        if (cur < 0 || g < tfirst || g >= tend) {
+            if (cur >= 0 && qn) {                // the previous job's starts
+                if (code_mask) fbn = drain_codes(vp, queue, 0, qn, code_ids, fbuf, fbn, fcap);
+                else fbn = drain_partial_found(vp, queue, qn, lane, fbuf, fbn, fcap);
+                qn = 0;
+            }
+            if (fbn) {                      // the buffer may lie where the next bitmap goes
+                flush_found_args(vp, fbuf, fbn);
+                fbn = 0;
+            }
+            uint32_t lo = 0, hi = njobs - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (jobs[mid].tile_first <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t j = uni32(lo);
+            const JobDesc &J = jobs[j];
+            cur = (int)j;
+            vp = &J.v;
+            tbase = uniptr(J.tbase);
+            delta = uni64(J.delta);
+            n = uni64(J.n);
+            tfirst = uni64(J.tile_first);
+            tend = tfirst + uni64(J.ntiles);
+            m = uni32(J.v.m);
+            slice_k = uni32(J.slice_k);
+            bshift = uni32(J.bshift);
+            hw = uni32(J.v.hw);
+            mw = uni32(J.v.mw);
+            lastmask = uni32(J.v.lastmask);
+            code_shift = uni32(J.code_shift);
+            code_rep = uni32(J.code_rep);
+            code_mask = uni32(J.code_mask);
+            code_ids = uniptr(J.code_ids);
+            tile = slice_k ? (uint32_t)kBatchSliceTile : (uint32_t)kDenseScanTile;
+            const uint32_t tvec = uni32(J.table_vec);
+            const uint4 *src = reinterpret_cast<const uint4 *>(uniptr(J.table));
+            const uint32_t spare = (kDBitsWords * 4u - tvec * 16u) / (8u * (kDT / 64));   // keys per wave
+            if (spare >= kDBitsWords * 4u / 2u / (8u * (kDT / 64))) {
+                fcap = spare < 1024u ? spare : 1024u;
+                fbuf = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(s_bits) + tvec * 16u) +
+                       (uint32_t)wave * fcap;
+            } else {
+                fcap = kFoundBuf;
+                fbuf = s_found + wave * kFoundBuf;
+            }
+            __syncthreads();                // the previous tile is done with the bitmap
+            uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
+            for (uint32_t v = tid; v < tvec; v += kDT) dst[v] = src[v];
+        }
+        const int64_t X0 = (int64_t)(g - tfirst) * tile;
+        int64_t e1 = X0 + (int64_t)tile + 48;            // bytes the tile's windows and probes touch
+        if (e1 > (int64_t)n) e1 = (int64_t)n;
+        const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
+        const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;
+        const __amdgpu_buffer_rsrc_t drs = tile_rsrc(tbase + da0, (uint32_t)(da1 - da0));
+        const uint32_t p0 = (uint32_t)(delta + (uint64_t)X0 - da0);
+        const int64_t last = (int64_t)n - (int64_t)m;
+        __syncthreads();                    // the bitmap is staged
+        if (wave == 0) {
+            uint64_t t = kNoTile;
+            if (!own_done) {
+                const uint64_t c = __shfl(pending, 0);
+                if (c < own_end) t = c;
+                else own_done = true;
+            }
+            if (t == kNoTile) t = steal_tile(next, ranges, G, me, lane);
+            if (lane == 0) s_ctl[slot ^ 1] = t;
+        }
+        if (slice_k) {
+            switch (slice_k) {
+                case 1: slice_tile<1>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 2: slice_tile<2>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 3: slice_tile<3>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 4: slice_tile<4>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 5: slice_tile<5>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 6: slice_tile<6>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 7: slice_tile<7>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                default: slice_tile<8>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+            }
+        } else if (code_mask) {
+            uint32_t W[10];
+            dense_load<kDT>(drs, (uint32_t)(da1 - da0), p0, tid, W);
+            code_test(W, p0 & 3u, X0 + 16 * (int64_t)tid, last, s_bits, code_shift, code_rep, code_mask, m, queue,
+                      qn, vp, code_ids, lane, nbloom, fbuf, fbn, fcap);
+        } else {
+            uint32_t W[10];
+            dense_load<kDT>(drs, (uint32_t)(da1 - da0), p0, tid, W);
+            dense_test_any(W, p0 & 3u, X0 + 16 * (int64_t)tid, last, s_bits, bshift, hw, mw, lastmask, queue, qn,
+                           vp, lane, nbloom, FoundBuf{fbuf, &fbn, fcap});
+        }
+        __syncthreads();                    // s_ctl for the next tile
+    }
+    if (cur >= 0 && qn) {
+        if (code_mask) fbn = drain_codes(vp, queue, 0, qn, code_ids, fbuf, fbn, fcap);
+        else fbn = drain_partial_found(vp, queue, qn, lane, fbuf, fbn, fcap);
+    }
+    if (fbn) flush_found_args(vp, fbuf, fbn);
+    unsigned long long nh = nbloom + nslice;
+    for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
+    if (lane == 0 && nh) {
+        atomicAdd((unsigned long long *)&counters[1], nh);
+        atomicAdd((unsigned long long *)&counters[2], nh);
+    }
 }
 
 // Claim counters back to the first tile of each workgroup's range.
@@ -463,6 +700,25 @@ mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "batch scan launch");
+}
+
+int batch_dense_occupancy() {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_batch_dense, kDT, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return occ;
+}
+
+mag_status launch_batch_dense(const BatchLaunch &b, hipStream_t stream) {
+    if (!b.total_tiles || !b.grid) return MAG_OK;
+    hipLaunchKernelGGL(k_batch_init, dim3((b.grid + 255) / 256), dim3(256), 0, stream, b.ranges,
+                       b.next, b.grid);
+    hipLaunchKernelGGL(k_batch_dense, dim3(b.grid), dim3(kDT), 0, stream, b.jobs, b.njobs, b.ranges, b.next,
+                       b.counters);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch dense scan launch");
 }
 
 mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,

@@ -13,8 +13,9 @@ namespace mag {
 
 constexpr int kBatchThreads = 512;               // threads per workgroup
 // Filter tiles hold 512 * words-per-lane samples, words per lane (the Shift-Or
-// run of one lane) 8, 16 (default) or 32, chosen per batch; dense jobs always
-// take tiles of kDenseTilePositions start positions (16 per lane).
+// run of one lane) 8, 16 (default) or 32, chosen per batch. Dense jobs run in
+// a launch of their own (k_batch_dense): tiles of kBatchSliceTile start
+// positions with the slice bitmap, else kDenseScanTile with the Bloom bitmap.
 constexpr int kBatchWordsDefault = 16;
 constexpr int kBatchMaxWarm = 32;                // warm-up entries before a tile (>= m' - 1)
 constexpr int kBatchQueue = 128;                 // per-wave queue of start positions
@@ -22,8 +23,8 @@ constexpr int kBatchQueue = 128;                 // per-wave queue of start posi
 // 16-byte vectors
 constexpr uint32_t batch_entry_bytes(int TS) { return ((TS + kBatchMaxWarm) * 4 + 127) / 128 * 128; }
 constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
-static_assert(kBatchThreads == kDenseThreads, "dense tiles of the batch kernel are the dense kernel's tiles");
-static_assert((1u << kBloomBatchLog2) / 8 <= kBatchTableLds, "batched Bloom bitmaps fit in LDS");
+constexpr int kBatchSliceLane = 16;              // start positions per lane of a slice tile
+constexpr int kBatchSliceTile = slice_scan_tile(kBatchSliceLane);
 // alphabet map, two claimed-tile slots, queues, entries, table
 constexpr uint32_t batch_lds_bytes(int TS) {
     return 256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + batch_entry_bytes(TS) + kBatchTableLds;
@@ -41,8 +42,14 @@ struct JobDesc {
     uint32_t q, k, kq, mprime, W, sp, esz, w0;
     uint32_t tlds;             // table staged in LDS
     uint32_t table_vec;        // 16-byte vectors of the table
-    uint32_t dense;            // test every start position; `table` is then the Bloom bitmap
-    uint32_t bshift;           // 32 - log2(Bloom bits) of a dense job
+    uint32_t dense;            // test every start position; `table` is then the job's bitmap
+    uint32_t bshift;           // 32 - log2(bitmap bits) of a dense job
+    uint32_t slice_k;          // dense job: slices per pattern of its slice bitmap (0: Bloom bitmap)
+    // dense job with exact window codes (code_mask != 0; `table` is then the
+    // code bitmap): the field shift, the bytes of the four codes and the
+    // code of each distinct pattern's index + 1
+    uint32_t code_shift, code_rep, code_mask;
+    const uint32_t *code_ids;
     VerifyArgs v;              // verification, with the job number in key_or
 };
 
@@ -62,6 +69,10 @@ struct BatchLaunch {
 int batch_occupancy(int words_per_lane);
 mag_status batch_configure();
 mag_status launch_batch(const BatchLaunch &b, hipStream_t stream);
+// The dense jobs' launch: b.jobs holds only dense jobs, with their own tile
+// sequence, ranges and claims; one 1024-thread workgroup per compute unit.
+int batch_dense_occupancy();
+mag_status launch_batch_dense(const BatchLaunch &b, hipStream_t stream);
 // Verifies the starts that batched jobs deferred: entry = job << kBatchJobShift
 // | start (batch.hip).
 constexpr int kBatchJobShift = 40;

@@ -213,7 +213,9 @@ mag_status ensure_device(mag_plan *p) {
     const uint64_t o_bloom = round16(o_ids + p->ids.size() * 4 + 16);
     const uint64_t o_bloomb = round16(o_bloom + p->bloom.size() * 4);
     const uint64_t o_sl = round16(o_bloomb + p->bloom_batch.size() * 4 + 16);
-    const uint64_t o_wf = round16(o_sl + p->slices.size() * 4 + 16);
+    const uint64_t o_cb = round16(o_sl + p->slices.size() * 4 + 16);
+    const uint64_t o_ci = round16(o_cb + p->code_bits.size() * 4);
+    const uint64_t o_wf = round16(o_ci + p->code_ids.size() * 4 + 16);
     const uint64_t o_pwoff = round16(o_wf + p->wfilter.size() * 8 + 16);
     const uint64_t o_plen = round16(o_pwoff + p->pwoff.size() * 4);
     const uint64_t o_gstart = round16(o_plen + p->plen.size() * 4);
@@ -235,6 +237,8 @@ mag_status ensure_device(mag_plan *p) {
     if (!p->bloom_batch.empty())
         std::memcpy(&host[o_bloomb], p->bloom_batch.data(), p->bloom_batch.size() * 4);
     if (!p->slices.empty()) std::memcpy(&host[o_sl], p->slices.data(), p->slices.size() * 4);
+    if (!p->code_bits.empty()) std::memcpy(&host[o_cb], p->code_bits.data(), p->code_bits.size() * 4);
+    if (!p->code_ids.empty()) std::memcpy(&host[o_ci], p->code_ids.data(), p->code_ids.size() * 4);
     if (!p->wfilter.empty()) std::memcpy(&host[o_wf], p->wfilter.data(), p->wfilter.size() * 8);
     if (!p->pwoff.empty()) std::memcpy(&host[o_pwoff], p->pwoff.data(), p->pwoff.size() * 4);
     if (!p->plen.empty()) std::memcpy(&host[o_plen], p->plen.data(), p->plen.size() * 4);
@@ -254,6 +258,8 @@ mag_status ensure_device(mag_plan *p) {
     p->dev.bloom = reinterpret_cast<const uint32_t *>(base + o_bloom);
     p->dev.bloom_batch = reinterpret_cast<const uint32_t *>(base + o_bloomb);
     p->dev.slices = reinterpret_cast<const uint32_t *>(base + o_sl);
+    p->dev.code_bits = reinterpret_cast<const uint32_t *>(base + o_cb);
+    p->dev.code_ids = reinterpret_cast<const uint32_t *>(base + o_ci);
     p->dev.wfilter = p->wfilter.empty() ? nullptr : reinterpret_cast<const uint64_t *>(base + o_wf);
     p->dev.pwoff = reinterpret_cast<const uint32_t *>(base + o_pwoff);
     p->dev.plen = reinterpret_cast<const uint32_t *>(base + o_plen);

@@ -14,8 +14,6 @@
 
 namespace mag {
 
-constexpr int kDenseThreads = 512;                        // the batched kernel's dense jobs
-constexpr int kDenseTilePositions = 16 * kDenseThreads;   // 16 consecutive positions per thread
 // The single-job dense kernel: one 1024-thread workgroup holds a compute
 // unit's 16 wave slots (4 per SIMD at up to 128 VGPRs) beside a Bloom bitmap
 // of up to 128 KiB, where two 512-thread ones would not fit.
@@ -265,7 +263,7 @@ __device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::loa
                                            int64_t xb, int64_t room, const uint32_t *s_bits,
                                            uint32_t bshift, uint64_t *queue, uint32_t &qn,
                                            const VerifyArgs *vp, int lane, uint32_t &nhit, uint64_t *fbuf,
-                                           uint32_t &fbn) {
+                                           uint32_t &fbn, uint32_t fbcap = kFoundBuf) {
     uint32_t V[SliceLane<P>::kWords];
     slice_words<P, AL>(W, d, V);
     const uint32_t hm = slice_probes<P>(V, s_bits, bshift);
@@ -298,7 +296,7 @@ __device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::loa
         qn += (uint32_t)__popcll(bal);
         if (qn >= 64) {
             qn -= 64;
-            fbn = drain64_found(vp, queue, qn, lane, fbuf, fbn);
+            fbn = drain64_found(vp, queue, qn, lane, fbuf, fbn, fbcap);
         }
     }
 }
@@ -313,21 +311,6 @@ __device__ __forceinline__ void dense_test_any(const uint32_t (&W)[10], uint32_t
         dense_test<true>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit, fb);
     else
         dense_test<false>(W, d, xb, last, s_bloom, bshift, hw, mw, lastmask, queue, qn, vp, lane, nhit, fb);
-}
-
-// One whole tile: start positions x0 .. x0 + 16*NT - 1 (those up to `last`),
-// thread tid taking the 16 consecutive positions from x0 + 16*tid. rs covers
-// the tile's bytes, nrec is its size and p0 the resource offset of x0.
-template <int NT>
-__device__ __forceinline__ void dense_tile(__amdgpu_buffer_rsrc_t rs, uint32_t nrec, uint32_t p0,
-                                           int64_t x0, int64_t last, const uint32_t *s_bloom,
-                                           uint32_t bshift, uint32_t hw, uint32_t mw, uint32_t lastmask,
-                                           uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int tid,
-                                           int lane, uint64_t &nhit, FoundBuf fb = {}) {
-    uint32_t W[10];
-    dense_load<NT>(rs, nrec, p0, tid, W);
-    dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, last, s_bloom, bshift, hw, mw, lastmask, queue, qn,
-                   vp, lane, nhit, fb);
 }
 
 }  // namespace dev

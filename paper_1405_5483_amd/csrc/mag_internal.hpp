@@ -172,6 +172,8 @@ struct DeviceTables {
     const uint32_t *bloom = nullptr;   // 2^bloom_log2 bits
     const uint32_t *bloom_batch = nullptr;  // 2^min(bloom_log2, kBloomBatchLog2) bits
     const uint32_t *slices = nullptr;  // 2^bloom_log2 bits of the one-probe dense mode
+    const uint32_t *code_bits = nullptr;  // exact codes (build_codes)
+    const uint32_t *code_ids = nullptr;
     const uint64_t *wfilter = nullptr; // 2^wf_bits words: the word filter (one-probe dense mode)
     const uint32_t *pwoff = nullptr;   // unequal lengths: word offset of each distinct pattern
     const uint32_t *plen = nullptr;    //   its length
@@ -231,6 +233,17 @@ struct mag_plan {
     std::vector<uint32_t> pwoff, plen, gstart;
     uint64_t verify_buffer = 0;      // deferred-start buffer entries (0: sized per scan)
     std::vector<uint32_t> bloom, bloom_batch;
+    // exact codes of the batched dense scans (build_codes): when the pattern
+    // bytes are at most four and a 2-bit field (b >> code_shift) & 3 tells
+    // them apart, and 2m <= 16, a window's code (field t at bits 2t) is exact
+    // for windows of pattern bytes; code_bits has bit c set when code c is a
+    // distinct pattern's, code_ids[c] is that pattern's index + 1, and
+    // code_rep holds the byte of each code (another code's byte for unused
+    // ones), so that a window byte b is a pattern byte iff
+    // rep[(b >> code_shift) & 3] == b.
+    int code_shift = -1;             // -1: no exact codes
+    uint32_t code_rep = 0;
+    std::vector<uint32_t> code_bits, code_ids;
     // one-probe dense mode: slice_k slices per distinct pattern in a bitmap of
     // 2^bloom_log2 bits (slice_k = 0: the dense mode uses the Bloom bitmap)
     int dense_probe = MAG_DENSE_PROBE_AUTO;

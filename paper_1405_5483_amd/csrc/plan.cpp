@@ -284,6 +284,54 @@ void build_bloom(mag_plan *p) {
     }
 }
 
+// Exact window codes for the batched dense scans (see mag_plan::code_shift):
+// patterns of at most 8 bytes over at most four byte values that one 2-bit
+// field (b >> s) & 3, s = 0..6, tells apart (the smallest such s).
+void build_codes(mag_plan *p) {
+    p->code_shift = -1;
+    p->code_rep = 0;
+    p->code_bits.clear();
+    p->code_ids.clear();
+    if (p->var || p->m > 8 || p->n_unique == 0) return;
+    bool used[256] = {false};
+    for (uint8_t c : p->patterns) used[c] = true;
+    std::vector<int> alpha;
+    for (int b = 0; b < 256; ++b)
+        if (used[b]) alpha.push_back(b);
+    if (alpha.size() > 4) return;
+    for (int s = 0; s <= 6 && p->code_shift < 0; ++s) {
+        int seen = 0;
+        bool ok = true;
+        for (int b : alpha) {
+            const int c = (b >> s) & 3;
+            if (seen & (1 << c)) ok = false;
+            seen |= 1 << c;
+        }
+        if (!ok) continue;
+        p->code_shift = s;
+        uint32_t rep = 0;
+        for (int c = 0; c < 4; ++c) {
+            // an unused code gets a byte of another code: no byte with code c matches it
+            uint32_t byte = (uint32_t)(((c ^ 1) & 3) << s);
+            for (int b : alpha)
+                if (((b >> s) & 3) == c) byte = (uint32_t)b;
+            rep |= byte << (8 * c);
+        }
+        p->code_rep = rep;
+    }
+    if (p->code_shift < 0) return;
+    const int bits = 2 * (int)p->m;
+    p->code_bits.assign(std::max<size_t>((1ull << bits) / 32, 4), 0u);
+    p->code_ids.assign(1ull << bits, 0u);
+    for (uint32_t u = 0; u < p->n_unique; ++u) {
+        const uint8_t *w = reinterpret_cast<const uint8_t *>(&p->pwords[(size_t)u * p->mw]);
+        uint32_t code = 0;
+        for (uint32_t t = 0; t < p->m; ++t) code |= (uint32_t)((w[t] >> p->code_shift) & 3) << (2 * t);
+        p->code_bits[code >> 5] |= 1u << (code & 31);
+        p->code_ids[code] = u + 1;
+    }
+}
+
 // One-probe dense bitmap (slice_hash): built when the patterns are at least
 // kSliceBytes long and their bytes carry enough entropy that a 6-byte slice
 // spreads over the bitmap (6 H >= B + 4 bits, H the byte entropy of the
@@ -543,6 +591,7 @@ mag_status build_plan(mag_plan *p, const uint8_t *patterns, uint32_t r, uint32_t
     build_verifier(p);
     build_bloom(p);
     build_slices(p, prm.dense_probe);
+    build_codes(p);
     p->dense_probe = prm.dense_probe;
     p->chunk_bytes = prm.chunk_bytes;
     p->words_per_lane = prm.words_per_lane;

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import match as om
-from synth import batch_jobs, batch_recipes, gen_patterns, gen_text, make_job
+from synth import Job, batch_jobs, batch_recipes, gen_patterns, gen_text, make_job
 
 pytestmark = pytest.mark.gpu
 
@@ -153,6 +153,47 @@ def test_batch_dense_jobs_between_filter_jobs(torch_cuda, mag):
     total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
     assert total > 8192
     texts = _upload(torch, [j.text for j in jobs], [(5 * j) % 16 for j in range(len(jobs))])
+    b = mag.Batch(plans)
+    b.bind(texts, total + 64)
+    _check_jobs(b.run(), jobs)
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
+def test_batch_dense_exact_codes(torch_cuda, mag):
+    """Dense jobs whose patterns use at most four byte values that one 2-bit
+    field of the byte tells apart (DNA letters, or bytes 0..3) take exact
+    window codes; texts hold other bytes too (N, lowercase, 4..255), which
+    no window may match through a shared code. Lengths 1..8, a two-letter
+    pattern alphabet, texts at unaligned addresses and around tile ends."""
+    torch = torch_cuda
+    rng = np.random.default_rng(808)
+    jobs, plans = [], []
+
+    def job(text, pats):
+        pats = np.asarray(pats, dtype=np.uint8)
+        jobs.append(Job(text, pats, {}))
+        plans.append(mag.Plan(pats, mode="dense"))
+
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    for m, n in ((8, 100_003), (5, 16_384 * 3 + 5), (2, 40_000), (1, 9_000), (7, 16_383)):
+        t = acgt[rng.integers(0, 4, n)]
+        other = rng.random(n) < 0.01                      # N, n, a and random bytes
+        t[other] = rng.choice(np.frombuffer(b"NnaX\x00\xc1", dtype=np.uint8), int(other.sum()))
+        starts = rng.integers(0, n - m, 300)
+        pats = np.stack([t[i:i + m] for i in starts])
+        pats = pats[np.all(np.isin(pats, acgt), axis=1)]
+        job(t, pats)
+    # two letters of ACGT in the patterns
+    t = acgt[rng.integers(0, 4, 50_000)]
+    job(t, np.frombuffer(b"ACACCAAC" b"CCCCAAAA", dtype=np.uint8).reshape(2, 8))
+    # bytes 0..3 (field at shift 0) against text bytes 0..7
+    t = rng.integers(0, 8, 70_000).astype(np.uint8)
+    pats = rng.integers(0, 4, (400, 6)).astype(np.uint8)
+    job(t, pats)
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    assert total > 8192
+    texts = _upload(torch, [j.text for j in jobs], [(3 * j + 1) % 16 for j in range(len(jobs))])
     b = mag.Batch(plans)
     b.bind(texts, total + 64)
     _check_jobs(b.run(), jobs)
