@@ -22,7 +22,7 @@ constexpr int kBatchQueue = 128;                 // per-wave queue of start posi
 // mask entries of one tile of TS samples as u32, in whole groups of eight
 // 16-byte vectors
 constexpr uint32_t batch_entry_bytes(int TS) { return ((TS + kBatchMaxWarm) * 4 + 127) / 128 * 128; }
-constexpr uint32_t kBatchTableLds = 32 * 1024;   // larger mask tables are read from L2
+constexpr uint32_t kBatchTableLds = 64 * 1024;   // larger mask tables are read from L2
 constexpr int kBatchSliceLane = 16;              // start positions per lane of a slice tile
 constexpr int kBatchSliceTile = slice_scan_tile(kBatchSliceLane);
 // alphabet map, two claimed-tile slots, queues, entries, table

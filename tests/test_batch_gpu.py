@@ -75,7 +75,7 @@ def test_batch_mixed_jobs(torch_cuda, mag):
     plans = [mag.Plan(j.patterns, mode="dense" if i % 3 == 2 else "filter")
              for i, j in enumerate(jobs[:-1])]
     plans.append(mag.Plan(jobs[-1].patterns, q=4, k=1, sigma_prime=20, mode="filter"))
-    assert plans[-1].info()["table_bytes"] > 32 * 1024
+    assert plans[-1].info()["table_bytes"] > 64 * 1024
     # a plan shared by two jobs (same patterns, another text)
     t2 = gen_text(70_001, jobs[3].recipe["sigma"], rng=12)
     jobs.append(type(jobs[0])(t2, jobs[3].patterns, {"shared": True}))
