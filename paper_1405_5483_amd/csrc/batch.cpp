@@ -258,8 +258,9 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.X = X;
         J.tile_first = total_tiles;
         const bool slices = p->dense && p->slice_k > 0;
-        const uint64_t TS = slices ? (uint64_t)kBatchSliceTile
-                            : p->dense ? (uint64_t)kDenseScanTile : (uint64_t)kBatchThreads * wpl;
+        const uint64_t TS = slices ? (uint64_t)kBatchSliceTile * kBatchDenseChunk
+                            : p->dense ? (uint64_t)kDenseScanTile * kBatchDenseChunk
+                                       : (uint64_t)kBatchThreads * wpl;
         J.ntiles = (X + TS - 1) / TS;
         J.mu = p->dev.mu;
         J.table = p->dev.table;

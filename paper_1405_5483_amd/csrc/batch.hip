@@ -367,29 +367,49 @@ constexpr int kDQueue = 128;
 static_assert(kDQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 constexpr uint32_t kDBitsWords = 1u << (kBloomMaxLog2 - 5);
 
-// One slice tile: start positions x0 .. x0 + kBatchSliceTile - 1 (those up to
-// `last`), lane L < 63 of wave w owning the 16 from x0 + 16 (63 w + L). rs
-// covers the tile's bytes from a 16-byte boundary and p0 is the resource
-// offset of x0; loads past the resource read zeros, which only positions past
-// `last` see.
+// A claimed dense tile is kBatchDenseChunk consecutive sub-tiles of the
+// single-job kernels' size; a wave tests one sub-tile while the loads of the
+// next are in flight (the loads are unconditional, clamped to the last
+// sub-tile, so that the wait before a sub-tile counts the same loads on every
+// path), and the workgroup meets at a barrier once per claimed tile.
+constexpr int kDChunk = kBatchDenseChunk;
+
+// The slice sub-tiles x0 + s kBatchSliceTile, s < nsub, of one claimed tile:
+// lane L < 63 of wave w owns the 16 start positions from 16 (63 w + L) of
+// each. rs covers the tile's bytes from a 16-byte boundary and p0 is the
+// resource offset of x0; loads past the resource read zeros, which only
+// positions past `last` see.
 template <int K>
-__device__ __forceinline__ void slice_tile(__amdgpu_buffer_rsrc_t rs, uint32_t p0, int64_t x0, int64_t last,
-                                           const uint32_t *s_bits, uint32_t bshift, uint64_t *queue,
-                                           uint32_t &qn, const VerifyArgs *vp, int lane, int wave,
-                                           uint32_t &nhit, uint64_t *fbuf, uint32_t &fbn, uint32_t fbcap) {
+__device__ __forceinline__ void slice_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t p0, int64_t x0, int nsub,
+                                            int64_t last, const uint32_t *s_bits, uint32_t bshift,
+                                            uint64_t *queue, uint32_t &qn, const VerifyArgs *vp, int lane,
+                                            int wave, uint32_t &nhit, uint64_t *fbuf, uint32_t &fbn,
+                                            uint32_t fbcap) {
     constexpr int P = kBatchSliceLane;
     constexpr int kLW = SliceLane<P>::load_words(false);
     static_assert(kLW == 7, "one 16-byte and one 12-byte load per lane");
     const uint32_t lane_off = (uint32_t)(P * (kSliceOwners * wave + lane));
-    const int at = (int)((p0 & ~3u) + lane_off);
-    uint32_t W[kLW];
-    const uint4 x = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at, 0, 0));
-    const auto y = __builtin_amdgcn_raw_buffer_load_b96(rs, at + 16, 0, 0);
-    W[0] = x.x; W[1] = x.y; W[2] = x.z; W[3] = x.w;
-    W[4] = y[0]; W[5] = y[1]; W[6] = y[2];
-    const int64_t xb = x0 + lane_off;
-    slice_test<K, P, false>(W, p0 & 3u, xb, last - xb + 1, s_bits, bshift, queue, qn, vp, lane, nhit, fbuf,
-                            fbn, fbcap);
+    auto load = [&](int sub, uint32_t (&W)[kLW]) {
+        const int at = (int)((p0 & ~3u) + (uint32_t)sub * kBatchSliceTile + lane_off);
+        const uint4 x = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, at, 0, 0));
+        const auto y = __builtin_amdgcn_raw_buffer_load_b96(rs, at + 16, 0, 0);
+        W[0] = x.x; W[1] = x.y; W[2] = x.z; W[3] = x.w;
+        W[4] = y[0]; W[5] = y[1]; W[6] = y[2];
+    };
+    auto test = [&](int sub, const uint32_t (&W)[kLW]) {
+        const int64_t xb = x0 + (int64_t)sub * kBatchSliceTile + lane_off;
+        slice_test<K, P, false>(W, p0 & 3u, xb, last - xb + 1, s_bits, bshift, queue, qn, vp, lane, nhit, fbuf,
+                                fbn, fbcap);
+    };
+    uint32_t Wa[kLW], Wb[kLW];
+    load(0, Wa);
+    for (int sub = 0; sub < nsub; sub += 2) {
+        load(sub + 1 < nsub ? sub + 1 : nsub - 1, Wb);
+        test(sub, Wa);
+        if (sub + 1 >= nsub) break;
+        load(sub + 2 < nsub ? sub + 2 : nsub - 1, Wa);
+        test(sub + 1, Wb);
+    }
 }
 
 // Emits the occurrences of the queued starts of a job with exact codes:
@@ -556,7 +576,7 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
             code_rep = uni32(J.code_rep);
             code_mask = uni32(J.code_mask);
             code_ids = uniptr(J.code_ids);
-            tile = slice_k ? (uint32_t)kBatchSliceTile : (uint32_t)kDenseScanTile;
+            tile = slice_k ? (uint32_t)kBatchSliceTile : (uint32_t)kDenseScanTile;   // one sub-tile
             const uint32_t tvec = uni32(J.table_vec);
             const uint4 *src = reinterpret_cast<const uint4 *>(uniptr(J.table));
             const uint32_t spare = (kDBitsWords * 4u - tvec * 16u) / (8u * (kDT / 64));   // keys per wave
@@ -572,14 +592,18 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
             uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
             for (uint32_t v = tid; v < tvec; v += kDT) dst[v] = src[v];
         }
-        const int64_t X0 = (int64_t)(g - tfirst) * tile;
-        int64_t e1 = X0 + (int64_t)tile + 48;            // bytes the tile's windows and probes touch
+        const int64_t X0 = (int64_t)(g - tfirst) * tile * kDChunk;
+        const int64_t last = (int64_t)n - (int64_t)m;
+        // sub-tiles holding start positions up to `last`
+        const int64_t left = last - X0 + 1;
+        const int nsub = left >= (int64_t)tile * kDChunk ? kDChunk : (int)((left + tile - 1) / tile);
+        int64_t e1 = X0 + (int64_t)tile * kDChunk + 48;  // bytes the tile's windows and probes touch
         if (e1 > (int64_t)n) e1 = (int64_t)n;
         const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
         const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;
         const __amdgpu_buffer_rsrc_t drs = tile_rsrc(tbase + da0, (uint32_t)(da1 - da0));
         const uint32_t p0 = (uint32_t)(delta + (uint64_t)X0 - da0);
-        const int64_t last = (int64_t)n - (int64_t)m;
+        const uint32_t nrec = (uint32_t)(da1 - da0);
         __syncthreads();                    // the bitmap is staged
         if (wave == 0) {
             uint64_t t = kNoTile;
@@ -591,27 +615,39 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
             if (t == kNoTile) t = steal_tile(next, ranges, G, me, lane);
             if (lane == 0) s_ctl[slot ^ 1] = t;
         }
+        // every tile holds a start position (tiles = ceil(positions / tile size))
         if (slice_k) {
             switch (slice_k) {
-                case 1: slice_tile<1>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 2: slice_tile<2>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 3: slice_tile<3>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 4: slice_tile<4>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 5: slice_tile<5>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 6: slice_tile<6>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                case 7: slice_tile<7>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
-                default: slice_tile<8>(drs, p0, X0, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 1: slice_chunk<1>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 2: slice_chunk<2>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 3: slice_chunk<3>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 4: slice_chunk<4>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 5: slice_chunk<5>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 6: slice_chunk<6>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                case 7: slice_chunk<7>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
+                default: slice_chunk<8>(drs, p0, X0, nsub, last, s_bits, bshift, queue, qn, vp, lane, wave, nslice, fbuf, fbn, fcap); break;
             }
-        } else if (code_mask) {
-            uint32_t W[10];
-            dense_load<kDT>(drs, (uint32_t)(da1 - da0), p0, tid, W);
-            code_test(W, p0 & 3u, X0 + 16 * (int64_t)tid, last, s_bits, code_shift, code_rep, code_mask, m, queue,
-                      qn, vp, code_ids, lane, nbloom, fbuf, fbn, fcap);
         } else {
-            uint32_t W[10];
-            dense_load<kDT>(drs, (uint32_t)(da1 - da0), p0, tid, W);
-            dense_test_any(W, p0 & 3u, X0 + 16 * (int64_t)tid, last, s_bits, bshift, hw, mw, lastmask, queue, qn,
-                           vp, lane, nbloom, FoundBuf{fbuf, &fbn, fcap});
+            // Bloom or exact-code sub-tiles: 16 positions per thread
+            const bool codes = code_mask != 0;
+            auto test = [&](int sub, const uint32_t (&W)[10]) {
+                const int64_t xb = X0 + (int64_t)sub * tile + 16 * (int64_t)tid;
+                if (codes)
+                    code_test(W, p0 & 3u, xb, last, s_bits, code_shift, code_rep, code_mask, m, queue, qn, vp,
+                              code_ids, lane, nbloom, fbuf, fbn, fcap);
+                else
+                    dense_test_any(W, p0 & 3u, xb, last, s_bits, bshift, hw, mw, lastmask, queue, qn, vp, lane,
+                                   nbloom, FoundBuf{fbuf, &fbn, fcap});
+            };
+            uint32_t Wa[10], Wb[10];
+            dense_load<kDT>(drs, nrec, p0, tid, Wa);
+            for (int sub = 0; sub < nsub; sub += 2) {
+                dense_load<kDT>(drs, nrec, p0 + (uint32_t)(sub + 1 < nsub ? sub + 1 : nsub - 1) * tile, tid, Wb);
+                test(sub, Wa);
+                if (sub + 1 >= nsub) break;
+                dense_load<kDT>(drs, nrec, p0 + (uint32_t)(sub + 2 < nsub ? sub + 2 : nsub - 1) * tile, tid, Wa);
+                test(sub + 1, Wb);
+            }
         }
         __syncthreads();                    // s_ctl for the next tile
     }

@@ -25,6 +25,9 @@ constexpr uint32_t batch_entry_bytes(int TS) { return ((TS + kBatchMaxWarm) * 4 
 constexpr uint32_t kBatchTableLds = 64 * 1024;   // larger mask tables are read from L2
 constexpr int kBatchSliceLane = 16;              // start positions per lane of a slice tile
 constexpr int kBatchSliceTile = slice_scan_tile(kBatchSliceLane);
+// a dense job's claimed tile: this many sub-tiles of kBatchSliceTile or
+// kDenseScanTile start positions
+constexpr int kBatchDenseChunk = 4;
 // alphabet map, two claimed-tile slots, queues, entries, table
 constexpr uint32_t batch_lds_bytes(int TS) {
     return 256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + batch_entry_bytes(TS) + kBatchTableLds;
