@@ -330,15 +330,18 @@ void mag_batch_destroy(mag_batch *batch);
 mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const uint64_t *n,
                           uint64_t out_cap, void *stream);
 
-/* The batched kernel's tile shape (the batch autotuner's knob): each lane's
+/* The filter jobs' tile shape (the batch autotuner's knob): each lane's
  * Shift-Or run takes words_per_lane samples (8, 16 or 32), so filter jobs are
  * cut into tiles of 512 * words_per_lane samples (a tile is one workgroup's
- * unit of work in the persistent launch); dense jobs always take tiles of
- * 8192 start positions. Default 16. Takes effect at the next mag_batch_bind.
+ * unit of work in the filter jobs' persistent launch); dense jobs run in a
+ * launch of their own with tiles of four times the single-job dense
+ * kernels' (64,512 start positions with a slice bitmap, else 65,536).
+ * Default 16. Takes effect at the next mag_batch_bind.
  * Errors: other values -> MAG_E_INVALID. */
 mag_status mag_batch_set_words_per_lane(mag_batch *batch, int32_t words_per_lane);
 
-/* Scans every bound job in one persistent launch and sorts the output, all
+/* Scans every bound job (two persistent launches: the filter jobs, then the
+ * dense jobs) and sorts the output, all
  * enqueued on `stream` without host synchronization or allocation (so the
  * sequence can be captured in a hipGraph and replayed). Occurrences land in
  * d_out job by job, each job's records sorted by (pos, id) with positions

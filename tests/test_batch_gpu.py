@@ -130,10 +130,11 @@ def test_batch_device_wide_sort(torch_cuda, mag):
 
 def test_batch_dense_jobs_between_filter_jobs(torch_cuda, mag):
     """Dense jobs (protein-like and Zipf alphabets, m = 8, 16, 32), many of
-    whose patterns occur, with DNA dense jobs and filter jobs between them:
-    the waves' found-key buffers of dense tiles must be flushed before a
-    filter tile reuses their memory. Text lengths fall on and around multiples
-    of 8064 and 8192 start positions, at unaligned addresses."""
+    whose patterns occur, with DNA dense jobs and filter jobs between them in
+    the job order (the dense launch's job switches restage bitmaps and move
+    the found-key buffers, which must be flushed first). Text lengths fall on
+    and around multiples of the slice tiles (8064 positions per 8 waves), at
+    unaligned addresses."""
     torch = torch_cuda
     tile = 16 * 63 * 8
     jobs, plans = [], []
