@@ -331,8 +331,8 @@ mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const
                           uint64_t out_cap, void *stream);
 
 /* The filter jobs' tile shape (the batch autotuner's knob): each lane's
- * Shift-Or run takes words_per_lane samples (8, 16 or 32), so filter jobs are
- * cut into tiles of 512 * words_per_lane samples (a tile is one workgroup's
+ * Shift-Or run takes words_per_lane samples (8 or 16), so filter jobs are
+ * cut into tiles of 1024 * words_per_lane samples (a tile is one workgroup's
  * unit of work in the filter jobs' persistent launch); dense jobs run in a
  * launch of their own with tiles of four times the single-job dense
  * kernels' (64,512 start positions with a slice bitmap, else 65,536).
@@ -501,8 +501,8 @@ mag_status mag_autotune(const uint8_t *patterns, uint32_t r, uint32_t m,
  * log2(r), and mag_autotune (with opts) times candidates for each class on a
  * sample of its largest job's text (at most sample_bytes, 0 = 4 MiB);
  * params[j] (host, njobs entries) receives the pick for job j's class. Then
- * the whole batch, planned with those parameters, is timed with 8, 16 and 32
- * words per lane (tiles of 512 times that many samples) and the fastest goes
+ * the whole batch, planned with those parameters, is timed with 8 and 16
+ * words per lane (filter tiles of 1024 times that many samples) and the fastest goes
  * to *words_per_lane. jobs[j].plan is ignored (may be NULL); the patterns
  * come from pat[j] (host, r[j] * m[j] bytes). Allocates and waits; not for
  * graph capture. Errors: NULL arrays -> MAG_E_INVALID; errors of

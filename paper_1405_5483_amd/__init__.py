@@ -283,7 +283,7 @@ class Batch:
             self.set_words_per_lane(words_per_lane)
 
     def set_words_per_lane(self, words_per_lane: int) -> None:
-        """Filter tiles of 512 * words_per_lane samples (8, 16 or 32); takes
+        """Filter tiles of 1024 * words_per_lane samples (8 or 16); takes
         effect at the next bind."""
         check(lib().mag_batch_set_words_per_lane(self.handle, int(words_per_lane)),
               "mag_batch_set_words_per_lane")

@@ -110,7 +110,7 @@ struct mag_batch {
     uint64_t *d_dnext = nullptr;
     size_t dnext_bytes = 0;
     bool defer = false;              // some job defers its verification
-    int words_per_lane = mag::kBatchWordsDefault;   // filter tiles of 512 * words samples
+    int words_per_lane = mag::kBatchWordsDefault;   // filter tiles of 1024 * words samples
     int bound_words = mag::kBatchWordsDefault;      // the value the bound tile layout uses
     mag::Scratch sc;
 };
@@ -414,8 +414,8 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
 
 mag_status mag_batch_set_words_per_lane(mag_batch *b, int32_t words_per_lane) {
     if (!b) return fail(MAG_E_INVALID, "batch is NULL");
-    if (words_per_lane != 8 && words_per_lane != 16 && words_per_lane != 32)
-        return fail(MAG_E_INVALID, "words_per_lane must be 8, 16 or 32");
+    if (words_per_lane != 8 && words_per_lane != 16)
+        return fail(MAG_E_INVALID, "words_per_lane must be 8 or 16");
     std::lock_guard<std::mutex> lock(b->mtx);
     b->words_per_lane = words_per_lane;
     return MAG_OK;

@@ -1,7 +1,7 @@
 // Batched MAG scans: many independent (text, pattern set) jobs in one
 // persistent launch.
 //
-// Every filter job is cut into tiles of 512 * words-per-lane samples; the
+// Every filter job is cut into tiles of 1024 * words-per-lane samples; the
 // tiles of all filter jobs form one global sequence (job after job) that the
 // host splits into contiguous ranges of about equal text bytes, one per
 // workgroup, so a workgroup restages a job's alphabet map and mask table in
@@ -147,7 +147,7 @@ __device__ uint64_t steal_tile(uint64_t *next, const uint64_t *ranges, uint32_t 
     }
 }
 
-// TS: samples per filter tile (512 * words per lane).
+// TS: samples per filter tile (1024 * words per lane).
 template <int TS>
 __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jobs, uint32_t njobs,
                                                const uint64_t *__restrict__ ranges,
@@ -700,7 +700,6 @@ namespace {
 const void *batch_kernel(int words_per_lane) {
     switch (words_per_lane) {
         case 8: return (const void *)k_batch<8 * kBT>;
-        case 32: return (const void *)k_batch<32 * kBT>;
         default: return (const void *)k_batch<16 * kBT>;
     }
 }
@@ -723,10 +722,6 @@ mag_status launch_batch(const BatchLaunch &b, hipStream_t stream) {
     switch (b.words_per_lane) {
         case 8:
             hipLaunchKernelGGL(k_batch<8 * kBT>, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
-                               b.ranges, b.next, b.counters);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_batch<32 * kBT>, dim3(b.grid), dim3(kBT), 0, stream, b.jobs, b.njobs,
                                b.ranges, b.next, b.counters);
             break;
         default:

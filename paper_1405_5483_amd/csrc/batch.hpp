@@ -11,9 +11,12 @@
 
 namespace mag {
 
-constexpr int kBatchThreads = 512;               // threads per workgroup
-// Filter tiles hold 512 * words-per-lane samples, words per lane (the Shift-Or
-// run of one lane) 8, 16 (default) or 32, chosen per batch. Dense jobs run in
+constexpr int kBatchThreads = 1024;               // threads per workgroup
+// Filter tiles hold 1024 * words-per-lane samples, words per lane (the
+// Shift-Or run of one lane) 8 or 16 (default), chosen per batch: 1024-thread
+// workgroups with 64 KiB tables in LDS leave room for the entries of 16
+// words per lane, and ran the batch's filter jobs in 0.50 ms against 0.66
+// with 512 threads (one workgroup per compute unit either way). Dense jobs run in
 // a launch of their own (k_batch_dense): tiles of kBatchSliceTile start
 // positions with the slice bitmap, else kDenseScanTile with the Bloom bitmap.
 constexpr int kBatchWordsDefault = 16;
@@ -64,7 +67,7 @@ struct BatchLaunch {
     uint32_t grid;
     uint64_t total_tiles;
     uint64_t *counters;
-    uint32_t words_per_lane;   // 8, 16 or 32: filter tiles of 512 * words samples
+    uint32_t words_per_lane;   // 8 or 16: filter tiles of 1024 * words samples
 };
 
 // Workgroups of the batch kernel with `words_per_lane` that fit on one

@@ -357,7 +357,7 @@ extern "C" mag_status mag_autotune_batch(const mag_job *jobs, const uint8_t *con
         if (he != hipSuccess) st = hip_fail(he, "batch autotuner setup");
     }
     float best_t = INFINITY;
-    for (int w : {16, 8, 32}) {
+    for (int w : {16, 8}) {
         if (st != MAG_OK) break;
         st = mag_batch_set_words_per_lane(b, w);
         if (st == MAG_OK) st = mag_batch_bind(b, texts.data(), n.data(), cap, stream_);

@@ -307,9 +307,9 @@ def test_scan_batch_one_shot(torch_cuda, mag):
     assert mag.scan_batch([], []) == []
 
 
-@pytest.mark.parametrize("words", [8, 16, 32])
+@pytest.mark.parametrize("words", [8, 16])
 def test_batch_words_per_lane(torch_cuda, mag, words):
-    """Filter tiles of 512 * words samples (dense jobs keep 8192 positions):
+    """Filter tiles of 1024 * words samples (dense jobs take their own launch):
     the same lists for every tile shape, jobs of a few tiles each."""
     jobs = _small_jobs(20, seed=303, n_log2=(12.0, 19.0))
     plans = [mag.Plan(j.patterns, mode="dense" if i % 4 == 3 else "filter") for i, j in enumerate(jobs)]
@@ -328,7 +328,7 @@ def test_autotuned_batch(torch_cuda, mag):
     texts = _upload(torch_cuda, [j.text for j in jobs])
     kws, words = mag.autotune_batch([j.patterns for j in jobs], texts, sample_bytes=1 << 16,
                                     max_candidates=4, repeats=1)
-    assert words in (8, 16, 32) and len(kws) == len(jobs)
+    assert words in (8, 16) and len(kws) == len(jobs)
     assert all(kw["mode"] in ("filter", "dense") for kw in kws)
     plans = [mag.Plan(j.patterns, **kw) for j, kw in zip(jobs, kws)]
     b = mag.Batch(plans, words_per_lane=words)
