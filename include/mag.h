@@ -334,8 +334,9 @@ mag_status mag_batch_bind(mag_batch *batch, const uint8_t *const *d_texts, const
  * Shift-Or run takes words_per_lane samples (8 or 16), so filter jobs are
  * cut into tiles of 1024 * words_per_lane samples (a tile is one workgroup's
  * unit of work in the filter jobs' persistent launch); dense jobs run in a
- * launch of their own with tiles of four times the single-job dense
- * kernels' (64,512 start positions with a slice bitmap, else 65,536).
+ * launch of their own with tiles of 1 to 8 times the single-job dense
+ * kernels' (16,128 start positions with a slice bitmap, else 16,384), fewer
+ * for jobs whose positions pass the dense test more often.
  * Default 16. Takes effect at the next mag_batch_bind.
  * Errors: other values -> MAG_E_INVALID. */
 mag_status mag_batch_set_words_per_lane(mag_batch *batch, int32_t words_per_lane);

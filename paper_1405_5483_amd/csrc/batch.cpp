@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -23,6 +24,10 @@ int ceil_log2(uint64_t v) {
 // Fixed cost of a tile (barriers, setup) in text-byte equivalents, for the
 // split of the tile sequence among workgroups.
 constexpr uint64_t kTileOverheadBytes = 2048;
+// A dense start position that passes (its key emitted or its window
+// verified) costs about this many positions that fail (measured on jobs of
+// exact codes with DNA patterns, whose emission took longer than their test).
+constexpr double kDensePassCost = 32.0;
 // Jobs with texts up to this size may defer their verification; the batch's
 // deferred-start buffer holds this many entries (starts past a segment's
 // share are verified inline, so the result never depends on it).
@@ -242,6 +247,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     // dense jobs: their own tile sequence (tiles of the single-job dense kernels)
     std::vector<JobDesc> djobs;
     std::vector<uint64_t> dtiles_of, dtile_pos, dtail_pos, dstage_bytes;
+    std::vector<double> dcost;
     uint64_t dense_tiles = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
         const mag_plan *p = b->plans[j];
@@ -258,8 +264,19 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.X = X;
         J.tile_first = total_tiles;
         const bool slices = p->dense && p->slice_k > 0;
-        const uint64_t TS = slices ? (uint64_t)kBatchSliceTile * kBatchDenseChunk
-                            : p->dense ? (uint64_t)kDenseScanTile * kBatchDenseChunk
+        const bool codes = p->dense && p->code_shift >= 0;
+        // dense jobs: the expected share of start positions that pass (the
+        // codes of the distinct patterns among the 4^m, else the bitmap's
+        // estimate), and the cost of a position relative to one that fails;
+        // claimed tiles of costly positions are shorter, so that the last
+        // tiles of the launch end close together
+        const double pass = codes ? (double)p->n_unique / (double)(1ull << (2 * p->m))
+                            : slices ? p->slice_fp : p->dense ? p->bloom_fp : 0.0;
+        const double cost = 1.0 + kDensePassCost * pass;
+        const uint32_t chunk = (uint32_t)std::max(1.0, std::min((double)kBatchDenseChunk,
+                                                                std::floor(kBatchDenseChunk / cost)));
+        const uint64_t TS = slices ? (uint64_t)kBatchSliceTile * chunk
+                            : p->dense ? (uint64_t)kDenseScanTile * chunk
                                        : (uint64_t)kBatchThreads * wpl;
         J.ntiles = (X + TS - 1) / TS;
         J.mu = p->dev.mu;
@@ -275,7 +292,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         J.tlds = p->table.size() <= kBatchTableLds ? 1 : 0;
         J.table_vec = (uint32_t)((p->table.size() + 15) / 16);
         J.dense = p->dense ? 1u : 0u;
-        const bool codes = p->dense && p->code_shift >= 0;
+        J.chunk = chunk;
         if (codes) {
             // exact window codes: the code bitmap (at most 8 KiB) in LDS
             J.table = p->dev.code_bits;
@@ -322,6 +339,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
             dtile_pos.push_back(TS);
             dtail_pos.push_back(X - (J.ntiles ? (J.ntiles - 1) * TS : 0));
             dstage_bytes.push_back((uint64_t)J.table_vec * 16);
+            dcost.push_back(cost);
             dense_tiles += J.ntiles;
             J.ntiles = 0;
         }
@@ -348,9 +366,10 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     if (dgrid > dense_tiles) dgrid = dense_tiles;
     const std::vector<uint64_t> dranges = split_ranges(dgrid, dtiles_of, dense_tiles, [&](uint32_t d, uint64_t t) {
         // a dense tile reads one byte per position but hashes every one of
-        // them; a job's first tile also stages its bitmap
+        // them (more for positions that pass); a job's first tile also
+        // stages its bitmap
         const uint64_t pos = t + 1 < dtiles_of[d] ? dtile_pos[d] : dtail_pos[d];
-        return pos * 4 + kTileOverheadBytes + (t == 0 ? dstage_bytes[d] : 0);
+        return (uint64_t)((double)pos * 4 * dcost[d]) + kTileOverheadBytes + (t == 0 ? dstage_bytes[d] : 0);
     });
     // deferred starts: one buffer for the batch, its segment counters zeroed
     // here once and by the finishing kernel of every run

@@ -367,12 +367,11 @@ constexpr int kDQueue = 128;
 static_assert(kDQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");
 constexpr uint32_t kDBitsWords = 1u << (kBloomMaxLog2 - 5);
 
-// A claimed dense tile is kBatchDenseChunk consecutive sub-tiles of the
+// A claimed dense tile is the job's `chunk` consecutive sub-tiles of the
 // single-job kernels' size; a wave tests one sub-tile while the loads of the
 // next are in flight (the loads are unconditional, clamped to the last
 // sub-tile, so that the wait before a sub-tile counts the same loads on every
 // path), and the workgroup meets at a barrier once per claimed tile.
-constexpr int kDChunk = kBatchDenseChunk;
 
 // The slice sub-tiles x0 + s kBatchSliceTile, s < nsub, of one claimed tile:
 // lane L < 63 of wave w owns the 16 start positions from 16 (63 w + L) of
@@ -413,8 +412,10 @@ __device__ __forceinline__ void slice_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t 
 }
 
 // Emits the occurrences of the queued starts of a job with exact codes:
-// entry = start | code << 48, code_ids[code] the distinct pattern's index + 1.
-// All 64 lanes call it; lanes at or past `count` hold no entry.
+// entry = start | code << 48. code_ids[code] is the pattern id | kCodeDirect
+// when the code's distinct pattern has one id (one load per start), else the
+// distinct pattern's index + 1, whose ids the id runs give. All 64 lanes call
+// it; lanes at or past `count` hold no entry.
 constexpr int kCodeShift = 48;
 __device__ static __attribute__((noinline)) uint32_t drain_codes(const VerifyArgs *v, const uint64_t *queue,
                                                                 uint32_t from, uint32_t count,
@@ -427,10 +428,17 @@ __device__ static __attribute__((noinline)) uint32_t drain_codes(const VerifyArg
     const bool active = lane < count;
     const uint64_t e = active ? queue[from + lane] : 0ull;
     __builtin_amdgcn_wave_barrier();
-    const uint32_t u1 = active ? code_ids[e >> kCodeShift] : 0u;
+    const uint32_t ent = active ? code_ids[e >> kCodeShift] : 0u;
     VerifyArgs args;
     __builtin_memcpy(&args, v, sizeof(args));
-    return emit_found_buffered(args, e & ((1ull << kCodeShift) - 1), u1, fbuf, fbn, fcap);
+    const bool direct = (ent & kCodeDirect) != 0;
+    uint32_t b = ent & ~kCodeDirect, c = direct ? 1u : 0u;
+    if (!direct && ent) {
+        b = args.idstart[ent - 1];
+        c = args.idstart[ent] - b;
+    }
+    return emit_runs_buffered(args, e & ((1ull << kCodeShift) - 1), c,
+                              [&](uint32_t t) { return direct ? b : args.ids[b + t]; }, fbuf, fbn, fcap);
 }
 
 // The 16 start positions xb .. xb + 15 of one lane in a job with exact codes
@@ -462,12 +470,17 @@ __device__ __forceinline__ void code_test(const uint32_t (&W)[10], uint32_t d, i
     const uint32_t hi16 = __builtin_amdgcn_perm(q[3], q[2], 0x0C0C0400u);
     const uint32_t Slo = __builtin_amdgcn_perm(hi16, lo16, 0x05040100u);   // codes of bytes 0..15
     const uint32_t Shi = __builtin_amdgcn_perm(q[5], q[4], 0x0C0C0400u);   // bytes 16..23
+    // the 16 bitmap words are read before any is used, so that the reads
+    // overlap (one at a time, each waits out the LDS latency)
+    uint32_t code[16], word[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) code[u] = (u ? __builtin_amdgcn_alignbit(Shi, Slo, 2u * u) : Slo) & cmask;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) word[u] = s_bits[code[u] >> 5];
+    __builtin_amdgcn_sched_barrier(0);
     uint32_t hm = 0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const uint32_t code = (u ? __builtin_amdgcn_alignbit(Shi, Slo, 2u * u) : Slo) & cmask;
-        hm |= __builtin_amdgcn_ubfe(s_bits[code >> 5], code, 1u) << u;
-    }
+    for (int u = 0; u < 16; ++u) hm |= __builtin_amdgcn_ubfe(word[u], code[u], 1u) << u;
     if (__ballot(bad != 0) && bad) {
         // byte k of the lane is not a pattern byte: drop the windows holding it
         uint32_t badk = 0;
@@ -532,7 +545,7 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
     const VerifyArgs *vp = nullptr;
     const uint8_t *tbase = nullptr;
     uint64_t delta = 0, n = 0, tfirst = 0, tend = 0;
-    uint32_t m = 1, slice_k = 0, bshift = 32, hw = 1, mw = 1, lastmask = 0, tile = kDenseScanTile;
+    uint32_t m = 1, slice_k = 0, bshift = 32, hw = 1, mw = 1, lastmask = 0, tile = kDenseScanTile, chunk = 1;
     uint32_t code_shift = 0, code_rep = 0, code_mask = 0;
     const uint32_t *code_ids = nullptr;
     for (uint32_t slot = 0;; slot ^= 1) {
@@ -577,6 +590,7 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
             code_mask = uni32(J.code_mask);
             code_ids = uniptr(J.code_ids);
             tile = slice_k ? (uint32_t)kBatchSliceTile : (uint32_t)kDenseScanTile;   // one sub-tile
+            chunk = uni32(J.chunk);
             const uint32_t tvec = uni32(J.table_vec);
             const uint4 *src = reinterpret_cast<const uint4 *>(uniptr(J.table));
             const uint32_t spare = (kDBitsWords * 4u - tvec * 16u) / (8u * (kDT / 64));   // keys per wave
@@ -592,12 +606,12 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
             uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
             for (uint32_t v = tid; v < tvec; v += kDT) dst[v] = src[v];
         }
-        const int64_t X0 = (int64_t)(g - tfirst) * tile * kDChunk;
+        const int64_t X0 = (int64_t)(g - tfirst) * tile * chunk;
         const int64_t last = (int64_t)n - (int64_t)m;
         // sub-tiles holding start positions up to `last`
         const int64_t left = last - X0 + 1;
-        const int nsub = left >= (int64_t)tile * kDChunk ? kDChunk : (int)((left + tile - 1) / tile);
-        int64_t e1 = X0 + (int64_t)tile * kDChunk + 48;  // bytes the tile's windows and probes touch
+        const int nsub = left >= (int64_t)tile * chunk ? (int)chunk : (int)((left + tile - 1) / tile);
+        int64_t e1 = X0 + (int64_t)tile * chunk + 48;    // bytes the tile's windows and probes touch
         if (e1 > (int64_t)n) e1 = (int64_t)n;
         const uint64_t da0 = (delta + (uint64_t)X0) & ~15ull;
         const uint64_t da1 = (delta + (uint64_t)e1 + 15) & ~15ull;

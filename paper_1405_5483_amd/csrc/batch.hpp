@@ -28,9 +28,10 @@ constexpr uint32_t batch_entry_bytes(int TS) { return ((TS + kBatchMaxWarm) * 4 
 constexpr uint32_t kBatchTableLds = 64 * 1024;   // larger mask tables are read from L2
 constexpr int kBatchSliceLane = 16;              // start positions per lane of a slice tile
 constexpr int kBatchSliceTile = slice_scan_tile(kBatchSliceLane);
-// a dense job's claimed tile: this many sub-tiles of kBatchSliceTile or
-// kDenseScanTile start positions
-constexpr int kBatchDenseChunk = 4;
+// a dense job's claimed tile: up to this many sub-tiles of kBatchSliceTile
+// or kDenseScanTile start positions (JobDesc::chunk: fewer for jobs whose
+// positions pass often, whose sub-tiles take longer)
+constexpr int kBatchDenseChunk = 8;
 // alphabet map, two claimed-tile slots, queues, entries, table
 constexpr uint32_t batch_lds_bytes(int TS) {
     return 256 + 16 + (kBatchThreads / 64) * kBatchQueue * 8 + batch_entry_bytes(TS) + kBatchTableLds;
@@ -51,6 +52,7 @@ struct JobDesc {
     uint32_t dense;            // test every start position; `table` is then the job's bitmap
     uint32_t bshift;           // 32 - log2(bitmap bits) of a dense job
     uint32_t slice_k;          // dense job: slices per pattern of its slice bitmap (0: Bloom bitmap)
+    uint32_t chunk;            // dense job: sub-tiles per claimed tile (1 .. kBatchDenseChunk)
     // dense job with exact window codes (code_mask != 0; `table` is then the
     // code bitmap): the field shift, the bytes of the four codes and the
     // code of each distinct pattern's index + 1

@@ -153,8 +153,8 @@ __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
     };
     auto run = [&](uint64_t tile, const uint32_t (&W)[kLW]) {
         const int64_t xb = (int64_t)tile * kTile + lane_off;
-        slice_test<K, P, AL>(W, d, xb, a.last - xb + 1, s_bits, a.bshift, queue, qn, vargs, lane, nhit, fbuf,
-                             fbn);
+        slice_test<K, P, AL, true>(W, d, xb, a.last - xb + 1, s_bits, a.bshift, queue, qn, vargs, lane, nhit,
+                                   fbuf, fbn);
     };
     const uint64_t G = gridDim.x;
     uint64_t tile = blockIdx.x;

@@ -86,6 +86,7 @@ struct FoundBuf {
 __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
                                            uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit,
                                            FoundBuf fb);
+template <bool INL = false>
 __device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
                                                   int lane, uint64_t *fbuf, uint32_t fbn,
                                                   uint32_t cap = kFoundBuf);
@@ -109,6 +110,9 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
     uint32_t hm = 0;                            // bit 4i+s: position xb+4i+s passed the bitmap
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        // the probes of 4 positions: all bitmap words are read before any is
+        // used, so that the LDS reads overlap
+        uint32_t p[4][kBloomBits], word[4][kBloomBits];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             uint32_t w[4];
@@ -126,12 +130,18 @@ __device__ __forceinline__ void dense_test(const uint32_t (&W)[10], uint32_t d, 
                 }
                 h = prefilter_hash(w, (int)hw);
             }
+#pragma unroll
+            for (int j = 0; j < kBloomBits; ++j) p[s][j] = bloom_probe(h, j);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int j = 0; j < kBloomBits; ++j) word[s][j] = s_bloom[p[s][j] >> (bshift + 5)];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
             uint32_t b = 1u;
 #pragma unroll
-            for (int j = 0; j < kBloomBits; ++j) {
-                const uint32_t p = bloom_probe(h, j);
-                b &= s_bloom[p >> (bshift + 5)] >> (p & 31u);
-            }
+            for (int j = 0; j < kBloomBits; ++j) b &= word[s][j] >> (p[s][j] & 31u);
             hm |= (b & 1u) << (4 * i + s);
         }
     }
@@ -231,7 +241,9 @@ __device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[SliceLane<P
     return hm;
 }
 
-// drain64 / drain_partial with the wave's found-key buffer.
+// drain64 / drain_partial with the wave's found-key buffer (INL: the
+// verification inlined, see verify_found_inline).
+template <bool INL>
 __device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
                                                   int lane, uint64_t *fbuf, uint32_t fbn, uint32_t cap) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -239,7 +251,8 @@ __device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uin
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const uint64_t e = queue[from + lane];
     __builtin_amdgcn_wave_barrier();
-    return verify_one_buffered(v, e, true, fbuf, fbn, cap);
+    if constexpr (INL) return verify_found_inline(v, e, true, fbuf, fbn, cap);
+    else return verify_one_buffered(v, e, true, fbuf, fbn, cap);
 }
 
 __device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, const uint64_t *queue,
@@ -257,8 +270,9 @@ __device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, con
 // One lane-run of the one-probe dense mode: probes, the K-slice test, and the
 // queueing of the passing positions (room: starts left from xb, <= 0 when
 // none), one per lane and round with a ballot; found keys collect in the
-// wave's buffer fbuf (fbn keys). Every lane of the wave calls it.
-template <int K, int P, bool AL>
+// wave's buffer fbuf (fbn keys). Every lane of the wave calls it. INL:
+// verification inlined (drain64_found).
+template <int K, int P, bool AL, bool INL = false>
 __device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::load_words(AL)], uint32_t d,
                                            int64_t xb, int64_t room, const uint32_t *s_bits,
                                            uint32_t bshift, uint64_t *queue, uint32_t &qn,
@@ -296,7 +310,7 @@ __device__ __forceinline__ void slice_test(const uint32_t (&W)[SliceLane<P>::loa
         qn += (uint32_t)__popcll(bal);
         if (qn >= 64) {
             qn -= 64;
-            fbn = drain64_found(vp, queue, qn, lane, fbuf, fbn, fbcap);
+            fbn = drain64_found<INL>(vp, queue, qn, lane, fbuf, fbn, fbcap);
         }
     }
 }

@@ -18,6 +18,7 @@ constexpr int kMaxM = 64;           // longest pattern the library verifies
 constexpr int kMaxQ = 8;            // longest q-gram
 constexpr int kMaxW = 64;           // automaton bits
 constexpr int kMaxK = 32;           // candidate mask of one window fits 32 bits
+constexpr uint32_t kCodeDirect = 1u << 31;   // code_ids entry holding a pattern id (ids < 2^31)
 constexpr uint64_t kMaxTableBytes = 1ull << 30;
 constexpr int kDefaultTableBudget = 96 * 1024;
 // alphabet mapping on q-grams: sigma' = 2^b codes with b <= 28; the heuristic
@@ -237,10 +238,10 @@ struct mag_plan {
     // bytes are at most four and a 2-bit field (b >> code_shift) & 3 tells
     // them apart, and 2m <= 16, a window's code (field t at bits 2t) is exact
     // for windows of pattern bytes; code_bits has bit c set when code c is a
-    // distinct pattern's, code_ids[c] is that pattern's index + 1, and
-    // code_rep holds the byte of each code (another code's byte for unused
-    // ones), so that a window byte b is a pattern byte iff
-    // rep[(b >> code_shift) & 3] == b.
+    // distinct pattern's, code_ids[c] is that pattern's id | kCodeDirect when
+    // it has one id, else its index + 1, and code_rep holds the byte of each
+    // code (another code's byte for unused ones), so that a window byte b is
+    // a pattern byte iff rep[(b >> code_shift) & 3] == b.
     int code_shift = -1;             // -1: no exact codes
     uint32_t code_rep = 0;
     std::vector<uint32_t> code_bits, code_ids;

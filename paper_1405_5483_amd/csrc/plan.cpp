@@ -328,7 +328,8 @@ void build_codes(mag_plan *p) {
         uint32_t code = 0;
         for (uint32_t t = 0; t < p->m; ++t) code |= (uint32_t)((w[t] >> p->code_shift) & 3) << (2 * t);
         p->code_bits[code >> 5] |= 1u << (code & 31);
-        p->code_ids[code] = u + 1;
+        const bool one = p->idstart[u + 1] - p->idstart[u] == 1;
+        p->code_ids[code] = one ? (p->ids[p->idstart[u]] | kCodeDirect) : u + 1;
     }
 }
 

@@ -173,9 +173,11 @@ __device__ static __attribute__((noinline)) void verify_one(const VerifyArgs *v,
 // verify_one with the keys of inline verification collected in the wave's
 // LDS buffer fbuf (holding fbn keys; see emit_found_buffered); returns the
 // new count. Deferred and unequal-length scans take verify_one's path.
-__device__ static __attribute__((noinline)) uint32_t verify_one_buffered(const VerifyArgs *v, uint64_t i0,
-                                                                         bool active, uint64_t *fbuf,
-                                                                         uint32_t fbn, uint32_t cap) {
+// verify_found_inline is the body, for kernels with registers to spare: a
+// call makes the callee wait for every load the caller has in flight (its
+// prefetched text among them), the inlined body only for its own.
+__device__ __forceinline__ uint32_t verify_found_inline(const VerifyArgs *v, uint64_t i0, bool active,
+                                                        uint64_t *fbuf, uint32_t fbn, uint32_t cap) {
     VerifyArgs args;
     __builtin_memcpy(&args, v, sizeof(args));
     if (args.pending || args.var) {
@@ -183,6 +185,11 @@ __device__ static __attribute__((noinline)) uint32_t verify_one_buffered(const V
         return fbn;
     }
     return emit_found_buffered(args, i0, active ? find_pattern(args, i0) : 0u, fbuf, fbn, cap);
+}
+__device__ static __attribute__((noinline)) uint32_t verify_one_buffered(const VerifyArgs *v, uint64_t i0,
+                                                                         bool active, uint64_t *fbuf,
+                                                                         uint32_t fbn, uint32_t cap) {
+    return verify_found_inline(v, i0, active, fbuf, fbn, cap);
 }
 
 __device__ static __attribute__((noinline)) void flush_found_args(const VerifyArgs *v, const uint64_t *fbuf,

@@ -318,24 +318,28 @@ __device__ inline void flush_found(const VerifyArgs &a, const uint64_t *buf, uin
     __builtin_amdgcn_wave_barrier();
 }
 
-// emit_found into buf (holding fbn of at most cap keys); returns the new
-// count. Keys that do not fit flush the buffer first; a round with more keys
-// than the buffer holds goes to the output directly.
-__device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0, uint32_t u1, uint64_t *buf,
-                                               uint32_t fbn, uint32_t cap = kFoundBuf) {
-    uint32_t b = 0, c = 0;
-    if (u1) {
-        b = a.idstart[u1 - 1];
-        c = a.idstart[u1] - b;
-    }
+// Buffered emission of id runs: each lane emits c keys, emit | id_at(t) for
+// t < c, into buf (holding fbn of at most cap keys); returns the new count.
+// Keys that do not fit flush the buffer first; a round with more keys than
+// the buffer holds goes to the output directly, with one atomic add.
+template <typename IdAt>
+__device__ inline uint32_t emit_runs_buffered(const VerifyArgs &a, uint64_t i0, uint32_t c, IdAt id_at,
+                                              uint64_t *buf, uint32_t fbn, uint32_t cap) {
     const uint32_t lane = __lane_id();
-    uint32_t inc = c;                         // inclusive prefix of c over the wave
+    uint32_t inc, total;                      // inclusive prefix of c over the wave, its sum
+    const uint64_t one = __ballot(c != 0);
+    if (__ballot(c > 1) == 0) {               // at most one key per lane: ballots only
+        inc = lanes_below(one) + c;
+        total = (uint32_t)__popcll(one);
+    } else {
+        inc = c;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(inc, off);
-        if (lane >= (uint32_t)off) inc += o;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane >= (uint32_t)off) inc += o;
+        }
+        total = __builtin_amdgcn_readlane(inc, 63);
     }
-    const uint32_t total = __shfl(inc, 63);
     if (total == 0) return fbn;
     if (fbn + total > cap) {
         flush_found(a, buf, fbn);
@@ -343,12 +347,29 @@ __device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0,
     }
     const uint64_t emit = a.key_or | (i0 << a.idbits);
     if (total > cap) {
-        emit_found(a, i0, u1);
+        unsigned long long base = 0;
+        if (lane == 63) base = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)total);
+        base = __shfl(base, 63);
+        const uint64_t at = base + inc - c;
+        for (uint32_t t = 0; t < c; ++t)
+            if (at + t < a.cap) a.keys[at + t] = emit | (uint64_t)id_at(t);
         return 0;
     }
     const uint32_t at = fbn + inc - c;
-    for (uint32_t t = 0; t < c; ++t) buf[at + t] = emit | (uint64_t)a.ids[b + t];
+    for (uint32_t t = 0; t < c; ++t) buf[at + t] = emit | (uint64_t)id_at(t);
     return fbn + total;
+}
+
+// emit_found into buf: every id of distinct pattern u1 - 1 (none for u1 = 0)
+// at start i0 (see emit_runs_buffered).
+__device__ inline uint32_t emit_found_buffered(const VerifyArgs &a, uint64_t i0, uint32_t u1, uint64_t *buf,
+                                               uint32_t fbn, uint32_t cap = kFoundBuf) {
+    uint32_t b = 0, c = 0;
+    if (u1) {
+        b = a.idstart[u1 - 1];
+        c = a.idstart[u1] - b;
+    }
+    return emit_runs_buffered(a, i0, c, [&](uint32_t t) { return a.ids[b + t]; }, buf, fbn, cap);
 }
 
 }  // namespace mag
