@@ -164,9 +164,12 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
     uint4 *s_E = reinterpret_cast<uint4 *>(smem + 256 + 16 + kWaves * kBatchQueue * 8);
     uint8_t *s_tab = smem + 256 + 16 + kWaves * kBatchQueue * 8 + batch_entry_bytes(TS);
 
+    __shared__ uint64_t s_found[kWaves * kFoundBuf];      // the waves' found-key buffers
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *queue = s_queue + wave * kBatchQueue;
-    uint32_t qn = 0;
+    uint64_t *fbuf = s_found + wave * kFoundBuf;
+    uint32_t qn = 0, fbn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t me = blockIdx.x, G = gridDim.x;
     const uint64_t own_end = uni64(ranges[3 * me + 1]);
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
             pending = atomicAdd((unsigned long long *)&next[me], 1ull);
         if (cur < 0 || g < tfirst || g >= tend) {
             if (cur >= 0 && qn) {
-                drain_partial(vp, queue, qn, lane);   // starts of the previous job
+                fbn = drain_partial_found(vp, queue, qn, lane, fbuf, fbn);   // starts of the previous job
                 qn = 0;
             }
             // the job holding tile g: the last one whose first tile is <= g
@@ -334,18 +337,18 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
                         qn += (uint32_t)__popcll(bal);
                         if (qn >= 64) {
                             qn -= 64;
-                            drain64(vp, queue, qn, lane);
+                            fbn = drain64_found(vp, queue, qn, lane, fbuf, fbn);
                         }
                     }
                 }
             }
         }
     }
-    if (cur >= 0 && qn) drain_partial(vp, queue, qn, lane);
-    if (lane == 0 && ncand) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)ncand);
+    if (cur >= 0 && qn) fbn = drain_partial_found(vp, queue, qn, lane, fbuf, fbn);
     unsigned long long nv = nver;
     for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
-    if (lane == 0 && nv) atomicAdd((unsigned long long *)&counters[2], nv);
+    __shared__ uint64_t s_wg[3 * (kBT / 64)];
+    workgroup_out<kBT / 64>(vp, fbuf, fbn, ncand, nv, counters, s_wg);
 }
 
 // ---- dense jobs ----
@@ -669,13 +672,10 @@ __global__ __launch_bounds__(kDT, 4) void k_batch_dense(const JobDesc *__restric
         if (code_mask) fbn = drain_codes(vp, queue, 0, qn, code_ids, fbuf, fbn, fcap);
         else fbn = drain_partial_found(vp, queue, qn, lane, fbuf, fbn, fcap);
     }
-    if (fbn) flush_found_args(vp, fbuf, fbn);
     unsigned long long nh = nbloom + nslice;
     for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
-    if (lane == 0 && nh) {
-        atomicAdd((unsigned long long *)&counters[1], nh);
-        atomicAdd((unsigned long long *)&counters[2], nh);
-    }
+    __shared__ uint64_t s_wg[3 * (kDT / 64)];
+    workgroup_out<kDT / 64>(vp, fbuf, fbn, nh, nh, counters, s_wg);
 }
 
 // Claim counters back to the first tile of each workgroup's range.

@@ -20,11 +20,12 @@ constexpr uint32_t kBloomWordsMax = 1u << (kBloomMaxLog2 - 5);
 
 // At least 4 waves per SIMD: at most 128 VGPRs, so one workgroup of 16
 // waves fills a compute unit. The bitmap and the queues are static LDS
-// (144 KiB, the bitmap at address 0): a Bloom word's address is then its
-// index times 4, with no base to add per probe.
+// (148 KiB with the found-key buffers, the bitmap at address 0): a Bloom
+// word's address is then its index times 4, with no base to add per probe.
 __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     __shared__ __align__(16) uint32_t s_bloom[kBloomWordsMax];
     __shared__ uint64_t s_queue[(kNT / 64) * kQueue];
+    __shared__ uint64_t s_found[(kNT / 64) * kFoundBuf];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the kernel's only argument is `a`, at the start of the argument segment
     const VerifyArgs *vargs = (const VerifyArgs *)((const __attribute__((address_space(4))) char *)
@@ -37,7 +38,8 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
     }
     __syncthreads();
     uint64_t *queue = s_queue + wave * kQueue;
-    uint32_t qn = 0;
+    uint64_t *fbuf = s_found + wave * kFoundBuf;
+    uint32_t qn = 0, fbn = 0;
     uint64_t nhit = 0;
     const uint32_t hw = a.v.hw, mw = a.v.mw, lastmask = a.v.lastmask;
     // a tile's resource, size and the offset of its first position
@@ -72,18 +74,16 @@ __global__ __launch_bounds__(kNT, 4) void k_dense(DenseArgs a) {
         }
         const int64_t x0 = (int64_t)tile * kDenseScanTile;
         dense_test_any(W, p0 & 3u, x0 + 16 * (int64_t)tid, a.last, s_bloom, a.bshift, hw, mw, lastmask,
-                       queue, qn, vargs, lane, nhit);
+                       queue, qn, vargs, lane, nhit, FoundBuf{fbuf, &fbn, kFoundBuf});
 #pragma unroll
         for (int t = 0; t < 10; ++t) W[t] = Wn[t];
         p0 = p0n;
     }
-    if (qn) drain_partial(vargs, queue, qn, lane);
+    if (qn) fbn = drain_partial_found(vargs, queue, qn, lane, fbuf, fbn);
     unsigned long long nh = nhit;
     for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
-    if (lane == 0 && nh) {
-        atomicAdd((unsigned long long *)&a.counters[1], nh);
-        atomicAdd((unsigned long long *)&a.counters[2], nh);
-    }
+    __shared__ uint64_t s_wg[3 * (kNT / 64)];
+    workgroup_out<kNT / 64>(vargs, fbuf, fbn, nh, nh, a.counters, s_wg);
 }
 
 // The one-probe dense scan (slice_test): the same grid and bitmap staging as
@@ -195,13 +195,10 @@ __global__ __launch_bounds__(kNT, 4) void k_dense_slices(DenseArgs a) {
         run(tile, W);
     }
     if (qn) fbn = drain_partial_found(vargs, queue, qn, lane, fbuf, fbn);
-    if (fbn) flush_found_args(vargs, fbuf, fbn);
     unsigned long long nh = nhit;
     for (int off = 32; off > 0; off >>= 1) nh += __shfl_xor(nh, off);
-    if (lane == 0 && nh) {
-        atomicAdd((unsigned long long *)&a.counters[1], nh);
-        atomicAdd((unsigned long long *)&a.counters[2], nh);
-    }
+    __shared__ uint64_t s_wg[3 * (kNT / 64)];
+    workgroup_out<kNT / 64>(vargs, fbuf, fbn, nh, nh, a.counters, s_wg);
 }
 
 int compute_units(int &ncu) {

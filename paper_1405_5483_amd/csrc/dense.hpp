@@ -86,10 +86,6 @@ struct FoundBuf {
 __device__ __forceinline__ void queue_hits(uint32_t hm, int64_t xb, int64_t last, uint64_t *queue,
                                            uint32_t &qn, const VerifyArgs *vp, int lane, uint64_t &nhit,
                                            FoundBuf fb);
-template <bool INL = false>
-__device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
-                                                  int lane, uint64_t *fbuf, uint32_t fbn,
-                                                  uint32_t cap = kFoundBuf);
 
 // Tests the 16 windows of thread tid (positions xb .. xb + 15, xb = x0 +
 // 16*tid; d = p0 & 3) whose bytes are in W, and queues those that pass.
@@ -239,32 +235,6 @@ __device__ __forceinline__ uint32_t slice_probes(const uint32_t (&V)[SliceLane<P
         hm |= __builtin_amdgcn_ubfe(w, h >> bshift, 1u) << u;
     }
     return hm;
-}
-
-// drain64 / drain_partial with the wave's found-key buffer (INL: the
-// verification inlined, see verify_found_inline).
-template <bool INL>
-__device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
-                                                  int lane, uint64_t *fbuf, uint32_t fbn, uint32_t cap) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint64_t e = queue[from + lane];
-    __builtin_amdgcn_wave_barrier();
-    if constexpr (INL) return verify_found_inline(v, e, true, fbuf, fbn, cap);
-    else return verify_one_buffered(v, e, true, fbuf, fbn, cap);
-}
-
-__device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, const uint64_t *queue,
-                                                        uint32_t qn, int lane, uint64_t *fbuf, uint32_t fbn,
-                                                        uint32_t cap = kFoundBuf) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const bool active = (uint32_t)lane < qn;
-    const uint64_t e = active ? queue[lane] : 0ull;
-    __builtin_amdgcn_wave_barrier();
-    return verify_one_buffered(v, e, active, fbuf, fbn, cap);
 }
 
 // One lane-run of the one-probe dense mode: probes, the K-slice test, and the

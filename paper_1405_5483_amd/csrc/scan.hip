@@ -217,6 +217,10 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     ET *s_E1 = reinterpret_cast<ET *>(smem + 256 + kConsumerWaves * kQueue * 8 + a.e_lds);
     ET *s_tab = reinterpret_cast<ET *>(smem + 256 + kConsumerWaves * kQueue * 8 + 2 * a.e_lds);
 
+    // the consumer waves' found-key buffers
+    __shared__ uint64_t s_found[kConsumerWaves * kFoundBuf];
+    static_assert(sizeof(s_found) <= kScanStaticLds, "static LDS beside the dynamic part");
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool producer = wave < kProducerWaves;
     // the kernel's only argument is `a`, at the start of the argument segment
@@ -236,7 +240,8 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
     // consumer state
     const int ct = tid - kProducerThreads;                // consumer lane index
     uint64_t *queue = s_queue + (producer ? 0 : (wave - kProducerWaves)) * kQueue;
-    uint32_t qn = 0;
+    uint64_t *fbuf = s_found + (producer ? 0 : (wave - kProducerWaves)) * kFoundBuf;
+    uint32_t qn = 0, fbn = 0;
     uint64_t ncand = 0, nver = 0;
     const uint32_t kmask = a.k >= 32 ? 0xFFFFFFFFu : ((1u << a.k) - 1u);
     const uint32_t topshift = a.W - a.k;
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
                             qn += (uint32_t)__popcll(bal);
                             if (qn >= 64) {
                                 qn -= 64;
-                                drain64(vargs, queue, qn, lane);
+                                fbn = drain64_found(vargs, queue, qn, lane, fbuf, fbn);
                             }
                         }
                     }
@@ -363,15 +368,16 @@ __global__ __launch_bounds__(kNT) void k_scan(ScanArgs a) {
         }
         __syncthreads();
     }
+    unsigned long long nv = 0;
     if (!producer) {
         // starts still queued
-        if (qn) drain_partial(vargs, queue, qn, lane);
-        if (lane == 0 && ncand)
-            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)ncand);
-        unsigned long long nv = nver;
+        if (qn) fbn = drain_partial_found(vargs, queue, qn, lane, fbuf, fbn);
+        nv = nver;
         for (int off = 32; off > 0; off >>= 1) nv += __shfl_xor(nv, off);
-        if (lane == 0 && nv) atomicAdd((unsigned long long *)&a.counters[2], nv);
     }
+    // the entry buffers (at least 4 KiB) are free after the last round's barrier
+    workgroup_out<kNT / 64>(vargs, fbuf, producer ? 0u : fbn, producer ? 0ull : ncand, nv, a.counters,
+                            reinterpret_cast<uint64_t *>(s_E0));
 }
 
 template <typename ET, typename DT, bool TLDS, int CODE, int PB = 0>

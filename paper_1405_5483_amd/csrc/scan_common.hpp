@@ -199,6 +199,63 @@ __device__ static __attribute__((noinline)) void flush_found_args(const VerifyAr
     flush_found(args, fbuf, fbn);
 }
 
+// The end of a persistent kernel: the found keys left in the waves' LDS
+// buffers (fbn in each wave's fbuf; none without buffers) go to the output,
+// and the waves' statistics c1, c2 (wave totals) to counters[1] and
+// counters[2], with one atomic add per counter for the whole workgroup.
+// Atomic adds to one address are serialized across the device, and
+// thousands of waves adding at their ends kept the kernels running for tens
+// of microseconds after their last tile. v may be null where no wave of the
+// workgroup holds a key. Every thread of the workgroup calls it; s_wg holds
+// 3 * WAVES words of LDS. Out of line, so that the scan loops' registers do
+// not pay for it.
+template <int WAVES>
+__device__ __attribute__((noinline)) void workgroup_out(const VerifyArgs *v, const uint64_t *fbuf,
+                                                        uint32_t fbn, uint64_t c1, uint64_t c2,
+                                                        uint64_t *counters, uint64_t *s_wg) {
+    static_assert(WAVES <= 64, "one lane per wave");
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_wg[wave] = fbn;
+        s_wg[WAVES + wave] = c1;
+        s_wg[2 * WAVES + wave] = c2;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const bool in = lane < (uint32_t)WAVES;
+        const uint64_t n = in ? s_wg[lane] : 0ull;
+        uint64_t t1 = in ? s_wg[WAVES + lane] : 0ull, t2 = in ? s_wg[2 * WAVES + lane] : 0ull;
+        uint64_t inc = n;                     // inclusive prefix of the waves' key counts
+#pragma unroll
+        for (int off = 1; off < WAVES; off <<= 1) {
+            const uint64_t o = __shfl_up(inc, off);
+            if (lane >= (uint32_t)off) inc += o;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            t1 += __shfl_xor(t1, off);
+            t2 += __shfl_xor(t2, off);
+        }
+        const uint64_t total = __shfl(inc, WAVES - 1);
+        unsigned long long base = 0;
+        if (lane == 0) {
+            if (total) base = atomicAdd((unsigned long long *)&v->counters[0], (unsigned long long)total);
+            if (t1) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)t1);
+            if (t2) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)t2);
+        }
+        base = __shfl(base, 0);
+        if (in) s_wg[lane] = base + inc - n;  // the wave's first output slot
+    }
+    __syncthreads();
+    if (fbn) {
+        const uint64_t at = s_wg[wave];
+        uint64_t *keys = v->keys;
+        const uint64_t cap = v->cap;
+        for (uint32_t i = lane; i < fbn; i += 64)
+            if (at + i < cap) keys[at + i] = fbuf[i];
+    }
+}
+
 // Verifies the 64 start positions queue[from .. from+64) of this wave, one per
 // lane. The queue is written by other lanes of the same wave.
 __device__ __forceinline__ void drain64(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
@@ -209,6 +266,33 @@ __device__ __forceinline__ void drain64(const VerifyArgs *v, const uint64_t *que
     const uint64_t e = queue[from + lane];
     __builtin_amdgcn_wave_barrier();
     verify_one(v, e, true);
+}
+
+// drain64 / drain_partial with the wave's found-key buffer (INL: the
+// verification inlined, see verify_found_inline).
+template <bool INL = false>
+__device__ __forceinline__ uint32_t drain64_found(const VerifyArgs *v, const uint64_t *queue, uint32_t from,
+                                                  int lane, uint64_t *fbuf, uint32_t fbn,
+                                                  uint32_t cap = kFoundBuf) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint64_t e = queue[from + lane];
+    __builtin_amdgcn_wave_barrier();
+    if constexpr (INL) return verify_found_inline(v, e, true, fbuf, fbn, cap);
+    else return verify_one_buffered(v, e, true, fbuf, fbn, cap);
+}
+
+__device__ __forceinline__ uint32_t drain_partial_found(const VerifyArgs *v, const uint64_t *queue,
+                                                        uint32_t qn, int lane, uint64_t *fbuf, uint32_t fbn,
+                                                        uint32_t cap = kFoundBuf) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const bool active = (uint32_t)lane < qn;
+    const uint64_t e = active ? queue[lane] : 0ull;
+    __builtin_amdgcn_wave_barrier();
+    return verify_one_buffered(v, e, active, fbuf, fbn, cap);
 }
 
 // Verifies the first qn queued starts of this wave (qn < 64).

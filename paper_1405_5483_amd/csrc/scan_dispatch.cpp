@@ -158,7 +158,7 @@ mag_status launch_scan(const mag_plan *p, const ScanLaunch &s, hipStream_t strea
         S = p->words_per_lane > 0 ? (uint32_t)p->words_per_lane
                                   : (uint32_t)((uint64_t)p->chunk_bytes / ((uint64_t)kScanConsumerLanes * a.kq));
         const uint64_t tab = p->table.size() <= kTableLdsMax ? p->table.size() : 0;
-        const uint64_t room = (kScanLdsMax - 256 - (kScanConsumerLanes / 64) * 128 * 8 - tab) / 2;
+        const uint64_t room = (kScanLdsMax - kScanStaticLds - 256 - (kScanConsumerLanes / 64) * 128 * 8 - tab) / 2;
         const uint64_t cap = (room - 128 * esz) / esz / kScanConsumerLanes;   // w0 + 16 <= 80 entries
         if (S > cap) S = (uint32_t)cap;
         S = S / epv * epv;
