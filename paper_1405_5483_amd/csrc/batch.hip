@@ -780,16 +780,23 @@ mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint
 namespace {
 
 constexpr int kBatchVerifyThreads = 256;
+constexpr uint32_t kVerifyFound = 256;   // found keys buffered per wave
 
 // The deferred starts of batched jobs (entry = job << kBatchJobShift |
 // start), spread over the buffer's segments like the single-job
 // verification kernel. Each lane reads its own job's verification
 // arguments; all jobs share the batch's counters, key buffer and capacity,
-// so the wave's collective output reservation still applies.
+// so the wave's collective output reservation still applies. Found keys
+// collect in a per-wave LDS buffer (rounds with a lane of an unequal-length
+// job emit directly).
 __global__ __launch_bounds__(kBatchVerifyThreads) void k_batch_verify(const JobDesc *jobs,
                                                                       const uint64_t *pending,
                                                                       const uint64_t *seg_count,
                                                                       uint64_t seg_cap) {
+    __shared__ uint64_t s_found[(kBatchVerifyThreads / 64) * kVerifyFound];
+    __shared__ uint64_t s_wg[3 * (kBatchVerifyThreads / 64)];
+    uint64_t *fbuf = s_found + (threadIdx.x >> 6) * kVerifyFound;
+    uint32_t fbn = 0;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * kBatchVerifyThreads + threadIdx.x) >> 6;
     const uint64_t waves = ((uint64_t)gridDim.x * kBatchVerifyThreads) >> 6;
@@ -807,9 +814,14 @@ __global__ __launch_bounds__(kBatchVerifyThreads) void k_batch_verify(const JobD
             const uint64_t e = active ? src[i] : 0ull;
             VerifyArgs v;
             __builtin_memcpy(&v, &jobs[(uint32_t)(e >> kBatchJobShift)].v, sizeof(v));
-            verify_wave(v, e & posmask, active);
+            const uint64_t i0 = e & posmask;
+            if (__ballot(active && v.var) == 0)
+                fbn = emit_found_buffered(v, i0, active ? find_pattern(v, i0) : 0u, fbuf, fbn, kVerifyFound);
+            else
+                verify_wave(v, i0, active);
         }
     }
+    workgroup_out<kBatchVerifyThreads / 64>(&jobs[0].v, fbuf, fbn, 0, 0, nullptr, s_wg);
 }
 
 }  // namespace

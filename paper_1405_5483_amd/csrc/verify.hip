@@ -7,18 +7,25 @@
 #include <hip/hip_runtime.h>
 
 #include "mag_internal.hpp"
+#include "scan_common.hpp"
 #include "verify.hpp"
 
 namespace mag {
 namespace {
 
 constexpr int kVerifyThreads = 256;
+constexpr uint32_t kVerifyFound = 256;   // found keys buffered per wave
 
 // The waves are spread evenly over the buffer's segments; each takes 64
 // consecutive starts of its segment per step, one per lane. Loop bounds are
-// wave-uniform, so every lane reaches verify_wave's collective output
-// reservation. The finishing kernel clears the segment counters afterwards.
+// wave-uniform, so every lane reaches the collective output reservation.
+// Found keys collect in a per-wave LDS buffer (patterns of equal length).
+// The finishing kernel clears the segment counters afterwards.
 __global__ __launch_bounds__(kVerifyThreads) void k_verify(VerifyArgs a) {
+    __shared__ uint64_t s_found[(kVerifyThreads / 64) * kVerifyFound];
+    __shared__ uint64_t s_wg[3 * (kVerifyThreads / 64)];
+    uint64_t *fbuf = s_found + (threadIdx.x >> 6) * kVerifyFound;
+    uint32_t fbn = 0;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * kVerifyThreads + threadIdx.x) >> 6;
     const uint64_t waves = ((uint64_t)gridDim.x * kVerifyThreads) >> 6;
@@ -33,9 +40,13 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(VerifyArgs a) {
             const uint64_t i = c + lane;
             const bool active = i < total;
             const uint64_t i0 = active ? src[i] : 0ull;
-            verify_wave(a, i0, active);
+            if (a.var) verify_wave(a, i0, active);
+            else fbn = emit_found_buffered(a, i0, active ? find_pattern(a, i0) : 0u, fbuf, fbn, kVerifyFound);
         }
     }
+    // the kernel's only argument is `a`, at the start of the argument segment
+    const VerifyArgs *va = (const VerifyArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    dev::workgroup_out<kVerifyThreads / 64>(va, fbuf, fbn, 0, 0, nullptr, s_wg);
 }
 
 }  // namespace
