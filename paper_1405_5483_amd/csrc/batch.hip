@@ -361,10 +361,10 @@ __global__ __launch_bounds__(kBT, 4) void k_batch(const JobDesc *__restrict__ jo
 // claim them from contiguous ranges of the dense tile sequence and steal as
 // the filter launch does, and restage the bitmap when the job changes. When
 // a job's bitmap leaves at least half of its array free, the free part holds
-// the waves' found-key buffers (up to 1,024 keys each instead of 32): jobs
-// with short DNA patterns find a match at several percent of their start
-// positions, and one output reservation per 32 keys would serialize them on
-// the output counter.
+// the waves' found-key buffers (up to 1,024 keys each instead of
+// kFoundBuf): jobs with short DNA patterns find a match at several percent
+// of their start positions, and one output reservation per kFoundBuf keys
+// would serialize them on the output counter.
 constexpr int kDT = kDenseScanThreads;
 constexpr int kDQueue = 128;
 static_assert(kDQueue >= (int)kDenseQueue, "dense_test fills up to kDenseQueue starts");

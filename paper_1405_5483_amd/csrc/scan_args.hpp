@@ -19,7 +19,7 @@ constexpr int kScanThreads = MAG_SCAN_THREADS;        // threads per scan workgr
 constexpr int kScanProducerWaves = MAG_SCAN_PRODUCERS; // waves that compute mask entries
 constexpr int kScanConsumerLanes = kScanThreads - 64 * kScanProducerWaves;  // Shift-Or lanes
 constexpr uint64_t kScanLdsMax = 160 * 1024;   // LDS of one workgroup on gfx950
-constexpr uint64_t kScanStaticLds = 2048;       // the scan kernel's static LDS, at most
+constexpr uint64_t kScanStaticLds = 4096;       // the scan kernel's static LDS, at most
 
 struct ScanArgs {
     const uint8_t *tbase;      // text pointer rounded down to 16 bytes

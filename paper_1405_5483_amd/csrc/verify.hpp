@@ -294,12 +294,12 @@ __device__ inline void emit_found(const VerifyArgs &a, uint64_t i0, uint32_t u1)
     }
 }
 
-// Per-wave buffering of output keys (the one-probe dense mode, whose waves
-// find matches in most of their verification rounds): a wave collects its
+// Per-wave buffering of output keys (every scan kernel): a wave collects its
 // keys in an LDS buffer of kFoundBuf keys and writes them to the output with
-// one atomic add per buffer, instead of one contended atomic add on the
-// output counter per round. All 64 lanes call these.
-constexpr uint32_t kFoundBuf = 32;
+// one atomic add per buffer, instead of one atomic add on the output counter
+// per round that finds a match (atomic adds to one address are serialized
+// across the device). All 64 lanes call these.
+constexpr uint32_t kFoundBuf = 64;
 
 // Writes buf[0 .. n) (n wave-uniform) to the output.
 __device__ inline void flush_found(const VerifyArgs &a, const uint64_t *buf, uint32_t n) {
