@@ -15,7 +15,7 @@ as log2 nanoseconds per text byte (outputs 0..31), and the scan's
 verification count, as log2 of verifications per text byte plus 2^-24
 (outputs 32..63). Set seeds come from SeedSequence(--seed, 5 by default) and
 text seeds from SeedSequence(5) (a separate spawn). The shipped model is
-trained on 20,000 sets with r over 10..10^4 (seed 5) and 5,000 with r over
+trained on 20,000 sets with r over 10..10^4 (seed 5) and 2,500 with r over
 10^4..10^5 (seed 7), which reaches the 100,000-pattern protein workload.
 
 train: the network (16 -> 64 -> 64 -> 64) is trained on the device by the
