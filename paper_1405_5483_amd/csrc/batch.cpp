@@ -95,8 +95,10 @@ struct mag_batch {
     int device = -1;
     bool bound = false;
     uint64_t cap = 0;
-    int idbits = 1, posbits = 1, nbits = 3;
+    int idbits = 1, posbits = 1, nbits = 3;   // posbits: the batch's text bytes
     uint64_t total_tiles = 0;
+    uint64_t *d_jbase = nullptr;     // njobs + 1: each job's first byte in the batch's texts
+    size_t jbase_bytes = 0;
     uint32_t grid = 0;
     mag::JobDesc *d_jobs = nullptr;
     size_t jobs_bytes = 0;
@@ -167,6 +169,7 @@ void mag_batch_destroy(mag_batch *b) {
         (void)hipFree(b->d_djobs);
         (void)hipFree(b->d_dranges);
         (void)hipFree(b->d_dnext);
+        (void)hipFree(b->d_jbase);
         (void)hipFree(b->sc.counters);
         (void)hipFree(b->sc.keys);
         (void)hipFree(b->sc.hist);
@@ -202,15 +205,21 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     b->device = dev;
 
-    // key layout: job | position | pattern id
-    int idbits = 1, posbits = 1;
+    // key layout: (the job's first byte in the texts laid end to end +
+    // position) << idbits | pattern id, so that keys sort by job, then
+    // position, and the sort passes over the bits of the total text length
+    // only (1.1 GB: 31 bits, 4 passes; job and longest-job bits took 33)
+    int idbits = 1, posbits = 1, jposbits = 1;
+    std::vector<uint64_t> jbase(njobs + 1, 0);
     for (uint32_t j = 0; j < njobs; ++j) {
         idbits = std::max(idbits, ceil_log2(std::max<uint64_t>(b->plans[j]->r, 2)));
-        posbits = std::max(posbits, ceil_log2(std::max<uint64_t>(n[j] + 1, 2)));
+        jposbits = std::max(jposbits, ceil_log2(std::max<uint64_t>(n[j] + 1, 2)));
+        if (n[j] > ~0ull - jbase[j]) return fail(MAG_E_UNSUPPORTED, "texts longer than 2^64 bytes in all");
+        jbase[j + 1] = jbase[j] + n[j];
     }
-    const int jobbits = ceil_log2(std::max<uint32_t>(njobs, 2));
-    if (idbits + posbits + jobbits > 64)
-        return fail(MAG_E_UNSUPPORTED, "job numbers, positions and ids need more than 64 key bits");
+    posbits = std::max(posbits, ceil_log2(std::max<uint64_t>(jbase[njobs] + 1, 2)));
+    if (idbits + posbits > 64)
+        return fail(MAG_E_UNSUPPORTED, "text positions and ids need more than 64 key bits");
 
     // scratch
     Scratch &sc = b->sc;
@@ -246,6 +255,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     uint64_t total_tiles = 0;
     // dense jobs: their own tile sequence (tiles of the single-job dense kernels)
     std::vector<JobDesc> djobs;
+    std::vector<uint32_t> djob_of;   // the batch's job number of each dense job
     std::vector<uint64_t> dtiles_of, dtile_pos, dtail_pos, dstage_bytes;
     std::vector<double> dcost;
     uint64_t dense_tiles = 0;
@@ -320,14 +330,14 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
         sl.counters = sc.counters;
         sl.idbits = idbits;
         J.v = make_verify_args(p, sl);
-        J.v.key_or = (uint64_t)j << (posbits + idbits);
+        J.v.key_or = jbase[j] << idbits;
         // a short text with many patterns keeps one workgroup verifying for
         // long; its starts go to the batch verification kernel instead
         const double expect = slices ? p->slice_fp * (double)X
                               : p->dense ? p->bloom_fp * (double)X : p->est_verif * (double)n[j];
         const double vwaves = (double)std::max<uint64_t>(J.ntiles, 1) *
                               ((p->dense ? kDenseScanThreads : kBatchThreads) / 64);
-        if (X && n[j] <= kBatchDeferMaxText && posbits <= kBatchJobShift &&
+        if (X && n[j] <= kBatchDeferMaxText && jposbits <= kBatchJobShift &&
             ((double)p->r * p->m * 4 >= (double)n[j] || expect >= kDeferPerWave * vwaves))
             defer[j] = 1;
         if (p->dense) {
@@ -335,6 +345,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
             JobDesc D = J;
             D.tile_first = dense_tiles;
             djobs.push_back(D);
+            djob_of.push_back(j);
             dtiles_of.push_back(J.ntiles);
             dtile_pos.push_back(TS);
             dtail_pos.push_back(X - (J.ntiles ? (J.ntiles - 1) * TS : 0));
@@ -399,17 +410,18 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     s = grow(&b->d_next, &b->next_bytes, std::max<size_t>(grid, 1) * sizeof(uint64_t), "tile claims");
     if (s != MAG_OK) return s;
     // the dense jobs carry the deferred-start fields set above
-    for (JobDesc &D : djobs) {
-        const uint32_t j = (uint32_t)(D.v.key_or >> (posbits + idbits));
-        D.v = jobs[j].v;
-    }
+    for (size_t d = 0; d < djobs.size(); ++d) djobs[d].v = jobs[djob_of[d]].v;
     s = grow(&b->d_djobs, &b->djobs_bytes, std::max<size_t>(djobs.size(), 1) * sizeof(JobDesc), "dense job table");
     if (s != MAG_OK) return s;
     s = grow(&b->d_dranges, &b->dranges_bytes, dranges.size() * sizeof(uint64_t), "dense tile ranges");
     if (s != MAG_OK) return s;
     s = grow(&b->d_dnext, &b->dnext_bytes, std::max<size_t>(dgrid, 1) * sizeof(uint64_t), "dense tile claims");
     if (s != MAG_OK) return s;
+    s = grow(&b->d_jbase, &b->jbase_bytes, jbase.size() * sizeof(uint64_t), "job text offsets");
+    if (s != MAG_OK) return s;
     if (njobs) e = hipMemcpy(b->d_jobs, jobs.data(), njobs * sizeof(JobDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_jbase, jbase.data(), jbase.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && !djobs.empty())
@@ -423,7 +435,7 @@ mag_status mag_batch_bind(mag_batch *b, const uint8_t *const *d_texts, const uin
     b->cap = out_cap;
     b->idbits = idbits;
     b->posbits = posbits;
-    b->nbits = idbits + posbits + jobbits;
+    b->nbits = idbits + posbits;
     b->total_tiles = total_tiles;
     b->grid = (uint32_t)grid;
     b->bound_words = wpl;
@@ -485,11 +497,14 @@ mag_status mag_batch_run_async(mag_batch *b, mag_match *d_out, uint64_t *d_offse
     if (s == MAG_OK && b->cap > small_sort_max()) {
         s = launch_radix_sort(sc, b->cap, b->cap, b->nbits, lo, stream);
         if (s == MAG_OK)
-            s = launch_expand(sc, b->cap, b->cap, b->nbits, lo, d_out, b->idbits, posmask, stream);
+            s = launch_expand(sc, b->cap, b->cap, b->nbits, lo, d_out, b->idbits, posmask, stream, b->d_jbase,
+                              njobs);
     }
+    // per-job offsets of the sorted keys (and the positions of records the
+    // finishing kernel wrote made relative to their jobs' texts)
     if (s == MAG_OK)
-        s = launch_batch_offsets(sorted, sc.counters + kSortCountSlot, b->cap, d_offsets, njobs,
-                                 b->posbits + b->idbits, stream);
+        s = launch_batch_offsets(sorted, sc.counters + kSortCountSlot, b->cap, d_offsets, njobs, b->d_jbase,
+                                 b->idbits, d_out, stream);
     profile_commit(prof, stream);
     return s;
 }

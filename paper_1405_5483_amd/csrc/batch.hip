@@ -687,7 +687,7 @@ __global__ void k_batch_init(const uint64_t *ranges, uint64_t *next, uint32_t G)
 // offsets[j] = first record of job j (binary search of the sorted keys on the
 // job field), offsets[njobs] = the count. One thread per entry.
 __global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
-                                uint64_t *offsets, uint32_t njobs, int job_shift) {
+                                uint64_t *offsets, uint32_t njobs, const uint64_t *jbase, int idbits) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j > njobs) return;
     const uint64_t z = *zp;
@@ -695,15 +695,29 @@ __global__ void k_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint
     if (j == njobs) {
         at = z;
     } else if (z <= cap) {
+        const uint64_t first = jbase[j] << idbits;    // the job's smallest key
         uint64_t lo = 0, hi = z;
         while (lo < hi) {
             const uint64_t mid = lo + (hi - lo) / 2;
-            if ((sorted[mid] >> job_shift) < j) lo = mid + 1;
+            if (sorted[mid] < first) lo = mid + 1;
             else hi = mid;
         }
         at = lo;
     }
     offsets[j] = at;
+}
+
+// The records the finishing kernel wrote (outputs of at most small_max keys;
+// larger ones are made relative in k_expand): each position less its job's
+// first byte in the batch's texts (see k_expand).
+__global__ __launch_bounds__(256) void k_batch_rebase(mag_match *out, const uint64_t *zp, uint64_t cap,
+                                                      uint64_t small_max, const uint64_t *jbase,
+                                                      uint32_t njobs) {
+    const uint64_t z = *zp;
+    if (z > cap || z > small_max) return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z; i += stride)
+        out[i].pos -= jbase[job_of_position(jbase, njobs, out[i].pos)];
 }
 
 }  // namespace
@@ -767,14 +781,22 @@ mag_status launch_batch_dense(const BatchLaunch &b, hipStream_t stream) {
 }
 
 mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
-                                uint64_t *d_offsets, uint32_t njobs, int job_shift,
-                                hipStream_t stream) {
+                                uint64_t *d_offsets, uint32_t njobs, const uint64_t *jbase, int idbits,
+                                mag_match *out, hipStream_t stream) {
     const uint32_t threads = 256;
     const uint32_t blocks = (njobs + 1 + threads - 1) / threads;
     hipLaunchKernelGGL(k_batch_offsets, dim3(blocks), dim3(threads), 0, stream, sorted, zp, cap,
-                       d_offsets, njobs, job_shift);
+                       d_offsets, njobs, jbase, idbits);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch offsets launch");
+    if (e != hipSuccess) return hip_fail(e, "batch offsets launch");
+    if (!out || !cap || !njobs) return MAG_OK;
+    const uint64_t small = small_sort_max();
+    const uint64_t most = std::min<uint64_t>(cap, small);
+    const uint32_t rblocks = (uint32_t)std::min<uint64_t>((most + threads - 1) / threads, 1024);
+    hipLaunchKernelGGL(k_batch_rebase, dim3(rblocks), dim3(threads), 0, stream, out, zp, cap, small, jbase,
+                       njobs);
+    e = hipGetLastError();
+    return e == hipSuccess ? MAG_OK : hip_fail(e, "batch rebase launch");
 }
 
 namespace {

@@ -86,9 +86,12 @@ mag_status launch_batch_dense(const BatchLaunch &b, hipStream_t stream);
 constexpr int kBatchJobShift = 40;
 mag_status launch_batch_verify(const JobDesc *jobs, const uint64_t *pending, const uint64_t *seg_count,
                                uint64_t seg_cap, hipStream_t stream);
-// offsets[j] = first record of job j in the sorted keys, offsets[njobs] = count.
+// offsets[j] = first record of job j in the sorted keys (the first key at
+// or above jbase[j] << idbits), offsets[njobs] = count; for outputs the
+// finishing kernel sorted (at most small_sort_max keys), each record's
+// position less its job's jbase (out: their records).
 mag_status launch_batch_offsets(const uint64_t *sorted, const uint64_t *zp, uint64_t cap,
-                                uint64_t *d_offsets, uint32_t njobs, int job_shift,
-                                hipStream_t stream);
+                                uint64_t *d_offsets, uint32_t njobs, const uint64_t *jbase, int idbits,
+                                mag_match *out, hipStream_t stream);
 
 }  // namespace mag

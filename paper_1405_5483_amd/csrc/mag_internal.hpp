@@ -370,8 +370,22 @@ mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream)
 // keys (its scratch: 256 * chunks u32 counts, 256 * chunks + 256 u64 offsets).
 uint64_t radix_scratch_chunks(uint64_t bound);
 mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream);
+// jbase (batches; njobs + 1 offsets): positions made relative to their jobs'
+// texts (see k_expand).
 mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, mag_match *out,
-                         int idbits, uint64_t posmask, hipStream_t stream);
+                         int idbits, uint64_t posmask, hipStream_t stream, const uint64_t *jbase = nullptr,
+                         uint32_t njobs = 0);
+// The job of position p of a batch's texts laid end to end: the last j <
+// njobs with jb[j] <= p (jb: njobs + 1 ascending first bytes; njobs >= 1).
+__host__ __device__ inline uint32_t job_of_position(const uint64_t *jb, uint32_t njobs, uint64_t p) {
+    uint32_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (jb[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 // The key buffer that holds the sorted keys after the radix passes.
 uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits, int lo);
 // Lowest key bit the radix passes sort on. With equal-length patterns every

@@ -406,13 +406,29 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
     }
 }
 
-__global__ void k_expand(const uint64_t *keys, const uint64_t *zp, uint64_t cap, mag_match *out,
-                         int idbits, uint64_t posmask) {
+// Records of the sorted keys. Batches (jbase not null) key positions in their
+// texts laid end to end: a record's position is made relative to its job's
+// text, jbase[j] (njobs + 1 ascending offsets) being job j's first byte, the
+// job the last j with jbase[j] <= the position (empty jobs share their offset
+// with the next). The offsets are staged in LDS when they fit.
+constexpr uint32_t kExpandJobsLds = 2048;
+__global__ __launch_bounds__(256) void k_expand(const uint64_t *keys, const uint64_t *zp, uint64_t cap,
+                                                mag_match *out, int idbits, uint64_t posmask,
+                                                const uint64_t *jbase, uint32_t njobs) {
+    __shared__ uint64_t s_jb[kExpandJobsLds];
     uint64_t z;
     if (!radix_active(zp, cap, &z)) return;
+    const bool staged = jbase && njobs <= kExpandJobsLds;
+    if (staged)
+        for (uint32_t t = threadIdx.x; t < njobs; t += blockDim.x) s_jb[t] = jbase[t];
+    __syncthreads();
+    const uint64_t *jb = staged ? s_jb : jbase;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z; i += stride)
-        out[i] = to_record(keys[i], idbits, posmask);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z; i += stride) {
+        mag_match r = to_record(keys[i], idbits, posmask);
+        if (jb) r.pos -= jb[job_of_position(jb, njobs, r.pos)];
+        out[i] = r;
+    }
 }
 
 // Chunks of the largest count a sort of at most `bound` keys can take.
@@ -517,14 +533,16 @@ uint64_t *sorted_keys(Scratch &sc, uint64_t cap, int nbits, int lo) {
 }
 
 mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, mag_match *out,
-                         int idbits, uint64_t posmask, hipStream_t stream) {
+                         int idbits, uint64_t posmask, hipStream_t stream, const uint64_t *jbase,
+                         uint32_t njobs) {
     if (bound <= kSmallMax) return MAG_OK;
     if (bound > cap) bound = cap;
     uint64_t blocks = (bound + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_expand, dim3((uint32_t)blocks), dim3(256), 0, stream,
                        (const uint64_t *)sorted_keys(sc, cap, nbits, lo),
-                       (const uint64_t *)(sc.counters + kSortCountSlot), cap, out, idbits, posmask);
+                       (const uint64_t *)(sc.counters + kSortCountSlot), cap, out, idbits, posmask, jbase,
+                       njobs);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MAG_OK : hip_fail(e, "expand launch");
 }

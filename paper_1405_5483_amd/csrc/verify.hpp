@@ -19,9 +19,9 @@ struct VerifyArgs {
     uint32_t slot_shift, slot_mask, idbits, pad_;
     const uint64_t *slots;     // (hash << 32) | (u + 1), 0 = empty
     const uint32_t *pwords, *idstart, *ids;
-    uint64_t *keys;            // output keys (pos << idbits | id) | key_or
+    uint64_t *keys;            // output keys key_or + (pos << idbits) | id
     uint64_t cap;
-    uint64_t key_or;           // batched scans: the job number in the key's top bits
+    uint64_t key_or;           // batched scans: the job's first byte in the batch's texts << idbits
     uint64_t *counters;        // [0] = occurrences found
     uint64_t *pending;         // deferred start positions (NULL: verify inline), kPendingSegments
                                // segments of seg_cap entries; wave w of workgroup g appends to
@@ -206,7 +206,7 @@ __device__ inline void verify_wave_var(const VerifyArgs &a, uint64_t i0, bool ac
     }
     const uint32_t lane = __lane_id();
     const uint32_t first = (uint32_t)__builtin_ctzll(__ballot(true));
-    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    const uint64_t emit = a.key_or + (i0 << a.idbits);
     while (__ballot(it < end)) {
         uint32_t b = 0, c = 0;
         if (it < end) {
@@ -259,7 +259,7 @@ __device__ inline void emit_found(const VerifyArgs &a, uint64_t i0, uint32_t u1)
     }
     const uint64_t exec = __ballot(true);
     const uint32_t lane = __lane_id();
-    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    const uint64_t emit = a.key_or + (i0 << a.idbits);
     if (exec == ~0ull) {
         uint32_t inc = c;                     // inclusive prefix of c over the wave
 #pragma unroll
@@ -345,7 +345,7 @@ __device__ inline uint32_t emit_runs_buffered(const VerifyArgs &a, uint64_t i0, 
         flush_found(a, buf, fbn);
         fbn = 0;
     }
-    const uint64_t emit = a.key_or | (i0 << a.idbits);
+    const uint64_t emit = a.key_or + (i0 << a.idbits);
     if (total > cap) {
         unsigned long long base = 0;
         if (lane == 63) base = atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)total);
