@@ -307,6 +307,45 @@ def test_scan_batch_one_shot(torch_cuda, mag):
     assert mag.scan_batch([], []) == []
 
 
+def test_batch_positions_past_32_bits(torch_cuda, mag):
+    """Keys hold positions in the jobs' texts laid end to end: five views of
+    one 900 MB text (4.5 GB in all, past 2^32) with planted patterns. Text
+    bytes are A..T and every pattern starts with Z, so the planted copies
+    are the only occurrences; each view starts 7 bytes later than the one
+    before, and filter and dense plans alternate."""
+    torch = torch_cuda
+    rng = np.random.default_rng(4242)
+    n = 900_000_000
+    big = torch.randint(65, 85, (n,), dtype=torch.uint8, device="cuda")
+    r, m = 150, 16
+    pats = np.empty((r, m), dtype=np.uint8)
+    pats[:, 0] = ord("Z")
+    pats[:, 1:] = rng.integers(65, 85, (r, m - 1))
+    pats = np.unique(pats, axis=0)
+    r = pats.shape[0]
+    starts = np.sort(rng.choice(n // 64, 400, replace=False)) * 64 + 40
+    which = rng.integers(0, r, starts.size)
+    idx = torch.from_numpy((starts[:, None] + np.arange(m)).reshape(-1)).cuda()
+    big[idx] = torch.from_numpy(pats[which].reshape(-1)).cuda()
+    plans = [mag.Plan(pats, mode="filter"), mag.Plan(pats, mode="dense")]
+    views, bplans, expect = [], [], []
+    for j in range(5):
+        sh = 7 * j
+        views.append(big[sh:])
+        bplans.append(plans[j % 2])
+        keep = starts >= sh
+        expect.append((starts[keep] - sh, which[keep]))
+    b = mag.Batch(bplans)
+    b.bind(views, 5 * starts.size + 64)
+    for res in (b.run(), b.run()):
+        for j, (occ, (pos, ids)) in enumerate(zip(res, expect)):
+            occ = occ.cpu().numpy()
+            assert occ.shape[0] == pos.size, (j, occ.shape[0], pos.size)
+            assert np.array_equal(occ[:, 0], pos.astype(np.int64)), j
+            assert np.array_equal(occ[:, 1], ids.astype(np.int64)), j
+    b.close()
+
+
 @pytest.mark.parametrize("words", [8, 16])
 def test_batch_words_per_lane(torch_cuda, mag, words):
     """Filter tiles of 1024 * words samples (dense jobs take their own launch):
