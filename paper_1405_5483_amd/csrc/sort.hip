@@ -380,15 +380,10 @@ __global__ __launch_bounds__(256) void k_radix_scan(const uint32_t *cnt, uint64_
     if (tid == 0) tot[d] = carry;
 }
 
-// cnt (sorts of at most kFusedScanChunks chunks; else null): the raw digit
-// counts, which each workgroup scans itself for its chunks (every workgroup
-// reads its digit's C counts), so that no scan kernel is launched: small
-// sorts are launch-bound.
-constexpr uint64_t kFusedScanChunks = 256;
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t *src, uint64_t *dst,
                                                                  const uint64_t *zp, uint64_t cap,
                                                                  int shift, const uint64_t *off,
-                                                                 const uint64_t *tot, const uint32_t *cnt) {
+                                                                 const uint64_t *tot) {
     __shared__ uint64_t s_base[256];
     __shared__ uint64_t s_off[256];
     __shared__ uint64_t s_tmp[4];
@@ -400,22 +395,10 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
     const uint64_t K = radix_chunk_keys(z), C = (z + K - 1) / K;
     const uint32_t tid = threadIdx.x;
     uint64_t all;
-    uint64_t t = 0;
-    if (cnt) {
-        for (uint64_t c2 = 0; c2 < C; ++c2) t += cnt[(size_t)tid * C + c2];
-    } else {
-        t = tot[tid];
-    }
-    s_base[tid] = block_exclusive_scan256(t, s_tmp, &all);
+    s_base[tid] = block_exclusive_scan256(tot[tid], s_tmp, &all);
     for (int v = 0; v < kScatterWaves; ++v) s_run[v][tid] = 0;
     for (uint64_t c = blockIdx.x; c < C; c += gridDim.x) {
-        uint64_t before = 0;                 // digit tid's keys in the chunks before c
-        if (cnt) {
-            for (uint64_t c2 = 0; c2 < c; ++c2) before += cnt[(size_t)tid * C + c2];
-        } else {
-            before = off[(size_t)tid * C + c];
-        }
-        s_off[tid] = s_base[tid] + before;
+        s_off[tid] = s_base[tid] + off[(size_t)tid * C + c];
         __syncthreads();
         const uint64_t beg = c * K;
         const uint64_t end = beg + K < z ? beg + K : z;
@@ -528,18 +511,15 @@ mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbit
     const uint64_t *zp = sc.counters + kSortCountSlot;
     uint64_t *src = sc.keys, *dst = sc.keys + cap;
     uint64_t *tot = sc.radix_off + (size_t)256 * sc.radix_chunks;
-    // bounds of at most kFusedScanChunks chunks: the scatter scans the counts
-    const bool fused = radix_chunks(bound) <= kFusedScanChunks;
     for (int p = 0; p < radix_passes(nbits, lo); ++p) {
         const int shift = lo + 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kRadixThreads), 0, stream,
                            (const uint64_t *)src, zp, cap, shift, sc.hist);
-        if (!fused)
-            hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, stream, (const uint32_t *)sc.hist,
-                               sc.radix_off, tot, zp, cap);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, stream, (const uint32_t *)sc.hist,
+                           sc.radix_off, tot, zp, cap);
         hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kRadixThreads), 0, stream,
                            (const uint64_t *)src, dst, zp, cap, shift, (const uint64_t *)sc.radix_off,
-                           (const uint64_t *)tot, fused ? (const uint32_t *)sc.hist : nullptr);
+                           (const uint64_t *)tot);
         uint64_t *t = src;
         src = dst;
         dst = t;
