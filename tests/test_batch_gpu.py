@@ -307,6 +307,27 @@ def test_scan_batch_one_shot(torch_cuda, mag):
     assert mag.scan_batch([], []) == []
 
 
+def test_batch_rounds_with_more_keys_than_the_buffer(torch_cuda, mag):
+    """Jobs whose verification rounds emit more keys than a wave's buffer:
+    a^n against six copies of a^8 (384 keys per round of 64 starts), short
+    enough to defer its starts to the batch verification kernel, as a filter
+    and as a dense job, between two ordinary jobs."""
+    torch = torch_cuda
+    a = np.full(30_000, ord("a"), dtype=np.uint8)
+    dup = np.full((6, 8), ord("a"), dtype=np.uint8)
+    jobs = _small_jobs(2, seed=909)
+    jobs[1:1] = [Job(a, dup, {"dup": "filter"}), Job(a.copy(), dup, {"dup": "dense"})]
+    plans = [mag.Plan(jobs[0].patterns), mag.Plan(dup, q=2, k=2, sigma_prime=2, mode="filter"),
+             mag.Plan(dup, mode="dense"), mag.Plan(jobs[3].patterns)]
+    texts = _upload(torch, [j.text for j in jobs], [3, 0, 5, 1])
+    total = sum(om.occ_hashed(j.text, j.patterns)[0].size for j in jobs)
+    b = mag.Batch(plans)
+    b.bind(texts, total + 64)
+    _check_jobs(b.run(), jobs)
+    _check_jobs(b.run(), jobs)
+    b.close()
+
+
 def test_batch_positions_past_32_bits(torch_cuda, mag):
     """Keys hold positions in the jobs' texts laid end to end: five views of
     one 900 MB text (4.5 GB in all, past 2^32) with planted patterns. Text

@@ -414,6 +414,27 @@ def test_many_matches_radix_path(torch_cuda, mag, kw):
     assert st["verifications"] == n - m + 1
 
 
+@pytest.mark.parametrize("kw", [dict(q=2, k=2, sigma_prime=2, mode="filter"),
+                                dict(q=2, k=2, sigma_prime=2, mode="filter", verify="deferred",
+                                     verify_buffer=1 << 20),
+                                dict(mode="dense"),
+                                dict(mode="dense", verify="deferred", verify_buffer=1 << 20)],
+                         ids=["filter", "filter-deferred", "dense", "dense-deferred"])
+def test_rounds_with_more_keys_than_the_buffer(torch_cuda, mag, kw):
+    # a^n against {a^m} x 6 ids: every verification round of 64 starts emits
+    # 384 keys, more than a wave's found-key buffer holds (64 keys in the
+    # scan kernels, 256 in the verification kernel), so those rounds go to
+    # the output directly; the buffers' leftovers are flushed per workgroup.
+    n, m, dup = 50_000, 8, 6
+    T = np.full(n, ord("a"), dtype=np.uint8)
+    P = np.full((dup, m), ord("a"), dtype=np.uint8)
+    plan = mag.Plan(P, **kw)
+    pos, ids, _ = _gpu_occ(torch_cuda, mag, T, plan)
+    assert pos.size == dup * (n - m + 1)
+    assert np.array_equal(pos, np.repeat(np.arange(n - m + 1, dtype=np.uint64), dup))
+    assert np.array_equal(ids, np.tile(np.arange(dup, dtype=np.uint32), n - m + 1))
+
+
 def test_many_matches_unequal_lengths_radix_path(torch_cuda, mag):
     # a^n against {a^10, a^8, a^9, a^8}: every pattern that fits matches at
     # every start, found through one prefix group in member order (not id
