@@ -328,6 +328,36 @@ def test_batch_rounds_with_more_keys_than_the_buffer(torch_cuda, mag):
     b.close()
 
 
+@pytest.mark.parametrize("plants", [3, 5], ids=["lds-sort", "radix-sort"])
+def test_batch_many_jobs(torch_cuda, mag, plants):
+    """2,100 jobs (more than the record writer stages in LDS), each a
+    256-byte slice of one buffer scanned with one shared plan: 3 planted
+    occurrences per job (6,300, sorted in the finishing kernel) or 5 (10,500,
+    the device-wide sort)."""
+    torch = torch_cuda
+    rng = np.random.default_rng(77 + plants)
+    njobs, seg, m = 2100, 256, 8
+    pats = np.unique(np.concatenate([np.full((6, 1), ord("Z"), np.uint8),
+                                     rng.integers(65, 85, (6, m - 1)).astype(np.uint8)], axis=1), axis=0)
+    text = rng.integers(65, 85, njobs * seg).astype(np.uint8)
+    at = np.array([10, 60, 110, 160, 210][:plants])
+    which = rng.integers(0, pats.shape[0], (njobs, plants))
+    for j in range(njobs):
+        for t in range(plants):
+            text[j * seg + at[t]:j * seg + at[t] + m] = pats[which[j, t]]
+    big = torch.from_numpy(text).cuda()
+    plan = mag.Plan(pats)
+    b = mag.Batch([plan] * njobs)
+    b.bind([big[j * seg:(j + 1) * seg] for j in range(njobs)], njobs * plants + 64)
+    res = b.run()
+    assert len(res) == njobs
+    for j, occ in enumerate(res):
+        occ = occ.cpu().numpy()
+        assert np.array_equal(occ[:, 0], at.astype(np.int64)), j
+        assert np.array_equal(occ[:, 1], which[j].astype(np.int64)), j
+    b.close()
+
+
 def test_batch_positions_past_32_bits(torch_cuda, mag):
     """Keys hold positions in the jobs' texts laid end to end: five views of
     one 900 MB text (4.5 GB in all, past 2^32) with planted patterns. Text
