@@ -618,8 +618,9 @@ mag_status scan_enqueue(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_matc
     if (s != MAG_OK) return s;
     if (sort_on_device) {
         const int lo = sort_low_bit(p->var, idbits);
-        s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, lo, stream);
-        if (s == MAG_OK)
+        // the last pass writes the records
+        s = launch_radix_sort(sc, out_cap, out_cap, idbits + posbits, lo, stream, d_out, idbits, ~0ull);
+        if (s == MAG_OK && radix_passes(idbits + posbits, lo) == 0)
             s = launch_expand(sc, out_cap, out_cap, idbits + posbits, lo, d_out, idbits, ~0ull, stream);
         if (s != MAG_OK) return s;
     }
@@ -785,8 +786,9 @@ mag_status mag_scan(mag_plan *p, const uint8_t *d_text, uint64_t n, mag_match *d
         std::lock_guard<std::mutex> lock(p->mtx);
         s = ensure_radix_scratch(p->scratch, host[4], stream);
         const int lo = sort_low_bit(p->var, idbits);
-        if (s == MAG_OK) s = launch_radix_sort(p->scratch, host[4], out_cap, nbits, lo, stream);
         if (s == MAG_OK)
+            s = launch_radix_sort(p->scratch, host[4], out_cap, nbits, lo, stream, d_out, idbits, ~0ull);
+        if (s == MAG_OK && radix_passes(nbits, lo) == 0)
             s = launch_expand(p->scratch, host[4], out_cap, nbits, lo, d_out, idbits, ~0ull, stream);
     }
     return s;

@@ -369,7 +369,12 @@ mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream)
 // Chunks of the device-wide radix sort's counts for outputs of up to `bound`
 // keys (its scratch: 256 * chunks u32 counts, 256 * chunks + 256 u64 offsets).
 uint64_t radix_scratch_chunks(uint64_t bound);
-mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream);
+// out (not null): the last pass writes the records ((key >> idbits) &
+// posmask, the id bits) instead of the sorted keys, which then need no
+// launch_expand (when radix_passes(nbits, lo) > 0).
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream,
+                             mag_match *out = nullptr, int idbits = 0, uint64_t posmask = 0);
+int radix_passes(int nbits, int lo);
 // jbase (batches; njobs + 1 offsets): positions made relative to their jobs'
 // texts (see k_expand).
 mag_status launch_expand(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, mag_match *out,

@@ -96,7 +96,8 @@ static_assert(kRadixChunk % kRadixThreads == 0 && kRadixChunkSmall % kRadixThrea
 constexpr int kScatterMaxRounds = kRadixChunk / kRadixThreads;   // keys per lane
 __device__ void chunk_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg, uint64_t end, uint64_t K,
                               int shift, const uint64_t *s_off, uint64_t *s_keys,
-                              uint32_t (*s_run)[256], uint32_t *s_start, uint64_t *s_tmp) {
+                              uint32_t (*s_run)[256], uint32_t *s_start, uint64_t *s_tmp, mag_match *out,
+                              int idbits, uint64_t posmask) {
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t n = (uint32_t)(end - beg);
     const uint32_t per = (uint32_t)(K / kScatterWaves);          // keys per wave, a multiple of 64
@@ -152,7 +153,9 @@ __device__ void chunk_scatter(const uint64_t *src, uint64_t *dst, uint64_t beg, 
     for (uint32_t i = tid; i < n; i += kRadixThreads) {
         const uint64_t k = s_keys[i];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
-        dst[s_off[d] + (i - s_start[d])] = k;
+        const uint64_t at = s_off[d] + (i - s_start[d]);
+        if (out) out[at] = to_record(k, idbits, posmask);
+        else dst[at] = k;
     }
 #pragma unroll
     for (int v = 0; v < kScatterWaves; ++v) s_run[v][tid] = 0;
@@ -380,10 +383,13 @@ __global__ __launch_bounds__(256) void k_radix_scan(const uint32_t *cnt, uint64_
     if (tid == 0) tot[d] = carry;
 }
 
+// out (the last pass of a sort whose records need no job offsets; else
+// null): the records are written in place of the sorted keys.
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t *src, uint64_t *dst,
                                                                  const uint64_t *zp, uint64_t cap,
                                                                  int shift, const uint64_t *off,
-                                                                 const uint64_t *tot) {
+                                                                 const uint64_t *tot, mag_match *out,
+                                                                 int idbits, uint64_t posmask) {
     __shared__ uint64_t s_base[256];
     __shared__ uint64_t s_off[256];
     __shared__ uint64_t s_tmp[4];
@@ -402,7 +408,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t 
         __syncthreads();
         const uint64_t beg = c * K;
         const uint64_t end = beg + K < z ? beg + K : z;
-        chunk_scatter(src, dst, beg, end, K, shift, s_off, s_keys, s_run, s_start, s_tmp);
+        chunk_scatter(src, dst, beg, end, K, shift, s_off, s_keys, s_run, s_start, s_tmp, out, idbits, posmask);
     }
 }
 
@@ -502,7 +508,8 @@ mag_status ensure_radix_scratch(Scratch &sc, uint64_t bound, hipStream_t stream)
     return MAG_OK;
 }
 
-mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream) {
+mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbits, int lo, hipStream_t stream,
+                             mag_match *out, int idbits, uint64_t posmask) {
     if (bound <= kSmallMax) return MAG_OK;
     if (sc.radix_chunks < radix_chunks(bound) || !sc.hist)
         return fail(MAG_E_INVALID, "radix scratch smaller than the bound");
@@ -511,7 +518,8 @@ mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbit
     const uint64_t *zp = sc.counters + kSortCountSlot;
     uint64_t *src = sc.keys, *dst = sc.keys + cap;
     uint64_t *tot = sc.radix_off + (size_t)256 * sc.radix_chunks;
-    for (int p = 0; p < radix_passes(nbits, lo); ++p) {
+    const int passes = radix_passes(nbits, lo);
+    for (int p = 0; p < passes; ++p) {
         const int shift = lo + 8 * p;
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kRadixThreads), 0, stream,
                            (const uint64_t *)src, zp, cap, shift, sc.hist);
@@ -519,7 +527,7 @@ mag_status launch_radix_sort(Scratch &sc, uint64_t bound, uint64_t cap, int nbit
                            sc.radix_off, tot, zp, cap);
         hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kRadixThreads), 0, stream,
                            (const uint64_t *)src, dst, zp, cap, shift, (const uint64_t *)sc.radix_off,
-                           (const uint64_t *)tot);
+                           (const uint64_t *)tot, p + 1 == passes ? out : nullptr, idbits, posmask);
         uint64_t *t = src;
         src = dst;
         dst = t;
